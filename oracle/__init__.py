@@ -1,0 +1,18 @@
+"""Plain FP64 CPU oracle for randUTV (Alg. 3) and powerURV (Alg. 1).
+
+TEST INFRASTRUCTURE, not product code. Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
+import, call or run anything in this package. It shares no code with the HIP
+library in ``paper_2106_13402_amd`` and never imports it.
+"""
+from .philox import gaussian, philox4x64_10
+from .hqr import apply_q, form_q, hqr
+from .small_svd import canonical_signs, small_svd
+from .randutv import randutv
+from .powerurv import powerurv
+from . import metrics
+
+__all__ = [
+    "gaussian", "philox4x64_10", "hqr", "apply_q", "form_q",
+    "small_svd", "canonical_signs", "randutv", "powerurv", "metrics",
+]

@@ -1,0 +1,14 @@
+"""Seeded synthetic test matrices, shared by the tests, the smoke check and
+the benchmark. Holds none of the factorization's arithmetic: only the input
+recipes (Gaussian matrices and ``Q1 diag(s) Q2^T`` with Haar-distributed
+orthogonal factors, Sec. 5.2 "fast decay" construction).
+"""
+from .matrices import (
+    SPECTRA,
+    gaussian_matrix,
+    haar,
+    spectral_matrix,
+    spectrum,
+)
+
+__all__ = ["SPECTRA", "gaussian_matrix", "haar", "spectral_matrix", "spectrum"]
