@@ -1,0 +1,279 @@
+#!/usr/bin/env python3
+"""Time-to-factor of randUTV (Alg. 3) on one MI355X, FP64 path.
+
+Workload (default): A = Q1 diag(s) Q2^T, n = 16384, s_j = exp(-j/800), Q1/Q2
+Haar (synthetic, seeded, generated on the GPU), b = 128, q = 2, sketch seed 1,
+U and V accumulated. One "step" is one complete factorization A = U T V^T with
+A, U, T, V and the workspace resident in HBM before the timed region starts.
+
+Printed: ONE JSON line with the time per factorization (`value`, seconds,
+lower is better), the roofline entry of the dominant kernel measured live
+with HIP events on the library's stream, the accuracy of the result against
+the known spectrum, and the FP64 CPU oracle timed on a bounded sample of the
+same workload.
+
+    python bench.py [--steps K] [--warmup W] [--n N] [--b B] [--q Q]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-factor & %MFMA peak, n=16384 randUTV FP64 vs mixed at equal e_k"
+PEAK_FP64_TFLOPS = 78.6     # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------- algorithmic work
+def step_flops(m: int, n: int, b: int, q: int, i: int) -> float:
+    """Flops of loop iteration i (1-based) of Alg. 3 with U and V accumulated.
+
+    Sketch (2 + 4q) M N b; the two compact-WY applications of V_i (to T: m
+    rows, to V: n rows) and of U_i (to T(I2uI3, J3) and to U: m rows), each
+    4 rows x cols x b; the two panel QRs 2 (M + N) b^2; the small b x b block
+    updates. The O(b^3) Jacobi SVD is not counted.
+    """
+    c0 = b * (i - 1)
+    M, N = m - c0, n - c0
+    if c0 + b >= n:
+        nb = N
+        f = 2.0 * c0 * nb * nb + 2.0 * (m + n) * nb * nb
+        if M > nb:
+            f += 2.0 * M * nb * nb + 4.0 * m * M * nb
+        return f
+    f = (2.0 + 4.0 * q) * M * N * b
+    f += 4.0 * m * N * b + 4.0 * M * (N - b) * b
+    f += 4.0 * n * N * b + 4.0 * m * M * b
+    f += 2.0 * (M + N) * b * b
+    f += 2.0 * b * b * (N - b) + 2.0 * c0 * b * b + 2.0 * (m + n) * b * b
+    return f
+
+
+def total_flops(m: int, n: int, b: int, q: int) -> float:
+    return sum(step_flops(m, n, b, q, i) for i in range(1, math.ceil(n / b) + 1))
+
+
+# ----------------------------------------------------------- error estimates
+def _power_norm(apply, apply_t, n, device, iters=40, seed=0):
+    """||M||_2 by power iteration on M^T M (matvecs only)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    x = torch.randn(n, 1, dtype=torch.float64, device=device, generator=g)
+    x /= torch.linalg.vector_norm(x)
+    est = 0.0
+    for _ in range(iters):
+        y = apply_t(apply(x))
+        nrm = float(torch.linalg.vector_norm(y))
+        if nrm == 0.0:
+            return 0.0
+        est = math.sqrt(nrm)
+        x = y / nrm
+    return est
+
+
+def accuracy(A, U, T, V, s, kgrid):
+    import torch
+    dev = A.device
+    n = A.shape[1]
+    nA = float(s[0])
+
+    def orth(Q):
+        return _power_norm(lambda x: Q.t() @ (Q @ x) - x, lambda x: Q.t() @ (Q @ x) - x,
+                           Q.shape[1], dev, iters=30)
+
+    rec = _power_norm(lambda x: A @ x - U @ (T @ (V.t() @ x)),
+                      lambda y: A.t() @ y - V @ (T.t() @ (U.t() @ y)), n, dev) / nA
+    ratios = []
+    for k in kgrid:
+        Tk = T[k:, k:]
+        ek = _power_norm(lambda x: Tk @ x, lambda y: Tk.t() @ y, n - k, dev, iters=30)
+        ratios.append(ek / float(s[k]))
+    worst = max(range(len(kgrid)), key=lambda i: ratios[i])
+    return {
+        "orth_U": orth(U), "orth_V": orth(V), "recon": rec,
+        "ek_over_sigma_max": ratios[worst], "ek_over_sigma_argmax_k": int(kgrid[worst]),
+        "ek_over_sigma_min": min(ratios), "k_grid": [int(k) for k in kgrid],
+        "norm_estimator": "power iteration (30-40 steps)",
+    }
+
+
+# -------------------------------------------------------------- CPU baseline
+def cpu_baseline(A_host, b, q, seed, budget_s):
+    """Time the oracle on its first steps of the same factorization and scale
+    by the algorithmic flop model to a whole factorization."""
+    import numpy as np
+    import oracle
+
+    m, n = A_host.shape
+    marks = [time.perf_counter()]
+
+    class Enough(Exception):
+        pass
+
+    def on_step(i, T):
+        marks.append(time.perf_counter())
+        if marks[-1] - marks[0] >= budget_s:
+            raise Enough()
+
+    try:
+        oracle.randutv(np.asfortranarray(A_host), b, q, seed, on_step=on_step)
+    except Enough:
+        pass
+    steps = len(marks) - 1
+    elapsed = marks[-1] - marks[0]
+    done = sum(step_flops(m, n, b, q, i) for i in range(1, steps + 1))
+    rate = done / elapsed
+    total = total_flops(m, n, b, q)
+    cores = len(os.sched_getaffinity(0))
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max(int(p.get("num_threads", 0)) for p in threadpool_info()) or cores
+    except Exception:
+        pass
+    return {
+        "value": total / rate, "unit": "s", "cores": cores, "kind": "oracle",
+        "sample": (f"first {steps} of {math.ceil(n / b)} steps of the same randUTV "
+                   f"(n={n}, b={b}, q={q}, U and V accumulated) in {elapsed:.1f} s; "
+                   f"time per factorization extrapolated by the algorithmic flop model "
+                   f"({rate / 1e9:.1f} GFLOP/s over the sample)"),
+    }
+
+
+# ---------------------------------------------------------------------- main
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--b", type=int, default=128)
+    ap.add_argument("--q", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2106_13402_amd as rrf
+    from synthetic import spectral_matrix, spectrum
+
+    dev = torch.device("cuda:0")
+    n, b, q = args.n, args.b, args.q
+    s = spectrum("exp", n, scale=800.0)
+    log(f"generating A = Q1 diag(exp(-j/800)) Q2^T, n={n}")
+    A = spectral_matrix(n, n, s, seed=0, device=dev)
+    U = rrf.empty_colmajor(n, n, dev)
+    T = rrf.empty_colmajor(n, n, dev)
+    V = rrf.empty_colmajor(n, n, dev)
+    torch.cuda.synchronize()
+
+    def factor():
+        # same entry point as rrf.randutv, with preallocated outputs
+        import ctypes as C
+        from paper_2106_13402_amd import _lib
+        nbytes = rrf.workspace_size("randutv", n, n, b, q)
+        ws = rrf._workspace(dev, nbytes)
+        opts = _lib.rrf_opts()
+        rrf.lib.rrf_opts_init(C.byref(opts))
+        opts.stream = torch.cuda.current_stream(dev).cuda_stream
+        opts.workspace = ws.data_ptr()
+        opts.workspace_bytes = ws.numel()
+        st = rrf.lib.rrf_randutv_ex(n, n, A.data_ptr(), n, b, q, args.seed, U.data_ptr(),
+                                    T.data_ptr(), V.data_ptr(), C.byref(opts))
+        if st != 0:
+            raise RuntimeError(f"rrf_randutv_ex failed: {st} "
+                               f"{rrf.lib.rrf_last_error().decode()}")
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        factor()
+        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t0:.3f} s")
+    rrf.trace_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        factor()
+        log(f"step {k + 1}/{args.steps} done at {time.perf_counter() - t0:.3f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = rrf.trace_read()
+    rrf.trace_enable(False)
+    per = elapsed / args.steps
+
+    gemms = [e for e in kern if e["name"].startswith("dgemm")]
+    dom = max(gemms, key=lambda e: e["ms"])
+    gemm_ms = sum(e["ms"] for e in gemms)
+    gemm_flops = sum(e["flops"] for e in gemms)
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    breakdown = {e["name"]: {"launches": e["launches"] // args.steps,
+                             "ms_per_step": e["ms"] / args.steps,
+                             "tflops": (e["flops"] / (e["ms"] * 1e-3) / 1e12) if e["flops"] else None,
+                             "gbs": (e["bytes"] / (e["ms"] * 1e-3) / 1e9) if e["bytes"] else None}
+                 for e in kern}
+    model_flops = total_flops(n, n, b, q)
+
+    out = {
+        "metric": METRIC,
+        "value": per,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": per * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"randUTV n={n} b={b} q={q}, A=Q1 diag(exp(-j/800)) Q2^T, "
+                               f"U and V accumulated, FP64", "n": n, "b": b, "q": q,
+                   "precision": "fp64", "sketch_seed": args.seed},
+        "roofline": {
+            "bound": "mfma", "kernel": dom["name"], "achieved": achieved,
+            "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": dom["flops"] / dom["launches"],
+            "avg_launch_ms": dom["ms"] / dom["launches"],
+        },
+        "gemm_all": {"tflops": gemm_flops / (gemm_ms * 1e-3) / 1e12,
+                     "frac": gemm_flops / (gemm_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                     "ms_per_step": gemm_ms / args.steps},
+        "model_tflops": model_flops / per / 1e12,
+        "kernels": breakdown,
+    }
+    if not args.no_accuracy:
+        kgrid = [k for k in (0, 64, 127, 128, 129, 256, 1000, 2000, 4000, 8000, 12000) if k < n]
+        out["accuracy"] = accuracy(A, U, T, V, s, kgrid)
+        log(f"accuracy: {out['accuracy']}")
+    if not args.no_cpu_baseline:
+        log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
+        A_host = A.cpu().numpy()
+        del U, T, V
+        out["cpu_baseline"] = cpu_baseline(A_host, b, q, args.seed, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

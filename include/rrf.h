@@ -1,0 +1,187 @@
+/*
+ * rrf.h -- randomized rank-revealing UTV factorizations on AMD MI355X (gfx950).
+ *
+ * Heavner, Chen, Gopal, Martinsson, "Efficient algorithms for computing
+ * rank-revealing factorizations on a GPU" (arXiv 2106.13402).
+ *
+ * Given A (m x n, m >= n), every factorization here returns
+ *     A = U * T * V^T,
+ * U (m x m) and V (n x n) orthogonal, T (m x n) upper trapezoidal
+ * (Sec. 1, the UTV problem statement).
+ *
+ * Conventions shared by every entry point:
+ *  - All matrices are column-major IEEE binary64 in DEVICE memory of the
+ *    current HIP device, allocated and owned by the caller. The library keeps
+ *    no pointer to them after the call returns and frees nothing it did not
+ *    allocate.
+ *  - Leading dimensions: A has lda >= m; U, T and V are tight: ldu = m,
+ *    ldt = m, ldv = n. T may alias A only when lda == m (factor in place).
+ *  - U or V may be NULL: that factor is then not accumulated (Sec. 4.1
+ *    forms U and V only "when the U and V matrices are desired").
+ *  - Return value: RRF_OK (0) on success; -k when argument k (1-based) is
+ *    invalid (LAPACK info convention), checked before any device work; a
+ *    positive RRF_E_* code otherwise. rrf_last_error() describes the last
+ *    failure of the calling thread.
+ *  - The sketch matrices are drawn from a counter-based generator:
+ *    Philox4x64-10 keyed by (seed, stream) with counter (row/4, col, 0, 0),
+ *    turned into N(0,1) numbers by Box-Muller; entry (r, c) of a stream is a
+ *    function of (seed, stream, r, c) only. randUTV step i (1-based) uses
+ *    stream i; powerURV uses stream 0.
+ *  - Unless rrf_opts.async is set, a call returns after the device work is
+ *    complete and its status covers device-side failures.
+ */
+#ifndef RRF_H_
+#define RRF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define RRF_OK          0
+#define RRF_E_HIP       1  /* a HIP runtime call or a kernel failed            */
+#define RRF_E_NOMEM     2  /* workspace too small or device allocation failed  */
+#define RRF_E_NOTSUP    3  /* valid request outside what is implemented        */
+#define RRF_E_NUMERIC   4  /* non-finite input (only with check_finite)         */
+#define RRF_E_INTERNAL  5  /* a device-side consistency check failed           */
+
+/* ---- precision modes -------------------------------------------------- */
+#define RRF_PREC_FP64   0  /* every step in binary64                           */
+
+/* ---- algorithms (for rrf_workspace_size) -------------------------------- */
+#define RRF_ALG_RANDUTV  0
+#define RRF_ALG_POWERURV 1
+
+typedef struct rrf_opts {
+  int precision;          /* RRF_PREC_*                                        */
+  void* stream;           /* hipStream_t to order the work on; NULL = null stream */
+  void* workspace;        /* device scratch; NULL = library-managed cache      */
+  size_t workspace_bytes; /* size of `workspace` (>= rrf_workspace_size(...))  */
+  int async;              /* 0: return after completion; 1: only enqueue       */
+  int check_finite;       /* 1: reject A with NaN/Inf (RRF_E_NUMERIC) before any
+                             work is enqueued; synchronizes the stream        */
+} rrf_opts;
+
+/* Fill `opts` with the defaults (FP64, null stream, library workspace,
+ * synchronous, no finiteness check). */
+void rrf_opts_init(rrf_opts* opts);
+
+/*
+ * randUTV_basic -- Alg. 3 (Appendix B), the blocked randomized UTV of Sec. 4.1.
+ *
+ * Loop over s = ceil(n/b) steps; step i sketches the trailing block T22 with
+ * Y = (T22^T T22)^q T22^T G_i, takes V_i from an unpivoted Householder QR of
+ * Y, updates T <- T V_i, takes U_i and R from the Householder QR of the new
+ * panel T(I2 u I3, J2), updates T <- U_i^T T, and diagonalizes the b x b block
+ * R by an SVD. The last step takes the SVD of the remaining block (as a
+ * Householder QR followed by an SVD of its square R factor when it is tall).
+ *
+ *  m, n   : rows and columns of A, 1 <= n <= m            (args 1, 2)
+ *  A      : input, read only unless T == A                 (arg 3)
+ *  lda    : leading dimension of A, lda >= m               (arg 4)
+ *  b      : block size, b >= 1                             (arg 5)
+ *  q      : number of power iterations, q >= 0             (arg 6)
+ *  seed   : generator key                                  (arg 7)
+ *  U      : m x m output or NULL                           (arg 8)
+ *  T      : m x n output, upper trapezoidal; every b x b diagonal block is
+ *           diagonal with non-negative entries in descending order (arg 9)
+ *  V      : n x n output or NULL                           (arg 10)
+ * m < n returns RRF_E_NOTSUP.
+ */
+int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                int32_t q, uint64_t seed, double* U, double* T, double* V);
+int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                   int32_t q, uint64_t seed, double* U, double* T, double* V,
+                   const rrf_opts* opts);
+
+/*
+ * powerURV -- Alg. 1 (Sec. 3.2).
+ *
+ * V starts as an n x n Gaussian; q rounds of  Y_hat = A V,
+ * V_hat = HQR_thin(Y_hat), Y = A^T V_hat, V = HQR_thin(Y); then
+ * A_hat = A V and [U, R] = HQR_full(A_hat), T = R. With q = 0 the method is
+ * RURV (Sec. 3.1) and V is the orthogonal factor of the Householder QR of the
+ * Gaussian. T(k,k) carries the sign of the Householder R diagonal.
+ *
+ * Arguments as for rrf_randutv, except that b is the panel width of the
+ * blocked Householder QR (it changes rounding only).
+ */
+int rrf_powerurv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                 int32_t q, uint64_t seed, double* U, double* T, double* V);
+int rrf_powerurv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                    int32_t q, uint64_t seed, double* U, double* T, double* V,
+                    const rrf_opts* opts);
+
+/* Bytes of device workspace an _ex call with these arguments needs
+ * (alg = RRF_ALG_*); 0 for invalid arguments. */
+size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
+                          int precision);
+
+/* Release the library-managed workspace cache of the current device. */
+int rrf_release_workspace(void);
+
+/* ---- building blocks, exported for component tests ------------------------
+ * Each runs on `stream` (hipStream_t, NULL = null stream) and returns after
+ * the work is enqueued; device memory and ownership as above. */
+
+/* The sketch generator: out(r, c) = N(0,1) entry (r, c) of (seed, stream),
+ * 0 <= r < rows, 0 <= c < cols, column-major with leading dimension ld. */
+int rrf_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+                 double* out, int64_t ld, void* stream);
+
+/* C = alpha * op(A) * op(B) + beta * C in binary64 (op = transpose when the
+ * trans flag is 1). op(A) is M x K, op(B) is K x N. With beta == 0, C is not
+ * read. `work`/`work_bytes` provide scratch for split-K partial sums (may be
+ * NULL/0: no split). */
+int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+              double* C, int64_t ldc, void* work, size_t work_bytes, void* stream);
+
+/* Householder QR of the M x k panel P (M >= k, 1 <= k <= 256), Sec. 2.3:
+ * reflectors H_i = I - tau_i v_i v_i^T with the LAPACK dlarfg sign rule,
+ * Q = H_1 ... H_k = I - W Tf W^T (compact WY). Outputs: W (M x k, explicit
+ * unit lower trapezoidal, ld ldw; may alias P when ldw == ldp), R (k x k upper
+ * triangular, ld ldr; may be NULL), Tf (k x k upper triangular, ld ldt), tau
+ * (k). `work` must hold rrf_panel_workspace_size(M, k) bytes. */
+size_t rrf_panel_workspace_size(int64_t M, int64_t k);
+int rrf_householder_panel(int64_t M, int64_t k, double* P, int64_t ldp, double* W,
+                          int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt,
+                          double* tau, void* work, size_t work_bytes, void* stream);
+
+/* SVD of a k x k matrix B (1 <= k <= 256): B = Us diag(d) Vs^T with d in
+ * descending order and each pair (u_j, v_j) signed so that the entry of v_j
+ * of largest magnitude is positive (lowest index on ties). Us, Vs k x k with
+ * ld k. `work` must hold rrf_block_svd_workspace_size(k) bytes. */
+size_t rrf_block_svd_workspace_size(int64_t k);
+int rrf_block_svd(int64_t k, const double* B, int64_t ldb, double* Us, double* d,
+                  double* Vs, void* work, size_t work_bytes, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------- */
+const char* rrf_status_string(int status);
+const char* rrf_last_error(void);
+
+/* Per-kernel timing. When enabled, the library records a pair of HIP events
+ * around every kernel launch, on the launch's own stream, and the launch's
+ * algorithmic flop and byte counts (GEMM: 2 M N K flops; panel: the panel
+ * read and the reflectors written; generator: the matrix written).
+ * rrf_trace_enable(on) clears the totals and switches recording on or off.
+ * rrf_trace_read() waits for the recorded events and fills up to
+ * max_entries totals, one per kernel class that ran; returns how many. */
+typedef struct rrf_trace_entry {
+  char name[48];     /* kernel class, e.g. "dgemm_mfma_128x128_NT"          */
+  int64_t launches;  /* launches recorded                                  */
+  double ms;         /* summed event-measured duration, milliseconds       */
+  double flops;      /* summed algorithmic floating-point operations       */
+  double bytes;      /* summed algorithmic HBM bytes (read + written)      */
+} rrf_trace_entry;
+int rrf_trace_enable(int on);
+int rrf_trace_read(rrf_trace_entry* out, int max_entries);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RRF_H_ */

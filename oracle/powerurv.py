@@ -55,17 +55,3 @@ def powerurv(A: np.ndarray, q: int, seed: int, *, rounds: int | None = None):
     T = np.triu(W)                         # m x n upper trapezoidal R
     return U, T, V
 
-
-def total_flops(m: int, n: int, q: int) -> float:
-    """Algorithmic flop count: GEMMs, Householder QRs and explicit Q forms."""
-    gemm = 2.0 * m * n * n
-    qr_mn = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0          # dgeqrf, m x n
-    orgqr_mn = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0        # thin Q, m x n
-    qr_nn = 4.0 * n ** 3 / 3.0
-    f = 0.0
-    if q == 0:
-        f += 2 * qr_nn
-    f += q * (2 * gemm + qr_mn + orgqr_mn + 2 * qr_nn)
-    f += gemm + qr_mn
-    f += 4.0 * m * m * n - 2.0 * m * n * n + 2.0 * n ** 3 / 3.0  # full m x m Q
-    return f

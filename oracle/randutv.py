@@ -117,34 +117,3 @@ def randutv(
             on_step(i, T)
     return U, T, V
 
-
-def step_flops(m: int, n: int, b: int, q: int, i: int, want_uv: bool = True) -> float:
-    """Algorithmic flop count of loop iteration i (1-based) of Alg. 3.
-
-    Counts the sketch products, the two compact-WY applications of V_i (to T
-    and V) and of U_i (to T and U) as GEMMs, the two panel QRs, and the small
-    block updates; the O(b^3) small SVD is excluded.
-    """
-    c0 = b * (i - 1)
-    M, N = m - c0, n - c0
-    if c0 + b >= n:
-        nb = N
-        f = 0.0
-        if M > nb:
-            f += 2.0 * M * nb * nb + (4.0 * m * M * nb if want_uv else 0.0)
-        f += 2.0 * c0 * nb * nb + (2.0 * (m + n) * nb * nb if want_uv else 0.0)
-        return f
-    f = (2.0 + 4.0 * q) * M * N * b            # sketch
-    f += 4.0 * m * N * b                        # T(:, J2∪J3) V_i
-    f += 4.0 * M * (N - b) * b                  # U_i^T T(I2∪I3, J3)
-    f += 2.0 * (M + N) * b * b                  # two panel QRs
-    f += 2.0 * b * b * (N - b) + 2.0 * c0 * b * b  # U_s^T T(I2,J3), T(I1,J2) V_s
-    if want_uv:
-        f += 4.0 * n * N * b + 4.0 * m * M * b  # V and U accumulation
-        f += 2.0 * (m + n) * b * b              # U(:,I2) U_s, V(:,J2) V_s
-    return f
-
-
-def total_flops(m: int, n: int, b: int, q: int, want_uv: bool = True) -> float:
-    s = math.ceil(n / b)
-    return sum(step_flops(m, n, b, q, i, want_uv) for i in range(1, s + 1))

@@ -1,0 +1,218 @@
+"""Randomized rank-revealing UTV factorizations on AMD MI355X (gfx950).
+
+Python binding of librrf (include/rrf.h): argument marshalling only. Torch
+supplies device memory and the current HIP stream; every step of the
+factorizations runs in the library's HIP kernels. There is no CPU fallback:
+without the built library the import fails.
+
+Matrices are column-major float64 device tensors (``x.stride(0) == 1``);
+``colmajor(x)`` makes such a copy of any 2-D tensor.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from . import _lib
+from ._lib import RRFError
+
+__all__ = [
+    "RRFError", "randutv", "powerurv", "gaussian", "dgemm", "householder_panel",
+    "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
+    "trace_read",
+]
+
+lib = _lib.load()
+
+
+def _check(status: int, where: str) -> None:
+    if status != 0:
+        detail = lib.rrf_last_error().decode(errors="replace")
+        raise RRFError(status, where, detail)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _require(x, name: str, rows: int | None = None):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or x.dim() != 2:
+        raise TypeError(f"{name}: expected a 2-D torch tensor")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name}: expected float64, got {x.dtype}")
+    if not x.is_cuda:
+        raise TypeError(f"{name}: expected a device (HIP) tensor")
+    if x.shape[0] > 1 and x.stride(0) != 1:
+        raise ValueError(f"{name}: expected column-major storage (stride(0) == 1); use colmajor()")
+    if rows is not None and x.shape[0] != rows:
+        raise ValueError(f"{name}: expected {rows} rows, got {x.shape[0]}")
+
+
+def _ld(x) -> int:
+    return max(int(x.stride(1)), int(x.shape[0]), 1) if x.shape[1] > 1 else max(int(x.shape[0]), 1)
+
+
+def empty_colmajor(rows: int, cols: int, device, dtype=None):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype or torch.float64, device=device).t()
+
+
+def colmajor(x):
+    """A column-major copy (or ``x`` itself if it already is one)."""
+    if x.dim() == 2 and (x.shape[0] <= 1 or x.stride(0) == 1):
+        return x
+    return x.t().contiguous().t()
+
+
+_WS = {}
+
+
+def _workspace(device, nbytes: int):
+    torch = _torch()
+    key = (str(device),)
+    buf = _WS.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+        _WS[key] = buf
+    return buf
+
+
+def workspace_size(alg: str, m: int, n: int, b: int, q: int) -> int:
+    code = _lib.RRF_ALG_RANDUTV if alg == "randutv" else _lib.RRF_ALG_POWERURV
+    return int(lib.rrf_workspace_size(code, m, n, b, q, _lib.RRF_PREC_FP64))
+
+
+def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, want_v: bool,
+            check_finite: bool, inplace: bool):
+    _require(A, "A")
+    m, n = int(A.shape[0]), int(A.shape[1])
+    dev = A.device
+    U = empty_colmajor(m, m, dev) if want_u else None
+    V = empty_colmajor(n, n, dev) if want_v else None
+    if inplace:
+        if _ld(A) != m:
+            raise ValueError("in-place factorization needs a tight A (lda == m)")
+        T = A
+    else:
+        T = empty_colmajor(m, n, dev)
+    nbytes = workspace_size(alg, m, n, b, q)
+    if nbytes == 0:
+        raise RRFError(_lib.RRF_E_NOTSUP, fname, "no workspace size for these arguments")
+    ws = _workspace(dev, nbytes)
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.stream = _stream_ptr(dev)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = ws.numel()
+    opts.async_ = 0
+    opts.check_finite = 1 if check_finite else 0
+    fn = getattr(lib, fname)
+    st = fn(m, n, A.data_ptr(), _ld(A), b, q, seed,
+            U.data_ptr() if U is not None else None, T.data_ptr(),
+            V.data_ptr() if V is not None else None, C.byref(opts))
+    _check(st, fname)
+    return U, T, V
+
+
+def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
+            check_finite: bool = False, inplace: bool = False):
+    """randUTV (Alg. 3): returns (U, T, V) with A = U T V^T (U/V None if not wanted)."""
+    return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
+                   inplace)
+
+
+def powerurv(A, q: int, seed: int, *, b: int = 128, want_u: bool = True, want_v: bool = True,
+             check_finite: bool = False, inplace: bool = False):
+    """powerURV (Alg. 1): returns (U, T, V); b is the QR panel width."""
+    n = int(A.shape[1])
+    return _factor("rrf_powerurv_ex", "powerurv", A, min(b, max(n, 1)), q, seed, want_u, want_v,
+                   check_finite, inplace)
+
+
+def gaussian(seed: int, stream_id: int, rows: int, cols: int, device="cuda"):
+    """The rows x cols sketch Gaussian of (seed, stream) (column-major)."""
+    out = empty_colmajor(rows, cols, device)
+    _check(lib.rrf_gaussian(seed, stream_id, rows, cols, out.data_ptr() if out.numel() else None,
+                            max(rows, 1), _stream_ptr(out.device)), "rrf_gaussian")
+    return out
+
+
+def dgemm(A, B, *, transa: bool = False, transb: bool = False, alpha: float = 1.0,
+          beta: float = 0.0, C_out=None, split_work: bool = True):
+    """C = alpha op(A) op(B) + beta C on the FP64 MFMA kernel."""
+    torch = _torch()
+    _require(A, "A")
+    _require(B, "B")
+    M = int(A.shape[1] if transa else A.shape[0])
+    K = int(A.shape[0] if transa else A.shape[1])
+    Kb = int(B.shape[1] if transb else B.shape[0])
+    N = int(B.shape[0] if transb else B.shape[1])
+    if K != Kb:
+        raise ValueError("inner dimensions differ")
+    if C_out is None:
+        C_out = empty_colmajor(M, N, A.device)
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs C_out")
+    _require(C_out, "C", rows=M)
+    work = torch.empty(8 * M * N * 8 if split_work else 0, dtype=torch.uint8, device=A.device)
+    _check(lib.rrf_dgemm(int(transa), int(transb), M, N, K, alpha, A.data_ptr(), _ld(A),
+                         B.data_ptr(), _ld(B), beta, C_out.data_ptr(), _ld(C_out),
+                         work.data_ptr() if work.numel() else None, work.numel(),
+                         _stream_ptr(A.device)), "rrf_dgemm")
+    return C_out
+
+
+def householder_panel(P, *, inplace: bool = False):
+    """Householder QR of a tall panel: returns (W, R, Tf, tau), Q = I - W Tf W^T."""
+    torch = _torch()
+    _require(P, "P")
+    M, k = int(P.shape[0]), int(P.shape[1])
+    W = P if inplace else empty_colmajor(M, k, P.device)
+    R = empty_colmajor(k, k, P.device)
+    Tf = empty_colmajor(k, k, P.device)
+    tau = torch.empty(k, dtype=torch.float64, device=P.device)
+    nbytes = int(lib.rrf_panel_workspace_size(M, k))
+    if nbytes == 0:
+        raise RRFError(_lib.RRF_E_NOTSUP, "householder_panel", "shape not supported")
+    work = torch.empty(nbytes, dtype=torch.uint8, device=P.device)
+    _check(lib.rrf_householder_panel(M, k, P.data_ptr(), _ld(P), W.data_ptr(), _ld(W),
+                                     R.data_ptr(), k, Tf.data_ptr(), k, tau.data_ptr(),
+                                     work.data_ptr(), nbytes, _stream_ptr(P.device)),
+           "rrf_householder_panel")
+    return W, R, Tf, tau
+
+
+def trace_enable(on: bool = True) -> None:
+    """Switch the library's per-kernel event timing on/off (clears totals)."""
+    _check(lib.rrf_trace_enable(1 if on else 0), "rrf_trace_enable")
+
+
+def trace_read() -> list[dict]:
+    """Per-kernel-class totals recorded since trace_enable()."""
+    buf = (_lib.rrf_trace_entry * 64)()
+    n = lib.rrf_trace_read(buf, 64)
+    return [dict(name=e.name.decode(), launches=int(e.launches), ms=float(e.ms),
+                 flops=float(e.flops), bytes=float(e.bytes)) for e in buf[:n]]
+
+
+def block_svd(B):
+    """SVD of a small k x k block: returns (Us, d, Vs) with B = Us diag(d) Vs^T."""
+    torch = _torch()
+    _require(B, "B")
+    k = int(B.shape[0])
+    if int(B.shape[1]) != k:
+        raise ValueError("block_svd needs a square block")
+    Us = empty_colmajor(k, k, B.device)
+    Vs = empty_colmajor(k, k, B.device)
+    d = torch.empty(k, dtype=torch.float64, device=B.device)
+    nbytes = int(lib.rrf_block_svd_workspace_size(k))
+    work = torch.empty(nbytes, dtype=torch.uint8, device=B.device)
+    _check(lib.rrf_block_svd(k, B.data_ptr(), _ld(B), Us.data_ptr(), d.data_ptr(), Vs.data_ptr(),
+                             work.data_ptr(), nbytes, _stream_ptr(B.device)), "rrf_block_svd")
+    return Us, d, Vs

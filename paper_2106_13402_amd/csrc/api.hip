@@ -1,0 +1,327 @@
+// The C-ABI of librrf: argument checks (before any HIP call), workspace
+// management, status read-back, and the exported building blocks.
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+
+#include "common.hpp"
+#include "driver.hpp"
+#include "kernels.hpp"
+
+namespace rrf {
+
+namespace {
+thread_local std::string g_last_error;
+
+struct DeviceCache {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_cache_mu;
+std::unordered_map<int, DeviceCache> g_cache;
+}  // namespace
+
+int set_hip_error(hipError_t e, const char* what, const char* file, int line) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  g_last_error = buf;
+  return RRF_E_HIP;
+}
+
+int set_error(int status, const char* msg) {
+  g_last_error = msg;
+  return status;
+}
+
+namespace {
+
+int device_ready(int* dev) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) return set_error(RRF_E_HIP, "no HIP device available");
+  RRF_CHECK_HIP(hipGetDevice(dev));
+  return RRF_OK;
+}
+
+// -k if `p` (argument k) is not device memory of a HIP device.
+int check_device_ptr(const void* p, int argpos) {
+  if (p == nullptr) return RRF_OK;
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error(-argpos, "argument is not a HIP device pointer");
+    return -argpos;
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged) {
+    set_error(-argpos, "argument is not device memory");
+    return -argpos;
+  }
+  return RRF_OK;
+}
+
+// Library-managed workspace of the current device (grown, never shrunk).
+int cached_workspace(int dev, size_t bytes, void** out) {
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  DeviceCache& c = g_cache[dev];
+  if (c.bytes < bytes) {
+    if (c.ptr) {
+      RRF_CHECK_HIP(hipDeviceSynchronize());
+      RRF_CHECK_HIP(hipFree(c.ptr));
+      c.ptr = nullptr;
+      c.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&c.ptr, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      c.ptr = nullptr;
+      return set_error(RRF_E_NOMEM, "device allocation of the workspace failed");
+    }
+    c.bytes = bytes;
+  }
+  *out = c.ptr;
+  return RRF_OK;
+}
+
+// Read the status words written by the kernels (stream-ordered, synchronous).
+int finish(hipStream_t st, const int* status_dev) {
+  int h[2] = {0, 0};
+  RRF_CHECK_HIP(hipMemcpyAsync(h, status_dev, sizeof h, hipMemcpyDeviceToHost, st));
+  RRF_CHECK_HIP(hipStreamSynchronize(st));
+  if (h[1] & 1) return set_error(RRF_E_NUMERIC, "input holds NaN or infinity");
+  if (h[0] & 4) return set_error(RRF_E_INTERNAL, "panel kernel: grid barrier did not complete");
+  if (h[0] & 2) return set_error(RRF_E_INTERNAL, "block SVD: Jacobi sweeps did not converge");
+  if (h[0]) return set_error(RRF_E_INTERNAL, "device-side failure");
+  return RRF_OK;
+}
+
+// Shared argument checks of rrf_randutv / rrf_powerurv (LAPACK numbering).
+int check_args(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+               const double* T) {
+  if (m < 1) return set_error(-1, "m must be >= 1"), -1;
+  if (n < 1) return set_error(-2, "n must be >= 1"), -2;
+  if (A == nullptr) return set_error(-3, "A is NULL"), -3;
+  if (lda < m) return set_error(-4, "lda must be >= m"), -4;
+  if (b < 1) return set_error(-5, "b must be >= 1"), -5;
+  if (q < 0) return set_error(-6, "q must be >= 0"), -6;
+  if (T == nullptr) return set_error(-9, "T is NULL"), -9;
+  if (T == A && lda != m) return set_error(-4, "T may alias A only when lda == m"), -4;
+  if (m < n) return set_error(RRF_E_NOTSUP, "m < n is not supported (factor A^T instead)");
+  return RRF_OK;
+}
+
+typedef bool (*SupportedFn)(int64_t, int64_t, int64_t);
+
+template <typename Run>
+int run_alg(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+            double* U, double* T, double* V, const rrf_opts* opts, Run run) {
+  RRF_TRY(check_args(m, n, A, lda, b, q, T));
+  rrf_opts o;
+  rrf_opts_init(&o);
+  if (opts) o = *opts;
+  if (o.precision != RRF_PREC_FP64)
+    return set_error(RRF_E_NOTSUP, "only RRF_PREC_FP64 is implemented");
+  const bool ok = alg == RRF_ALG_RANDUTV ? randutv_supported(m, n, b) : powerurv_supported(m, n, b);
+  if (!ok) return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  RRF_TRY(check_device_ptr(A, 3));
+  RRF_TRY(check_device_ptr(U, 8));
+  RRF_TRY(check_device_ptr(T, 9));
+  RRF_TRY(check_device_ptr(V, 10));
+  const size_t need = rrf_workspace_size(alg, m, n, b, q, o.precision);
+  void* ws = o.workspace;
+  size_t ws_bytes = o.workspace_bytes;
+  if (ws == nullptr) {
+    RRF_TRY(cached_workspace(dev, need, &ws));
+    ws_bytes = need;
+  } else if (ws_bytes < need) {
+    return set_error(RRF_E_NOMEM, "workspace smaller than rrf_workspace_size()");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
+  if (o.check_finite) {
+    // Reject non-finite input before any factorization work is enqueued
+    // (this check synchronizes the stream, also in async mode).
+    int* flag = reinterpret_cast<int*>(ws) + 1;
+    RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(flag), 1, 0u));
+    RRF_TRY(check_finite(st, m, n, A, lda, flag));
+    int h = 0;
+    RRF_CHECK_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, st));
+    RRF_CHECK_HIP(hipStreamSynchronize(st));
+    if (h) return set_error(RRF_E_NUMERIC, "input holds NaN or infinity");
+  }
+  RRF_TRY(run(st, ws, ws_bytes, false));
+  if (o.async) return RRF_OK;
+  return finish(st, reinterpret_cast<const int*>(ws));
+}
+
+}  // namespace
+}  // namespace rrf
+
+using namespace rrf;
+
+extern "C" {
+
+void rrf_opts_init(rrf_opts* opts) {
+  if (!opts) return;
+  memset(opts, 0, sizeof *opts);
+  opts->precision = RRF_PREC_FP64;
+}
+
+size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q, int precision) {
+  if (m < 1 || n < 1 || b < 1 || q < 0 || m < n || precision != RRF_PREC_FP64) return 0;
+  if (alg == RRF_ALG_RANDUTV) return randutv_supported(m, n, b) ? randutv_workspace(m, n, b) : 0;
+  if (alg == RRF_ALG_POWERURV)
+    return powerurv_supported(m, n, b) ? powerurv_workspace(m, n, b, q) : 0;
+  return 0;
+}
+
+int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                   uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
+  return run_alg(RRF_ALG_RANDUTV, m, n, A, lda, b, q, U, T, V, opts,
+                 [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
+                   int dummy = 0;
+                   return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
+                                      &dummy);
+                 });
+}
+
+int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                uint64_t seed, double* U, double* T, double* V) {
+  return rrf_randutv_ex(m, n, A, lda, b, q, seed, U, T, V, nullptr);
+}
+
+int rrf_powerurv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                    uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
+  return run_alg(RRF_ALG_POWERURV, m, n, A, lda, b, q, U, T, V, opts,
+                 [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
+                   return powerurv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk);
+                 });
+}
+
+int rrf_powerurv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                 uint64_t seed, double* U, double* T, double* V) {
+  return rrf_powerurv_ex(m, n, A, lda, b, q, seed, U, T, V, nullptr);
+}
+
+int rrf_release_workspace(void) {
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  auto it = g_cache.find(dev);
+  if (it != g_cache.end() && it->second.ptr) {
+    RRF_CHECK_HIP(hipDeviceSynchronize());
+    RRF_CHECK_HIP(hipFree(it->second.ptr));
+    g_cache.erase(it);
+  }
+  return RRF_OK;
+}
+
+int rrf_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, double* out,
+                 int64_t ld, void* stream) {
+  if (rows < 0) return set_error(-3, "rows must be >= 0"), -3;
+  if (cols < 0) return set_error(-4, "cols must be >= 0"), -4;
+  if (out == nullptr && rows > 0 && cols > 0) return set_error(-5, "out is NULL"), -5;
+  if (ld < (rows > 1 ? rows : 1)) return set_error(-6, "ld must be >= rows"), -6;
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  return gaussian(reinterpret_cast<hipStream_t>(stream), seed, stream_id, rows, cols, out, ld);
+}
+
+int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+              int64_t ldc, void* work, size_t work_bytes, void* stream) {
+  if (transa != 0 && transa != 1) return set_error(-1, "transa must be 0 or 1"), -1;
+  if (transb != 0 && transb != 1) return set_error(-2, "transb must be 0 or 1"), -2;
+  if (M < 0) return set_error(-3, "M must be >= 0"), -3;
+  if (N < 0) return set_error(-4, "N must be >= 0"), -4;
+  if (K < 0) return set_error(-5, "K must be >= 0"), -5;
+  const int64_t arows = transa ? K : M, brows = transb ? N : K;
+  if (K > 0 && M > 0 && A == nullptr) return set_error(-7, "A is NULL"), -7;
+  if (lda < (arows > 1 ? arows : 1)) return set_error(-8, "lda too small"), -8;
+  if (K > 0 && N > 0 && B == nullptr) return set_error(-9, "B is NULL"), -9;
+  if (ldb < (brows > 1 ? brows : 1)) return set_error(-10, "ldb too small"), -10;
+  if (M > 0 && N > 0 && C == nullptr) return set_error(-12, "C is NULL"), -12;
+  if (ldc < (M > 1 ? M : 1)) return set_error(-13, "ldc too small"), -13;
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  return dgemm(reinterpret_cast<hipStream_t>(stream), transa != 0, transb != 0, M, N, K, alpha, A,
+               lda, B, ldb, beta, C, ldc, reinterpret_cast<double*>(work), work_bytes / 8);
+}
+
+size_t rrf_panel_workspace_size(int64_t M, int64_t k) {
+  PanelPlan p;
+  if (k < 1 || M < k || !panel_plan(M, (int)k, &p)) return 0;
+  return p.work + 256;
+}
+
+int rrf_householder_panel(int64_t M, int64_t k, double* P, int64_t ldp, double* W, int64_t ldw,
+                          double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
+                          void* work, size_t work_bytes, void* stream) {
+  if (k < 1 || k > 256) return set_error(-2, "k must be in [1, 256]"), -2;
+  if (M < k) return set_error(-1, "M must be >= k"), -1;
+  if (P == nullptr) return set_error(-3, "P is NULL"), -3;
+  if (ldp < M) return set_error(-4, "ldp must be >= M"), -4;
+  if (W == nullptr) return set_error(-5, "W is NULL"), -5;
+  if (ldw < M) return set_error(-6, "ldw must be >= M"), -6;
+  if (W == P && ldw != ldp) return set_error(-6, "W may alias P only with ldw == ldp"), -6;
+  if (R != nullptr && ldr < k) return set_error(-8, "ldr must be >= k"), -8;
+  if (Tf == nullptr) return set_error(-9, "Tf is NULL"), -9;
+  if (ldt < k) return set_error(-10, "ldt must be >= k"), -10;
+  if (tau == nullptr) return set_error(-11, "tau is NULL"), -11;
+  const size_t need = rrf_panel_workspace_size(M, k);
+  if (need == 0) return set_error(RRF_E_NOTSUP, "panel too large for one launch");
+  if (work == nullptr || work_bytes < need)
+    return set_error(RRF_E_NOMEM, "work smaller than rrf_panel_workspace_size()");
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  // status word in the first 256 bytes of work; the panel scratch follows it
+  int* status = reinterpret_cast<int*>(work);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(status), 1, 0u));
+  return householder_panel(st, M, (int)k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, nullptr, 0,
+                           reinterpret_cast<char*>(work) + 256, work_bytes - 256, status);
+}
+
+size_t rrf_block_svd_workspace_size(int64_t k) {
+  if (k < 1 || k > 256) return 0;
+  return block_svd_work_bytes((int)k) + 256;
+}
+
+int rrf_block_svd(int64_t k, const double* B, int64_t ldb, double* Us, double* d, double* Vs,
+                  void* work, size_t work_bytes, void* stream) {
+  if (k < 1 || k > 256) return set_error(-1, "k must be in [1, 256]"), -1;
+  if (B == nullptr) return set_error(-2, "B is NULL"), -2;
+  if (ldb < k) return set_error(-3, "ldb must be >= k"), -3;
+  if (Us == nullptr) return set_error(-4, "Us is NULL"), -4;
+  if (d == nullptr) return set_error(-5, "d is NULL"), -5;
+  if (Vs == nullptr) return set_error(-6, "Vs is NULL"), -6;
+  const size_t need = rrf_block_svd_workspace_size(k);
+  if (work == nullptr || work_bytes < need)
+    return set_error(RRF_E_NOMEM, "work smaller than rrf_block_svd_workspace_size()");
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  int* status = reinterpret_cast<int*>(work);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(status), 1, 0u));
+  return block_svd(st, (int)k, B, ldb, Us, d, Vs, reinterpret_cast<char*>(work) + 256,
+                   work_bytes - 256, status);
+}
+
+const char* rrf_status_string(int status) {
+  switch (status) {
+    case RRF_OK: return "success";
+    case RRF_E_HIP: return "HIP runtime or kernel failure";
+    case RRF_E_NOMEM: return "workspace too small or device allocation failed";
+    case RRF_E_NOTSUP: return "request outside what is implemented";
+    case RRF_E_NUMERIC: return "non-finite input";
+    case RRF_E_INTERNAL: return "device-side consistency check failed";
+    default: return status < 0 ? "invalid argument" : "unknown status";
+  }
+}
+
+const char* rrf_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,319 @@
+// SVD of the small k x k diagonal blocks (k <= 256) on one workgroup.
+//
+// Alg. 3 diagonalizes each b x b block R produced by the panel QR with an
+// SVD (and the last trailing block, after its own QR); the paper ships those
+// blocks to the host for MAGMA. Here the block never leaves the GPU: a
+// one-sided (Hestenes) Jacobi iteration orthogonalizes the columns of
+// A_work = R V by plane rotations, accumulating V, so that A_work = Us diag(d)
+// with d_j = ||A_work(:, j)||. One-sided Jacobi computes small singular
+// values to high relative accuracy, which is what makes T(k,k) ~ sigma_k
+// meaningful deep into a decaying spectrum.
+//
+//  * 1024 threads = 16 wave64s; each round of the round-robin (circle)
+//    ordering pairs all k columns disjointly, a wave takes one pair at a
+//    time, its lanes stride over the k rows, and the three inner products
+//    are butterfly-reduced across the wave;
+//  * rotation: zeta = (a_qq - a_pp) / (2 a_pq), t = sign(zeta) /
+//    (|zeta| + sqrt(1 + zeta^2)), c = 1/sqrt(1+t^2), s = c t (Rutishauser);
+//    a pair is rotated while |a_pq| > max(sqrt(k), 8) eps sqrt(a_pp a_qq)
+//    (the rounding level of the wave-tree dot product is ~log2(k) eps, so
+//    this converges, and the cosines left keep ||Us^T Us - I|| ~ k eps);
+//  * A_work and V live in LDS when 2 k^2 doubles fit, else in global scratch;
+//  * finally: singular values sorted descending (stable in column index),
+//    Us = A_work / d, columns with d = 0 completed to an orthonormal basis
+//    by projecting the coordinate vector least covered by the columns so
+//    far, and each pair (u_j, v_j) signed so that the entry of v_j of largest
+//    magnitude is positive (lowest index on ties).
+#include <cfloat>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "trace.hpp"
+
+namespace rrf {
+
+namespace {
+
+constexpr int kThreads = 1024;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxK = 256;
+constexpr size_t kLdsBudget = 144 * 1024;
+constexpr int kMaxSweeps = 60;
+
+struct SvdArgs {
+  int k;           // size of blocks 0 .. count-2
+  int k_last;      // size of the last block
+  int count;       // number of blocks (one workgroup each)
+  int64_t stride;  // elements between consecutive blocks of B, Us, Vs
+  int64_t dstride; // elements between consecutive d vectors
+  const double* B;
+  int64_t ldb;     // leading dimension of each B block (>= its size)
+  double* Us;      // each block k x k, ld k
+  double* d;
+  double* Vs;
+  double* gA;  // global scratch: per block 2 k^2 doubles when not in LDS
+  int use_lds;
+  int* status;
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void jacobi_svd_kernel(SvdArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double sig[kMaxK];
+  __shared__ int perm[kMaxK];
+  __shared__ int rotated;
+  __shared__ double coef[kMaxK];
+  __shared__ int pick;
+
+  const int blk = blockIdx.x;
+  const int k = (blk == a.count - 1) ? a.k_last : a.k;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* gbase = a.use_lds ? nullptr : a.gA + (size_t)blk * 2 * a.k * a.k;
+  double* Aw = a.use_lds ? lds : gbase;
+  double* Vw = a.use_lds ? lds + (size_t)k * k : gbase + (size_t)a.k * a.k;
+  const double* Bb = a.B + (int64_t)blk * a.stride;
+  double* Usb = a.Us + (int64_t)blk * a.stride;
+  double* Vsb = a.Vs + (int64_t)blk * a.stride;
+  double* db = a.d + (int64_t)blk * a.dstride;
+
+  for (int idx = tid; idx < k * k; idx += kThreads) {
+    const int i = idx % k, j = idx / k;
+    Aw[idx] = Bb[i + (int64_t)j * a.ldb];
+    Vw[idx] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  const int kk = k + (k & 1);
+  const double tol = DBL_EPSILON * fmax(sqrt((double)k), 8.0);
+  bool converged = (k == 1);
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    if (tid == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < kk - 1; ++round) {
+      for (int pi = wave; pi < kk / 2; pi += kWaves) {
+        int p, q;
+        if (pi == 0) {
+          p = round;
+          q = kk - 1;
+        } else {
+          p = (round + pi) % (kk - 1);
+          q = (round - pi + kk - 1) % (kk - 1);
+        }
+        if (p > q) {
+          const int t = p;
+          p = q;
+          q = t;
+        }
+        if (q >= k) continue;
+        double* ap = Aw + (size_t)p * k;
+        double* aq = Aw + (size_t)q * k;
+        double app = 0.0, aqq = 0.0, apq = 0.0;
+        for (int r = lane; r < k; r += 64) {
+          const double x = ap[r], y = aq[r];
+          app += x * x;
+          aqq += y * y;
+          apq += x * y;
+        }
+        app = wave_sum(app);
+        aqq = wave_sum(aqq);
+        apq = wave_sum(apq);
+        if (apq != 0.0 && fabs(apq) > tol * sqrt(app) * sqrt(aqq)) {
+          const double zeta = (aqq - app) / (2.0 * apq);
+          double t;
+          if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+          else t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t);
+          const double s = c * t;
+          double* vp = Vw + (size_t)p * k;
+          double* vq = Vw + (size_t)q * k;
+          for (int r = lane; r < k; r += 64) {
+            const double x = ap[r], y = aq[r];
+            ap[r] = c * x - s * y;
+            aq[r] = s * x + c * y;
+            const double u = vp[r], w = vq[r];
+            vp[r] = c * u - s * w;
+            vq[r] = s * u + c * w;
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    converged = (rotated == 0);
+    __syncthreads();
+  }
+  if (!converged && tid == 0) atomicOr(a.status, 2);
+
+  // Column norms = singular values.
+  for (int c = wave; c < k; c += kWaves) {
+    double s = 0.0;
+    for (int r = lane; r < k; r += 64) {
+      const double x = Aw[(size_t)c * k + r];
+      s += x * x;
+    }
+    s = wave_sum(s);
+    if (lane == 0) sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  // Descending order, ties broken by column index. The sort key maps NaN
+  // (non-finite input) below every norm, so (key, index) is a strict total
+  // order and the ranks always form a permutation of 0..k-1.
+  for (int c = tid; c < k; c += kThreads) {
+    int rank = 0;
+    const double sc = (sig[c] == sig[c]) ? sig[c] : -1.0;
+    for (int i = 0; i < k; ++i) {
+      const double si = (sig[i] == sig[i]) ? sig[i] : -1.0;
+      rank += (si > sc) || (si == sc && i < c);
+    }
+    perm[rank] = c;
+  }
+  __syncthreads();
+  const double tiny = DBL_MIN * (double)k;
+  for (int idx = tid; idx < k * k; idx += kThreads) {
+    const int r = idx % k, pos = idx / k;
+    const int c = perm[pos];
+    const double sc = sig[c];
+    Vsb[(size_t)pos * k + r] = Vw[(size_t)c * k + r];
+    Usb[(size_t)pos * k + r] = (sc > tiny) ? Aw[(size_t)c * k + r] / sc : 0.0;
+  }
+  for (int pos = tid; pos < k; pos += kThreads) db[pos] = sig[perm[pos]];
+  __syncthreads();
+
+  // Complete Us where d = 0 (these positions come last in the sorted order).
+  for (int pos = 0; pos < k; ++pos) {
+    if (sig[perm[pos]] > tiny) continue;
+    double* U = Usb;
+    // coverage of coordinate i by the columns 0..pos-1
+    for (int i = tid; i < k; i += kThreads) {
+      double s = 0.0;
+      for (int c = 0; c < pos; ++c) {
+        const double x = U[(size_t)c * k + i];
+        s += x * x;
+      }
+      coef[i] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int best = 0;
+      for (int i = 1; i < k; ++i)
+        if (coef[i] < coef[best]) best = i;
+      pick = best;
+    }
+    __syncthreads();
+    const int ip = pick;
+    // u = e_ip - U U(ip,:)^T, then one re-orthogonalization pass.
+    double* u = U + (size_t)pos * k;
+    for (int r = tid; r < k; r += kThreads) {
+      double s = (r == ip) ? 1.0 : 0.0;
+      for (int c = 0; c < pos; ++c) s -= U[(size_t)c * k + r] * U[(size_t)c * k + ip];
+      u[r] = s;
+    }
+    __syncthreads();
+    for (int c = tid; c < pos; c += kThreads) {
+      double s = 0.0;
+      for (int r = 0; r < k; ++r) s += U[(size_t)c * k + r] * u[r];
+      coef[c] = s;
+    }
+    __syncthreads();
+    for (int r = tid; r < k; r += kThreads) {
+      double s = u[r];
+      for (int c = 0; c < pos; ++c) s -= U[(size_t)c * k + r] * coef[c];
+      u[r] = s;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double s = 0.0;
+      for (int r = lane; r < k; r += 64) s += u[r] * u[r];
+      s = wave_sum(s);
+      if (lane == 0) coef[0] = 1.0 / sqrt(s);
+    }
+    __syncthreads();
+    const double inv = coef[0];
+    for (int r = tid; r < k; r += kThreads) u[r] *= inv;
+    __syncthreads();
+  }
+
+  // Sign rule: the entry of v_j of largest magnitude is positive.
+  for (int pos = wave; pos < k; pos += kWaves) {
+    double best = -1.0;
+    int bi = 0;  // stays a valid row even if every entry is NaN
+    for (int r = lane; r < k; r += 64) {
+      const double x = fabs(Vsb[(size_t)pos * k + r]);
+      if (x > best || (x == best && r < bi)) {
+        best = x;
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    const bool flip = Vsb[(size_t)pos * k + bi] < 0.0;
+    if (flip) {
+      for (int r = lane; r < k; r += 64) {
+        Vsb[(size_t)pos * k + r] = -Vsb[(size_t)pos * k + r];
+        Usb[(size_t)pos * k + r] = -Usb[(size_t)pos * k + r];
+      }
+    }
+  }
+}
+
+bool g_attr_set = false;
+
+}  // namespace
+
+size_t block_svd_work_bytes(int k) { return (size_t)2 * k * k * 8 + 256; }
+
+int block_svd_batched(hipStream_t st, int count, int k, int k_last, const double* B, int64_t ldb,
+                      int64_t stride, double* Us, double* d, int64_t dstride, double* Vs,
+                      void* work, size_t work_bytes, int* status) {
+  if (count < 1) return RRF_OK;
+  if (k < 1 || k > kMaxK || k_last < 1 || k_last > k)
+    return set_error(RRF_E_NOTSUP, "block svd: need 1 <= k_last <= k <= 256");
+  const size_t need = (size_t)2 * k * k * 8;
+  const bool in_lds = need <= kLdsBudget;
+  if (!in_lds && (work == nullptr || work_bytes < need * count))
+    return set_error(RRF_E_NOMEM, "block svd: workspace too small");
+  if (!g_attr_set) {
+    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)kLdsBudget));
+    g_attr_set = true;
+  }
+  SvdArgs a{};
+  a.k = k;
+  a.k_last = k_last;
+  a.count = count;
+  a.stride = stride;
+  a.dstride = dstride;
+  a.B = B;
+  a.ldb = ldb;
+  a.Us = Us;
+  a.d = d;
+  a.Vs = Vs;
+  a.gA = in_lds ? nullptr : reinterpret_cast<double*>(work);
+  a.use_lds = in_lds ? 1 : 0;
+  a.status = status;
+  int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * k * k * count);
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(count), dim3(kThreads), in_lds ? need : 0, st, a);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int block_svd(hipStream_t st, int k, const double* B, int64_t ldb, double* Us, double* d,
+              double* Vs, void* work, size_t work_bytes, int* status) {
+  return block_svd_batched(st, 1, k, k, B, ldb, 0, Us, d, 0, Vs, work, work_bytes, status);
+}
+
+}  // namespace rrf

@@ -1,0 +1,60 @@
+// Internal launch interfaces of the rrf kernels (not part of the C-ABI).
+#pragma once
+
+#include "common.hpp"
+
+namespace rrf {
+
+// ---- gemm_f64.hip --------------------------------------------------------
+// C = alpha op(A) op(B) + beta C (FP64 MFMA). `work` (work_elems doubles) is
+// split-K scratch; fewer elements only limit the split.
+int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+          const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+          int64_t ldc, double* work, size_t work_elems);
+
+// ---- philox.hip ----------------------------------------------------------
+int gaussian(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+             double* out, int64_t ld);
+
+// ---- util.hip ------------------------------------------------------------
+int set_identity(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld);
+int copy_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int64_t lds,
+                double* D, int64_t ldd);
+int fill_matrix(hipStream_t st, int64_t rows, int64_t cols, double v, double* X, int64_t ld);
+// X(0:rows, 0:cols) = 0 except X(k, k) = d[k], k < min(rows, cols).
+int set_diag(hipStream_t st, int64_t rows, int64_t cols, const double* d, double* X, int64_t ld);
+int fill_u32(hipStream_t st, unsigned* p, int64_t count, unsigned v);
+// status[0] |= 1 when X (rows x cols) holds a NaN or an infinity.
+int check_finite(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+                 int* status);
+
+// ---- panel_qr.hip --------------------------------------------------------
+struct PanelPlan {
+  int G = 0;          // workgroups
+  int rows_per = 0;   // rows owned by each workgroup
+  size_t lds = 0;     // dynamic LDS bytes
+  size_t work = 0;    // global scratch bytes
+};
+bool panel_plan(int64_t M, int k, PanelPlan* plan);
+// Householder QR of the M x k panel P; see rrf_householder_panel. When
+// `zero` is non-null the M x k region it points to (ld ldz) is set to 0 after
+// the panel has been read (used to clear T(I2 u I3, J2) in place).
+int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp,
+                      double* W, int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt,
+                      double* tau, double* zero, int64_t ldz, void* work, size_t work_bytes,
+                      int* status);
+
+// ---- jacobi_svd.hip ------------------------------------------------------
+size_t block_svd_work_bytes(int k);
+int block_svd(hipStream_t st, int k, const double* B, int64_t ldb, double* Us, double* d,
+              double* Vs, void* work, size_t work_bytes, int* status);
+// `count` independent SVDs in one launch (one workgroup each): blocks 0..count-2
+// are k x k, the last is k_last x k_last (k_last <= k); block i of B / Us / Vs
+// starts at i * stride (B with leading dimension ldb, Us and Vs tight), d_i at
+// i * dstride. Global scratch when a block does not fit in LDS:
+// count * block_svd_work_bytes(k).
+int block_svd_batched(hipStream_t st, int count, int k, int k_last, const double* B, int64_t ldb,
+                      int64_t stride, double* Us, double* d, int64_t dstride, double* Vs,
+                      void* work, size_t work_bytes, int* status);
+
+}  // namespace rrf

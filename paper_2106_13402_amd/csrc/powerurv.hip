@@ -1,0 +1,164 @@
+// powerURV (Alg. 1) on one GPU.
+//
+//   V = Gaussian(seed, stream 0)        (n x n, generated in HBM)
+//   q = 0: V = Q of HQR(V)              (RURV, Sec. 3.1 step 2)
+//   repeat q times:
+//     Y_hat = A V;   V_hat = Q of HQR_thin(Y_hat)   (m x n)
+//     Y = A^T V_hat; V = Q of HQR_thin(Y)           (n x n)
+//   A_hat = A V;  [U, R] = HQR_full(A_hat);  T = [R; 0]
+//
+// The QRs are blocked Householder factorizations: the panel kernel factors
+// nb columns at a time (compact WY, Sec. 2.3) and the trailing columns are
+// updated with two GEMMs, A <- A - (W Tf^T)(W^T A). Explicit Q factors are
+// formed by applying the stored blocks in reverse to [I; 0], touching only
+// the rows and columns each block can change, as LAPACK's dorgqr does.
+#include <algorithm>
+
+#include "common.hpp"
+#include "driver.hpp"
+#include "kernels.hpp"
+
+namespace rrf {
+
+namespace {
+
+struct PBufs {
+  int* status = nullptr;
+  double* Yh = nullptr;    // m x n
+  double* Wall = nullptr;  // m x n explicit reflectors
+  double* Tall = nullptr;  // nb x n compact-WY factors, block p at column c0
+  double* R = nullptr;     // n x n
+  double* Vw = nullptr;    // n x n (only when the caller passes no V)
+  double* Z = nullptr;     // nb x max(m, n)
+  double* Wt = nullptr;    // m x nb
+  double* tau = nullptr;   // n
+  double* split = nullptr;
+  size_t split_elems = 0;
+  void* panel = nullptr;
+  size_t panel_bytes = 0;
+};
+
+bool plan(Arena& ar, int64_t m, int64_t n, int64_t nb, bool need_v, PBufs* B) {
+  const int64_t mx = std::max(m, n);
+  B->status = ar.take<int>(64);
+  B->Yh = ar.take<double>((size_t)m * n);
+  B->Wall = ar.take<double>((size_t)m * n);
+  B->Tall = ar.take<double>((size_t)nb * n);
+  B->R = ar.take<double>((size_t)n * n);
+  if (need_v) B->Vw = ar.take<double>((size_t)n * n);
+  B->Z = ar.take<double>((size_t)nb * mx);
+  B->Wt = ar.take<double>((size_t)mx * nb);
+  B->tau = ar.take<double>((size_t)n);
+  B->split_elems = (size_t)8 * mx * nb;
+  B->split = ar.take<double>(B->split_elems);
+  PanelPlan pp;
+  if (!panel_plan(mx, (int)nb, &pp)) return false;
+  B->panel_bytes = pp.work;
+  B->panel = ar.take<char>(pp.work);
+  return true;
+}
+
+// Householder QR of X (M x N, ld ldx, destroyed): reflectors to W (M x N,
+// ld M), block factors to Tall, R (N x N, ld N).
+int hqr_blocked(hipStream_t st, int64_t M, int64_t N, int64_t nb, double* X, int64_t ldx,
+                PBufs& B, double* Rout) {
+  RRF_TRY(fill_matrix(st, N, N, 0.0, Rout, N));
+  for (int64_t c0 = 0; c0 < N; c0 += nb) {
+    const int64_t k = std::min(nb, N - c0);
+    const int64_t Mp = M - c0;
+    double* Wp = B.Wall + c0 + c0 * M;
+    double* Tp = B.Tall + c0 * nb;
+    RRF_TRY(householder_panel(st, Mp, (int)k, X + c0 + c0 * ldx, ldx, Wp, M, Rout + c0 + c0 * N,
+                              N, Tp, nb, B.tau + c0, nullptr, 0, B.panel, B.panel_bytes,
+                              B.status));
+    const int64_t Nr = N - c0 - k;
+    if (Nr > 0) {
+      double* Xr = X + c0 + (c0 + k) * ldx;
+      RRF_TRY(dgemm(st, false, true, Mp, k, k, 1.0, Wp, M, Tp, nb, 0.0, B.Wt, Mp, nullptr, 0));
+      RRF_TRY(dgemm(st, true, false, k, Nr, Mp, 1.0, Wp, M, Xr, ldx, 0.0, B.Z, k, B.split,
+                    B.split_elems));
+      RRF_TRY(dgemm(st, false, false, Mp, Nr, k, -1.0, B.Wt, Mp, B.Z, k, 1.0, Xr, ldx, nullptr, 0));
+      RRF_TRY(copy_matrix(st, k, Nr, Xr, ldx, Rout + c0 + (c0 + k) * N, N));
+    }
+  }
+  return RRF_OK;
+}
+
+// Q(:, 0:ncols) of the factorization held in B.Wall / B.Tall (M x N
+// reflectors), written to Q (M x ncols, ld M).
+int form_q(hipStream_t st, int64_t M, int64_t N, int64_t nb, int64_t ncols, PBufs& B, double* Q) {
+  RRF_TRY(set_identity(st, M, ncols, Q, M));
+  const int64_t nblk = ceil_div(N, nb);
+  for (int64_t p = nblk - 1; p >= 0; --p) {
+    const int64_t c0 = p * nb;
+    const int64_t k = std::min(nb, N - c0);
+    const int64_t Mp = M - c0;
+    const int64_t Nc = ncols - c0;
+    const double* Wp = B.Wall + c0 + c0 * M;
+    const double* Tp = B.Tall + c0 * nb;
+    double* Qp = Q + c0 + c0 * M;
+    // Q(c0:, c0:) <- (I - W Tf W^T) Q(c0:, c0:) = Q - (W Tf)(W^T Q)
+    RRF_TRY(dgemm(st, false, false, Mp, k, k, 1.0, Wp, M, Tp, nb, 0.0, B.Wt, Mp, nullptr, 0));
+    RRF_TRY(dgemm(st, true, false, k, Nc, Mp, 1.0, Wp, M, Qp, M, 0.0, B.Z, k, B.split,
+                  B.split_elems));
+    RRF_TRY(dgemm(st, false, false, Mp, Nc, k, -1.0, B.Wt, Mp, B.Z, k, 1.0, Qp, M, nullptr, 0));
+  }
+  return RRF_OK;
+}
+
+}  // namespace
+
+bool powerurv_supported(int64_t m, int64_t n, int64_t b) {
+  if (b > 256) return false;
+  PanelPlan pp;
+  return panel_plan(std::max(m, n), (int)std::min(b, n), &pp);
+}
+
+size_t powerurv_workspace(int64_t m, int64_t n, int64_t b, int q) {
+  (void)q;
+  Arena ar;
+  ar.counting = true;
+  PBufs B;
+  if (!plan(ar, m, n, std::min(b, n), true, &B)) return 0;
+  return ar.used;
+}
+
+int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                 int q, uint64_t seed, double* U, double* T, double* V, void* ws, size_t ws_bytes,
+                 bool check_input) {
+  const int64_t nb = std::min(b, n);
+  Arena ar;
+  ar.base = reinterpret_cast<char*>(ws);
+  ar.cap = ws_bytes;
+  PBufs B;
+  if (!plan(ar, m, n, nb, V == nullptr, &B) || ar.used > ws_bytes)
+    return set_error(RRF_E_NOMEM, "powerurv: workspace too small");
+  RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(B.status), 64, 0u));
+  if (check_input) RRF_TRY(check_finite(st, m, n, A, lda, B.status + 1));
+  double* Vm = V ? V : B.Vw;
+
+  RRF_TRY(gaussian(st, seed, 0, n, n, Vm, n));
+  if (q == 0) {
+    RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R));
+    RRF_TRY(form_q(st, n, n, nb, n, B, Vm));
+  }
+  for (int it = 0; it < q; ++it) {
+    RRF_TRY(dgemm(st, false, false, m, n, n, 1.0, A, lda, Vm, n, 0.0, B.Yh, m, B.split,
+                  B.split_elems));
+    RRF_TRY(hqr_blocked(st, m, n, nb, B.Yh, m, B, B.R));
+    RRF_TRY(form_q(st, m, n, nb, n, B, B.Yh));  // V_hat in Yh
+    RRF_TRY(dgemm(st, true, false, n, n, m, 1.0, A, lda, B.Yh, m, 0.0, Vm, n, B.split,
+                  B.split_elems));
+    RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R));
+    RRF_TRY(form_q(st, n, n, nb, n, B, Vm));
+  }
+  RRF_TRY(dgemm(st, false, false, m, n, n, 1.0, A, lda, Vm, n, 0.0, B.Yh, m, B.split,
+                B.split_elems));
+  RRF_TRY(hqr_blocked(st, m, n, nb, B.Yh, m, B, B.R));
+  if (U) RRF_TRY(form_q(st, m, n, nb, m, B, U));
+  RRF_TRY(fill_matrix(st, m, n, 0.0, T, m));
+  RRF_TRY(copy_matrix(st, n, n, B.R, n, T, m));
+  return RRF_OK;
+}
+
+}  // namespace rrf

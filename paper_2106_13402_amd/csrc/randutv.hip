@@ -1,0 +1,293 @@
+// randUTV_basic (Alg. 3) on one GPU.
+//
+// Per step i (0-based here, c0 = i b, J2 = [c0, c2), I2 = [c0, r2)):
+//   1. G_i = Gaussian(seed, stream i+1), (m-c0) x b, generated in HBM;
+//   2. Y = T22^T G_i, then q times Z = T22 Y, Y = T22^T Z  (MFMA GEMMs);
+//   3. [W_v, Tf_v] = Householder QR of Y (panel kernel; W_v overwrites Y);
+//   4. T(:, J2uJ3) -= (T W_v)(W_v Tf_v^T)^T, same for V  (= T V_i);
+//   5. [W_u, Tf_u, R] = Householder QR of T(I2uI3, J2); that panel of T is
+//      cleared in the same kernel (T(I3,J2) = 0 of Alg. 3, and T(I2,J2)
+//      receives D below);
+//   6. T(I2uI3, J3) -= (W_u Tf_u^T)(W_u^T T(I2uI3, J3))  (= U_i^T T) and
+//      U(:, I2uI3) -= (U W_u)(W_u Tf_u^T)^T  (= U U_i);
+//   7. [Us, D, Vs] = SVD(R) (one-workgroup Jacobi), then U(:,I2) Us,
+//      V(:,J2) Vs, T(I2,J2) = D, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) Vs.
+// The last step (J3 empty) takes the SVD of the trailing block, through a
+// Householder QR first when the block is tall (Sec. 4.2, tall-thin SVD).
+//
+// Both compact-WY applications use W Tf W^T = W (W Tf^T)^T: the small
+// triangular factor is folded into one operand once per step and each update
+// is exactly two GEMMs.
+//
+// Schedule. The data dependences of a step, not the order in which Alg. 3
+// lists its statements, decide what may overlap:
+//  * the caller's stream carries the critical path -- generator, sketch,
+//    both panels and both updates of T;
+//  * a side stream accumulates V and U: V(:, J2uJ3) V_i needs only W_v and
+//    U(:, I2uI3) U_i only W_u, and nothing on the critical path reads U or V;
+//  * no later step depends on a block's SVD. After step i no step touches
+//    columns J2 of T, U or V, and rows I2 of T are only multiplied from the
+//    right, which commutes with the left rotation by Us^T. So every R is kept
+//    and all the small SVDs run as one batched launch (one workgroup per
+//    block) after the loop, followed by T(I2,J2) = D, T(I1,J2) Vs, U(:,I2) Us,
+//    V(:,J2) Vs and T(I2,J3) <- Us^T T(I2,J3) for every block.
+// W_v, W_v Tf_v^T, W_u and W_u Tf_u^T live in two-deep rings, so the
+// critical path reuses a slot only after the side stream finished with it
+// two steps earlier.
+#include <algorithm>
+
+#include "common.hpp"
+#include "context.hpp"
+#include "driver.hpp"
+#include "kernels.hpp"
+
+namespace rrf {
+
+namespace {
+
+struct Bufs {
+  int* status = nullptr;
+  double* G = nullptr;      // m x b
+  double* Z = nullptr;      // m x b
+  double* Y[2] = {};        // n x b  sketch, then W_v
+  double* Wr[2] = {};       // n x b  W_v Tf_v^T
+  double* Wu[2] = {};       // m x b
+  double* Wl[2] = {};       // m x b  W_u Tf_u^T
+  double* X0 = nullptr;     // max(m,n) x b   (critical stream)
+  double* X1 = nullptr;     // max(m,n) x b   (side stream)
+  double* Zl = nullptr;     // b x n          (critical stream)
+  double* Tv = nullptr;     // b x b
+  double* Tu = nullptr;     // b x b
+  double* tau = nullptr;    // b
+  double* R = nullptr;      // s x (b x b)
+  double* Us = nullptr;     // s x (b x b)
+  double* Vs = nullptr;     // s x (b x b)
+  double* d = nullptr;      // s x b
+  double* split[2] = {};
+  size_t split_elems = 0;
+  void* panel = nullptr;
+  size_t panel_bytes = 0;
+  void* svd = nullptr;
+  size_t svd_bytes = 0;
+};
+
+bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, Bufs* B) {
+  const int64_t mx = std::max(m, n);
+  const int64_t kb = std::min(b, n);
+  const int64_t s = ceil_div(n, b);
+  B->status = ar.take<int>(64);
+  B->G = ar.take<double>((size_t)m * kb);
+  B->Z = ar.take<double>((size_t)m * kb);
+  for (int r = 0; r < 2; ++r) {
+    B->Y[r] = ar.take<double>((size_t)n * kb);
+    B->Wr[r] = ar.take<double>((size_t)n * kb);
+    B->Wu[r] = ar.take<double>((size_t)m * kb);
+    B->Wl[r] = ar.take<double>((size_t)m * kb);
+  }
+  B->X0 = ar.take<double>((size_t)mx * kb);
+  B->X1 = ar.take<double>((size_t)mx * kb);
+  B->Zl = ar.take<double>((size_t)kb * n);
+  B->Tv = ar.take<double>((size_t)kb * kb);
+  B->Tu = ar.take<double>((size_t)kb * kb);
+  B->tau = ar.take<double>((size_t)kb);
+  B->R = ar.take<double>((size_t)s * kb * kb);
+  B->Us = ar.take<double>((size_t)s * kb * kb);
+  B->Vs = ar.take<double>((size_t)s * kb * kb);
+  B->d = ar.take<double>((size_t)s * kb);
+  B->split_elems = (size_t)8 * mx * kb;
+  for (int k = 0; k < 2; ++k) B->split[k] = ar.take<double>(B->split_elems);
+  PanelPlan pp;
+  if (!panel_plan(mx, (int)kb, &pp)) return false;
+  B->panel_bytes = pp.work;
+  B->panel = ar.take<char>(pp.work);
+  B->svd_bytes = (size_t)s * block_svd_work_bytes((int)kb);
+  B->svd = ar.take<char>(B->svd_bytes);
+  return true;
+}
+
+// X(:, 0:k) <- X(:, 0:k) S  (rows x k times k x k) through `tmp`.
+int right_mult(hipStream_t st, int64_t rows, int64_t k, double* X, int64_t ldx, const double* S,
+               double* tmp, double* split, size_t split_elems) {
+  if (rows <= 0 || k <= 0) return RRF_OK;
+  RRF_TRY(dgemm(st, false, false, rows, k, k, 1.0, X, ldx, S, k, 0.0, tmp, rows, split,
+                split_elems));
+  return copy_matrix(st, rows, k, tmp, rows, X, ldx);
+}
+
+// Event slots of the device context.
+enum { kEvStart = 0, kEvV = 1, kEvU = 3, kEvVdone = 5, kEvUdone = 7, kEvS1 = 9, kEvSvd = 10 };
+
+}  // namespace
+
+bool randutv_supported(int64_t m, int64_t n, int64_t b) {
+  if (b > 256) return false;
+  PanelPlan pp;
+  return panel_plan(std::max(m, n), (int)std::min(b, n), &pp);
+}
+
+size_t randutv_workspace(int64_t m, int64_t n, int64_t b) {
+  Arena ar;
+  ar.counting = true;
+  Bufs B;
+  if (!plan(ar, m, n, b, &B)) return 0;
+  return ar.used;
+}
+
+int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                int q, uint64_t seed, double* U, double* T, double* V, void* ws,
+                size_t ws_bytes, bool check_input, int* status_out) {
+  Arena ar;
+  ar.base = reinterpret_cast<char*>(ws);
+  ar.cap = ws_bytes;
+  Bufs B;
+  if (!plan(ar, m, n, b, &B) || ar.used > ws_bytes)
+    return set_error(RRF_E_NOMEM, "randutv: workspace too small");
+  *status_out = 0;
+  DeviceContext* ctx = nullptr;
+  RRF_TRY(device_context(&ctx));
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t s1 = ctx->side[0];
+  hipEvent_t* ev = ctx->ev;
+  const size_t SE = B.split_elems;
+
+  RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(B.status), 64, 0u));
+  if (check_input) RRF_TRY(check_finite(st, m, n, A, lda, B.status + 1));
+  const int64_t ldt = m, ldu = m, ldv = n;
+  if (T != A) RRF_TRY(copy_matrix(st, m, n, A, lda, T, ldt));
+  RRF_CHECK_HIP(hipEventRecord(ev[kEvStart], st));
+  RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvStart], 0));
+  if (U) RRF_TRY(set_identity(s1, m, m, U, ldu));
+  if (V) RRF_TRY(set_identity(s1, n, n, V, ldv));
+
+  const int64_t s = ceil_div(n, b);
+  const int64_t bb = std::min(b, n);  // block slot size of R, Us, Vs, d
+  for (int64_t i = 0; i < s; ++i) {
+    const int64_t c0 = i * b;
+    const int64_t c2 = std::min(c0 + b, n);
+    const int64_t r2 = std::min(c0 + b, m);
+    const int64_t Mi = m - c0, Ni = n - c0;
+    const int r = (int)(i & 1);
+    double* T22 = T + c0 + c0 * ldt;
+    double* Tc = T + c0 * ldt;  // T(:, J2uJ3)
+    double* Ri = B.R + i * bb * bb;  // ld bb
+    if (r2 < m && c2 < n) {
+      const int64_t kb = b;
+      const int64_t N3 = n - c2;
+      // ---- critical stream: sketch and V_i
+      if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvVdone + r], 0));
+      RRF_TRY(gaussian(st, seed, (uint64_t)(i + 1), Mi, kb, B.G, Mi));
+      RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.G, Mi, 0.0, B.Y[r], Ni,
+                    B.split[0], SE));
+      for (int it = 0; it < q; ++it) {
+        RRF_TRY(dgemm(st, false, false, Mi, kb, Ni, 1.0, T22, ldt, B.Y[r], Ni, 0.0, B.Z, Mi,
+                      B.split[0], SE));
+        RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.Z, Mi, 0.0, B.Y[r], Ni,
+                      B.split[0], SE));
+      }
+      RRF_TRY(householder_panel(st, Ni, (int)kb, B.Y[r], Ni, B.Y[r], Ni, nullptr, 0, B.Tv, kb,
+                                B.tau, nullptr, 0, B.panel, B.panel_bytes, B.status));
+      RRF_TRY(dgemm(st, false, true, Ni, kb, kb, 1.0, B.Y[r], Ni, B.Tv, kb, 0.0, B.Wr[r], Ni,
+                    nullptr, 0));
+      RRF_CHECK_HIP(hipEventRecord(ev[kEvV + r], st));
+      // T(:, J2uJ3) <- T(:, J2uJ3) V_i
+      RRF_TRY(dgemm(st, false, false, m, kb, Ni, 1.0, Tc, ldt, B.Y[r], Ni, 0.0, B.X0, m,
+                    B.split[0], SE));
+      RRF_TRY(dgemm(st, false, true, m, Ni, kb, -1.0, B.X0, m, B.Wr[r], Ni, 1.0, Tc, ldt,
+                    nullptr, 0));
+      // ---- critical stream: U_i and R from the panel T(I2uI3, J2)
+      if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvUdone + r], 0));
+      RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, B.Wu[r], Mi, Ri, bb, B.Tu, kb, B.tau,
+                                T22, ldt, B.panel, B.panel_bytes, B.status));
+      RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, B.Wl[r], Mi,
+                    nullptr, 0));
+      RRF_CHECK_HIP(hipEventRecord(ev[kEvU + r], st));
+      // T(I2uI3, J3) <- U_i^T T(I2uI3, J3)
+      double* T23 = T + c0 + c2 * ldt;
+      RRF_TRY(dgemm(st, true, false, kb, N3, Mi, 1.0, B.Wu[r], Mi, T23, ldt, 0.0, B.Zl, kb,
+                    B.split[0], SE));
+      RRF_TRY(dgemm(st, false, false, Mi, N3, kb, -1.0, B.Wl[r], Mi, B.Zl, kb, 1.0, T23, ldt,
+                    nullptr, 0));
+
+      // ---- side stream: V V_i and U U_i
+      RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvV + r], 0));
+      if (V) {
+        double* Vc = V + c0 * ldv;
+        RRF_TRY(dgemm(s1, false, false, n, kb, Ni, 1.0, Vc, ldv, B.Y[r], Ni, 0.0, B.X1, n,
+                      B.split[1], SE));
+        RRF_TRY(dgemm(s1, false, true, n, Ni, kb, -1.0, B.X1, n, B.Wr[r], Ni, 1.0, Vc, ldv,
+                      nullptr, 0));
+      }
+      RRF_CHECK_HIP(hipEventRecord(ev[kEvVdone + r], s1));
+      RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvU + r], 0));
+      if (U) {
+        double* Uc = U + c0 * ldu;
+        RRF_TRY(dgemm(s1, false, false, m, kb, Mi, 1.0, Uc, ldu, B.Wu[r], Mi, 0.0, B.X1, m,
+                      B.split[1], SE));
+        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, B.Wl[r], Mi, 1.0, Uc, ldu,
+                      nullptr, 0));
+      }
+      RRF_CHECK_HIP(hipEventRecord(ev[kEvUdone + r], s1));
+
+    } else {
+      // Last block: its SVD is of T(I2uI3, J2uJ3), Mi x Ni with Mi >= Ni;
+      // a tall block is first reduced by a Householder QR.
+      const int64_t kb = Ni;
+      if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvUdone + r], 0));
+      if (Mi > Ni) {
+        RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, B.Wu[r], Mi, Ri, bb, B.Tu, kb,
+                                  B.tau, nullptr, 0, B.panel, B.panel_bytes, B.status));
+        RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, B.Wl[r], Mi,
+                      nullptr, 0));
+      } else {
+        RRF_TRY(copy_matrix(st, kb, kb, T22, ldt, Ri, bb));
+      }
+      RRF_CHECK_HIP(hipEventRecord(ev[kEvU + r], st));
+      RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvU + r], 0));
+      if (U && Mi > Ni) {
+        double* Uc = U + c0 * ldu;
+        RRF_TRY(dgemm(s1, false, false, m, kb, Mi, 1.0, Uc, ldu, B.Wu[r], Mi, 0.0, B.X1, m,
+                      B.split[1], SE));
+        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, B.Wl[r], Mi, 1.0, Uc, ldu,
+                      nullptr, 0));
+      }
+      RRF_CHECK_HIP(hipEventRecord(ev[kEvUdone + r], s1));
+    }
+  }
+  // ---- after the loop: all block SVDs in one launch, then the updates
+  // of the processed columns they feed.
+  RRF_CHECK_HIP(hipEventRecord(ev[kEvS1], s1));
+  RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvS1], 0));
+  const int64_t k_last = n - (s - 1) * b;
+  RRF_TRY(block_svd_batched(st, (int)s, (int)bb, (int)k_last, B.R, bb, bb * bb, B.Us, B.d, bb,
+                            B.Vs, B.svd, B.svd_bytes, B.status));
+  RRF_CHECK_HIP(hipEventRecord(ev[kEvSvd], st));
+  RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvSvd], 0));
+  for (int64_t i = 0; i < s; ++i) {
+    const int64_t c0 = i * b;
+    const int64_t kb = std::min(b, n - c0);
+    const int64_t c2 = c0 + kb;
+    const bool last = (i == s - 1);
+    const double* Usi = B.Us + i * bb * bb;  // kb x kb, ld kb
+    const double* Vsi = B.Vs + i * bb * bb;
+    double* T22 = T + c0 + c0 * ldt;
+    // T(I2uI3, J2) = [D; 0] (the panel already cleared it; the last block is
+    // written whole)
+    RRF_TRY(set_diag(st, last ? m - c0 : kb, kb, B.d + i * bb, T22, ldt));
+    RRF_TRY(right_mult(st, c0, kb, T + c0 * ldt, ldt, Vsi, B.X0, B.split[0], SE));  // T(I1, J2)
+    if (!last) {
+      const int64_t N3 = n - c2;
+      double* T2r = T + c0 + c2 * ldt;  // T(I2, J3) <- Us^T T(I2, J3)
+      RRF_TRY(dgemm(st, true, false, kb, N3, kb, 1.0, Usi, kb, T2r, ldt, 0.0, B.Zl, kb, nullptr,
+                    0));
+      RRF_TRY(copy_matrix(st, kb, N3, B.Zl, kb, T2r, ldt));
+    }
+    if (U) RRF_TRY(right_mult(s1, m, kb, U + c0 * ldu, ldu, Usi, B.X1, B.split[1], SE));
+    if (V) RRF_TRY(right_mult(s1, n, kb, V + c0 * ldv, ldv, Vsi, B.X1, B.split[1], SE));
+  }
+  RRF_CHECK_HIP(hipEventRecord(ev[kEvS1], s1));
+  RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvS1], 0));
+  *status_out = 0;
+  return RRF_OK;
+}
+
+}  // namespace rrf

@@ -1,0 +1,124 @@
+// Optional per-kernel timing: a pair of HIP events around each launch of a
+// kernel class, on the stream the kernel runs on, plus the algorithmic flop
+// and byte counts of that launch. Off by default (one branch per launch).
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.hpp"
+#include "trace.hpp"
+
+namespace rrf {
+
+namespace {
+
+struct Record {
+  int cls;
+  double flops, bytes;
+  hipEvent_t e0, e1;
+};
+
+struct Totals {
+  int64_t launches = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Record> g_pending;
+std::vector<hipEvent_t> g_free;
+Totals g_tot[kTraceClasses];
+
+const char* kNames[kTraceClasses] = {
+    "dgemm_mfma_128x128_NN", "dgemm_mfma_128x128_TN", "dgemm_mfma_128x128_NT",
+    "dgemm_mfma_128x128_TT", "dgemm_mfma_64x64_NN",   "dgemm_mfma_64x64_TN",
+    "dgemm_mfma_64x64_NT",   "dgemm_mfma_64x64_TT",   "splitk_reduce",
+    "householder_panel",     "jacobi_svd",            "gaussian",
+    "elementwise",
+};
+
+hipEvent_t get_event() {
+  if (!g_free.empty()) {
+    hipEvent_t e = g_free.back();
+    g_free.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void drain_locked() {
+  for (Record& r : g_pending) {
+    float ms = 0.f;
+    if (r.e0 && r.e1 && hipEventSynchronize(r.e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+      Totals& t = g_tot[r.cls];
+      t.launches += 1;
+      t.ms += ms;
+      t.flops += r.flops;
+      t.bytes += r.bytes;
+    }
+    if (r.e0) g_free.push_back(r.e0);
+    if (r.e1) g_free.push_back(r.e1);
+  }
+  g_pending.clear();
+}
+
+}  // namespace
+
+bool trace_on() { return g_on; }
+
+int trace_begin(hipStream_t st, int cls, double flops, double bytes) {
+  if (!g_on) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  Record r{cls, flops, bytes, get_event(), get_event()};
+  if (r.e0) (void)hipEventRecord(r.e0, st);
+  g_pending.push_back(r);
+  return (int)g_pending.size() - 1;
+}
+
+void trace_end(hipStream_t st, int token) {
+  if (token < 0) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (token < (int)g_pending.size() && g_pending[token].e1)
+    (void)hipEventRecord(g_pending[token].e1, st);
+  if (g_pending.size() > 4096) drain_locked();
+}
+
+int gemm_trace_class(int tile, bool ta, bool tb) {
+  return (tile == 128 ? 0 : 4) + (ta ? 1 : 0) + (tb ? 2 : 0);
+}
+
+}  // namespace rrf
+
+using namespace rrf;
+
+extern "C" {
+
+int rrf_trace_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  drain_locked();
+  for (auto& t : g_tot) t = Totals{};
+  g_on = on != 0;
+  return RRF_OK;
+}
+
+int rrf_trace_read(rrf_trace_entry* out, int max_entries) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  drain_locked();
+  int n = 0;
+  for (int c = 0; c < kTraceClasses && n < max_entries; ++c) {
+    if (g_tot[c].launches == 0) continue;
+    rrf_trace_entry& e = out[n++];
+    memset(&e, 0, sizeof e);
+    strncpy(e.name, kNames[c], sizeof e.name - 1);
+    e.launches = g_tot[c].launches;
+    e.ms = g_tot[c].ms;
+    e.flops = g_tot[c].flops;
+    e.bytes = g_tot[c].bytes;
+  }
+  return n;
+}
+
+}  // extern "C"

@@ -1,0 +1,21 @@
+// Internal interface of the optional per-kernel timing (trace.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace rrf {
+
+enum TraceClass {
+  kTrGemm128NN = 0, kTrGemm128TN, kTrGemm128NT, kTrGemm128TT,
+  kTrGemm64NN, kTrGemm64TN, kTrGemm64NT, kTrGemm64TT,
+  kTrSplitReduce, kTrPanel, kTrJacobi, kTrGaussian, kTrElementwise,
+  kTraceClasses
+};
+
+bool trace_on();
+// Returns a token for trace_end (-1 when tracing is off).
+int trace_begin(hipStream_t st, int cls, double flops, double bytes);
+void trace_end(hipStream_t st, int token);
+int gemm_trace_class(int tile, bool ta, bool tb);
+
+}  // namespace rrf

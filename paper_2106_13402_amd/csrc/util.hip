@@ -1,0 +1,141 @@
+// Element-wise helpers: identity start for U and V (Alg. 3 first line), the
+// copy of A into T, block copies, the diagonal write T(I2,J2) = D, and the
+// finiteness check of the input. All are HBM-bound grid-stride loops that
+// walk column-major storage with consecutive threads on consecutive rows.
+#include "common.hpp"
+#include "kernels.hpp"
+#include "trace.hpp"
+
+namespace rrf {
+
+namespace {
+
+inline unsigned blocks_for(int64_t elems) {
+  int64_t b = ceil_div(elems, 256);
+  if (b > 16384) b = 16384;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+__global__ __launch_bounds__(256) void identity_kernel(int64_t rows, int64_t cols, double* X,
+                                                       int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t % rows, j = t / rows;
+    X[i + j * ld] = (i == j) ? 1.0 : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void copy_kernel(int64_t rows, int64_t cols,
+                                                   const double* __restrict__ S, int64_t lds,
+                                                   double* __restrict__ D, int64_t ldd) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t % rows, j = t / rows;
+    D[i + j * ldd] = S[i + j * lds];
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(int64_t rows, int64_t cols, double v, double* X,
+                                                   int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t % rows, j = t / rows;
+    X[i + j * ld] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void diag_kernel(int64_t rows, int64_t cols, const double* d,
+                                                   double* X, int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t % rows, j = t / rows;
+    X[i + j * ld] = (i == j) ? d[i] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < count;
+       t += (int64_t)gridDim.x * 256)
+    p[t] = v;
+}
+
+__global__ __launch_bounds__(256) void finite_kernel(int64_t rows, int64_t cols,
+                                                     const double* X, int64_t ld, int* status) {
+  const int64_t total = rows * cols;
+  bool bad = false;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * 256) {
+    const int64_t i = t % rows, j = t / rows;
+    const double v = X[i + j * ld];
+    if (!(v - v == 0.0)) bad = true;  // NaN or +-Inf
+  }
+  if (bad) atomicOr(status, 1);
+}
+
+}  // namespace
+
+int set_identity(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
+  hipLaunchKernelGGL(identity_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols,
+                     X, ld);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int copy_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int64_t lds,
+                double* D, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrElementwise, 0.0, 16.0 * rows * cols);
+  hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols, S,
+                     lds, D, ldd);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int fill_matrix(hipStream_t st, int64_t rows, int64_t cols, double v, double* X, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
+  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols, v,
+                     X, ld);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int set_diag(hipStream_t st, int64_t rows, int64_t cols, const double* d, double* X, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
+  hipLaunchKernelGGL(diag_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols, d,
+                     X, ld);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int fill_u32(hipStream_t st, unsigned* p, int64_t count, unsigned v) {
+  if (count <= 0) return RRF_OK;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(count)), dim3(256), 0, st, p, count, v);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int check_finite(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+                 int* status) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
+  hipLaunchKernelGGL(finite_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols,
+                     X, ld, status);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+}  // namespace rrf

@@ -1,0 +1,78 @@
+// Stand-alone C-ABI client: factor a Gaussian n x n matrix with librrf and
+// print one line of timings. Used to profile the library without any Python
+// or torch runtime in the process (rocprofv3 --kernel-trace / --pmc).
+//
+//   rrf_bench [--alg randutv|powerurv] [--n N] [--b B] [--q Q] [--reps R] [--trace]
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "rrf.h"
+
+static int fail(const char* what, int st) {
+  fprintf(stderr, "rrf_bench: %s failed: %d (%s)\n", what, st, rrf_last_error());
+  return 1;
+}
+
+int main(int argc, char** argv) {
+  std::string alg = "randutv";
+  long n = 16384, b = 128, q = 2, reps = 1;
+  bool trace = false;
+  for (int i = 1; i < argc; ++i) {
+    std::string a = argv[i];
+    auto next = [&](long& v) { if (i + 1 < argc) v = atol(argv[++i]); };
+    if (a == "--alg" && i + 1 < argc) alg = argv[++i];
+    else if (a == "--n") next(n);
+    else if (a == "--b") next(b);
+    else if (a == "--q") next(q);
+    else if (a == "--reps") next(reps);
+    else if (a == "--trace") trace = true;
+    else { fprintf(stderr, "unknown argument %s\n", a.c_str()); return 2; }
+  }
+  const size_t bytes = (size_t)n * n * sizeof(double);
+  double *A = nullptr, *U = nullptr, *T = nullptr, *V = nullptr;
+  void* ws = nullptr;
+  const int code = alg == "powerurv" ? RRF_ALG_POWERURV : RRF_ALG_RANDUTV;
+  const size_t wsb = rrf_workspace_size(code, n, n, b, (int)q, RRF_PREC_FP64);
+  if (wsb == 0) return fail("rrf_workspace_size", -1);
+  if (hipMalloc(&A, bytes) != hipSuccess || hipMalloc(&U, bytes) != hipSuccess ||
+      hipMalloc(&T, bytes) != hipSuccess || hipMalloc(&V, bytes) != hipSuccess ||
+      hipMalloc(&ws, wsb) != hipSuccess) {
+    fprintf(stderr, "rrf_bench: device allocation failed\n");
+    return 1;
+  }
+  int st = rrf_gaussian(0, 1ull << 40, n, n, A, n, nullptr);
+  if (st) return fail("rrf_gaussian", st);
+  rrf_opts o;
+  rrf_opts_init(&o);
+  o.workspace = ws;
+  o.workspace_bytes = wsb;
+  if (trace) rrf_trace_enable(1);
+  double best = 1e30, total = 0.0;
+  for (long r = 0; r < reps; ++r) {
+    auto t0 = std::chrono::steady_clock::now();
+    st = code == RRF_ALG_RANDUTV ? rrf_randutv_ex(n, n, A, n, b, (int)q, 1, U, T, V, &o)
+                                 : rrf_powerurv_ex(n, n, A, n, b, (int)q, 1, U, T, V, &o);
+    if (st) return fail(alg.c_str(), st);
+    double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    best = s < best ? s : best;
+    total += s;
+    printf("rrf_bench: %s n=%ld b=%ld q=%ld rep %ld: %.4f s\n", alg.c_str(), n, b, q, r, s);
+    fflush(stdout);
+  }
+  if (trace) {
+    rrf_trace_entry e[64];
+    int k = rrf_trace_read(e, 64);
+    for (int i = 0; i < k; ++i)
+      printf("  %-24s launches %8lld  %10.3f ms  %8.2f TF/s  %8.1f GB/s\n", e[i].name,
+             (long long)e[i].launches, e[i].ms, e[i].flops / (e[i].ms * 1e-3) / 1e12,
+             e[i].bytes / (e[i].ms * 1e-3) / 1e9);
+  }
+  printf("rrf_bench: best %.4f s, mean %.4f s\n", best, total / reps);
+  hipFree(A); hipFree(U); hipFree(T); hipFree(V); hipFree(ws);
+  return 0;
+}

@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/rrf.h declares, and rejects invalid arguments (LAPACK-style -k)
+before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2106_13402_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "rrf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rrf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("rrf_randutv", "rrf_powerurv", "rrf_randutv_ex", "rrf_powerurv_ex",
+                 "rrf_workspace_size", "rrf_status_string", "rrf_last_error"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert missing == []
+    # and the binding's prototype table covers them all
+    assert sorted(_lib.PROTOTYPES) == _declared()
+
+
+NULL = None
+DUMMY = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 1, DUMMY, 1, 1, 0), -1),        # m < 1
+    ((4, 0, DUMMY, 4, 1, 0), -2),        # n < 1
+    ((4, 4, NULL, 4, 1, 0), -3),         # A NULL
+    ((4, 4, DUMMY, 3, 1, 0), -4),        # lda < m
+    ((4, 4, DUMMY, 4, 0, 0), -5),        # b < 1
+    ((4, 4, DUMMY, 4, 2, -1), -6),       # q < 0
+])
+@pytest.mark.parametrize("fn", ["rrf_randutv", "rrf_powerurv"])
+def test_argument_errors(lib, fn, args, code):
+    m, n, A, lda, b, q = args
+    st = getattr(lib, fn)(m, n, A, lda, b, q, 1, NULL, DUMMY, NULL)
+    assert st == code
+    assert lib.rrf_last_error()
+
+
+@pytest.mark.parametrize("fn", ["rrf_randutv", "rrf_powerurv"])
+def test_null_T_and_wide_input(lib, fn):
+    assert getattr(lib, fn)(4, 4, DUMMY, 4, 2, 0, 1, NULL, NULL, NULL) == -9
+    assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, 0, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP
+
+
+def test_alias_requires_tight_lda(lib):
+    assert lib.rrf_randutv(4, 4, DUMMY, 6, 2, 0, 1, NULL, DUMMY, NULL) == -4
+
+
+def test_workspace_size(lib):
+    f = lib.rrf_workspace_size
+    assert f(_lib.RRF_ALG_RANDUTV, 512, 512, 32, 1, 0) > 0
+    assert f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 1, 0) > 0
+    assert f(_lib.RRF_ALG_RANDUTV, 512, 600, 32, 1, 0) == 0     # m < n
+    assert f(_lib.RRF_ALG_RANDUTV, 512, 512, 300, 1, 0) == 0    # b > 256
+    assert f(7, 512, 512, 32, 1, 0) == 0
+    big = f(_lib.RRF_ALG_RANDUTV, 16384, 16384, 128, 2, 0)
+    assert 0 < big < 2 ** 31  # the FP64 path keeps its scratch small (O(n b))
+
+
+def test_component_argument_errors(lib):
+    assert lib.rrf_dgemm(2, 0, 1, 1, 1, 1.0, DUMMY, 1, DUMMY, 1, 0.0, DUMMY, 1, NULL, 0, NULL) == -1
+    assert lib.rrf_dgemm(0, 0, 4, 4, 4, 1.0, DUMMY, 3, DUMMY, 4, 0.0, DUMMY, 4, NULL, 0, NULL) == -8
+    assert lib.rrf_householder_panel(3, 4, DUMMY, 3, DUMMY, 3, NULL, 4, DUMMY, 4, DUMMY, NULL, 0,
+                                     NULL) == -1
+    assert lib.rrf_block_svd(0, DUMMY, 1, DUMMY, DUMMY, DUMMY, NULL, 0, NULL) == -1
+    assert lib.rrf_gaussian(1, 1, -1, 2, DUMMY, 1, NULL) == -3
+    assert lib.rrf_panel_workspace_size(16384, 128) > 0
+    assert lib.rrf_panel_workspace_size(10, 20) == 0
+
+
+def test_status_strings(lib):
+    for code in range(0, 6):
+        assert lib.rrf_status_string(code)
+    assert b"invalid" in lib.rrf_status_string(-3)
+
+
+def test_opts_init(lib):
+    o = _lib.rrf_opts()
+    o.precision = 9
+    o.async_ = 1
+    lib.rrf_opts_init(C.byref(o))
+    assert o.precision == 0 and o.async_ == 0 and o.workspace is None

@@ -1,0 +1,201 @@
+"""GPU component parity: the sketch generator, the FP64 MFMA GEMM, the
+Householder panel and the block SVD, each called through the C-ABI and
+compared with an independent CPU computation (the oracle's generator, numpy
+products, LAPACK dgeqrf, numpy's SVD).
+
+Tolerances come from the arithmetic: a K-term FP64 dot product is within
+gamma_K |a|^T |b| of the exact value (gamma_K ~ K u); Householder QR and
+one-sided Jacobi are backward stable, so factors agree to a small multiple of
+n u relative to the input's norm when the problem is well conditioned.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.hqr import form_q, hqr
+
+pytestmark = pytest.mark.gpu
+U64 = np.finfo(np.float64).eps / 2
+
+
+def _to_dev(x, gpu):
+    import torch
+    from paper_2106_13402_amd import colmajor
+    return colmajor(torch.as_tensor(np.asfortranarray(x), device=gpu))
+
+
+def _host(x):
+    return x.detach().cpu().numpy()
+
+
+# ------------------------------------------------------------- generator
+@pytest.mark.parametrize("seed,stream,rows,cols", [
+    (1, 1, 37, 11), (0, 0, 4, 1), (1, 7, 4096, 128), (2**40 + 3, 2**32 + 5, 1001, 3)])
+def test_gaussian_matches_oracle(gpu, seed, stream, rows, cols):
+    from paper_2106_13402_amd import gaussian
+    g = _host(gaussian(seed, stream, rows, cols, gpu))
+    ref = oracle.gaussian(seed, stream, rows, cols)
+    # same uniforms bit for bit; log/sqrt/cos/sin may differ by a few ulp
+    np.testing.assert_allclose(g, ref, rtol=0, atol=16 * U64 * np.maximum(1.0, np.abs(ref)).max())
+
+
+# ------------------------------------------------------------------ GEMM
+GEMM_CASES = [
+    (1, 1, 1), (17, 33, 5), (64, 64, 64), (130, 70, 300), (257, 129, 1000),
+    (200, 128, 5000),   # skinny: split-K path
+    (3000, 128, 8192),  # sketch-like, split-K, several tiles and a ragged tail
+    (1000, 1100, 128),  # rank-b update shape
+]
+
+
+@pytest.mark.parametrize("M,N,K", GEMM_CASES)
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_dgemm(gpu, M, N, K, ta, tb):
+    from paper_2106_13402_amd import dgemm
+    rng = np.random.default_rng(M * 7 + N * 3 + K)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    C0 = rng.standard_normal((M, N))
+    alpha, beta = 0.75, -1.25
+    Cd = _to_dev(C0, gpu)
+    dgemm(_to_dev(A, gpu), _to_dev(B, gpu), transa=ta, transb=tb, alpha=alpha, beta=beta, C_out=Cd)
+    opA = A.T if ta else A
+    opB = B.T if tb else B
+    ref = alpha * (opA @ opB) + beta * C0
+    bound = (K + 2) * 2 * U64 * (abs(alpha) * (np.abs(opA) @ np.abs(opB)) + abs(beta) * np.abs(C0))
+    err = np.abs(_host(Cd) - ref)
+    assert np.all(err <= 4 * bound + 1e-300), float((err / (bound + 1e-300)).max())
+
+
+def test_dgemm_strided_views(gpu):
+    """Operands are sub-blocks of larger matrices (lda > rows), as in T22."""
+    import torch
+    from paper_2106_13402_amd import colmajor, dgemm
+    rng = np.random.default_rng(5)
+    big = rng.standard_normal((700, 650))
+    Bm = rng.standard_normal((600, 40))
+    dbig = _to_dev(big, gpu)
+    sub = dbig[50:650, 30:620]  # 600 x 590, lda 700
+    Cd = dgemm(sub, _to_dev(Bm, gpu), transa=True)
+    ref = big[50:650, 30:620].T @ Bm
+    np.testing.assert_allclose(_host(Cd), ref, atol=1e-11 * np.abs(ref).max())
+    assert isinstance(sub, torch.Tensor) and sub.stride(0) == 1 and colmajor(sub) is sub
+
+
+def test_dgemm_k_zero_scales(gpu):
+    import torch
+    from paper_2106_13402_amd import dgemm
+    A = torch.zeros((5, 0), dtype=torch.float64, device=gpu)
+    B = torch.zeros((0, 3), dtype=torch.float64, device=gpu)
+    C = _to_dev(np.ones((5, 3)), gpu)
+    dgemm(A, B, beta=2.0, C_out=C)
+    assert np.all(_host(C) == 2.0)
+
+
+# ---------------------------------------------------------- panel QR
+def _larft(W, tau):
+    """Forward compact-WY factor from explicit reflectors (Schreiber-Van Loan)."""
+    k = tau.size
+    T = np.zeros((k, k))
+    for i in range(k):
+        T[:i, i] = -tau[i] * T[:i, :i] @ (W[:, :i].T @ W[:, i])
+        T[i, i] = tau[i]
+    return T
+
+
+PANEL_CASES = [(5, 1), (64, 32), (1000, 7), (513, 32), (4096, 128), (16384, 128), (20000, 64),
+               (32768, 128), (3000, 256)]
+
+
+@pytest.mark.parametrize("M,k", PANEL_CASES)
+def test_householder_panel_matches_lapack(gpu, M, k):
+    from paper_2106_13402_amd import householder_panel
+    rng = np.random.default_rng(M + k)
+    P = rng.standard_normal((M, k))
+    W, R, Tf, tau = (_host(x) for x in householder_panel(_to_dev(P, gpu)))
+    qr, tau_ref = hqr(P)
+    W_ref = np.tril(qr[:, :k], -1) + np.eye(M, k)
+    np.testing.assert_allclose(tau, tau_ref, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(W, W_ref, atol=1e-11)
+    np.testing.assert_allclose(R, np.triu(qr[:k, :k]), atol=1e-11 * np.abs(P).max() * np.sqrt(M))
+    np.testing.assert_allclose(Tf, _larft(W_ref, tau_ref), atol=1e-10)
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.tril(Tf, -1) == 0)
+    # Q from the compact-WY factors equals LAPACK's Q (leading columns)
+    Q = np.eye(M, k) - W @ (Tf @ W[:k, :].T)
+    np.testing.assert_allclose(Q, form_q(qr, tau_ref, k), atol=1e-11)
+
+
+def test_householder_panel_zero_and_rank_deficient(gpu):
+    from paper_2106_13402_amd import householder_panel
+    rng = np.random.default_rng(1)
+    P = rng.standard_normal((300, 8))
+    P[:, 2] = 0.0                  # zero column: H = I (tau = 0)
+    P[:, 5] = P[:, 1] * 3.0        # dependent column
+    P[1:, 0] = 0.0                 # zero sub-column below the diagonal
+    W, R, Tf, tau = (_host(x) for x in householder_panel(_to_dev(P, gpu)))
+    qr, tau_ref = hqr(P)
+    assert tau[0] == 0.0 and tau[2] == 0.0
+    # columns 0..4 are determined by P; column 5 lies in the span of the
+    # earlier ones, so its reflector (and every later one) is fixed by
+    # rounding noise alone: only R(5,5) ~ 0 and P = Q R are well-posed there.
+    np.testing.assert_allclose(tau[:5], tau_ref[:5], atol=1e-12)
+    np.testing.assert_allclose(np.abs(np.diag(R))[:5], np.abs(np.diag(qr))[:5], atol=1e-12 * 20)
+    assert abs(R[5, 5]) < 1e-13 * np.abs(P).max() * 20
+    Q = np.eye(300) - W @ Tf @ W.T
+    assert np.linalg.norm(Q.T @ Q - np.eye(300), 2) < 1e-13
+    np.testing.assert_allclose(Q[:, :8] @ R, P, atol=1e-12 * 20)
+
+
+def test_householder_panel_inplace(gpu):
+    from paper_2106_13402_amd import householder_panel
+    rng = np.random.default_rng(2)
+    P = rng.standard_normal((2000, 16))
+    dP = _to_dev(P, gpu)
+    W, R, Tf, tau = householder_panel(dP, inplace=True)
+    qr, tau_ref = hqr(P)
+    np.testing.assert_allclose(_host(dP), np.tril(qr, -1) + np.eye(2000, 16), atol=1e-11)
+
+
+# ------------------------------------------------------------- block SVD
+@pytest.mark.parametrize("k", [1, 2, 7, 32, 64, 100, 128, 256])
+def test_block_svd(gpu, k):
+    from paper_2106_13402_amd import block_svd
+    rng = np.random.default_rng(k)
+    B = np.triu(rng.standard_normal((k, k)))  # shape of the panel's R
+    Us, d, Vs = (_host(x) for x in block_svd(_to_dev(B, gpu)))
+    Ur, dr, Vr = oracle.small_svd(B)
+    nB = np.linalg.norm(B, 2)
+    np.testing.assert_allclose(d, dr, atol=8 * k * U64 * nB)
+    assert np.all(np.diff(d) <= 0)
+    assert np.linalg.norm(Us.T @ Us - np.eye(k), 2) < 1e-13
+    assert np.linalg.norm(Vs.T @ Vs - np.eye(k), 2) < 1e-13
+    assert np.linalg.norm(Us @ np.diag(d) @ Vs.T - B, 2) < 8 * k * U64 * nB
+    for j in range(k):
+        assert Vs[np.argmax(np.abs(Vs[:, j])), j] > 0
+    # singular vectors agree with the oracle where the gaps are large
+    gaps = np.minimum(np.abs(np.diff(np.r_[np.inf, dr])), np.abs(np.diff(np.r_[dr, -np.inf])))
+    ok = gaps > 1e-6 * nB
+    np.testing.assert_allclose(Vs[:, ok], Vr[:, ok], atol=1e-8)
+
+
+def test_block_svd_graded_and_degenerate(gpu):
+    from paper_2106_13402_amd import block_svd
+    from synthetic import haar
+    k = 32
+    s = 10.0 ** -np.arange(k, dtype=float) * 0.5  # 1 down to 1e-31: relative accuracy matters
+    B = haar(k, k, seed=3, stream=1) @ np.diag(s) @ haar(k, k, seed=3, stream=2).T
+    _, d, _ = (_host(x) for x in block_svd(_to_dev(np.triu(np.linalg.qr(B)[1]), gpu)))
+    # forming B rounds at eps ||B||, so only values well above that are fixed
+    np.testing.assert_allclose(d[:6], s[:6], rtol=1e-9)
+    assert np.all(d[6:] < 1e-4)
+    # zero block: d = 0, U and V orthogonal
+    Us, d, Vs = (_host(x) for x in block_svd(_to_dev(np.zeros((16, 16)), gpu)))
+    assert np.all(d == 0)
+    assert np.linalg.norm(Us.T @ Us - np.eye(16)) < 1e-14
+    assert np.linalg.norm(Vs.T @ Vs - np.eye(16)) < 1e-14
+    # rank 3
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((24, 3)) @ rng.standard_normal((3, 24))
+    Us, d, Vs = (_host(x) for x in block_svd(_to_dev(B, gpu)))
+    assert np.all(d[3:] < 1e-13 * d[0])
+    assert np.linalg.norm(Us.T @ Us - np.eye(24), 2) < 1e-13
