@@ -20,15 +20,20 @@
 //    the dot products v_{j-1}^T v_l for column j-1 of Tf, and the owner's
 //    copy of row j. Threads are laid out one (or a few) per column, so the
 //    sums need no cross-lane reductions;
-//  * each worker publishes its partial sums in a slot of a double-buffered
-//    global array and meets the others at a counter barrier (device-scope
-//    release/acquire, bounded spin); every workgroup then sums the slots in a
-//    fixed order, so all compute bit-identical scalars and results are
-//    reproducible run to run;
+//  * each worker publishes its partial sums in its slot of a ring of global
+//    buffers with device-coherent (write-through) stores, waits for their
+//    completion and raises its own flag (one 64-byte line per workgroup);
+//    the others poll the flags with a bounded spin and read the slots with
+//    device-coherent loads. No cache-wide write-back or invalidation and no
+//    contended atomic counter sits between two columns;
+//  * every workgroup sums the slots in the same fixed order, spread over all
+//    of its threads with the loads in flight together, so all compute
+//    bit-identical scalars and results are reproducible run to run;
 //  * one extra "coordinator" workgroup owns no rows: it keeps Tf in LDS,
 //    builds column j-1 by the forward recurrence
-//    Tf(1:j-1, j) = -tau_j Tf(1:j-1, 1:j-1) W^T v_j while the workers move on,
-//    and writes R, tau and Tf;
+//    Tf(1:j-1, j) = -tau_j Tf(1:j-1, 1:j-1) W^T v_j and writes R, tau and Tf.
+//    Workers wait for it only when they are about to reuse a ring buffer, so
+//    it may trail them by up to kRing - 2 rounds;
 //  * the launch is cooperative so that all workgroups are co-resident.
 #include <hip/hip_cooperative_groups.h>
 
@@ -46,6 +51,8 @@ constexpr int kThreads = 256;
 constexpr int kMaxCols = 256;
 constexpr int64_t kLdsBudget = 144 * 1024;  // dynamic LDS bytes per workgroup
 constexpr int kMaxGroups = 256;
+constexpr int kRing = 4;                     // slot buffers in flight
+constexpr int kFlagStride = 16;              // unsigned per flag: one 64-byte line
 constexpr long kSpinLimit = 1L << 22;
 
 struct PanelArgs {
@@ -62,13 +69,13 @@ struct PanelArgs {
   double* tau;
   double* zero;
   int64_t ldz;
-  double* red;        // 2 * Gw * slot doubles
-  unsigned* counter;  // zero at launch
+  double* red;        // kRing * Gw * slot doubles
+  unsigned* flags;    // (Gw + 1) * kFlagStride, zero at launch
   int* status;
   int Gw;             // worker workgroups; workgroup Gw is the coordinator
   int rows_per;
-  int ldr_lds;        // LDS row stride of the row block (k + 1)
-  int slot;           // 3 * k
+  int ldl;            // LDS row stride of the row block (k + 1)
+  int slot;           // doubles per slot: Gram row, row j, Tf dots (3k, padded)
   int tf_in_lds;      // coordinator keeps Tf in LDS
 };
 
@@ -76,43 +83,78 @@ __device__ inline int clampi(int64_t v, int lo, int hi) {
   return (int)(v < lo ? lo : (v > hi ? hi : v));
 }
 
-// Counter barrier across the workgroups of a cooperative launch.
-// Returns false (and flags status) if the spin limit is hit.
-__device__ bool grid_barrier(unsigned* counter, unsigned target, int* status) {
-  __shared__ int ok;
+// Device-coherent accesses: written through to, and read from, the level
+// that all XCDs share.
+__device__ inline void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_dev(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Announce round `epoch` (after this workgroup's slot stores are complete)
+// and wait until every worker has announced it and, when coord_epoch > 0, the
+// coordinator has announced coord_epoch. Returns false (status bit 4) when a
+// spin limit is hit or another workgroup has flagged an error.
+__device__ bool announce_and_wait(const PanelArgs& a, unsigned epoch, bool wait,
+                                  unsigned coord_epoch) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int good = 1;
-    __threadfence();
-    atomicAdd(counter, 1u);
+  const int tid = threadIdx.x;
+  if (tid == 0)
+    __hip_atomic_store(a.flags + (size_t)kFlagStride * blockIdx.x, epoch, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  if (!wait) return true;
+  int good = 1;
+  const int nwait = a.Gw + (coord_epoch > 0 ? 1 : 0);
+  if (tid < nwait) {
+    const unsigned target = (tid < a.Gw) ? epoch : coord_epoch;
+    const unsigned* f = a.flags + (size_t)kFlagStride * tid;
     long spins = 0;
-    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > kSpinLimit ||
-          __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          __hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
         good = 0;
-        atomicOr(status, 4);
+        atomicOr(a.status, 4);
         break;
       }
     }
-    __threadfence();
-    ok = good;
   }
-  __syncthreads();
-  return ok != 0;
+  return __syncthreads_and(good) != 0;
 }
 
-// Sum of base[g * stride + idx] over g = 0..G-1 in a fixed association
-// (eight interleaved partial sums, combined pairwise), loads unrolled.
-__device__ inline double sum_slots(const double* base, size_t stride, int idx, int G) {
-  double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int g = 0;
-  for (; g + 8 <= G; g += 8) {
+// dst[e] = sum over workers g of slot_g[off + e], e < n, in one fixed order
+// (a function of n and Gw only, so every workgroup gets identical sums).
+// The threads split the workers into tpe ranges per entry and keep up to 32
+// loads in flight each. Ends with dst visible to the workgroup.
+__device__ void reduce_slots(const double* base, int slot, int Gw, int off, int n, double* dst,
+                             double* part) {
+  const int tid = threadIdx.x;
+  int sp = 1;
+  while (sp < n) sp <<= 1;
+  const int tpe = kThreads / sp;
+  const int e = tid % sp, p = tid / sp;
+  double acc = 0.0;
+  if (e < n) {
+    const int g0 = (int)((int64_t)Gw * p / tpe), g1 = (int)((int64_t)Gw * (p + 1) / tpe);
+    for (int gb = g0; gb < g1; gb += 32) {
+      double v[32];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] += base[(size_t)(g + u) * stride + idx];
+      for (int u = 0; u < 32; ++u)
+        v[u] = (gb + u < g1) ? ld_dev(base + (size_t)(gb + u) * slot + off + e) : 0.0;
+#pragma unroll
+      for (int u = 0; u < 32; ++u) acc += v[u];
+    }
   }
-  for (int u = 0; g < G; ++g, ++u) s[u] += base[(size_t)g * stride + idx];
-  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  part[tid] = acc;
+  __syncthreads();
+  if (tid < n) {
+    double s = 0.0;
+    for (int u = 0; u < tpe; ++u) s += part[tid + u * sp];
+    dst[tid] = s;
+  }
+  __syncthreads();
 }
 
 __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
@@ -126,12 +168,11 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
   const bool coord = (g == a.Gw);
   const int k = a.k;
   const int RP = a.rows_per;
-  const int L = a.ldr_lds;
+  const int L = a.ldl;
   const int64_t r0 = (int64_t)g * RP;
   const int rows = coord ? 0 : (int)((a.M - r0) < RP ? (a.M - r0) : RP);
-  double* Ls = smem;                                  // workers: rows x k, stride L
-  double* Tl = a.tf_in_lds ? smem : nullptr;          // coordinator: k x k, ld k
-  const int G = a.Gw + 1;
+  double* Ls = smem;                          // workers: rows x k, stride L
+  double* Tl = a.tf_in_lds ? smem : nullptr;  // coordinator: k x k, ld k
 
   if (!coord) {
     for (int idx = tid; idx < rows * k; idx += kThreads) {
@@ -151,105 +192,124 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
   for (int j = 0; j <= k; ++j) {
     const int ns = (j < k) ? (k - j) : 0;   // Gram entries s_c, c in [j, k)
     const int nt = (j >= 2) ? (j - 1) : 0;  // Tf dots v_{j-1}^T v_l, l in [0, j-1)
-    double* slot = a.red + ((size_t)(j & 1) * a.Gw + g) * a.slot;
+    const unsigned epoch = (unsigned)j + 1;
+    double* ring = a.red + (size_t)(j % kRing) * a.Gw * a.slot;
     if (!coord) {
-      // (a) column j of H_{j-1} applied to owned rows r >= j.
+      double* slot = ring + (size_t)g * a.slot;
       const int rlj = clampi((int64_t)j - r0, 0, rows);      // first local row >= j
-      if (j >= 1 && j < k && tau_prev != 0.0) {
-        const double wj = tau_prev * w_s[j];
-        for (int rl = rlj + tid; rl < rows; rl += kThreads)
-          Ls[rl * L + j] -= wj * Ls[rl * L + j - 1];
-      }
-      __syncthreads();
-      // (b) one pass over the columns: update the rest of H_{j-1} and form
-      // this workgroup's partial sums. Consecutive threads take consecutive
-      // columns of a row; tpc threads share a column over interleaved rows.
+      const int rlx = clampi((int64_t)j + 1 - r0, 0, rows);  // first local row > j
+      const double twj = (j >= 1 && j < k) ? tau_prev * w_s[j] : 0.0;
+      // (b) one pass over the columns: apply H_{j-1} to columns c > j and
+      // form the Gram partials x^T a_c (c >= j) with x = column j below row
+      // j after H_{j-1}, recomputed on the fly; threads ci >= ns form the Tf
+      // dots v_{j-1}^T v_l. Consecutive threads take consecutive columns of a
+      // row; tpc threads share a column over interleaved rows.
       const int nc = ns + nt;
-      if (nc > 0) {
-        int ncp = 1;
-        while (ncp < nc) ncp <<= 1;
-        const int tpc = kThreads / ncp;  // >= 1
-        const int ci = tid % ncp, sub = tid / ncp;
-        double acc = 0.0;
-        if (ci < nc) {
-          if (ci < ns) {
-            const int c = j + ci;
-            const double tw = (j >= 1 && tau_prev != 0.0) ? tau_prev * w_s[c] : 0.0;
-            const int rlx = clampi((int64_t)j + 1 - r0, 0, rows);  // first local row > j
-            for (int rl = rlj + sub; rl < rows; rl += tpc) {
-              double y = Ls[rl * L + c];
-              if (c > j && tw != 0.0) {
-                y -= tw * Ls[rl * L + j - 1];
-                Ls[rl * L + c] = y;
-              }
-              if (rl >= rlx) acc += Ls[rl * L + j] * y;
-            }
-          } else {
-            const int l = ci - ns;
-            const int rlv = clampi((int64_t)j - 1 - r0, 0, rows);
-            for (int rl = rlv + sub; rl < rows; rl += tpc) {
-              const double vv = (r0 + rl == j - 1) ? 1.0 : Ls[rl * L + j - 1];
-              acc += vv * Ls[rl * L + l];
+      int ncp = 1;
+      while (ncp < nc) ncp <<= 1;
+      const int tpc = kThreads / ncp;  // >= 1
+      const int ci = tid % ncp, sub = tid / ncp;
+      double acc = 0.0;
+      if (ci < ns) {
+        const int c = j + ci;
+        const double twc = (j >= 1) ? tau_prev * w_s[c] : 0.0;
+        const int jm = (j >= 1) ? j - 1 : 0;
+        for (int rl = rlj + sub; rl < rows; rl += 4 * tpc) {
+          double vv[4], xo[4], yo[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = rl + u * tpc;
+            const int rr = (r < rows) ? r : rl;
+            vv[u] = (j >= 1) ? Ls[rr * L + jm] : 0.0;
+            xo[u] = Ls[rr * L + j];
+            yo[u] = Ls[rr * L + c];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = rl + u * tpc;
+            if (r < rows) {
+              const double xj = xo[u] - twj * vv[u];
+              const double y = (c == j) ? xj : yo[u] - twc * vv[u];
+              if (c > j) Ls[r * L + c] = y;
+              if (r >= rlx) acc += xj * y;
             }
           }
         }
-        part[tid] = acc;
-        __syncthreads();
-        if (tid < nc) {
-          double s = 0.0;
-          for (int u = 0; u < tpc; ++u) s += part[tid + u * ncp];
-          if (tid < ns) slot[j + tid] = s;
-          else slot[2 * k + (tid - ns)] = s;
+      } else if (ci < nc) {
+        const int l = ci - ns;
+        const int rlv = clampi((int64_t)j - 1 - r0, 0, rows);  // first local row >= j-1
+        for (int rl = rlv + sub; rl < rows; rl += 4 * tpc) {
+          double vv[4], yl[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int r = rl + u * tpc;
+            const int rr = (r < rows) ? r : rl;
+            vv[u] = (r0 + rr == j - 1) ? 1.0 : Ls[rr * L + j - 1];
+            yl[u] = Ls[rr * L + l];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (rl + u * tpc < rows) acc += vv[u] * yl[u];
         }
       }
-      // (c) the owner of row j publishes it (after the updates of (b))
+      part[tid] = acc;
       __syncthreads();
-      if (j < k && (int64_t)j >= r0 && (int64_t)j < r0 + rows) {
-        const int rl = (int)(j - r0);
-        for (int c = j + tid; c < k; c += kThreads) slot[k + c] = Ls[rl * L + c];
+      // (c) publish: partial sums, row j of the panel (its owner), and column
+      // j of H_{j-1} A into LDS.
+      if (tid < nc) {
+        double s = 0.0;
+        for (int u = 0; u < tpc; ++u) s += part[tid + u * ncp];
+        st_dev(slot + ((tid < ns) ? j + tid : 2 * k + (tid - ns)), s);
       }
-    }
-
-    if (G > 1) {
-      if (!grid_barrier(a.counter, (unsigned)(j + 1) * (unsigned)G, a.status)) return;
+      if (j < k) {
+        const bool owner = (int64_t)j >= r0 && (int64_t)j < r0 + rows;
+        const int rlo = (int)(j - r0);
+        if (owner)
+          for (int c = j + 1 + tid; c < k; c += kThreads) st_dev(slot + k + c, Ls[rlo * L + c]);
+        for (int rl = rlj + tid; rl < rows; rl += kThreads) {
+          double x = Ls[rl * L + j];
+          if (j >= 1) {
+            x -= twj * Ls[rl * L + j - 1];
+            Ls[rl * L + j] = x;
+          }
+          if (rl == rlo && owner) st_dev(slot + k + j, x);
+        }
+      }
+      // the last round only feeds the coordinator
+      const unsigned ce = (epoch + 2 > (unsigned)kRing) ? epoch + 2 - kRing : 0u;
+      if (!announce_and_wait(a, epoch, j < k, ce)) return;
+      if (j == k) break;
     } else {
-      __syncthreads();
+      if (!announce_and_wait(a, epoch, true, 0u)) return;
     }
 
-    // (d) sum the worker slots in a fixed order (every workgroup alike).
-    {
-      const double* base = a.red + (size_t)(j & 1) * a.Gw * a.slot;
-      const int owner = (j < k) ? (int)(j / RP) : 0;
-      const int ne = 2 * ns + nt;
-      for (int e = tid; e < ne; e += kThreads) {
-        int idx;
-        double v;
-        if (e < ns) {
-          idx = j + e;
-          v = sum_slots(base, a.slot, idx, a.Gw);
-        } else if (e < 2 * ns) {
-          idx = k + j + (e - ns);
-          v = base[(size_t)owner * a.slot + idx];
-        } else {
-          idx = 2 * k + (e - 2 * ns);
-          v = sum_slots(base, a.slot, idx, a.Gw);
-        }
-        red_s[idx] = v;
-      }
+    // (d) sums over the worker slots, the same order in every workgroup.
+    if (ns > 0) {
+      const int owner = (int)(j / RP);
+      if (tid < ns) red_s[k + j + tid] = ld_dev(ring + (size_t)owner * a.slot + k + j + tid);
+      reduce_slots(ring, a.slot, a.Gw, j, ns, red_s + j, part);
     }
-    __syncthreads();
+    if (coord && nt > 0) reduce_slots(ring, a.slot, a.Gw, 2 * k, nt, red_s + 2 * k, part);
 
     // (e) coordinator: column j-1 of Tf.
     if (coord && j >= 1) {
       const int jj = j - 1;
+      const double* dots = red_s + 2 * k;
       for (int i = tid; i < jj; i += kThreads) {
-        double s = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int c = i;
         if (Tl) {
-          for (int c = i; c < jj; ++c) s += Tl[i + c * k] * red_s[2 * k + c];
+          for (; c + 4 <= jj; c += 4) {
+            s0 += Tl[i + c * k] * dots[c];
+            s1 += Tl[i + (c + 1) * k] * dots[c + 1];
+            s2 += Tl[i + (c + 2) * k] * dots[c + 2];
+            s3 += Tl[i + (c + 3) * k] * dots[c + 3];
+          }
+          for (; c < jj; ++c) s0 += Tl[i + c * k] * dots[c];
         } else {
-          for (int c = i; c < jj; ++c) s += a.Tf[i + (int64_t)c * a.ldt] * red_s[2 * k + c];
+          for (; c < jj; ++c) s0 += a.Tf[i + (int64_t)c * a.ldt] * dots[c];
         }
-        const double v = -tau_prev * s;
+        const double v = -tau_prev * ((s0 + s1) + (s2 + s3));
         if (Tl) Tl[i + jj * k] = v;
         else a.Tf[i + (int64_t)jj * a.ldt] = v;
       }
@@ -274,14 +334,15 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
       tau = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    for (int c = j + 1 + tid; c < k; c += kThreads) w_s[c] = red_s[k + c] + scal * red_s[c];
-    __syncthreads();
+    for (int c = j + 1 + tid; c < k; c += kThreads) {
+      const double w = red_s[k + c] + scal * red_s[c];
+      w_s[c] = w;
+      if (coord && a.R) a.R[j + (int64_t)c * a.ldr] = red_s[k + c] - tau * w;
+    }
     if (coord) {
       if (tid == 0) a.tau[j] = tau;
       if (a.R) {
         if (tid == 0) a.R[j + (int64_t)j * a.ldr] = beta;
-        for (int c = j + 1 + tid; c < k; c += kThreads)
-          a.R[j + (int64_t)c * a.ldr] = red_s[k + c] - tau * w_s[c];
         for (int i = j + 1 + tid; i < k; i += kThreads) a.R[i + (int64_t)j * a.ldr] = 0.0;
       }
     } else {
@@ -314,6 +375,9 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
 
 bool g_attr_set = false;
 
+size_t flag_bytes(int Gw) { return (size_t)round_up((int64_t)(Gw + 1) * kFlagStride * 4, 256); }
+int slot_doubles(int k) { return (int)round_up((int64_t)3 * k, 32); }
+
 }  // namespace
 
 bool panel_plan(int64_t M, int k, PanelPlan* plan) {
@@ -328,7 +392,7 @@ bool panel_plan(int64_t M, int k, PanelPlan* plan) {
   plan->G = (int)Gw;
   plan->rows_per = (int)rp;
   plan->lds = (size_t)std::max<int64_t>(rp * L, tf_lds ? (int64_t)k * k : 0) * 8;
-  plan->work = 256 + (size_t)2 * Gw * 3 * k * 8;
+  plan->work = flag_bytes((int)Gw) + (size_t)kRing * Gw * slot_doubles(k) * 8;
   return true;
 }
 
@@ -347,7 +411,7 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                                       (int)kLdsBudget));
     g_attr_set = true;
   }
-  unsigned* counter = reinterpret_cast<unsigned*>(work);
+  unsigned* flags = reinterpret_cast<unsigned*>(work);
   PanelArgs a{};
   a.M = M;
   a.k = k;
@@ -362,19 +426,19 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
   a.tau = tau;
   a.zero = zero;
   a.ldz = ldz;
-  a.red = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + 256);
-  a.counter = counter;
+  a.red = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + flag_bytes(plan.G));
+  a.flags = flags;
   a.status = status;
   a.Gw = plan.G;
   a.rows_per = plan.rows_per;
-  a.ldr_lds = k + 1;
-  a.slot = 3 * k;
+  a.ldl = k + 1;
+  a.slot = slot_doubles(k);
   a.tf_in_lds = ((int64_t)k * k * 8 <= kLdsBudget) ? 1 : 0;
   // Algorithmic traffic: the panel read once, W written, and the in-place
   // clear of the source panel when requested.
   const double pbytes = 8.0 * (double)M * k * (zero ? 3.0 : 2.0);
   const double pflops = 2.0 * (double)M * k * k;
-  RRF_TRY(fill_u32(st, counter, 1, 0u));
+  RRF_TRY(fill_u32(st, flags, (int64_t)(plan.G + 1) * kFlagStride, 0u));
   void* args[] = {&a};
   int tok = trace_begin(st, kTrPanel, pflops, pbytes);
   hipError_t e = hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(plan.G + 1),
