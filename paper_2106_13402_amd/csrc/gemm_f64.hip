@@ -218,17 +218,19 @@ __global__ __launch_bounds__(kThreads, 2) void dgemm_mfma_kernel(GemmF64Args g) 
   }
 }
 
-// C = alpha * sum_z P[z] + beta * C, summed in z order.
+// C = alpha * sum_z P_z + beta * C over a 2-D grid (rows in x, columns in
+// y), partials added in split order.
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N, int S,
                                                             const double* __restrict__ P,
                                                             double alpha, double beta,
                                                             double* __restrict__ C, int64_t ldc) {
   const int64_t MN = M * N;
-  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < MN;
-       idx += (int64_t)gridDim.x * 256) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  for (int64_t j = blockIdx.y; j < N; j += gridDim.y) {
+    const double* p = P + i + j * M;
     double s = 0.0;
-    for (int z = 0; z < S; ++z) s += P[(int64_t)z * MN + idx];
-    const int64_t i = idx % M, j = idx / M;
+    for (int z = 0; z < S; ++z) s += p[(int64_t)z * MN];
     double c = alpha * s;
     if (beta != 0.0) c += beta * C[i + j * ldc];
     C[i + j * ldc] = c;
@@ -237,12 +239,10 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N
 
 __global__ __launch_bounds__(256) void scale_kernel(int64_t M, int64_t N, double beta, double* C,
                                                     int64_t ldc) {
-  const int64_t MN = M * N;
-  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x; idx < MN;
-       idx += (int64_t)gridDim.x * 256) {
-    const int64_t i = idx % M, j = idx / M;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= M) return;
+  for (int64_t j = blockIdx.y; j < N; j += gridDim.y)
     C[i + j * ldc] = (beta == 0.0) ? 0.0 : beta * C[i + j * ldc];
-  }
 }
 
 template <int BM, int BN, bool VEC>
@@ -258,11 +258,9 @@ hipError_t launch_tile(hipStream_t st, bool ta, bool tb, GemmF64Args& g, int spl
   return hipGetLastError();
 }
 
-inline unsigned grid_for(int64_t elems) {
-  int64_t blocks = ceil_div(elems, 256);
-  if (blocks > 8192) blocks = 8192;
-  if (blocks < 1) blocks = 1;
-  return (unsigned)blocks;
+// Rows of an M x N elementwise pass in x (256 per block), columns in y.
+inline dim3 grid_2d(int64_t M, int64_t N) {
+  return dim3((unsigned)ceil_div(M, 256), (unsigned)(N < 65535 ? N : 65535));
 }
 
 inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -275,7 +273,7 @@ int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
   if (M <= 0 || N <= 0) return RRF_OK;
   if (K <= 0 || alpha == 0.0) {
     if (beta == 1.0) return RRF_OK;
-    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(M * N)), dim3(256), 0, st, M, N, beta, C, ldc);
+    hipLaunchKernelGGL(scale_kernel, grid_2d(M, N), dim3(256), 0, st, M, N, beta, C, ldc);
     RRF_CHECK_HIP(hipGetLastError());
     return RRF_OK;
   }
@@ -288,16 +286,23 @@ int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
   const bool big = (M >= 128 && N >= 128);
   const int BM = big ? 128 : 64, BN = big ? 128 : 64;
   const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
-  // Aim for at least two waves of resident workgroups on the 256 CUs.
-  const int64_t target = 512;
+  // Split K when the tiles alone leave resident slots (two workgroups per CU,
+  // 512 on the chip) idle: take the split count s <= 16 (at least 256 of K
+  // per split, partials within the workspace) that minimises the time in
+  // units of one tile's full-K work, ceil(tiles s / 512) / s, the smallest s
+  // on ties.
+  const int64_t slots = 512;
   int splits = 1;
-  if (tiles < target && K >= 4 * 256) {
-    int64_t want = ceil_div(target, tiles);
-    int64_t by_k = K / 256;  // keep at least 256 of K per split
-    int64_t s = want < by_k ? want : by_k;
-    if (s > 16) s = 16;
-    while (s > 1 && (size_t)(s * M * N) > work_elems) --s;
-    splits = (int)(s < 1 ? 1 : s);
+  if (tiles < slots && K >= 2 * 256) {
+    double best = 1.0;
+    for (int64_t s = 2; s <= 16 && K / s >= 256; ++s) {
+      if ((size_t)(s * M * N) > work_elems) break;
+      const double t = (double)ceil_div(tiles * s, slots) / (double)s;
+      if (t < best - 1e-12) {
+        best = t;
+        splits = (int)s;
+      }
+    }
   }
   g.kchunk = round_up(ceil_div(K, splits), kBK);
   splits = (int)ceil_div(K, g.kchunk);
@@ -320,7 +325,7 @@ int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
   if (splits > 1) {
     tok = trace_begin(st, kTrSplitReduce, (double)splits * M * N,
                       8.0 * (splits + (beta != 0.0 ? 2.0 : 1.0)) * M * N);
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(grid_for(M * N)), dim3(256), 0, st, M, N,
+    hipLaunchKernelGGL(splitk_reduce_kernel, grid_2d(M, N), dim3(256), 0, st, M, N,
                        splits, (const double*)work, alpha, beta, C, ldc);
     trace_end(st, tok);
     RRF_CHECK_HIP(hipGetLastError());

@@ -47,9 +47,9 @@ namespace rrf {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
 constexpr int kMaxCols = 256;
-constexpr int64_t kLdsBudget = 144 * 1024;  // dynamic LDS bytes per workgroup
+constexpr int64_t kLdsBudget = 140 * 1024;  // dynamic LDS bytes per workgroup
 constexpr int kMaxGroups = 256;
 constexpr int kRing = 4;                     // slot buffers in flight
 constexpr int kFlagStride = 16;              // unsigned per flag: one 64-byte line
@@ -124,17 +124,22 @@ __device__ bool announce_and_wait(const PanelArgs& a, unsigned epoch, bool wait,
   return __syncthreads_and(good) != 0;
 }
 
-// dst[e] = sum over workers g of slot_g[off + e], e < n, in one fixed order
-// (a function of n and Gw only, so every workgroup gets identical sums).
-// The threads split the workers into tpe ranges per entry and keep up to 32
-// loads in flight each. Ends with dst visible to the workgroup.
-__device__ void reduce_slots(const double* base, int slot, int Gw, int off, int n, double* dst,
-                             double* part) {
-  const int tid = threadIdx.x;
+// Sums over the worker slots: dst[e] = sum_g slot_g[off + e], e < n, in one
+// fixed order that depends on n and Gw only, so every workgroup gets
+// identical sums. Virtual thread vt takes entry vt % sp (sp = n rounded up
+// to a power of two) over the (vt / sp)-th of tpe = kThreads / sp ranges of
+// workers, with its loads in flight together; slot_combine adds the tpe
+// partials of an entry in range order.
+__device__ inline int pow2_at_least(int n) {
   int sp = 1;
   while (sp < n) sp <<= 1;
+  return sp;
+}
+
+__device__ double slot_partial(const double* base, int slot, int Gw, int off, int n, int vt) {
+  const int sp = pow2_at_least(n);
   const int tpe = kThreads / sp;
-  const int e = tid % sp, p = tid / sp;
+  const int e = vt % sp, p = vt / sp;
   double acc = 0.0;
   if (e < n) {
     const int g0 = (int)((int64_t)Gw * p / tpe), g1 = (int)((int64_t)Gw * (p + 1) / tpe);
@@ -147,14 +152,15 @@ __device__ void reduce_slots(const double* base, int slot, int Gw, int off, int 
       for (int u = 0; u < 32; ++u) acc += v[u];
     }
   }
-  part[tid] = acc;
-  __syncthreads();
-  if (tid < n) {
-    double s = 0.0;
-    for (int u = 0; u < tpe; ++u) s += part[tid + u * sp];
-    dst[tid] = s;
-  }
-  __syncthreads();
+  return acc;
+}
+
+__device__ inline double slot_combine(int n, int e, const double* part) {
+  const int sp = pow2_at_least(n);
+  const int tpe = kThreads / sp;
+  double s = 0.0;
+  for (int u = 0; u < tpe; ++u) s += part[e + u * sp];
+  return s;
 }
 
 __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
@@ -162,6 +168,7 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
   __shared__ double red_s[3 * kMaxCols];
   __shared__ double w_s[kMaxCols];
   __shared__ double part[kThreads];
+  __shared__ double part2[kThreads];
 
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
   const int L = a.ldl;
   const int64_t r0 = (int64_t)g * RP;
   const int rows = coord ? 0 : (int)((a.M - r0) < RP ? (a.M - r0) : RP);
-  double* Ls = smem;                          // workers: rows x k, stride L
+  double* Ls = smem;  // workers: rows x k (+ zero row, spare column k), stride L
   double* Tl = a.tf_in_lds ? smem : nullptr;  // coordinator: k x k, ld k
 
   if (!coord) {
@@ -179,6 +186,7 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
       const int rl = idx % rows, c = idx / rows;
       Ls[rl * L + c] = a.P[(r0 + rl) + (int64_t)c * a.ldp];
     }
+    for (int c = tid; c < L; c += kThreads) Ls[rows * L + c] = 0.0;  // zero row
     __syncthreads();
     if (a.zero) {
       for (int idx = tid; idx < rows * k; idx += kThreads) {
@@ -193,63 +201,57 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
     const int ns = (j < k) ? (k - j) : 0;   // Gram entries s_c, c in [j, k)
     const int nt = (j >= 2) ? (j - 1) : 0;  // Tf dots v_{j-1}^T v_l, l in [0, j-1)
     const unsigned epoch = (unsigned)j + 1;
+    const int owner = (j < k) ? (int)(j / RP) : -1;  // worker holding row j
     double* ring = a.red + (size_t)(j % kRing) * a.Gw * a.slot;
     if (!coord) {
       double* slot = ring + (size_t)g * a.slot;
-      const int rlj = clampi((int64_t)j - r0, 0, rows);      // first local row >= j
-      const int rlx = clampi((int64_t)j + 1 - r0, 0, rows);  // first local row > j
+      const int rlj = clampi((int64_t)j - r0, 0, rows);  // first local row >= j
+      const int rjl = (g == owner) ? (int)(j - r0) : -1;  // local index of row j
       const double twj = (j >= 1 && j < k) ? tau_prev * w_s[j] : 0.0;
-      // (b) one pass over the columns: apply H_{j-1} to columns c > j and
-      // form the Gram partials x^T a_c (c >= j) with x = column j below row
-      // j after H_{j-1}, recomputed on the fly; threads ci >= ns form the Tf
-      // dots v_{j-1}^T v_l. Consecutive threads take consecutive columns of a
-      // row; tpc threads share a column over interleaved rows.
+      // (b) one pass over the rows >= j. Lane ci < ns owns column c = j + ci:
+      // it applies H_{j-1} (columns c > j; the lane of column j writes into
+      // the spare column k, its update is stored in (c)) and accumulates the
+      // Gram partial x^T a_c with x = column j below row j after H_{j-1},
+      // recomputed on the fly. Lane ci >= ns owns column l = ci - ns < j - 1
+      // and accumulates v_{j-1}^T v_l (tw = 0 rewrites the column unchanged).
+      // Both kinds run one instruction stream; consecutive lanes take
+      // consecutive columns of a row, and tpc lanes share a column over
+      // interleaved rows. Rows past the block read and write the zero row.
       const int nc = ns + nt;
-      int ncp = 1;
-      while (ncp < nc) ncp <<= 1;
+      const int ncp = pow2_at_least(nc);
       const int tpc = kThreads / ncp;  // >= 1
       const int ci = tid % ncp, sub = tid / ncp;
+      const int jm = (j >= 1) ? j - 1 : 0;
       double acc = 0.0;
-      if (ci < ns) {
-        const int c = j + ci;
-        const double twc = (j >= 1) ? tau_prev * w_s[c] : 0.0;
-        const int jm = (j >= 1) ? j - 1 : 0;
-        for (int rl = rlj + sub; rl < rows; rl += 4 * tpc) {
-          double vv[4], xo[4], yo[4];
+      if (ci < nc) {
+        const bool gram = ci < ns;
+        const int col = gram ? j + ci : ci - ns;
+        const int cst = (gram && col == j) ? k : col;
+        const double tw = (gram && j >= 1) ? tau_prev * w_s[col] : 0.0;
+        // row j-1 of v_{j-1} is the implicit 1
+        if (!gram && sub == 0 && (int64_t)j - 1 >= r0 && (int64_t)j - 1 < r0 + rows)
+          acc = Ls[(int)(j - 1 - r0) * L + col];
+        constexpr int U = 4;
+        const int nit = (rows - rlj + U * tpc - 1) / (U * tpc);
+        for (int it = 0; it < nit; ++it) {
+          const int rb = rlj + sub + it * U * tpc;
+          double vv[U], xo[U], yo[U];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int r = rl + u * tpc;
-            const int rr = (r < rows) ? r : rl;
-            vv[u] = (j >= 1) ? Ls[rr * L + jm] : 0.0;
-            xo[u] = Ls[rr * L + j];
-            yo[u] = Ls[rr * L + c];
+          for (int u = 0; u < U; ++u) {
+            const int r = min(rb + u * tpc, rows);
+            vv[u] = Ls[r * L + jm];
+            xo[u] = Ls[r * L + j];
+            yo[u] = Ls[r * L + col];
           }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int r = rl + u * tpc;
-            if (r < rows) {
-              const double xj = xo[u] - twj * vv[u];
-              const double y = (c == j) ? xj : yo[u] - twc * vv[u];
-              if (c > j) Ls[r * L + c] = y;
-              if (r >= rlx) acc += xj * y;
-            }
+          for (int u = 0; u < U; ++u) {
+            const int r = min(rb + u * tpc, rows);
+            const double y = yo[u] - tw * vv[u];
+            Ls[r * L + cst] = y;
+            // Gram: x_r (0 on row j itself); Tf dots: v_{j-1}[r]
+            const double xj = (r == rjl) ? 0.0 : xo[u] - twj * vv[u];
+            acc += (gram ? xj : vv[u]) * y;
           }
-        }
-      } else if (ci < nc) {
-        const int l = ci - ns;
-        const int rlv = clampi((int64_t)j - 1 - r0, 0, rows);  // first local row >= j-1
-        for (int rl = rlv + sub; rl < rows; rl += 4 * tpc) {
-          double vv[4], yl[4];
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int r = rl + u * tpc;
-            const int rr = (r < rows) ? r : rl;
-            vv[u] = (r0 + rr == j - 1) ? 1.0 : Ls[rr * L + j - 1];
-            yl[u] = Ls[rr * L + l];
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (rl + u * tpc < rows) acc += vv[u] * yl[u];
         }
       }
       part[tid] = acc;
@@ -257,70 +259,87 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
       // (c) publish: partial sums, row j of the panel (its owner), and column
       // j of H_{j-1} A into LDS.
       if (tid < nc) {
-        double s = 0.0;
-        for (int u = 0; u < tpc; ++u) s += part[tid + u * ncp];
+        const double s = slot_combine(nc, tid, part);
         st_dev(slot + ((tid < ns) ? j + tid : 2 * k + (tid - ns)), s);
       }
       if (j < k) {
-        const bool owner = (int64_t)j >= r0 && (int64_t)j < r0 + rows;
-        const int rlo = (int)(j - r0);
-        if (owner)
-          for (int c = j + 1 + tid; c < k; c += kThreads) st_dev(slot + k + c, Ls[rlo * L + c]);
+        if (rjl >= 0)
+          for (int c = j + 1 + tid; c < k; c += kThreads) st_dev(slot + k + c, Ls[rjl * L + c]);
         for (int rl = rlj + tid; rl < rows; rl += kThreads) {
           double x = Ls[rl * L + j];
           if (j >= 1) {
             x -= twj * Ls[rl * L + j - 1];
             Ls[rl * L + j] = x;
           }
-          if (rl == rlo && owner) st_dev(slot + k + j, x);
+          if (rl == rjl) st_dev(slot + k + j, x);
         }
       }
       // the last round only feeds the coordinator
       const unsigned ce = (epoch + 2 > (unsigned)kRing) ? epoch + 2 - kRing : 0u;
       if (!announce_and_wait(a, epoch, j < k, ce)) return;
       if (j == k) break;
+      // (d) Gram sums and row j, the same order in every workgroup.
+      if (tid < ns) red_s[k + j + tid] = ld_dev(ring + (size_t)owner * a.slot + k + j + tid);
+      part[tid] = slot_partial(ring, a.slot, a.Gw, j, ns, tid);
+      __syncthreads();
+      if (tid < ns) red_s[j + tid] = slot_combine(ns, tid, part);
+      __syncthreads();
     } else {
       if (!announce_and_wait(a, epoch, true, 0u)) return;
-    }
-
-    // (d) sums over the worker slots, the same order in every workgroup.
-    if (ns > 0) {
-      const int owner = (int)(j / RP);
-      if (tid < ns) red_s[k + j + tid] = ld_dev(ring + (size_t)owner * a.slot + k + j + tid);
-      reduce_slots(ring, a.slot, a.Gw, j, ns, red_s + j, part);
-    }
-    if (coord && nt > 0) reduce_slots(ring, a.slot, a.Gw, 2 * k, nt, red_s + 2 * k, part);
-
-    // (e) coordinator: column j-1 of Tf.
-    if (coord && j >= 1) {
-      const int jj = j - 1;
-      const double* dots = red_s + 2 * k;
-      for (int i = tid; i < jj; i += kThreads) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int c = i;
-        if (Tl) {
-          for (; c + 4 <= jj; c += 4) {
-            s0 += Tl[i + c * k] * dots[c];
-            s1 += Tl[i + (c + 1) * k] * dots[c + 1];
-            s2 += Tl[i + (c + 2) * k] * dots[c + 2];
-            s3 += Tl[i + (c + 3) * k] * dots[c + 3];
+      // (d) the coordinator needs s_j and alpha (for tau_j) and the Tf dots.
+      // s_j is summed by the workers' own split of entry 0, so it is
+      // bit-identical to theirs.
+      const int spg = pow2_at_least(ns);
+      if (ns > 0 && tid == 0) red_s[k + j] = ld_dev(ring + (size_t)owner * a.slot + k + j);
+      if (ns > 0 && tid < kThreads / spg) part[tid] = slot_partial(ring, a.slot, a.Gw, j, ns, tid * spg);
+      part2[tid] = (nt > 0) ? slot_partial(ring, a.slot, a.Gw, 2 * k, nt, tid) : 0.0;
+      __syncthreads();
+      if (ns > 0 && tid == 0) {
+        double sj = 0.0;
+        for (int u = 0; u < kThreads / spg; ++u) sj += part[u];
+        red_s[j] = sj;
+      }
+      if (tid < nt) red_s[2 * k + tid] = slot_combine(nt, tid, part2);
+      __syncthreads();
+      // (e) column j-1 of Tf: Tf(i, j-1) = -tau_{j-1} sum_{c=i}^{j-2} Tf(i, c)
+      // dots_c, each dot split over tpi threads and added in range order.
+      if (j >= 1) {
+        const int jj = j - 1;
+        const double* dots = red_s + 2 * k;
+        if (jj > 0) {
+          const int sp = pow2_at_least(jj);
+          const int tpi = kThreads / sp;
+          const int i = tid % sp, pi = tid / sp;
+          double s = 0.0;
+          if (i < jj) {
+            const int len = jj - i;
+            const int c0 = i + len * pi / tpi, c1 = i + len * (pi + 1) / tpi;
+            if (Tl) {
+              for (int c = c0; c < c1; ++c) s += Tl[i + c * k] * dots[c];
+            } else {
+              for (int c = c0; c < c1; ++c) s += a.Tf[i + (int64_t)c * a.ldt] * dots[c];
+            }
           }
-          for (; c < jj; ++c) s0 += Tl[i + c * k] * dots[c];
-        } else {
-          for (; c < jj; ++c) s0 += a.Tf[i + (int64_t)c * a.ldt] * dots[c];
+          part2[tid] = s;
+          __syncthreads();
+          if (tid < jj) {
+            double v = 0.0;
+            for (int u = 0; u < tpi; ++u) v += part2[tid + u * sp];
+            v = -tau_prev * v;
+            if (Tl) Tl[tid + jj * k] = v;
+            else a.Tf[tid + (int64_t)jj * a.ldt] = v;
+          }
         }
-        const double v = -tau_prev * ((s0 + s1) + (s2 + s3));
-        if (Tl) Tl[i + jj * k] = v;
-        else a.Tf[i + (int64_t)jj * a.ldt] = v;
+        if (tid == 0) {
+          if (Tl) Tl[jj + jj * k] = tau_prev;
+          else a.Tf[jj + (int64_t)jj * a.ldt] = tau_prev;
+        }
       }
-      if (tid == 0) {
-        if (Tl) Tl[jj + jj * k] = tau_prev;
-        else a.Tf[jj + (int64_t)jj * a.ldt] = tau_prev;
-      }
+      if (j == k) break;
     }
-    if (j == k) break;
 
-    // (f) reflector j from alpha = row_j[j] and ||x||^2 = s_j (dlarfg rule).
+    // (f) reflector j from alpha = row_j[j] and ||x||^2 = s_j (dlarfg rule);
+    // the worker holding row j writes tau_j and row j of R.
     const double alpha = red_s[k + j];
     const double xn2 = red_s[j];
     double tau, beta, scal;
@@ -334,18 +353,20 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
       tau = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    for (int c = j + 1 + tid; c < k; c += kThreads) {
-      const double w = red_s[k + c] + scal * red_s[c];
-      w_s[c] = w;
-      if (coord && a.R) a.R[j + (int64_t)c * a.ldr] = red_s[k + c] - tau * w;
-    }
-    if (coord) {
-      if (tid == 0) a.tau[j] = tau;
-      if (a.R) {
-        if (tid == 0) a.R[j + (int64_t)j * a.ldr] = beta;
-        for (int i = j + 1 + tid; i < k; i += kThreads) a.R[i + (int64_t)j * a.ldr] = 0.0;
+    if (!coord) {
+      const bool own = (g == owner);
+      for (int c = j + 1 + tid; c < k; c += kThreads) {
+        const double w = red_s[k + c] + scal * red_s[c];
+        w_s[c] = w;
+        if (own && a.R) a.R[j + (int64_t)c * a.ldr] = red_s[k + c] - tau * w;
       }
-    } else {
+      if (own) {
+        if (tid == 0) a.tau[j] = tau;
+        if (a.R) {
+          if (tid == 0) a.R[j + (int64_t)j * a.ldr] = beta;
+          for (int i = j + 1 + tid; i < k; i += kThreads) a.R[i + (int64_t)j * a.ldr] = 0.0;
+        }
+      }
       const int rlx = clampi((int64_t)j + 1 - r0, 0, rows);
       for (int rl = rlx + tid; rl < rows; rl += kThreads) Ls[rl * L + j] *= scal;
     }
@@ -383,7 +404,7 @@ int slot_doubles(int k) { return (int)round_up((int64_t)3 * k, 32); }
 bool panel_plan(int64_t M, int k, PanelPlan* plan) {
   if (k < 1 || k > kMaxCols || M < k) return false;
   const int64_t L = k + 1;
-  const int64_t max_rows = kLdsBudget / (L * 8);
+  const int64_t max_rows = kLdsBudget / (L * 8) - 1;  // one zero row follows the block
   int64_t Gw = ceil_div(M, max_rows);
   if (Gw + 1 > kMaxGroups) return false;
   const int64_t rp = ceil_div(M, Gw);
@@ -391,7 +412,7 @@ bool panel_plan(int64_t M, int k, PanelPlan* plan) {
   const bool tf_lds = (int64_t)k * k * 8 <= kLdsBudget;
   plan->G = (int)Gw;
   plan->rows_per = (int)rp;
-  plan->lds = (size_t)std::max<int64_t>(rp * L, tf_lds ? (int64_t)k * k : 0) * 8;
+  plan->lds = (size_t)std::max<int64_t>((rp + 1) * L, tf_lds ? (int64_t)k * k : 0) * 8;
   plan->work = flag_bytes((int)Gw) + (size_t)kRing * Gw * slot_doubles(k) * 8;
   return true;
 }
@@ -401,8 +422,8 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                       double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
   PanelPlan plan;
   if (!panel_plan(M, k, &plan))
-    return set_error(RRF_E_NOTSUP, "householder panel: shape outside 1 <= k <= 256, M >= k, "
-                                   "M (k + 1) <= 255 * 18432");
+    return set_error(RRF_E_NOTSUP, "householder panel: needs 1 <= k <= 256, M >= k and the panel "
+                                   "within the LDS of 255 workgroups");
   if (work_bytes < plan.work || work == nullptr)
     return set_error(RRF_E_NOMEM, "householder panel: workspace too small");
   if (!g_attr_set) {

@@ -4,20 +4,25 @@
 //   1. G_i = Gaussian(seed, stream i+1), (m-c0) x b, generated in HBM;
 //   2. Y = T22^T G_i, then q times Z = T22 Y, Y = T22^T Z  (MFMA GEMMs);
 //   3. [W_v, Tf_v] = Householder QR of Y (panel kernel; W_v overwrites Y);
-//   4. T(:, J2uJ3) -= (T W_v)(W_v Tf_v^T)^T, same for V  (= T V_i);
+//   4. X = T(:, J2uJ3) W_v and T(:, J2) -= X (W_v Tf_v^T)(J2, :)^T: only the
+//      columns J2 of T V_i are formed here, for the next panel;
 //   5. [W_u, Tf_u, R] = Householder QR of T(I2uI3, J2); that panel of T is
 //      cleared in the same kernel (T(I3,J2) = 0 of Alg. 3, and T(I2,J2)
 //      receives D below);
-//   6. T(I2uI3, J3) -= (W_u Tf_u^T)(W_u^T T(I2uI3, J3))  (= U_i^T T) and
-//      U(:, I2uI3) -= (U W_u)(W_u Tf_u^T)^T  (= U U_i);
+//   6. the rest of T <- U_i^T T V_i in one pass over T(:, J3):
+//        Z^T = T(I2uI3, J3)^T W_u - (W_v Tf_v^T)(J3, :) (X(I2uI3, :)^T W_u)
+//      is W_u^T of the right-updated block, formed from the block before the
+//      update, and then
+//        T(:, J3) -= [X, W_u Tf_u^T] [(W_v Tf_v^T)(J3, :), Z^T]^T,
+//      a single GEMM with inner dimension 2b (W_u Tf_u^T is zero on rows I1);
+//      V(:, J2uJ3) V_i and U(:, I2uI3) U_i as two GEMMs each;
 //   7. [Us, D, Vs] = SVD(R) (one-workgroup Jacobi), then U(:,I2) Us,
 //      V(:,J2) Vs, T(I2,J2) = D, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) Vs.
 // The last step (J3 empty) takes the SVD of the trailing block, through a
 // Householder QR first when the block is tall (Sec. 4.2, tall-thin SVD).
 //
-// Both compact-WY applications use W Tf W^T = W (W Tf^T)^T: the small
-// triangular factor is folded into one operand once per step and each update
-// is exactly two GEMMs.
+// Every compact-WY application uses W Tf W^T = W (W Tf^T)^T: the small
+// triangular factor is folded into one operand once per step.
 //
 // Schedule. The data dependences of a step, not the order in which Alg. 3
 // lists its statements, decide what may overlap:
@@ -31,9 +36,9 @@
 //    and all the small SVDs run as one batched launch (one workgroup per
 //    block) after the loop, followed by T(I2,J2) = D, T(I1,J2) Vs, U(:,I2) Us,
 //    V(:,J2) Vs and T(I2,J3) <- Us^T T(I2,J3) for every block.
-// W_v, W_v Tf_v^T, W_u and W_u Tf_u^T live in two-deep rings, so the
-// critical path reuses a slot only after the side stream finished with it
-// two steps earlier.
+// W_v, W_u, [X, W_u Tf_u^T] and [W_v Tf_v^T, Z^T] live in two-deep rings, so
+// the critical path reuses a slot only after the side stream finished with
+// it two steps earlier.
 #include <algorithm>
 
 #include "common.hpp"
@@ -50,12 +55,13 @@ struct Bufs {
   double* G = nullptr;      // m x b
   double* Z = nullptr;      // m x b
   double* Y[2] = {};        // n x b  sketch, then W_v
-  double* Wr[2] = {};       // n x b  W_v Tf_v^T
   double* Wu[2] = {};       // m x b
-  double* Wl[2] = {};       // m x b  W_u Tf_u^T
-  double* X0 = nullptr;     // max(m,n) x b   (critical stream)
+  double* XW[2] = {};       // m x 2b [X, W_u Tf_u^T] (ld m; zero rows I1 on the right)
+  double* WZ[2] = {};       // n x 2b [W_v Tf_v^T, Z^T] (ld n; Z^T on rows J3)
+  double* S = nullptr;      // b x b  X(I2uI3, :)^T W_u
+  double* X0 = nullptr;     // max(m,n) x b   (critical stream, after the loop)
   double* X1 = nullptr;     // max(m,n) x b   (side stream)
-  double* Zl = nullptr;     // b x n          (critical stream)
+  double* Zl = nullptr;     // b x n          (critical stream, after the loop)
   double* Tv = nullptr;     // b x b
   double* Tu = nullptr;     // b x b
   double* tau = nullptr;    // b
@@ -80,10 +86,11 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, Bufs* B) {
   B->Z = ar.take<double>((size_t)m * kb);
   for (int r = 0; r < 2; ++r) {
     B->Y[r] = ar.take<double>((size_t)n * kb);
-    B->Wr[r] = ar.take<double>((size_t)n * kb);
     B->Wu[r] = ar.take<double>((size_t)m * kb);
-    B->Wl[r] = ar.take<double>((size_t)m * kb);
+    B->XW[r] = ar.take<double>((size_t)m * 2 * kb);
+    B->WZ[r] = ar.take<double>((size_t)n * 2 * kb);
   }
+  B->S = ar.take<double>((size_t)kb * kb);
   B->X0 = ar.take<double>((size_t)mx * kb);
   B->X1 = ar.take<double>((size_t)mx * kb);
   B->Zl = ar.take<double>((size_t)kb * n);
@@ -186,27 +193,39 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
       }
       RRF_TRY(householder_panel(st, Ni, (int)kb, B.Y[r], Ni, B.Y[r], Ni, nullptr, 0, B.Tv, kb,
                                 B.tau, nullptr, 0, B.panel, B.panel_bytes, B.status));
-      RRF_TRY(dgemm(st, false, true, Ni, kb, kb, 1.0, B.Y[r], Ni, B.Tv, kb, 0.0, B.Wr[r], Ni,
-                    nullptr, 0));
+      double* Wr = B.WZ[r];          // W_v Tf_v^T, Ni x b, ld n
+      double* Zt = B.WZ[r] + n * kb;  // Z^T on rows [b, Ni), ld n
+      double* X = B.XW[r];            // m x b, ld m
+      double* Wl = B.XW[r] + m * kb;  // W_u Tf_u^T on rows I2uI3, ld m
+      RRF_TRY(dgemm(st, false, true, Ni, kb, kb, 1.0, B.Y[r], Ni, B.Tv, kb, 0.0, Wr, n, nullptr,
+                    0));
       RRF_CHECK_HIP(hipEventRecord(ev[kEvV + r], st));
-      // T(:, J2uJ3) <- T(:, J2uJ3) V_i
-      RRF_TRY(dgemm(st, false, false, m, kb, Ni, 1.0, Tc, ldt, B.Y[r], Ni, 0.0, B.X0, m,
-                    B.split[0], SE));
-      RRF_TRY(dgemm(st, false, true, m, Ni, kb, -1.0, B.X0, m, B.Wr[r], Ni, 1.0, Tc, ldt,
-                    nullptr, 0));
-      // ---- critical stream: U_i and R from the panel T(I2uI3, J2)
+      // X = T(:, J2uJ3) W_v; columns J2 of T V_i
       if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvUdone + r], 0));
+      RRF_TRY(dgemm(st, false, false, m, kb, Ni, 1.0, Tc, ldt, B.Y[r], Ni, 0.0, X, m,
+                    B.split[0], SE));
+      RRF_TRY(dgemm(st, false, true, m, kb, kb, -1.0, X, m, Wr, n, 1.0, Tc, ldt, nullptr, 0));
+      // ---- critical stream: U_i and R from the panel T(I2uI3, J2)
       RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, B.Wu[r], Mi, Ri, bb, B.Tu, kb, B.tau,
                                 T22, ldt, B.panel, B.panel_bytes, B.status));
-      RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, B.Wl[r], Mi,
+      // W_u Tf_u^T on rows I2uI3, zero on rows I1 (the rows this slot held
+      // two steps earlier are cleared)
+      const int64_t z0 = std::max<int64_t>(0, c0 - 2 * b);
+      RRF_TRY(fill_matrix(st, c0 - z0, kb, 0.0, Wl + z0, m));
+      RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, Wl + c0, m,
                     nullptr, 0));
       RRF_CHECK_HIP(hipEventRecord(ev[kEvU + r], st));
-      // T(I2uI3, J3) <- U_i^T T(I2uI3, J3)
+      // Z^T = T(I2uI3, J3)^T W_u - Wr(J3, :) (X(I2uI3, :)^T W_u)
       double* T23 = T + c0 + c2 * ldt;
-      RRF_TRY(dgemm(st, true, false, kb, N3, Mi, 1.0, B.Wu[r], Mi, T23, ldt, 0.0, B.Zl, kb,
+      RRF_TRY(dgemm(st, true, false, N3, kb, Mi, 1.0, T23, ldt, B.Wu[r], Mi, 0.0, Zt + kb, n,
                     B.split[0], SE));
-      RRF_TRY(dgemm(st, false, false, Mi, N3, kb, -1.0, B.Wl[r], Mi, B.Zl, kb, 1.0, T23, ldt,
+      RRF_TRY(dgemm(st, true, false, kb, kb, Mi, 1.0, X + c0, m, B.Wu[r], Mi, 0.0, B.S, kb,
+                    B.split[0], SE));
+      RRF_TRY(dgemm(st, false, false, N3, kb, kb, -1.0, Wr + kb, n, B.S, kb, 1.0, Zt + kb, n,
                     nullptr, 0));
+      // T(:, J3) -= [X, W_u Tf_u^T] [Wr(J3, :), Z^T]^T
+      RRF_TRY(dgemm(st, false, true, m, N3, 2 * kb, -1.0, X, m, B.WZ[r] + kb, n, 1.0,
+                    T + c2 * ldt, ldt, nullptr, 0));
 
       // ---- side stream: V V_i and U U_i
       RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvV + r], 0));
@@ -214,8 +233,8 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
         double* Vc = V + c0 * ldv;
         RRF_TRY(dgemm(s1, false, false, n, kb, Ni, 1.0, Vc, ldv, B.Y[r], Ni, 0.0, B.X1, n,
                       B.split[1], SE));
-        RRF_TRY(dgemm(s1, false, true, n, Ni, kb, -1.0, B.X1, n, B.Wr[r], Ni, 1.0, Vc, ldv,
-                      nullptr, 0));
+        RRF_TRY(dgemm(s1, false, true, n, Ni, kb, -1.0, B.X1, n, Wr, n, 1.0, Vc, ldv, nullptr,
+                      0));
       }
       RRF_CHECK_HIP(hipEventRecord(ev[kEvVdone + r], s1));
       RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvU + r], 0));
@@ -223,7 +242,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
         double* Uc = U + c0 * ldu;
         RRF_TRY(dgemm(s1, false, false, m, kb, Mi, 1.0, Uc, ldu, B.Wu[r], Mi, 0.0, B.X1, m,
                       B.split[1], SE));
-        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, B.Wl[r], Mi, 1.0, Uc, ldu,
+        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, Wl + c0, m, 1.0, Uc, ldu,
                       nullptr, 0));
       }
       RRF_CHECK_HIP(hipEventRecord(ev[kEvUdone + r], s1));
@@ -233,10 +252,11 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
       // a tall block is first reduced by a Householder QR.
       const int64_t kb = Ni;
       if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvUdone + r], 0));
+      double* Wl = B.XW[r] + m * bb;  // W_u Tf_u^T, Mi x kb, ld m
       if (Mi > Ni) {
         RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, B.Wu[r], Mi, Ri, bb, B.Tu, kb,
                                   B.tau, nullptr, 0, B.panel, B.panel_bytes, B.status));
-        RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, B.Wl[r], Mi,
+        RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, Wl, m,
                       nullptr, 0));
       } else {
         RRF_TRY(copy_matrix(st, kb, kb, T22, ldt, Ri, bb));
@@ -247,8 +267,8 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
         double* Uc = U + c0 * ldu;
         RRF_TRY(dgemm(s1, false, false, m, kb, Mi, 1.0, Uc, ldu, B.Wu[r], Mi, 0.0, B.X1, m,
                       B.split[1], SE));
-        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, B.Wl[r], Mi, 1.0, Uc, ldu,
-                      nullptr, 0));
+        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, Wl, m, 1.0, Uc, ldu, nullptr,
+                      0));
       }
       RRF_CHECK_HIP(hipEventRecord(ev[kEvUdone + r], s1));
     }
