@@ -167,8 +167,13 @@ def test_block_svd(gpu, k):
     nB = np.linalg.norm(B, 2)
     np.testing.assert_allclose(d, dr, atol=8 * k * U64 * nB)
     assert np.all(np.diff(d) <= 0)
-    assert np.linalg.norm(Us.T @ Us - np.eye(k), 2) < 1e-13
-    assert np.linalg.norm(Vs.T @ Vs - np.eye(k), 2) < 1e-13
+    # Us and Vs come out of ~(sweeps * k) plane rotations per column, each
+    # orthogonal to within a few eps: their departure from orthogonality is
+    # bounded by a small multiple of k eps (the scale LAPACK's own SVD tests
+    # measure it in), with a 1e-13 floor for the small blocks.
+    orth = max(1e-13, 4 * k * np.finfo(float).eps)
+    assert np.linalg.norm(Us.T @ Us - np.eye(k), 2) < orth
+    assert np.linalg.norm(Vs.T @ Vs - np.eye(k), 2) < orth
     assert np.linalg.norm(Us @ np.diag(d) @ Vs.T - B, 2) < 8 * k * U64 * nB
     for j in range(k):
         assert Vs[np.argmax(np.abs(Vs[:, j])), j] > 0
