@@ -1,0 +1,96 @@
+"""Reduced-precision sketch of randUTV's mixed mode, on the CPU.
+
+TEST INFRASTRUCTURE: only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import anything under ``oracle/``.
+
+The paper computes everything in FP64. The sketch of Alg. 3,
+Y = (T22^T T22)^q T22^T G, only has to capture the dominant right singular
+subspace of T22, so the mixed mode forms it from bfloat16 copies of T22 and
+G with FP32 accumulation; the QR of Y and every update of T, U and V stay in
+FP64. The definitions the GPU path follows:
+
+* ``bf16_round(x)``: round-to-nearest, ties-to-even, of a binary64 value to
+  bfloat16 (8 significant bits, the exponent range of binary32), directly from
+  binary64 (no intermediate binary32 rounding). Below 2^-126 the quantum is
+  fixed at 2^-133 (gradual underflow); beyond the largest finite bfloat16
+  value the result is +-inf.
+* ``pow2_scale(x)``: the power of two 2^-e with max|x| 2^-e in [0.5, 1),
+  e from frexp of max|x| (1 when x is all zero). Multiplying by it is exact.
+* ``sketch_bf16(T22, G, q)``: T22 is scaled by its pow2_scale and rounded
+  to bfloat16, G (standard normal, in range) is rounded as it is;
+  Y = T^T G; then q times: round Y column by column
+  after scaling each column by its own pow2_scale, Z = T Y, the same for Z,
+  Y = T^T Z. Positive column scalings commute with the products and leave
+  the column space (hence the Householder Q of Y) unchanged; they only keep
+  the FP32 range. This reference forms the products of the rounded values in
+  FP64; the GPU accumulates them in FP32, so the two agree to within the FP32
+  accumulation bound of ``fp32_gemm_bound`` per product.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+_SIG = 8                    # significant bits of bfloat16
+_EMIN = -126                # smallest normal exponent (value 2^-126)
+_MAX = (2.0 - 2.0 ** -7) * 2.0 ** 127  # largest finite bfloat16
+U32 = 2.0 ** -24            # unit roundoff of binary32
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round binary64 values to the nearest bfloat16 value (ties to even)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    fin = np.isfinite(x) & (x != 0.0)
+    _, e = np.frexp(x[fin])           # x = f 2^e, 0.5 <= |f| < 1, so 2^(e-1) <= |x|
+    # exponent of the leading bit is e - 1; the last kept bit is 2^(e-1-7),
+    # never below the subnormal quantum 2^(-126-7)
+    lead = np.maximum(e - 1, _EMIN)
+    quantum_exp = lead - (_SIG - 1)
+    q = np.rint(np.ldexp(x[fin], -quantum_exp))  # numpy rint: ties to even
+    r = np.ldexp(q, quantum_exp)
+    r[np.abs(r) > _MAX] = np.copysign(np.inf, r[np.abs(r) > _MAX])
+    out[fin] = r
+    out[~fin] = x[~fin]               # zeros (with sign), infs and NaNs pass through
+    return out
+
+
+def pow2_scale(x: np.ndarray) -> float:
+    """2^-e with max|x| 2^-e in [0.5, 1); 1.0 for an all-zero input."""
+    m = float(np.max(np.abs(x))) if x.size else 0.0
+    if m == 0.0:
+        return 1.0
+    _, e = np.frexp(m)
+    return float(np.ldexp(1.0, -int(e)))
+
+
+def gemm_tn_reference(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """A^T B of bfloat16-exact inputs, formed in FP64 (the products are exact)."""
+    return np.asarray(A, np.float64).T @ np.asarray(B, np.float64)
+
+
+def fp32_gemm_bound(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Elementwise bound on |fl32(A^T B) - A^T B| for any summation order:
+    gamma_K |A|^T |B| with gamma_K = K u / (1 - K u), u = 2^-24, plus the
+    final rounding of the result to binary32."""
+    K = A.shape[0]
+    g = K * U32 / (1.0 - K * U32)
+    absprod = np.abs(A).T @ np.abs(B)
+    return g * absprod + U32 * absprod
+
+
+def _round_columns(X: np.ndarray) -> np.ndarray:
+    out = np.empty_like(X)
+    for j in range(X.shape[1]):
+        out[:, j] = bf16_round(X[:, j] * pow2_scale(X[:, j]))
+    return out
+
+
+def sketch_bf16(T22: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
+    """The mixed sketch's steps (module docstring), products in FP64."""
+    Tb = bf16_round(T22 * pow2_scale(T22))
+    Gb = bf16_round(G)
+    Y = Tb.T @ Gb
+    for _ in range(q):
+        Z = Tb @ _round_columns(Y)
+        Y = Tb.T @ _round_columns(Z)
+    return Y

@@ -252,9 +252,9 @@ int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double al
 }
 
 size_t rrf_panel_workspace_size(int64_t M, int64_t k) {
-  PanelPlan p;
-  if (k < 1 || M < k || !panel_plan(M, (int)k, &p)) return 0;
-  return p.work + 256;
+  if (k < 1 || k > 256 || M < k) return 0;
+  const size_t w = panel_work_bytes(M, (int)k);
+  return w == 0 ? 0 : w + 256;
 }
 
 int rrf_householder_panel(int64_t M, int64_t k, double* P, int64_t ldp, double* W, int64_t ldw,

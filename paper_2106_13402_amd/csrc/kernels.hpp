@@ -35,7 +35,11 @@ struct PanelPlan {
   size_t lds = 0;     // dynamic LDS bytes
   size_t work = 0;    // global scratch bytes
 };
-bool panel_plan(int64_t M, int k, PanelPlan* plan);
+bool panel_plan(int64_t M, int k, PanelPlan* plan);  // one launch
+// Workspace of householder_panel for every panel height up to Mmax with k
+// columns (0 when unsupported); taller panels than one launch takes are split
+// by columns.
+size_t panel_work_bytes(int64_t Mmax, int k);
 // Householder QR of the M x k panel P; see rrf_householder_panel. When
 // `zero` is non-null the M x k region it points to (ld ldz) is set to 0 after
 // the panel has been read (used to clear T(I2 u I3, J2) in place).

@@ -417,7 +417,10 @@ bool panel_plan(int64_t M, int k, PanelPlan* plan) {
   return true;
 }
 
-int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
+namespace {
+
+// One cooperative launch; the panel must satisfy panel_plan.
+int panel_launch(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
                       int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
                       double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
   PanelPlan plan;
@@ -466,6 +469,93 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                                             dim3(kThreads), args, (unsigned)plan.lds, st);
   trace_end(st, tok);
   RRF_CHECK_HIP(e);
+  return RRF_OK;
+}
+
+// Largest panel height one launch takes for k columns (0 if none).
+int64_t fit_rows(int k) {
+  const int64_t max_rows = kLdsBudget / ((int64_t)(k + 1) * 8) - 1;
+  return max_rows < 1 ? 0 : max_rows * (kMaxGroups - 1);
+}
+
+// Scratch of the split below: Z, T1^T Z and W1^T W2 (k1 x k2 each) and the
+// split-K partials of the GEMMs with inner dimension M.
+constexpr int kSplitParts = 16;
+size_t split_temp_bytes(int k1, int k2) { return (size_t)(3 + kSplitParts) * k1 * k2 * 8; }
+
+}  // namespace
+
+size_t panel_work_bytes(int64_t Mmax, int k) {
+  if (k < 1 || k > kMaxCols || Mmax < k) return 0;
+  const int64_t fit = fit_rows(k);
+  size_t need = 0;
+  if (fit >= k) {
+    PanelPlan p;
+    if (panel_plan(std::min(Mmax, fit), k, &p)) need = p.work;
+  }
+  if (Mmax > fit) {
+    if (k < 2) return 0;
+    const int k1 = k / 2, k2 = k - k1;
+    const size_t a = panel_work_bytes(Mmax, k1), b = panel_work_bytes(Mmax - k1, k2);
+    if (a == 0 || b == 0) return 0;
+    need = std::max(need, (size_t)round_up((int64_t)std::max(a, b), 256) + split_temp_bytes(k1, k2));
+  }
+  return need;
+}
+
+// A panel taller than one launch takes is split by columns (recursive
+// blocked Householder QR): with P = [P1 P2], P1 = Q1 [R11; 0] with
+// Q1 = I - W1 T1 W1^T, then Q1^T P2 = [R12; P2'] and P2' = Q2' R22, and
+// Q = Q1 Q2 = I - W T W^T with W = [W1, [0; W2']] and
+// T = [T1, -T1 (W1^T W2) T2; 0, T2]. In exact arithmetic these are the
+// reflectors of the unblocked factorization.
+int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
+                      int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
+                      double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
+  PanelPlan plan;
+  if (panel_plan(M, k, &plan))
+    return panel_launch(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
+                        work_bytes, status);
+  if (k < 2 || M < k)
+    return set_error(RRF_E_NOTSUP, "householder panel: shape not supported");
+  const int k1 = k / 2, k2 = k - k1;
+  const size_t sub = std::max(panel_work_bytes(M, k1), panel_work_bytes(M - k1, k2));
+  if (sub == 0) return set_error(RRF_E_NOTSUP, "householder panel: shape not supported");
+  const size_t sub_r = (size_t)round_up((int64_t)sub, 256);
+  if (work == nullptr || work_bytes < sub_r + split_temp_bytes(k1, k2))
+    return set_error(RRF_E_NOMEM, "householder panel: workspace too small");
+  double* Z = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + sub_r);
+  double* Z2 = Z + (size_t)k1 * k2;
+  double* S = Z2 + (size_t)k1 * k2;
+  double* split = S + (size_t)k1 * k2;
+  const size_t split_elems = (size_t)kSplitParts * k1 * k2;
+
+  // P1 = Q1 [R11; 0]
+  RRF_TRY(householder_panel(st, M, k1, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work, sub,
+                            status));
+  // W2 <- Q1^T P2 = P2 - W1 (T1^T (W1^T P2)), then R12 = its first k1 rows
+  double* W2 = W + (int64_t)k1 * ldw;
+  if (W != P || ldw != ldp) RRF_TRY(copy_matrix(st, M, k2, P + (int64_t)k1 * ldp, ldp, W2, ldw));
+  if (zero) RRF_TRY(fill_matrix(st, M, k2, 0.0, zero + (int64_t)k1 * ldz, ldz));
+  RRF_TRY(dgemm(st, true, false, k1, k2, M, 1.0, W, ldw, W2, ldw, 0.0, Z, k1, split, split_elems));
+  RRF_TRY(dgemm(st, true, false, k1, k2, k1, 1.0, Tf, ldt, Z, k1, 0.0, Z2, k1, nullptr, 0));
+  RRF_TRY(dgemm(st, false, false, M, k2, k1, -1.0, W, ldw, Z2, k1, 1.0, W2, ldw, nullptr, 0));
+  if (R) {
+    RRF_TRY(copy_matrix(st, k1, k2, W2, ldw, R + (int64_t)k1 * ldr, ldr));
+    RRF_TRY(fill_matrix(st, k2, k1, 0.0, R + k1, ldr));
+  }
+  // P2' (rows k1.. of W2, in place) = Q2' R22
+  RRF_TRY(householder_panel(st, M - k1, k2, W2 + k1, ldw, W2 + k1, ldw,
+                            R ? R + k1 + (int64_t)k1 * ldr : nullptr, ldr,
+                            Tf + k1 + (int64_t)k1 * ldt, ldt, tau + k1, nullptr, 0, work, sub,
+                            status));
+  RRF_TRY(fill_matrix(st, k1, k2, 0.0, W2, ldw));
+  // T12 = -T1 (W1^T W2) T2
+  RRF_TRY(dgemm(st, true, false, k1, k2, M, 1.0, W, ldw, W2, ldw, 0.0, S, k1, split, split_elems));
+  RRF_TRY(dgemm(st, false, false, k1, k2, k1, 1.0, Tf, ldt, S, k1, 0.0, Z, k1, nullptr, 0));
+  RRF_TRY(dgemm(st, false, false, k1, k2, k2, -1.0, Z, k1, Tf + k1 + (int64_t)k1 * ldt, ldt, 0.0,
+                Tf + (int64_t)k1 * ldt, ldt, nullptr, 0));
+  RRF_TRY(fill_matrix(st, k2, k1, 0.0, Tf + k1, ldt));
   return RRF_OK;
 }
 

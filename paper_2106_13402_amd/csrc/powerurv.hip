@@ -51,10 +51,9 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t nb, bool need_v, PBufs* B) {
   B->tau = ar.take<double>((size_t)n);
   B->split_elems = (size_t)8 * mx * nb;
   B->split = ar.take<double>(B->split_elems);
-  PanelPlan pp;
-  if (!panel_plan(mx, (int)nb, &pp)) return false;
-  B->panel_bytes = pp.work;
-  B->panel = ar.take<char>(pp.work);
+  B->panel_bytes = panel_work_bytes(mx, (int)nb);
+  if (B->panel_bytes == 0) return false;
+  B->panel = ar.take<char>(B->panel_bytes);
   return true;
 }
 
@@ -110,8 +109,7 @@ int form_q(hipStream_t st, int64_t M, int64_t N, int64_t nb, int64_t ncols, PBuf
 
 bool powerurv_supported(int64_t m, int64_t n, int64_t b) {
   if (b > 256) return false;
-  PanelPlan pp;
-  return panel_plan(std::max(m, n), (int)std::min(b, n), &pp);
+  return panel_work_bytes(std::max(m, n), (int)std::min(b, n)) > 0;
 }
 
 size_t powerurv_workspace(int64_t m, int64_t n, int64_t b, int q) {

@@ -103,10 +103,9 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, Bufs* B) {
   B->d = ar.take<double>((size_t)s * kb);
   B->split_elems = (size_t)8 * mx * kb;
   for (int k = 0; k < 2; ++k) B->split[k] = ar.take<double>(B->split_elems);
-  PanelPlan pp;
-  if (!panel_plan(mx, (int)kb, &pp)) return false;
-  B->panel_bytes = pp.work;
-  B->panel = ar.take<char>(pp.work);
+  B->panel_bytes = panel_work_bytes(mx, (int)kb);
+  if (B->panel_bytes == 0) return false;
+  B->panel = ar.take<char>(B->panel_bytes);
   B->svd_bytes = (size_t)s * block_svd_work_bytes((int)kb);
   B->svd = ar.take<char>(B->svd_bytes);
   return true;
@@ -128,8 +127,7 @@ enum { kEvStart = 0, kEvV = 1, kEvU = 3, kEvVdone = 5, kEvUdone = 7, kEvS1 = 9, 
 
 bool randutv_supported(int64_t m, int64_t n, int64_t b) {
   if (b > 256) return false;
-  PanelPlan pp;
-  return panel_plan(std::max(m, n), (int)std::min(b, n), &pp);
+  return panel_work_bytes(std::max(m, n), (int)std::min(b, n)) > 0;
 }
 
 size_t randutv_workspace(int64_t m, int64_t n, int64_t b) {

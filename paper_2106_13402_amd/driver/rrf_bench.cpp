@@ -2,7 +2,12 @@
 // print one line of timings. Used to profile the library without any Python
 // or torch runtime in the process (rocprofv3 --kernel-trace / --pmc).
 //
-//   rrf_bench [--alg randutv|powerurv] [--n N] [--b B] [--q Q] [--reps R] [--trace]
+//   rrf_bench [--alg randutv|powerurv] [--m M] [--n N] [--b B] [--q Q] [--reps R] [--trace]
+//             [--copy-bytes BYTES]
+//
+// --copy-bytes first runs one device-to-device copy of BYTES bytes: a plain
+// copy kernel of known traffic, against which the HBM byte counters of a
+// --pmc run are calibrated.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -20,33 +25,45 @@ static int fail(const char* what, int st) {
 
 int main(int argc, char** argv) {
   std::string alg = "randutv";
-  long n = 16384, b = 128, q = 2, reps = 1;
+  long m = 0, n = 16384, b = 128, q = 2, reps = 1, copy_bytes = 0;
   bool trace = false;
   for (int i = 1; i < argc; ++i) {
     std::string a = argv[i];
     auto next = [&](long& v) { if (i + 1 < argc) v = atol(argv[++i]); };
     if (a == "--alg" && i + 1 < argc) alg = argv[++i];
+    else if (a == "--m") next(m);
     else if (a == "--n") next(n);
     else if (a == "--b") next(b);
     else if (a == "--q") next(q);
     else if (a == "--reps") next(reps);
     else if (a == "--trace") trace = true;
+    else if (a == "--copy-bytes") next(copy_bytes);
     else { fprintf(stderr, "unknown argument %s\n", a.c_str()); return 2; }
   }
-  const size_t bytes = (size_t)n * n * sizeof(double);
+  if (m < n) m = n;
+  const size_t bytes = (size_t)m * n * sizeof(double);
   double *A = nullptr, *U = nullptr, *T = nullptr, *V = nullptr;
   void* ws = nullptr;
   const int code = alg == "powerurv" ? RRF_ALG_POWERURV : RRF_ALG_RANDUTV;
-  const size_t wsb = rrf_workspace_size(code, n, n, b, (int)q, RRF_PREC_FP64);
+  const size_t wsb = rrf_workspace_size(code, m, n, b, (int)q, RRF_PREC_FP64);
   if (wsb == 0) return fail("rrf_workspace_size", -1);
-  if (hipMalloc(&A, bytes) != hipSuccess || hipMalloc(&U, bytes) != hipSuccess ||
-      hipMalloc(&T, bytes) != hipSuccess || hipMalloc(&V, bytes) != hipSuccess ||
+  if (hipMalloc(&A, bytes) != hipSuccess || hipMalloc(&U, (size_t)m * m * 8) != hipSuccess ||
+      hipMalloc(&T, bytes) != hipSuccess || hipMalloc(&V, (size_t)n * n * 8) != hipSuccess ||
       hipMalloc(&ws, wsb) != hipSuccess) {
     fprintf(stderr, "rrf_bench: device allocation failed\n");
     return 1;
   }
-  int st = rrf_gaussian(0, 1ull << 40, n, n, A, n, nullptr);
+  int st = rrf_gaussian(0, 1ull << 40, m, n, A, m, nullptr);
   if (st) return fail("rrf_gaussian", st);
+  if (copy_bytes > 0) {
+    if ((size_t)copy_bytes > bytes) copy_bytes = (long)bytes;
+    if (hipMemcpyAsync(T, A, (size_t)copy_bytes, hipMemcpyDeviceToDevice, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+      fprintf(stderr, "rrf_bench: calibration copy failed\n");
+      return 1;
+    }
+    printf("rrf_bench: calibration copy of %ld bytes\n", copy_bytes);
+  }
   rrf_opts o;
   rrf_opts_init(&o);
   o.workspace = ws;
@@ -55,13 +72,14 @@ int main(int argc, char** argv) {
   double best = 1e30, total = 0.0;
   for (long r = 0; r < reps; ++r) {
     auto t0 = std::chrono::steady_clock::now();
-    st = code == RRF_ALG_RANDUTV ? rrf_randutv_ex(n, n, A, n, b, (int)q, 1, U, T, V, &o)
-                                 : rrf_powerurv_ex(n, n, A, n, b, (int)q, 1, U, T, V, &o);
+    st = code == RRF_ALG_RANDUTV ? rrf_randutv_ex(m, n, A, m, b, (int)q, 1, U, T, V, &o)
+                                 : rrf_powerurv_ex(m, n, A, m, b, (int)q, 1, U, T, V, &o);
     if (st) return fail(alg.c_str(), st);
     double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     best = s < best ? s : best;
     total += s;
-    printf("rrf_bench: %s n=%ld b=%ld q=%ld rep %ld: %.4f s\n", alg.c_str(), n, b, q, r, s);
+    printf("rrf_bench: %s m=%ld n=%ld b=%ld q=%ld rep %ld: %.4f s\n", alg.c_str(), m, n, b, q, r,
+           s);
     fflush(stdout);
   }
   if (trace) {

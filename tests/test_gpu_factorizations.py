@@ -171,6 +171,45 @@ def test_randutv_power_decay_1024(gpu, q):
     _diag_parity_derived(T, A, 128, q, 1)
 
 
+def _gpu_orth_error(Q, iters=40):
+    """||Q^T Q - I||_2 on the device by power iteration on the symmetric
+    error matrix (for factors too large to bring to the host)."""
+    import torch
+    E = Q.T @ Q
+    E.diagonal().sub_(1.0)
+    x = torch.randn(E.shape[0], 1, dtype=E.dtype, device=E.device,
+                    generator=torch.Generator(device=E.device).manual_seed(0))
+    lam = 0.0
+    for _ in range(iters):
+        y = E @ x
+        lam = float(torch.linalg.vector_norm(y))
+        if lam == 0.0:
+            return 0.0
+        x = y / lam
+    return lam
+
+
+def test_randutv_tall_panel_split(gpu):
+    """m = 20000, n = 384, b = 256 (the shape class of the 32768 x 8192,
+    b = 256 configuration): the 20000 x 256 panel of step 1 is taller than
+    one panel launch takes and is factored by the column split."""
+    from paper_2106_13402_amd import randutv
+    m, n, b, q = 20000, 384, 256, 1
+    s = spectrum("geometric", n, decades=8.0)
+    A = spectral_matrix(m, n, s, seed=0)
+    print(f"case: randutv tall split m={m} n={n} b={b} q={q}", flush=True)
+    dA = _to_dev(A, gpu)
+    U, T, V = randutv(dA, b, q, 1)
+    assert _gpu_orth_error(U) <= 1e-13
+    Th, Vh = _host(T), _host(V)
+    assert M.orth_error(Vh) <= 1e-13
+    R = dA - U @ T @ V.T
+    assert float(R.norm()) <= 1e-13 * np.linalg.norm(A)  # Frobenius >= spectral
+    assert np.all(np.tril(Th, -1) == 0.0)
+    _check_blocks(Th, b)
+    _diag_parity_derived(Th, A, b, q, 1)
+
+
 def test_randutv_edge_cases(gpu):
     # zero matrix: T = 0 exactly, U and V orthogonal
     A = np.zeros((50, 40))

@@ -103,8 +103,10 @@ def _larft(W, tau):
     return T
 
 
+# (32768, 256) and (40000, 256) exceed one panel launch: one and two levels
+# of the column split.
 PANEL_CASES = [(5, 1), (64, 32), (1000, 7), (513, 32), (4096, 128), (16384, 128), (20000, 64),
-               (32768, 128), (3000, 256)]
+               (32768, 128), (3000, 256), (32768, 256), (40000, 256)]
 
 
 @pytest.mark.parametrize("M,k", PANEL_CASES)

@@ -1,0 +1,133 @@
+"""Pins of the mixed-sketch reference (oracle/bf16.py) against what fixes it
+independently: torch's binary32 -> bfloat16 conversion (round to nearest
+even) on values binary32 holds exactly, hand-worked rounding cases, BLAS
+single-precision products, and exact arithmetic on representable inputs."""
+import numpy as np
+import pytest
+import torch
+
+from oracle.bf16 import bf16_round, fp32_gemm_bound, gemm_tn_reference, pow2_scale, sketch_bf16
+
+
+def _torch_bf16(x32):
+    return torch.from_numpy(np.asarray(x32, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def test_bf16_round_matches_torch_on_binary32_values():
+    rng = np.random.default_rng(0)
+    x = np.concatenate([
+        rng.standard_normal(20000),
+        rng.standard_normal(20000) * 2.0 ** rng.integers(-140, 120, 20000),
+        # exact ties between neighbouring bfloat16 values (odd and even)
+        (np.arange(256, 512) + 0.5) * 2.0 ** -8,
+        -(np.arange(256, 512) + 0.5) * 2.0 ** 20,
+        # the subnormal range and its edge
+        np.arange(1, 300) * 2.0 ** -136,
+        np.array([2.0 ** -126, 2.0 ** -127, 2.0 ** -133, 1.5 * 2.0 ** -133, 2.5 * 2.0 ** -133]),
+    ]).astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(bf16_round(x), _torch_bf16(x))
+
+
+def test_bf16_round_hand_cases():
+    # a tie rounds to the even neighbour: 1 + 2^-8 is halfway between 1 and 1 + 2^-7
+    assert bf16_round(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    assert bf16_round(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+    # directly from binary64: just above the tie rounds up, although rounding
+    # to binary32 first would land on the tie and then go down to 1
+    x = 1.0 + 2.0 ** -8 + 2.0 ** -30
+    assert np.float32(x) == np.float32(1.0 + 2.0 ** -8)
+    assert bf16_round(np.array([x]))[0] == 1.0 + 2.0 ** -7
+    # gradual underflow: quantum 2^-133 below 2^-126
+    assert bf16_round(np.array([3 * 2.0 ** -134]))[0] == 2.0 ** -132  # 1.5 quanta -> 2
+    assert bf16_round(np.array([2.0 ** -135]))[0] == 0.0              # a quarter quantum
+    # overflow
+    big = (2.0 - 2.0 ** -8) * 2.0 ** 127                              # tie with 2^128
+    assert np.isinf(bf16_round(np.array([big]))[0])
+    assert bf16_round(np.array([(2.0 - 2.0 ** -7) * 2.0 ** 127]))[0] == (2.0 - 2.0 ** -7) * 2.0 ** 127
+    # specials pass through, the sign of zero is kept
+    r = bf16_round(np.array([0.0, -0.0, np.inf, -np.inf, np.nan]))
+    assert r[0] == 0.0 and np.signbit(r[1]) and np.isinf(r[2]) and r[3] < 0 and np.isnan(r[4])
+
+
+def test_bf16_round_is_idempotent_and_monotone():
+    rng = np.random.default_rng(1)
+    x = np.sort(rng.standard_normal(100000) * 10.0)
+    r = bf16_round(x)
+    np.testing.assert_array_equal(bf16_round(r), r)
+    assert np.all(np.diff(r) >= 0)
+    # relative error at most half a unit in the 8th bit
+    nz = x != 0
+    assert np.max(np.abs(r[nz] - x[nz]) / np.abs(x[nz])) <= 2.0 ** -8
+
+
+def test_pow2_scale():
+    rng = np.random.default_rng(2)
+    for s in (1e-300, 1e-20, 0.3, 1.0, 7.0, 1e30):
+        x = rng.standard_normal((40, 7)) * s
+        f = pow2_scale(x)
+        assert np.frexp(f)[0] == 0.5                    # a power of two
+        assert 0.5 <= np.max(np.abs(x)) * f < 1.0
+    assert pow2_scale(np.zeros(5)) == 1.0
+    assert pow2_scale(np.array([1.0])) == 0.5
+
+
+def test_fp32_gemm_bound_covers_blas_single():
+    rng = np.random.default_rng(3)
+    for K in (16, 1000, 20000):
+        A = bf16_round(rng.standard_normal((K, 24)))
+        B = bf16_round(rng.standard_normal((K, 9)))
+        exact = gemm_tn_reference(A, B)
+        single = (A.astype(np.float32).T @ B.astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(single - exact) <= fp32_gemm_bound(A, B))
+        # the bound is not vacuous: well below the products' own size
+        assert np.max(fp32_gemm_bound(A, B) / (np.abs(A).T @ np.abs(B))) < 2e-3
+
+
+def test_sketch_bf16_exact_on_representable_inputs():
+    # small integers and powers of two are bfloat16-exact and their products
+    # and sums are exact in binary64, so q = 0 is exactly the scaled T^T G
+    rng = np.random.default_rng(4)
+    T = rng.integers(-8, 9, (50, 30)).astype(np.float64)
+    G = rng.integers(-4, 5, (50, 6)).astype(np.float64)
+    np.testing.assert_array_equal(sketch_bf16(T, G, 0), (T * pow2_scale(T)).T @ G)
+
+
+def test_sketch_bf16_captures_the_dominant_subspace():
+    # spectrum with a gap after 8 values: the mixed sketch spans the same
+    # dominant right singular subspace as the exact one, to bfloat16 accuracy
+    rng = np.random.default_rng(5)
+    m, n, k = 400, 300, 8
+    Q1, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.r_[np.linspace(10, 5, k), np.linspace(1e-2, 1e-4, n - k)]
+    T = (Q1 * s) @ Q2.T
+    G = rng.standard_normal((m, k))
+    for q in (0, 1, 2):
+        Y = sketch_bf16(T, G, q)
+        Ye = T.T @ G
+        for _ in range(q):
+            Ye = T.T @ (T @ Ye)
+        sin_mixed = np.linalg.norm(Q2[:, k:].T @ np.linalg.qr(Y)[0], 2)
+        sin_exact = np.linalg.norm(Q2[:, k:].T @ np.linalg.qr(Ye)[0], 2)
+        # as good as the exact sketch, down to the bfloat16 floor (~2^-8
+        # relative, damped by the gap)
+        assert sin_mixed <= max(1.2 * sin_exact, 2e-3), (q, sin_mixed, sin_exact)
+
+
+def test_sketch_bf16_power_of_two_invariance():
+    # scaling T or a column of G by a power of two changes no rounding:
+    # T is renormalised, and for q >= 1 every column is renormalised before
+    # each product, so the sketch is unchanged (q = 0 carries G's factor)
+    rng = np.random.default_rng(6)
+    T = rng.standard_normal((60, 40))
+    G = rng.standard_normal((60, 5))
+    D = 2.0 ** np.array([-60, -3, 0, 7, 90])
+    for q in (1, 2):
+        base = sketch_bf16(T, G, q)
+        np.testing.assert_array_equal(sketch_bf16(T * 2.0 ** -100, G, q), base)
+        np.testing.assert_array_equal(sketch_bf16(T, G * D, q), base)
+    np.testing.assert_array_equal(sketch_bf16(T, G * D, 0), sketch_bf16(T, G, 0) * D)
+    # far below the binary32 range: (1e-30)^5 would underflow without the
+    # renormalisation, the sketch stays finite and non-zero
+    Y = sketch_bf16(T * 1e-30, G, 2)
+    assert np.all(np.isfinite(Y)) and np.all(np.linalg.norm(Y, axis=0) > 0.1)
