@@ -18,6 +18,7 @@ RRF_E_NOTSUP = 3
 RRF_E_NUMERIC = 4
 RRF_E_INTERNAL = 5
 RRF_PREC_FP64 = 0
+RRF_PREC_BF16_SKETCH = 1
 RRF_ALG_RANDUTV = 0
 RRF_ALG_POWERURV = 1
 
@@ -65,6 +66,11 @@ PROTOTYPES = {
                                         _dp, _vp, _sz, _vp]),
     "rrf_block_svd_workspace_size": (_sz, [_i64]),
     "rrf_block_svd": (C.c_int, [_i64, _dp, _i64, _dp, _dp, _dp, _vp, _sz, _vp]),
+    "rrf_to_bf16": (C.c_int, [_i64, _i64, _dp, _i64, C.c_int, _vp, _i64, _vp, _i64, _vp, _sz,
+                              _vp]),
+    "rrf_gemm_bf16_workspace_size": (_sz, [_i64, _i64]),
+    "rrf_gemm_bf16_tn": (C.c_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _dp, _i64,
+                                   _vp, _sz, _vp]),
     "rrf_trace_enable": (C.c_int, [C.c_int]),
     "rrf_trace_read": (C.c_int, [C.POINTER(rrf_trace_entry), C.c_int]),
     "rrf_status_string": (C.c_char_p, [C.c_int]),
@@ -83,7 +89,7 @@ def load(path: str = LIB_PATH) -> C.CDLL:
         pass
     if not os.path.exists(path):
         raise ImportError(
-            f"{path} is missing: build it with `python -m paper_2106_13402_amd.build` "
+            f"{path} is missing: build it with `python paper_2106_13402_amd/build.py` "
             "(hipcc, gfx950). There is no fallback implementation.")
     lib = C.CDLL(path)
     for name, (res, args) in PROTOTYPES.items():

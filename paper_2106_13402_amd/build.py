@@ -1,6 +1,7 @@
 """Build librrf.so (the HIP kernels and the C-ABI) in-tree for gfx950.
 
-Usage: ``python -m paper_2106_13402_amd.build`` or ``build()``. Every source
+Usage: ``python paper_2106_13402_amd/build.py`` or ``build()`` (run as a
+script or loaded by path: importing the package would load the library). Every source
 is compiled with hipcc for gfx950 (cross-compiles without a GPU) and linked
 into ``paper_2106_13402_amd/librrf.so``. Packed-FP32 instruction selection is
 disabled for all device code.
