@@ -50,6 +50,13 @@ extern "C" {
 
 /* ---- precision modes -------------------------------------------------- */
 #define RRF_PREC_FP64   0  /* every step in binary64                           */
+/* randUTV only: the sketch Y = (T22^T T22)^q T22^T G of each step is formed
+ * from bfloat16 copies of T22 (scaled by a power of two) and G with binary32
+ * accumulation, each intermediate column rescaled by a power of two and
+ * rounded to bfloat16 (round to nearest even); the QR of Y and every update
+ * of T, U and V stay in binary64. The sketch only has to capture the
+ * dominant subspace of T22 (Alg. 3; the paper itself is binary64 throughout). */
+#define RRF_PREC_BF16_SKETCH 1
 
 /* ---- algorithms (for rrf_workspace_size) -------------------------------- */
 #define RRF_ALG_RANDUTV  0
@@ -158,6 +165,32 @@ int rrf_householder_panel(int64_t M, int64_t k, double* P, int64_t ldp, double* 
 size_t rrf_block_svd_workspace_size(int64_t k);
 int rrf_block_svd(int64_t k, const double* B, int64_t ldb, double* Us, double* d,
                   double* Vs, void* work, size_t work_bytes, void* stream);
+
+/* Building blocks of the RRF_PREC_BF16_SKETCH sketch.
+ *
+ * rrf_to_bf16: out (rows x cols, ld ldo, ldo a multiple of 8 >= rows) =
+ * bfloat16 bit patterns of X s rounded to nearest even directly from binary64;
+ * s = 1 when `scaled` is 0, else the power of two putting max|X| in
+ * [0.5, 1). Rows [rows, ldo) of out are written as 0. When outT is not NULL
+ * it receives the transpose (cols x rows, ld ldot, a multiple of 8 >= cols,
+ * rows [cols, ldot) zero). `work` must hold 256 bytes. Device pointers. */
+int rrf_to_bf16(int64_t rows, int64_t cols, const double* X, int64_t ldx, int scaled,
+                uint16_t* out, int64_t ldo, uint16_t* outT, int64_t ldot, void* work,
+                size_t work_bytes, void* stream);
+
+/* rrf_gemm_bf16_tn: the M x N product A^T B of bfloat16 matrices A (K x M,
+ * ld lda) and B (K x N, ld ldb), both leading dimensions multiples of 8 and
+ * both base addresses 16-byte aligned, with rows [K, ld) of A and B zero, on
+ * the bfloat16 matrix cores with binary32 accumulation. The result goes
+ * either to out16 (bfloat16, ld ld16 >= M a multiple of 8, rows [M, ld16)
+ * zero), each column scaled by the power of two that puts its max|.| in
+ * [0.5, 1) before rounding to nearest even, or, when out16 is NULL, to out64
+ * (binary64, ld ld64 >= M), widened exactly. `work` must hold
+ * rrf_gemm_bf16_workspace_size(M, N) bytes. */
+size_t rrf_gemm_bf16_workspace_size(int64_t M, int64_t N);
+int rrf_gemm_bf16_tn(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t lda,
+                     const uint16_t* B, int64_t ldb, uint16_t* out16, int64_t ld16,
+                     double* out64, int64_t ld64, void* work, size_t work_bytes, void* stream);
 
 /* ---- diagnostics ------------------------------------------------------- */
 const char* rrf_status_string(int status);

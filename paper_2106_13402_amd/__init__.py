@@ -18,8 +18,11 @@ from ._lib import RRFError
 __all__ = [
     "RRFError", "randutv", "powerurv", "gaussian", "dgemm", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
-    "trace_read",
+    "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS",
 ]
+
+# precision names of rrf_opts.precision
+PRECISIONS = {"fp64": _lib.RRF_PREC_FP64, "bf16_sketch": _lib.RRF_PREC_BF16_SKETCH}
 
 lib = _lib.load()
 
@@ -83,13 +86,13 @@ def _workspace(device, nbytes: int):
     return buf
 
 
-def workspace_size(alg: str, m: int, n: int, b: int, q: int) -> int:
+def workspace_size(alg: str, m: int, n: int, b: int, q: int, precision: str = "fp64") -> int:
     code = _lib.RRF_ALG_RANDUTV if alg == "randutv" else _lib.RRF_ALG_POWERURV
-    return int(lib.rrf_workspace_size(code, m, n, b, q, _lib.RRF_PREC_FP64))
+    return int(lib.rrf_workspace_size(code, m, n, b, q, PRECISIONS[precision]))
 
 
 def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, want_v: bool,
-            check_finite: bool, inplace: bool):
+            check_finite: bool, inplace: bool, precision: str = "fp64"):
     _require(A, "A")
     m, n = int(A.shape[0]), int(A.shape[1])
     dev = A.device
@@ -101,12 +104,13 @@ def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, wa
         T = A
     else:
         T = empty_colmajor(m, n, dev)
-    nbytes = workspace_size(alg, m, n, b, q)
+    nbytes = workspace_size(alg, m, n, b, q, precision)
     if nbytes == 0:
         raise RRFError(_lib.RRF_E_NOTSUP, fname, "no workspace size for these arguments")
     ws = _workspace(dev, nbytes)
     opts = _lib.rrf_opts()
     lib.rrf_opts_init(C.byref(opts))
+    opts.precision = PRECISIONS[precision]
     opts.stream = _stream_ptr(dev)
     opts.workspace = ws.data_ptr()
     opts.workspace_bytes = ws.numel()
@@ -121,10 +125,13 @@ def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, wa
 
 
 def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
-            check_finite: bool = False, inplace: bool = False):
-    """randUTV (Alg. 3): returns (U, T, V) with A = U T V^T (U/V None if not wanted)."""
+            check_finite: bool = False, inplace: bool = False, precision: str = "fp64"):
+    """randUTV (Alg. 3): returns (U, T, V) with A = U T V^T (U/V None if not wanted).
+
+    precision "bf16_sketch" forms each step's sketch from bfloat16 copies with
+    FP32 accumulation (RRF_PREC_BF16_SKETCH); everything else stays FP64."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
-                   inplace)
+                   inplace, precision)
 
 
 def powerurv(A, q: int, seed: int, *, b: int = 128, want_u: bool = True, want_v: bool = True,
@@ -216,3 +223,47 @@ def block_svd(B):
     _check(lib.rrf_block_svd(k, B.data_ptr(), _ld(B), Us.data_ptr(), d.data_ptr(), Vs.data_ptr(),
                              work.data_ptr(), nbytes, _stream_ptr(B.device)), "rrf_block_svd")
     return Us, d, Vs
+
+
+def _ld8(rows: int) -> int:
+    return (max(rows, 1) + 7) // 8 * 8
+
+
+def to_bf16(X, *, scaled: bool = False, transpose: bool = False):
+    """bfloat16 bit patterns (torch.int16, column-major, ld a multiple of 8)
+    of X, or of X times the power of two putting max|X| in [0.5, 1) when
+    `scaled`; with `transpose` also of X^T. Returns (out, outT or None), each
+    a (ld x cols) tensor whose first rows hold the values."""
+    torch = _torch()
+    _require(X, "X")
+    rows, cols = int(X.shape[0]), int(X.shape[1])
+    out = empty_colmajor(_ld8(rows), cols, X.device, torch.int16)
+    outT = empty_colmajor(_ld8(cols), rows, X.device, torch.int16) if transpose else None
+    work = torch.empty(256, dtype=torch.uint8, device=X.device)
+    _check(lib.rrf_to_bf16(rows, cols, X.data_ptr() if X.numel() else None, _ld(X),
+                           1 if scaled else 0, out.data_ptr(), _ld8(rows),
+                           outT.data_ptr() if outT is not None else None,
+                           _ld8(cols) if outT is not None else 0, work.data_ptr(), 256,
+                           _stream_ptr(X.device)), "rrf_to_bf16")
+    return out, outT
+
+
+def gemm_bf16_tn(A16, K: int, B16, *, out: str = "f64"):
+    """A^T B of bfloat16 matrices given as int16 bit patterns (K valid rows,
+    leading dimension = the tensors' first dimension, a multiple of 8, rows
+    past K zero). out "f64" widens the FP32 result; "bf16" returns it column-
+    rescaled by powers of two and rounded (as int16 bit patterns)."""
+    torch = _torch()
+    M, N = int(A16.shape[1]), int(B16.shape[1])
+    work_bytes = int(lib.rrf_gemm_bf16_workspace_size(M, N))
+    work = torch.empty(work_bytes, dtype=torch.uint8, device=A16.device)
+    if out == "f64":
+        C64 = empty_colmajor(M, N, A16.device)
+        o16, ld16, o64, ld64 = None, 0, C64.data_ptr(), M
+    else:
+        C16 = empty_colmajor(_ld8(M), N, A16.device, torch.int16)
+        o16, ld16, o64, ld64 = C16.data_ptr(), _ld8(M), None, 0
+    _check(lib.rrf_gemm_bf16_tn(M, N, K, A16.data_ptr(), int(A16.shape[0]), B16.data_ptr(),
+                                int(B16.shape[0]), o16, ld16, o64, ld64, work.data_ptr(),
+                                work_bytes, _stream_ptr(A16.device)), "rrf_gemm_bf16_tn")
+    return C64 if out == "f64" else C16

@@ -121,8 +121,9 @@ int run_alg(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t
   rrf_opts o;
   rrf_opts_init(&o);
   if (opts) o = *opts;
-  if (o.precision != RRF_PREC_FP64)
-    return set_error(RRF_E_NOTSUP, "only RRF_PREC_FP64 is implemented");
+  if (o.precision != RRF_PREC_FP64 &&
+      !(alg == RRF_ALG_RANDUTV && o.precision == RRF_PREC_BF16_SKETCH))
+    return set_error(RRF_E_NOTSUP, "precision mode not implemented for this algorithm");
   const bool ok = alg == RRF_ALG_RANDUTV ? randutv_supported(m, n, b) : powerurv_supported(m, n, b);
   if (!ok) return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
   int dev = 0;
@@ -171,8 +172,12 @@ void rrf_opts_init(rrf_opts* opts) {
 }
 
 size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q, int precision) {
-  if (m < 1 || n < 1 || b < 1 || q < 0 || m < n || precision != RRF_PREC_FP64) return 0;
-  if (alg == RRF_ALG_RANDUTV) return randutv_supported(m, n, b) ? randutv_workspace(m, n, b) : 0;
+  if (m < 1 || n < 1 || b < 1 || q < 0 || m < n) return 0;
+  if (alg == RRF_ALG_RANDUTV) {
+    if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
+    return randutv_supported(m, n, b) ? randutv_workspace(m, n, b, precision) : 0;
+  }
+  if (precision != RRF_PREC_FP64) return 0;
   if (alg == RRF_ALG_POWERURV)
     return powerurv_supported(m, n, b) ? powerurv_workspace(m, n, b, q) : 0;
   return 0;
@@ -184,7 +189,7 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;
                    return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
-                                      &dummy);
+                                      opts ? opts->precision : RRF_PREC_FP64, &dummy);
                  });
 }
 
@@ -283,6 +288,56 @@ int rrf_householder_panel(int64_t M, int64_t k, double* P, int64_t ldp, double* 
   RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(status), 1, 0u));
   return householder_panel(st, M, (int)k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, nullptr, 0,
                            reinterpret_cast<char*>(work) + 256, work_bytes - 256, status);
+}
+
+int rrf_to_bf16(int64_t rows, int64_t cols, const double* X, int64_t ldx, int scaled,
+                uint16_t* out, int64_t ldo, uint16_t* outT, int64_t ldot, void* work,
+                size_t work_bytes, void* stream) {
+  if (rows < 0) return set_error(-1, "rows must be >= 0"), -1;
+  if (cols < 0) return set_error(-2, "cols must be >= 0"), -2;
+  if (rows > 0 && cols > 0 && X == nullptr) return set_error(-3, "X is NULL"), -3;
+  if (ldx < (rows > 1 ? rows : 1)) return set_error(-4, "ldx too small"), -4;
+  if (rows > 0 && cols > 0 && out == nullptr) return set_error(-6, "out is NULL"), -6;
+  if (ldo < rows || (ldo & 7)) return set_error(-7, "ldo must be >= rows and a multiple of 8"), -7;
+  if (outT && (ldot < cols || (ldot & 7)))
+    return set_error(-9, "ldot must be >= cols and a multiple of 8"), -9;
+  if (work == nullptr || work_bytes < 256) return set_error(-10, "work needs 256 bytes"), -10;
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  unsigned long long* word = reinterpret_cast<unsigned long long*>(work);
+  if (scaled) RRF_TRY(maxabs(st, rows, cols, X, ldx, word));
+  return to_bf16(st, rows, cols, X, ldx, scaled ? word : nullptr, out, ldo, outT, ldot);
+}
+
+size_t rrf_gemm_bf16_workspace_size(int64_t M, int64_t N) {
+  if (M < 1 || N < 1) return 0;
+  return gemm_bf16_work_bytes(M, N);
+}
+
+int rrf_gemm_bf16_tn(int64_t M, int64_t N, int64_t K, const uint16_t* A, int64_t lda,
+                     const uint16_t* B, int64_t ldb, uint16_t* out16, int64_t ld16,
+                     double* out64, int64_t ld64, void* work, size_t work_bytes, void* stream) {
+  if (M < 1) return set_error(-1, "M must be >= 1"), -1;
+  if (N < 1) return set_error(-2, "N must be >= 1"), -2;
+  if (K < 0) return set_error(-3, "K must be >= 0"), -3;
+  if (K > 0 && A == nullptr) return set_error(-4, "A is NULL"), -4;
+  if (lda < K || (lda & 7)) return set_error(-5, "lda must be >= K and a multiple of 8"), -5;
+  if (K > 0 && B == nullptr) return set_error(-6, "B is NULL"), -6;
+  if (ldb < K || (ldb & 7)) return set_error(-7, "ldb must be >= K and a multiple of 8"), -7;
+  if (out16 == nullptr && out64 == nullptr) return set_error(-8, "no output"), -8;
+  if (out16 && (ld16 < M || (ld16 & 7)))
+    return set_error(-9, "ld16 must be >= M and a multiple of 8"), -9;
+  if (!out16 && ld64 < M) return set_error(-11, "ld64 must be >= M"), -11;
+  if (work == nullptr || work_bytes < gemm_bf16_work_bytes(M, N))
+    return set_error(RRF_E_NOMEM, "work smaller than rrf_gemm_bf16_workspace_size()");
+  if (K > 0 && ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15))
+    return set_error(RRF_E_NOTSUP, "A and B must be 16-byte aligned");
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  return gemm_bf16_tn(st, M, N, K, A, lda, B, ldb, out16, ld16, out16 ? nullptr : out64, ld64,
+                      work, work_bytes);
 }
 
 size_t rrf_block_svd_workspace_size(int64_t k) {

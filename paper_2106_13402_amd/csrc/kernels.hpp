@@ -48,6 +48,27 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                       double* tau, double* zero, int64_t ldz, void* work, size_t work_bytes,
                       int* status);
 
+// ---- sketch_bf16.hip ------------------------------------------------------
+// Leading dimension of a bfloat16 copy with `rows` rows (a multiple of 8).
+int64_t bf16_ld(int64_t rows);
+// *word = max|X| as binary64 bits (word zeroed first).
+int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+           unsigned long long* word);
+// out = bf16(X s) (rows x cols, ld ldo, rows [rows, ldo) zero) and, when
+// outT is non-null, its transpose (ld ldot, rows [cols, ldot) zero); s is the
+// power of two putting max|X| (from *word) in [0.5, 1), or 1 when word is null.
+int to_bf16(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+            const unsigned long long* word, uint16_t* out, int64_t ldo, uint16_t* outT,
+            int64_t ldot);
+size_t gemm_bf16_work_bytes(int64_t M, int64_t N);
+// A^T B (A: K x M, B: K x N, bfloat16, ld multiples of 8, rows past K zero)
+// with FP32 accumulation; the M x N result goes either to out16 as bfloat16
+// with each column scaled by its own power of two (rows [M, ld16) zero), or to
+// out64 widened to FP64.
+int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t* A,
+                 int64_t lda, const uint16_t* B, int64_t ldb, uint16_t* out16, int64_t ld16,
+                 double* out64, int64_t ld64, void* work, size_t work_bytes);
+
 // ---- jacobi_svd.hip ------------------------------------------------------
 size_t block_svd_work_bytes(int k);
 int block_svd(hipStream_t st, int k, const double* B, int64_t ldb, double* Us, double* d,

@@ -75,9 +75,18 @@ struct Bufs {
   size_t panel_bytes = 0;
   void* svd = nullptr;
   size_t svd_bytes = 0;
+  // mixed sketch (bfloat16 copies, ld a multiple of 8)
+  uint16_t* Tb = nullptr;   // m x n   T22, scaled
+  uint16_t* Tbt = nullptr;  // n x m   its transpose
+  uint16_t* Gb = nullptr;   // m x b
+  uint16_t* Yb = nullptr;   // n x b
+  uint16_t* Zb = nullptr;   // m x b
+  unsigned long long* word = nullptr;  // max|T22|
+  void* bwork = nullptr;
+  size_t bwork_bytes = 0;
 };
 
-bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, Bufs* B) {
+bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B) {
   const int64_t mx = std::max(m, n);
   const int64_t kb = std::min(b, n);
   const int64_t s = ceil_div(n, b);
@@ -108,6 +117,16 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, Bufs* B) {
   B->panel = ar.take<char>(B->panel_bytes);
   B->svd_bytes = (size_t)s * block_svd_work_bytes((int)kb);
   B->svd = ar.take<char>(B->svd_bytes);
+  if (precision == RRF_PREC_BF16_SKETCH) {
+    B->Tb = ar.take<uint16_t>((size_t)bf16_ld(m) * n);
+    B->Tbt = ar.take<uint16_t>((size_t)bf16_ld(n) * m);
+    B->Gb = ar.take<uint16_t>((size_t)bf16_ld(m) * kb);
+    B->Yb = ar.take<uint16_t>((size_t)bf16_ld(n) * kb);
+    B->Zb = ar.take<uint16_t>((size_t)bf16_ld(m) * kb);
+    B->word = ar.take<unsigned long long>(32);
+    B->bwork_bytes = gemm_bf16_work_bytes(mx, kb);
+    B->bwork = ar.take<char>(B->bwork_bytes);
+  }
   return true;
 }
 
@@ -120,6 +139,30 @@ int right_mult(hipStream_t st, int64_t rows, int64_t k, double* X, int64_t ldx, 
   return copy_matrix(st, rows, k, tmp, rows, X, ldx);
 }
 
+// The sketch of the mixed mode into Y (Ni x kb, FP64): bfloat16 copies of
+// the scaled T22 and of G, products with FP32 accumulation, each
+// intermediate column renormalised by a power of two; the last product is
+// widened to FP64. Needs G (Mi x kb) in B.G.
+int sketch_mixed(hipStream_t st, int64_t Mi, int64_t Ni, int64_t kb, int q, const double* T22,
+                 int64_t ldt, const Bufs& B, double* Y) {
+  const int64_t lm = bf16_ld(Mi), ln = bf16_ld(Ni);
+  RRF_TRY(to_bf16(st, Mi, kb, B.G, Mi, nullptr, B.Gb, lm, nullptr, 0));
+  RRF_TRY(maxabs(st, Mi, Ni, T22, ldt, B.word));
+  RRF_TRY(to_bf16(st, Mi, Ni, T22, ldt, B.word, B.Tb, lm, B.Tbt, ln));
+  // Y = T22^T G
+  RRF_TRY(gemm_bf16_tn(st, Ni, kb, Mi, B.Tb, lm, B.Gb, lm, q > 0 ? B.Yb : nullptr, ln,
+                       q > 0 ? nullptr : Y, Ni, B.bwork, B.bwork_bytes));
+  for (int it = 0; it < q; ++it) {
+    const bool last = it == q - 1;
+    // Z = T22 Y = Tbt^T Y, then Y = T22^T Z
+    RRF_TRY(gemm_bf16_tn(st, Mi, kb, Ni, B.Tbt, ln, B.Yb, ln, B.Zb, lm, nullptr, 0, B.bwork,
+                         B.bwork_bytes));
+    RRF_TRY(gemm_bf16_tn(st, Ni, kb, Mi, B.Tb, lm, B.Zb, lm, last ? nullptr : B.Yb, ln,
+                         last ? Y : nullptr, Ni, B.bwork, B.bwork_bytes));
+  }
+  return RRF_OK;
+}
+
 // Event slots of the device context.
 enum { kEvStart = 0, kEvV = 1, kEvU = 3, kEvVdone = 5, kEvUdone = 7, kEvS1 = 9, kEvSvd = 10 };
 
@@ -130,22 +173,22 @@ bool randutv_supported(int64_t m, int64_t n, int64_t b) {
   return panel_work_bytes(std::max(m, n), (int)std::min(b, n)) > 0;
 }
 
-size_t randutv_workspace(int64_t m, int64_t n, int64_t b) {
+size_t randutv_workspace(int64_t m, int64_t n, int64_t b, int precision) {
   Arena ar;
   ar.counting = true;
   Bufs B;
-  if (!plan(ar, m, n, b, &B)) return 0;
+  if (!plan(ar, m, n, b, precision, &B)) return 0;
   return ar.used;
 }
 
 int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                 int q, uint64_t seed, double* U, double* T, double* V, void* ws,
-                size_t ws_bytes, bool check_input, int* status_out) {
+                size_t ws_bytes, bool check_input, int precision, int* status_out) {
   Arena ar;
   ar.base = reinterpret_cast<char*>(ws);
   ar.cap = ws_bytes;
   Bufs B;
-  if (!plan(ar, m, n, b, &B) || ar.used > ws_bytes)
+  if (!plan(ar, m, n, b, precision, &B) || ar.used > ws_bytes)
     return set_error(RRF_E_NOMEM, "randutv: workspace too small");
   *status_out = 0;
   DeviceContext* ctx = nullptr;
@@ -181,13 +224,17 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
       // ---- critical stream: sketch and V_i
       if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvVdone + r], 0));
       RRF_TRY(gaussian(st, seed, (uint64_t)(i + 1), Mi, kb, B.G, Mi));
-      RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.G, Mi, 0.0, B.Y[r], Ni,
-                    B.split[0], SE));
-      for (int it = 0; it < q; ++it) {
-        RRF_TRY(dgemm(st, false, false, Mi, kb, Ni, 1.0, T22, ldt, B.Y[r], Ni, 0.0, B.Z, Mi,
+      if (precision == RRF_PREC_BF16_SKETCH) {
+        RRF_TRY(sketch_mixed(st, Mi, Ni, kb, q, T22, ldt, B, B.Y[r]));
+      } else {
+        RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.G, Mi, 0.0, B.Y[r], Ni,
                       B.split[0], SE));
-        RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.Z, Mi, 0.0, B.Y[r], Ni,
-                      B.split[0], SE));
+        for (int it = 0; it < q; ++it) {
+          RRF_TRY(dgemm(st, false, false, Mi, kb, Ni, 1.0, T22, ldt, B.Y[r], Ni, 0.0, B.Z, Mi,
+                        B.split[0], SE));
+          RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.Z, Mi, 0.0, B.Y[r], Ni,
+                        B.split[0], SE));
+        }
       }
       RRF_TRY(householder_panel(st, Ni, (int)kb, B.Y[r], Ni, B.Y[r], Ni, nullptr, 0, B.Tv, kb,
                                 B.tau, nullptr, 0, B.panel, B.panel_bytes, B.status));

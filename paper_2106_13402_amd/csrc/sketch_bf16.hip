@@ -1,0 +1,371 @@
+// Mixed-precision sketch of randUTV: bfloat16 inputs, FP32 accumulation.
+//
+// The sketch of Alg. 3, Y = (T22^T T22)^q T22^T G, only has to capture the
+// dominant right singular subspace of T22; the QR of Y and every update of
+// T, U and V stay in FP64. In the mixed mode
+//  * T22 is scaled by a power of two 2^-e (max|T22| 2^-e in [0.5, 1)) and
+//    rounded to bfloat16 twice, as Tb (M x N) and its transpose Tbt (N x M),
+//    so that both products of the power iteration read their operand along
+//    the inner dimension;
+//  * G is rounded as it is (standard normal values are in range);
+//  * every product is a "TN" GEMM C = A^T B with both operands contiguous
+//    along the inner dimension K, on the bfloat16 matrix cores
+//    (v_mfma_f32_16x16x32_bf16), FP32 accumulation, split over K with the
+//    partials summed in a fixed order;
+//  * between products each column of the FP32 result is scaled by its own
+//    power of two (max in [0.5, 1)) and rounded to bfloat16; positive column
+//    scalings commute with the products and leave the column space of Y
+//    unchanged, they only keep the values inside the binary32 range;
+//  * the last product is widened to FP64 exactly.
+// Rounding is to nearest, ties to even, directly from the source format.
+//
+// The products stream T22 in bfloat16 (2 bytes per element per product)
+// instead of FP64 (8 bytes, and FP64 matrix-core rates), so the sketch is
+// HBM-bound at b <= 256.
+#include <algorithm>
+#include <cfloat>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "trace.hpp"
+
+namespace rrf {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// --- rounding --------------------------------------------------------------
+
+// binary64 -> bfloat16 bits, round to nearest even, directly (no binary32
+// step). The leading bit's exponent is clamped at -126, below which the
+// quantum is 2^-133 (gradual underflow). Inputs here are pre-scaled to
+// magnitudes below 1, so there is no overflow.
+__device__ inline uint16_t bf16_from_f64(double x) {
+  if (x == 0.0) return (uint16_t)(__double_as_longlong(x) >> 48);  // keeps the sign
+  int lead = ilogb(x);
+  if (lead < -126) lead = -126;
+  const double q = rint(scalbn(x, 7 - lead));  // integer multiple of the quantum
+  const float r = (float)scalbn(q, lead - 7);  // exact: at most 8 significant bits
+  return (uint16_t)(__float_as_uint(r) >> 16);
+}
+
+// binary32 -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ inline uint16_t bf16_from_f32(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// 2^-e with m 2^-e in [0.5, 1) (frexp convention); 1 for m = 0.
+__device__ inline double pow2_scale(double m) {
+  if (!(m > 0.0)) return 1.0;
+  int e;
+  frexp(m, &e);
+  return ldexp(1.0, -e);
+}
+
+// --- max|X| ----------------------------------------------------------------
+
+// word = max over X of |x| as binary64 bits (non-negative doubles order like
+// their bit patterns). The word must be zero at launch.
+__global__ __launch_bounds__(256) void maxabs_kernel(int64_t rows, int64_t cols,
+                                                     const double* __restrict__ X, int64_t ld,
+                                                     unsigned long long* word) {
+  __shared__ double red[256];
+  double m = 0.0;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < rows)
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) m = fmax(m, fabs(X[i + j * ld]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] > 0.0)
+    atomicMax(word, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+// --- binary64 -> bfloat16, optionally scaled and transposed ----------------
+
+// out (rows x cols, ld ldo) = bf16(X * s), outT (cols x rows, ld ldot) its
+// transpose when non-null; s = pow2_scale(max) from `word` when non-null,
+// else 1. Rows [rows, ldo) of out and [cols, ldot) of outT are zero-filled so
+// that 16-byte loads along the inner dimension never need a ragged edge.
+// 64 x 64 tiles, transposed through LDS.
+__global__ __launch_bounds__(256) void to_bf16_kernel(int64_t rows, int64_t cols,
+                                                      const double* __restrict__ X, int64_t ld,
+                                                      const unsigned long long* word,
+                                                      uint16_t* __restrict__ out, int64_t ldo,
+                                                      uint16_t* __restrict__ outT, int64_t ldot) {
+  __shared__ uint16_t tile[64][65];
+  const double s = word ? pow2_scale(__longlong_as_double((long long)*word)) : 1.0;
+  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t r = r0 + tx, c = c0 + cc;
+    uint16_t v = 0;
+    if (r < rows && c < cols) v = bf16_from_f64(X[r + c * ld] * s);
+    if (r < ldo && c < cols) out[r + c * ldo] = v;
+    tile[cc][tx] = v;
+  }
+  if (!outT) return;
+  __syncthreads();
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t c = c0 + tx, r = r0 + rr;  // outT(c, r) = X(r, c)
+    if (c < ldot && r < rows) outT[c + r * ldot] = (c < cols) ? tile[tx][rr] : (uint16_t)0;
+  }
+}
+
+// --- C = A^T B on the bfloat16 matrix cores --------------------------------
+
+constexpr int kBM = 128, kBN = 128, kBK = 64;
+constexpr int kLK = kBK + 8;  // LDS row length in bfloat16 (16-byte pad)
+constexpr int kThreads = 256;
+
+struct GemmBf16Args {
+  int64_t M, N, K;
+  const uint16_t* A;  // K x M, ld lda (multiple of 8), rows [K, lda) zero
+  int64_t lda;
+  const uint16_t* B;  // K x N, ld ldb (multiple of 8), rows [K, ldb) zero
+  int64_t ldb;
+  float* P;           // partials: P[z * M * N + m + n * M]
+  int64_t kchunk;     // multiple of kBK
+  int tiles_m;
+};
+
+// Loads the 128 x 64 slice (rows mn0.., inner k0..) of a K-contiguous
+// operand as 16-byte chunks: 1024 chunks, four per thread.
+__device__ inline void load_slice(uint4 (&reg)[4], const uint16_t* X, int64_t ld, int64_t mn0,
+                                  int64_t mn_end, int64_t k0, int64_t k_end, int tid) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = tid + kThreads * i;
+    const int row = c >> 3, part = c & 7;
+    const int64_t mn = mn0 + row, k = k0 + part * 8;
+    if (mn < mn_end && k < k_end)
+      reg[i] = *reinterpret_cast<const uint4*>(X + k + mn * ld);
+    else
+      reg[i] = make_uint4(0, 0, 0, 0);
+  }
+}
+
+__device__ inline void store_slice(uint16_t* lds, const uint4 (&reg)[4], int tid) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = tid + kThreads * i;
+    const int row = c >> 3, part = c & 7;
+    *reinterpret_cast<uint4*>(lds + row * kLK + part * 8) = reg[i];
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void gemm_bf16_tn_kernel(GemmBf16Args g) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2][(kBM + kBN) * kLK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 64 x 64
+  const int tm = blockIdx.x % g.tiles_m, tn = blockIdx.x / g.tiles_m;
+  const int64_t m0 = (int64_t)tm * kBM, n0 = (int64_t)tn * kBN;
+  const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t kend = std::min(kbeg + g.kchunk, g.K);
+  // 16-byte chunks exist up to the zero-padded end of the inner dimension
+  const int64_t kpad = (g.K + 7) & ~(int64_t)7;
+  const int64_t kload_end = std::min(kbeg + g.kchunk, kpad);
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  if (kbeg < kend) {
+    uint4 ra[4], rb[4];
+    load_slice(ra, g.A, g.lda, m0, g.M, kbeg, kload_end, tid);
+    load_slice(rb, g.B, g.ldb, n0, g.N, kbeg, kload_end, tid);
+    store_slice(lds[0], ra, tid);
+    store_slice(lds[0] + kBM * kLK, rb, tid);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+      const bool more = k0 + kBK < kend;
+      if (more) {
+        load_slice(ra, g.A, g.lda, m0, g.M, k0 + kBK, kload_end, tid);
+        load_slice(rb, g.B, g.ldb, n0, g.N, k0 + kBK, kload_end, tid);
+      }
+      const uint16_t* la = lds[buf];
+      const uint16_t* lb = lds[buf] + kBM * kLK;
+#pragma unroll
+      for (int ks = 0; ks < kBK; ks += 32) {
+        bf16x8 af[4], bfr[4];
+        // lane l: row l % 16 of the 16 x 32 operand, inner 8 (l / 16) .. + 7
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          af[i] = *reinterpret_cast<const bf16x8*>(
+              la + (wm * 64 + i * 16 + (lane & 15)) * kLK + ks + 8 * (lane >> 4));
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          bfr[j] = *reinterpret_cast<const bf16x8*>(
+              lb + (wn * 64 + j * 16 + (lane & 15)) * kLK + ks + 8 * (lane >> 4));
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) {
+        store_slice(lds[buf ^ 1], ra, tid);
+        store_slice(lds[buf ^ 1] + kBM * kLK, rb, tid);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  // lane l, register r holds D(row 4 (l / 16) + r, column l % 16) of a sub-tile
+  float* P = g.P + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t n = n0 + wn * 64 + j * 16 + (lane & 15);
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        if (m < g.M) P[m + n * g.M] = acc[i][j][r];
+      }
+    }
+  }
+}
+
+// --- sum of the split partials, then per-column bfloat16 or FP64 ----------
+
+// One workgroup per column n: s = sum_z P_z(:, n) in split order, kept in
+// LDS when it fits (else in `col`, a global column buffer), then either
+// out16(:, n) = bf16(s pow2_scale(max|s|)) with rows [M, ld16) zeroed, or
+// out64(:, n) = s widened.
+constexpr int kColThreads = 1024;
+constexpr int64_t kColLds = 32768;  // floats of the column kept in LDS
+
+__global__ __launch_bounds__(kColThreads) void reduce_columns_kernel(
+    int64_t M, int64_t N, int S, const float* __restrict__ P, uint16_t* __restrict__ out16,
+    int64_t ld16, double* __restrict__ out64, int64_t ld64, float* __restrict__ col) {
+  extern __shared__ float sc[];
+  __shared__ float red[kColThreads];
+  const int64_t n = blockIdx.x;
+  const int tid = threadIdx.x;
+  const bool in_lds = M <= kColLds;
+  float* c = in_lds ? sc : col + n * M;
+  float m = 0.f;
+  for (int64_t i = tid; i < M; i += kColThreads) {
+    float s = 0.f;
+    for (int z = 0; z < S; ++z) s += P[(int64_t)z * M * N + i + n * M];
+    c[i] = s;
+    m = fmaxf(m, fabsf(s));
+  }
+  if (out64) {
+    for (int64_t i = tid; i < M; i += kColThreads) out64[i + n * ld64] = (double)c[i];
+    return;
+  }
+  red[tid] = m;
+  __syncthreads();
+  for (int w = kColThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const float s = (float)pow2_scale((double)red[0]);
+  for (int64_t i = tid; i < ld16; i += kColThreads)
+    out16[i + n * ld16] = (i < M) ? bf16_from_f32(c[i] * s) : (uint16_t)0;
+}
+
+bool g_col_attr = false;
+
+}  // namespace
+
+int64_t bf16_ld(int64_t rows) { return (rows + 7) & ~(int64_t)7; }
+
+int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+           unsigned long long* word) {
+  RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(word), 2, 0u));
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 1024));
+  int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
+  hipLaunchKernelGGL(maxabs_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int to_bf16(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+            const unsigned long long* word, uint16_t* out, int64_t ldo, uint16_t* outT,
+            int64_t ldot) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  const int64_t R = std::max(rows, ldo), C = outT ? std::max(cols, ldot) : cols;
+  dim3 grid((unsigned)ceil_div(R, 64), (unsigned)ceil_div(C, 64));
+  int tok = trace_begin(st, kTrElementwise, 0.0, (8.0 + (outT ? 4.0 : 2.0)) * rows * cols);
+  hipLaunchKernelGGL(to_bf16_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word, out, ldo,
+                     outT, ldot);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+size_t gemm_bf16_work_bytes(int64_t M, int64_t N) {
+  return (size_t)16 * M * N * sizeof(float) + (size_t)M * N * sizeof(float) + 256;
+}
+
+int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t* A,
+                 int64_t lda, const uint16_t* B, int64_t ldb, uint16_t* out16, int64_t ld16,
+                 double* out64, int64_t ld64, void* work, size_t work_bytes) {
+  if (M <= 0 || N <= 0) return RRF_OK;
+  if ((lda & 7) || (ldb & 7) || (reinterpret_cast<uintptr_t>(A) & 15) ||
+      (reinterpret_cast<uintptr_t>(B) & 15))
+    return set_error(RRF_E_INTERNAL, "bf16 gemm: operands must be 16-byte aligned");
+  if (work_bytes < gemm_bf16_work_bytes(M, N) || work == nullptr)
+    return set_error(RRF_E_NOMEM, "bf16 gemm: workspace too small");
+  const int64_t tiles_m = ceil_div(M, kBM), tiles = tiles_m * ceil_div(N, kBN);
+  // split K as for the FP64 GEMM: fill the 512 resident slots, at least 256
+  // of K per split, at most 16 splits
+  int splits = 1;
+  if (tiles < 512 && K >= 512) {
+    double best = 1.0;
+    for (int64_t s = 2; s <= 16 && K / s >= 256; ++s) {
+      const double t = (double)ceil_div(tiles * s, 512) / (double)s;
+      if (t < best - 1e-12) {
+        best = t;
+        splits = (int)s;
+      }
+    }
+  }
+  GemmBf16Args g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
+  g.kchunk = round_up(ceil_div(std::max<int64_t>(K, 1), splits), kBK);
+  splits = (int)std::max<int64_t>(1, ceil_div(K, g.kchunk));
+  g.tiles_m = (int)tiles_m;
+  float* P = reinterpret_cast<float*>(work);
+  float* col = P + (size_t)16 * M * N;
+  g.P = P;
+  int tok = trace_begin(st, kTrGemmBf16, 2.0 * M * N * K, 2.0 * ((double)M * K + (double)K * N) +
+                                                             4.0 * splits * M * N);
+  hipLaunchKernelGGL(gemm_bf16_tn_kernel, dim3((unsigned)tiles, 1, (unsigned)splits),
+                     dim3(kThreads), 0, st, g);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  if (!g_col_attr) {
+    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)reduce_columns_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(kColLds * sizeof(float))));
+    g_col_attr = true;
+  }
+  const size_t lds = M <= kColLds ? (size_t)M * sizeof(float) : 0;
+  tok = trace_begin(st, kTrSplitReduce, (double)splits * M * N,
+                    4.0 * splits * M * N + (out64 ? 8.0 : 2.0) * M * N);
+  hipLaunchKernelGGL(reduce_columns_kernel, dim3((unsigned)N), dim3(kColThreads), lds, st, M, N,
+                     splits, P, out16, ld16, out64, ld64, col);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+}  // namespace rrf

@@ -34,7 +34,7 @@ const char* kNames[kTraceClasses] = {
     "dgemm_mfma_128x128_TT", "dgemm_mfma_64x64_NN",   "dgemm_mfma_64x64_TN",
     "dgemm_mfma_64x64_NT",   "dgemm_mfma_64x64_TT",   "splitk_reduce",
     "householder_panel",     "jacobi_svd",            "gaussian",
-    "elementwise",
+    "elementwise",           "gemm_bf16_mfma_TN",
 };
 
 hipEvent_t get_event() {

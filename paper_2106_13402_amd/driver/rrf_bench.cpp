@@ -3,7 +3,7 @@
 // or torch runtime in the process (rocprofv3 --kernel-trace / --pmc).
 //
 //   rrf_bench [--alg randutv|powerurv] [--m M] [--n N] [--b B] [--q Q] [--reps R] [--trace]
-//             [--copy-bytes BYTES]
+//             [--copy-bytes BYTES] [--precision 0|1]
 //
 // --copy-bytes first runs one device-to-device copy of BYTES bytes: a plain
 // copy kernel of known traffic, against which the HBM byte counters of a
@@ -25,7 +25,7 @@ static int fail(const char* what, int st) {
 
 int main(int argc, char** argv) {
   std::string alg = "randutv";
-  long m = 0, n = 16384, b = 128, q = 2, reps = 1, copy_bytes = 0;
+  long m = 0, n = 16384, b = 128, q = 2, reps = 1, copy_bytes = 0, precision = RRF_PREC_FP64;
   bool trace = false;
   for (int i = 1; i < argc; ++i) {
     std::string a = argv[i];
@@ -38,6 +38,7 @@ int main(int argc, char** argv) {
     else if (a == "--reps") next(reps);
     else if (a == "--trace") trace = true;
     else if (a == "--copy-bytes") next(copy_bytes);
+    else if (a == "--precision") next(precision);
     else { fprintf(stderr, "unknown argument %s\n", a.c_str()); return 2; }
   }
   if (m < n) m = n;
@@ -45,7 +46,7 @@ int main(int argc, char** argv) {
   double *A = nullptr, *U = nullptr, *T = nullptr, *V = nullptr;
   void* ws = nullptr;
   const int code = alg == "powerurv" ? RRF_ALG_POWERURV : RRF_ALG_RANDUTV;
-  const size_t wsb = rrf_workspace_size(code, m, n, b, (int)q, RRF_PREC_FP64);
+  const size_t wsb = rrf_workspace_size(code, m, n, b, (int)q, (int)precision);
   if (wsb == 0) return fail("rrf_workspace_size", -1);
   if (hipMalloc(&A, bytes) != hipSuccess || hipMalloc(&U, (size_t)m * m * 8) != hipSuccess ||
       hipMalloc(&T, bytes) != hipSuccess || hipMalloc(&V, (size_t)n * n * 8) != hipSuccess ||
@@ -68,6 +69,7 @@ int main(int argc, char** argv) {
   rrf_opts_init(&o);
   o.workspace = ws;
   o.workspace_bytes = wsb;
+  o.precision = (int)precision;
   if (trace) rrf_trace_enable(1);
   double best = 1e30, total = 0.0;
   for (long r = 0; r < reps; ++r) {
@@ -78,8 +80,8 @@ int main(int argc, char** argv) {
     double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     best = s < best ? s : best;
     total += s;
-    printf("rrf_bench: %s m=%ld n=%ld b=%ld q=%ld rep %ld: %.4f s\n", alg.c_str(), m, n, b, q, r,
-           s);
+    printf("rrf_bench: %s m=%ld n=%ld b=%ld q=%ld precision=%ld rep %ld: %.4f s\n", alg.c_str(), m,
+           n, b, q, precision, r, s);
     fflush(stdout);
   }
   if (trace) {

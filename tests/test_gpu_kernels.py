@@ -206,3 +206,76 @@ def test_block_svd_graded_and_degenerate(gpu):
     Us, d, Vs = (_host(x) for x in block_svd(_to_dev(B, gpu)))
     assert np.all(d[3:] < 1e-13 * d[0])
     assert np.linalg.norm(Us.T @ Us - np.eye(24), 2) < 1e-13
+
+
+# ------------------------------------------------- bfloat16 sketch building blocks
+def _bf16_bits_to_f64(t16):
+    u = t16.detach().cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def _f64_to_bf16_bits(x):
+    """Bit patterns of bfloat16-exact binary64 values."""
+    return (np.asarray(x, np.float64).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+
+
+@pytest.mark.parametrize("scaled", [False, True])
+def test_to_bf16_bit_exact(gpu, scaled):
+    from oracle.bf16 import bf16_round, pow2_scale
+    from paper_2106_13402_amd import to_bf16
+    rng = np.random.default_rng(11)
+    M, N = 1000, 300
+    X = rng.standard_normal((M, N)) * 2.0 ** rng.integers(-60, 40, (M, N))
+    X[0, :5] = [0.0, -0.0, 3e-41, -2.2e-39, 1.0 + 2.0 ** -8 + 2.0 ** -30]  # zeros, underflow, direct rounding
+    X[1:17, 7] = (np.arange(256, 272) + 0.5) * 2.0 ** -9                     # exact ties
+    big = np.zeros((M + 9, N + 3))
+    big[4:4 + M, 2:2 + N] = X
+    dX = _to_dev(big, gpu)[4:4 + M, 2:2 + N]                                # strided view
+    out, outT = to_bf16(dX, scaled=scaled, transpose=True)
+    s = pow2_scale(X) if scaled else 1.0
+    want = _f64_to_bf16_bits(bf16_round(X * s))
+    got = out.detach().cpu().numpy().astype(np.uint16)
+    np.testing.assert_array_equal(got[:M], want)
+    assert np.all(got[M:] == 0)                                              # zero padding
+    gotT = outT.detach().cpu().numpy().astype(np.uint16)
+    np.testing.assert_array_equal(gotT[:N], want.T)
+    assert np.all(gotT[N:] == 0)
+
+
+BF16_GEMM_CASES = [(1, 1, 1), (130, 7, 1000), (300, 200, 77), (1000, 128, 16384),
+                   (4097, 128, 3000), (128, 128, 0)]
+
+
+@pytest.mark.parametrize("M,N,K", BF16_GEMM_CASES)
+def test_gemm_bf16_tn_exact_products(gpu, M, N, K):
+    from oracle.bf16 import bf16_round, fp32_gemm_bound, gemm_tn_reference, pow2_scale
+    from paper_2106_13402_amd import gemm_bf16_tn, to_bf16
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((max(K, 1), M))[:K]
+    B = rng.standard_normal((max(K, 1), N))[:K]
+    if K == 0:
+        import torch
+        A16 = torch.zeros((M, 8), dtype=torch.int16, device=gpu).t()  # 8 x M, column-major
+        B16 = torch.zeros((N, 8), dtype=torch.int16, device=gpu).t()
+    else:
+        A16, _ = to_bf16(_to_dev(A, gpu))
+        B16, _ = to_bf16(_to_dev(B, gpu))
+    Ar, Br = bf16_round(A), bf16_round(B)
+    exact = gemm_tn_reference(Ar, Br)
+    bound = fp32_gemm_bound(Ar, Br)
+    C = _host(gemm_bf16_tn(A16, K, B16, out="f64"))
+    assert np.all(np.abs(C - exact) <= bound), np.max(np.abs(C - exact) - bound)
+    # column-rescaled bfloat16 output: each column's power of two puts its
+    # max in [0.5, 1); values within one bfloat16 unit of the exact scaled ones
+    C16 = gemm_bf16_tn(A16, K, B16, out="bf16")
+    dec = _bf16_bits_to_f64(C16)
+    assert np.all(dec[M:] == 0)
+    for j in range(N):
+        s = pow2_scale(exact[:, j])
+        col = dec[:M, j]
+        if K == 0:
+            assert np.all(col == 0)
+            continue
+        ref = exact[:, j] * s
+        assert 0.5 <= np.max(np.abs(col)) <= 1.0
+        np.testing.assert_array_less(np.abs(col - ref), 2.0 ** -7 * np.abs(ref) + bound[:, j] * s + 1e-300)
