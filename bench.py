@@ -1,16 +1,18 @@
 #!/usr/bin/env python3
-"""Time-to-factor of randUTV (Alg. 3) on one MI355X, FP64 path.
+"""Time-to-factor of randUTV (Alg. 3) on one MI355X: FP64, and the mixed sketch.
 
 Workload (default): A = Q1 diag(s) Q2^T, n = 16384, s_j = exp(-j/800), Q1/Q2
 Haar (synthetic, seeded, generated on the GPU), b = 128, q = 2, sketch seed 1,
 U and V accumulated. One "step" is one complete factorization A = U T V^T with
 A, U, T, V and the workspace resident in HBM before the timed region starts.
 
-Printed: ONE JSON line with the time per factorization (`value`, seconds,
-lower is better), the roofline entry of the dominant kernel measured live
-with HIP events on the library's stream, the accuracy of the result against
-the known spectrum, and the FP64 CPU oracle timed on a bounded sample of the
-same workload.
+Printed: ONE JSON line with the time per FP64 factorization (`value`,
+seconds, lower is better), the roofline entry of the dominant kernel measured
+live with HIP events on the library's stream, the accuracy of the result
+against the known spectrum, the same factorization with the bfloat16 sketch
+(RRF_PREC_BF16_SKETCH) timed the same way and held to e_k <= max(1.5
+sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--n N] [--b B] [--q Q]
 """
@@ -96,16 +98,17 @@ def accuracy(A, U, T, V, s, kgrid):
 
     rec = _power_norm(lambda x: A @ x - U @ (T @ (V.t() @ x)),
                       lambda y: A.t() @ y - V @ (T.t() @ (U.t() @ y)), n, dev) / nA
-    ratios = []
+    ratios, eks = [], []
     for k in kgrid:
         Tk = T[k:, k:]
         ek = _power_norm(lambda x: Tk @ x, lambda y: Tk.t() @ y, n - k, dev, iters=30)
+        eks.append(ek)
         ratios.append(ek / float(s[k]))
     worst = max(range(len(kgrid)), key=lambda i: ratios[i])
     return {
         "orth_U": orth(U), "orth_V": orth(V), "recon": rec,
         "ek_over_sigma_max": ratios[worst], "ek_over_sigma_argmax_k": int(kgrid[worst]),
-        "ek_over_sigma_min": min(ratios), "k_grid": [int(k) for k in kgrid],
+        "ek_over_sigma_min": min(ratios), "k_grid": [int(k) for k in kgrid], "e_k": eks,
         "norm_estimator": "power iteration (30-40 steps)",
     }
 
@@ -165,6 +168,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -188,14 +192,15 @@ def main() -> int:
     V = rrf.empty_colmajor(n, n, dev)
     torch.cuda.synchronize()
 
-    def factor():
+    def factor(precision="fp64"):
         # same entry point as rrf.randutv, with preallocated outputs
         import ctypes as C
         from paper_2106_13402_amd import _lib
-        nbytes = rrf.workspace_size("randutv", n, n, b, q)
+        nbytes = rrf.workspace_size("randutv", n, n, b, q, precision)
         ws = rrf._workspace(dev, nbytes)
         opts = _lib.rrf_opts()
         rrf.lib.rrf_opts_init(C.byref(opts))
+        opts.precision = rrf.PRECISIONS[precision]
         opts.stream = torch.cuda.current_stream(dev).cuda_stream
         opts.workspace = ws.data_ptr()
         opts.workspace_bytes = ws.numel()
@@ -262,10 +267,37 @@ def main() -> int:
         "model_tflops": model_flops / per / 1e12,
         "kernels": breakdown,
     }
+    kgrid = [k for k in (0, 64, 127, 128, 129, 256, 1000, 2000, 4000, 8000, 12000) if k < n]
     if not args.no_accuracy:
-        kgrid = [k for k in (0, 64, 127, 128, 129, 256, 1000, 2000, 4000, 8000, 12000) if k < n]
         out["accuracy"] = accuracy(A, U, T, V, s, kgrid)
         log(f"accuracy: {out['accuracy']}")
+    if not args.no_mixed:
+        # the same factorization with the bfloat16 sketch, timed the same way
+        for w in range(args.warmup):
+            factor("bf16_sketch")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            factor("bf16_sketch")
+        torch.cuda.synchronize()
+        per_mixed = (time.perf_counter() - t0) / args.steps
+        log(f"mixed sketch: {per_mixed:.3f} s per factorization")
+        mixed = {"precision": "bf16_sketch", "value": per_mixed, "unit": "s",
+                 "ms_per_step": per_mixed * 1e3, "speedup_vs_fp64": per / per_mixed,
+                 "model_tflops": model_flops / per_mixed / 1e12}
+        if not args.no_accuracy:
+            acc = accuracy(A, U, T, V, s, kgrid)
+            ref = out["accuracy"]["e_k"]
+            # gate on the k with sigma_{k+1} well above the reconstruction error
+            ks = [i for i, k in enumerate(kgrid) if s[k] >= 100 * acc["recon"] * s[0]]
+            ratio = [acc["e_k"][i] / ref[i] for i in ks]
+            mixed["accuracy"] = acc
+            mixed["ek_over_fp64_max"] = max(ratio)
+            mixed["ek_gate"] = "e_k <= max(1.5 sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid"
+            mixed["ek_gate_pass"] = all(acc["e_k"][i] <= max(1.5 * s[kgrid[i]], 1.1 * ref[i])
+                                        for i in ks)
+            log(f"mixed accuracy: {acc}")
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         A_host = A.cpu().numpy()

@@ -69,23 +69,33 @@ __device__ inline double pow2_scale(double m) {
 // --- max|X| ----------------------------------------------------------------
 
 // word = max over X of |x| as binary64 bits (non-negative doubles order like
-// their bit patterns). The word must be zero at launch.
+// their bit patterns). The word must be zero at launch. Blocks take 256 rows
+// and stride over the columns, so one atomic per block (a few thousand per
+// matrix) reaches the word.
 __global__ __launch_bounds__(256) void maxabs_kernel(int64_t rows, int64_t cols,
                                                      const double* __restrict__ X, int64_t ld,
                                                      unsigned long long* word) {
-  __shared__ double red[256];
-  double m = 0.0;
+  __shared__ double red[4];
+  double m0 = 0.0, m1 = 0.0;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < rows)
-    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) m = fmax(m, fabs(X[i + j * ld]));
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
+  if (i < rows) {
+    int64_t j = blockIdx.y;
+    const int64_t step = gridDim.y;
+    for (; j + step < cols; j += 2 * step) {
+      m0 = fmax(m0, fabs(X[i + j * ld]));
+      m1 = fmax(m1, fabs(X[i + (j + step) * ld]));
+    }
+    if (j < cols) m0 = fmax(m0, fabs(X[i + j * ld]));
   }
-  if (threadIdx.x == 0 && red[0] > 0.0)
-    atomicMax(word, (unsigned long long)__double_as_longlong(red[0]));
+  double m = fmax(m0, m1);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (m > 0.0) atomicMax(word, (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // --- binary64 -> bfloat16, optionally scaled and transposed ----------------
@@ -288,7 +298,7 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
            unsigned long long* word) {
   RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(word), 2, 0u));
   if (rows <= 0 || cols <= 0) return RRF_OK;
-  dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 1024));
+  dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 32));
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
   hipLaunchKernelGGL(maxabs_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word);
   trace_end(st, tok);
