@@ -2,8 +2,9 @@
 //
 // Per step i (0-based here, c0 = i b, J2 = [c0, c2), I2 = [c0, r2)):
 //   1. G_i = Gaussian(seed, stream i+1), (m-c0) x b, generated in HBM;
-//   2. Y = T22^T G_i, then q times Z = T22 Y, Y = T22^T Z  (MFMA GEMMs);
-//   3. [W_v, Tf_v] = Householder QR of Y (panel kernel; W_v overwrites Y);
+//   2. Y = T22^T G_i, then q times Z = T22 Y, Y = T22^T Z  (MFMA GEMMs, or the
+//      bfloat16 sketch of sketch_bf16.hip in the mixed mode);
+//   3. [W_v, Tf_v] = Householder QR of Y (panel kernel);
 //   4. X = T(:, J2uJ3) W_v and T(:, J2) -= X (W_v Tf_v^T)(J2, :)^T: only the
 //      columns J2 of T V_i are formed here, for the next panel;
 //   5. [W_u, Tf_u, R] = Householder QR of T(I2uI3, J2); that panel of T is
@@ -15,31 +16,34 @@
 //      update, and then
 //        T(:, J3) -= [X, W_u Tf_u^T] [(W_v Tf_v^T)(J3, :), Z^T]^T,
 //      a single GEMM with inner dimension 2b (W_u Tf_u^T is zero on rows I1);
-//      V(:, J2uJ3) V_i and U(:, I2uI3) U_i as two GEMMs each;
 //   7. [Us, D, Vs] = SVD(R) (one-workgroup Jacobi), then U(:,I2) Us,
 //      V(:,J2) Vs, T(I2,J2) = D, T(I2,J3) = Us^T T(I2,J3), T(I1,J2) Vs.
 // The last step (J3 empty) takes the SVD of the trailing block, through a
 // Householder QR first when the block is tall (Sec. 4.2, tall-thin SVD).
 //
-// Every compact-WY application uses W Tf W^T = W (W Tf^T)^T: the small
-// triangular factor is folded into one operand once per step.
+// U and V. Alg. 3 multiplies U by U_i and V by V_i at every step. Nothing in
+// the loop reads U or V, so every step's reflectors (W_u, Tf_u, W_v, Tf_v)
+// are kept and the products U = U_1 ... U_s and V = V_1 ... V_s are formed
+// after the loop, backward from the identity as LAPACK's dorgqr forms Q:
+// applied last-first, U_i only touches the trailing (m - c0) x (m - c0)
+// block, which costs (4/3) m^3 instead of the 2 m^2 n of the forward
+// products. Consecutive steps are merged into one compact-WY factor
+// (groups of kGroup steps: T = [T1, -T1 W1^T W2 T2; 0, T2] recursively), so
+// each update is a GEMM with inner dimension kGroup b. U and V are formed on
+// two streams while the small SVDs run, then rotated by Us and Vs.
 //
 // Schedule. The data dependences of a step, not the order in which Alg. 3
 // lists its statements, decide what may overlap:
-//  * the caller's stream carries the critical path -- generator, sketch,
-//    both panels and both updates of T;
-//  * a side stream accumulates V and U: V(:, J2uJ3) V_i needs only W_v and
-//    U(:, I2uI3) U_i only W_u, and nothing on the critical path reads U or V;
+//  * the caller's stream carries the loop: generator, sketch, both panels
+//    and the updates of T, with the whole GPU to itself;
 //  * no later step depends on a block's SVD. After step i no step touches
 //    columns J2 of T, U or V, and rows I2 of T are only multiplied from the
 //    right, which commutes with the left rotation by Us^T. So every R is kept
 //    and all the small SVDs run as one batched launch (one workgroup per
-//    block) after the loop, followed by T(I2,J2) = D, T(I1,J2) Vs, U(:,I2) Us,
-//    V(:,J2) Vs and T(I2,J3) <- Us^T T(I2,J3) for every block.
-// W_v, W_u, [X, W_u Tf_u^T] and [W_v Tf_v^T, Z^T] live in two-deep rings, so
-// the critical path reuses a slot only after the side stream finished with
-// it two steps earlier.
+//    block) after the loop, followed by T(I2,J2) = D, T(I1,J2) Vs and
+//    T(I2,J3) <- Us^T T(I2,J3) for every block.
 #include <algorithm>
+#include <vector>
 
 #include "common.hpp"
 #include "context.hpp"
@@ -50,27 +54,41 @@ namespace rrf {
 
 namespace {
 
+constexpr int kGroup = 4;  // steps merged into one compact-WY factor for U and V
+
+// Scratch of one backward accumulation (one per stream).
+struct Back {
+  double* TG = nullptr;  // gk x gk merged triangular factor
+  double* Sx = nullptr;  // gk x k
+  double* Sy = nullptr;  // gk x k
+  double* Z = nullptr;   // gk x max(m, n)
+  double* Z2 = nullptr;  // gk x max(m, n)
+  double* tmp = nullptr; // max(m, n) x k  (rotation by Us / Vs)
+  double* split = nullptr;
+};
+
 struct Bufs {
   int* status = nullptr;
   double* G = nullptr;      // m x b
   double* Z = nullptr;      // m x b
-  double* Y[2] = {};        // n x b  sketch, then W_v
-  double* Wu[2] = {};       // m x b
-  double* XW[2] = {};       // m x 2b [X, W_u Tf_u^T] (ld m; zero rows I1 on the right)
-  double* WZ[2] = {};       // n x 2b [W_v Tf_v^T, Z^T] (ld n; Z^T on rows J3)
+  double* Y = nullptr;      // n x b  sketch
+  double* XW = nullptr;     // m x 2b [X, W_u Tf_u^T] (ld m; zero rows I1 on the right)
+  double* WZ = nullptr;     // n x 2b [W_v Tf_v^T, Z^T] (ld n; Z^T on rows J3)
   double* S = nullptr;      // b x b  X(I2uI3, :)^T W_u
-  double* X0 = nullptr;     // max(m,n) x b   (critical stream, after the loop)
-  double* X1 = nullptr;     // max(m,n) x b   (side stream)
-  double* Zl = nullptr;     // b x n          (critical stream, after the loop)
-  double* Tv = nullptr;     // b x b
-  double* Tu = nullptr;     // b x b
+  double* X0 = nullptr;     // max(m,n) x b   (after the loop)
+  double* Zl = nullptr;     // b x n          (after the loop)
+  double* WU = nullptr;     // m x n  every step's W_u (block i at rows/cols c0), zero elsewhere
+  double* WV = nullptr;     // n x n  every step's W_v
+  double* TU = nullptr;     // s x (b x b)  Tf_u per step (ld b)
+  double* TV = nullptr;     // s x (b x b)  Tf_v per step
   double* tau = nullptr;    // b
   double* R = nullptr;      // s x (b x b)
   double* Us = nullptr;     // s x (b x b)
   double* Vs = nullptr;     // s x (b x b)
   double* d = nullptr;      // s x b
-  double* split[2] = {};
+  double* split = nullptr;
   size_t split_elems = 0;
+  Back back[2];
   void* panel = nullptr;
   size_t panel_bytes = 0;
   void* svd = nullptr;
@@ -90,28 +108,37 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B) {
   const int64_t mx = std::max(m, n);
   const int64_t kb = std::min(b, n);
   const int64_t s = ceil_div(n, b);
+  const int64_t gk = kGroup * kb;
   B->status = ar.take<int>(64);
   B->G = ar.take<double>((size_t)m * kb);
   B->Z = ar.take<double>((size_t)m * kb);
-  for (int r = 0; r < 2; ++r) {
-    B->Y[r] = ar.take<double>((size_t)n * kb);
-    B->Wu[r] = ar.take<double>((size_t)m * kb);
-    B->XW[r] = ar.take<double>((size_t)m * 2 * kb);
-    B->WZ[r] = ar.take<double>((size_t)n * 2 * kb);
-  }
+  B->Y = ar.take<double>((size_t)n * kb);
+  B->XW = ar.take<double>((size_t)m * 2 * kb);
+  B->WZ = ar.take<double>((size_t)n * 2 * kb);
   B->S = ar.take<double>((size_t)kb * kb);
   B->X0 = ar.take<double>((size_t)mx * kb);
-  B->X1 = ar.take<double>((size_t)mx * kb);
   B->Zl = ar.take<double>((size_t)kb * n);
-  B->Tv = ar.take<double>((size_t)kb * kb);
-  B->Tu = ar.take<double>((size_t)kb * kb);
+  B->WU = ar.take<double>((size_t)m * n);
+  B->WV = ar.take<double>((size_t)n * n);
+  B->TU = ar.take<double>((size_t)s * kb * kb);
+  B->TV = ar.take<double>((size_t)s * kb * kb);
   B->tau = ar.take<double>((size_t)kb);
   B->R = ar.take<double>((size_t)s * kb * kb);
   B->Us = ar.take<double>((size_t)s * kb * kb);
   B->Vs = ar.take<double>((size_t)s * kb * kb);
   B->d = ar.take<double>((size_t)s * kb);
   B->split_elems = (size_t)8 * mx * kb;
-  for (int k = 0; k < 2; ++k) B->split[k] = ar.take<double>(B->split_elems);
+  B->split = ar.take<double>(B->split_elems);
+  for (int t = 0; t < 2; ++t) {
+    Back& k = B->back[t];
+    k.TG = ar.take<double>((size_t)gk * gk);
+    k.Sx = ar.take<double>((size_t)gk * kb);
+    k.Sy = ar.take<double>((size_t)gk * kb);
+    k.Z = ar.take<double>((size_t)gk * mx);
+    k.Z2 = ar.take<double>((size_t)gk * mx);
+    k.tmp = ar.take<double>((size_t)mx * kb);
+    k.split = ar.take<double>(B->split_elems);
+  }
   B->panel_bytes = panel_work_bytes(mx, (int)kb);
   if (B->panel_bytes == 0) return false;
   B->panel = ar.take<char>(B->panel_bytes);
@@ -139,6 +166,60 @@ int right_mult(hipStream_t st, int64_t rows, int64_t k, double* X, int64_t ldx, 
   return copy_matrix(st, rows, k, tmp, rows, X, ldx);
 }
 
+// Q (N x N, ld ldq) <- H_0 H_1 ... H_{s-1}, formed backward from the
+// identity. Step i's reflectors are the kbs[i] columns of Wall (N x *, ld
+// ldw) starting at row and column i*b (zero above), with triangular factor
+// Tall + i*bb*bb (ld bb); kbs[i] = 0 means none. Groups of up to kGroup
+// consecutive steps are merged into one compact-WY factor
+// T_G = [T_1, -T_1 (W_1^T W_2) T_2; 0, T_2] (recursively) and applied to the
+// trailing block Q(ca:, ca:) as three GEMMs.
+int accumulate_backward(hipStream_t st, int64_t N, double* Q, int64_t ldq, const double* Wall,
+                        int64_t ldw, const double* Tall, int64_t bb, int64_t b,
+                        const std::vector<int64_t>& kbs, const Back& k, size_t split_elems) {
+  RRF_TRY(set_identity(st, N, N, Q, ldq));
+  int64_t i1 = (int64_t)kbs.size();
+  while (i1 > 0) {
+    while (i1 > 0 && kbs[i1 - 1] == 0) --i1;
+    if (i1 == 0) break;
+    int64_t i0 = std::max<int64_t>(0, i1 - kGroup);
+    for (int64_t i = i1 - 1; i >= i0; --i)
+      if (kbs[i] == 0) { i0 = i + 1; break; }
+    const int64_t ca = i0 * b;
+    int64_t width = 0;
+    for (int64_t i = i0; i < i1; ++i) width += kbs[i];
+    const int64_t Nq = N - ca;
+    const double* WG = Wall + ca + ca * ldw;
+    RRF_TRY(fill_matrix(st, width, width, 0.0, k.TG, width));
+    int64_t p = 0;
+    for (int64_t i = i0; i < i1; ++i) {
+      const int64_t kbi = kbs[i];
+      const double* Ti = Tall + i * bb * bb;
+      const double* Wi = WG + p * ldw;  // rows ca.., zero above row ca + p
+      if (p > 0) {
+        // T_G(0:p, p:p+kbi) = -T_G(0:p, 0:p) (W_G(:, 0:p)^T W_i) T_i
+        RRF_TRY(dgemm(st, true, false, p, kbi, Nq, 1.0, WG, ldw, Wi, ldw, 0.0, k.Sx, p, k.split,
+                      split_elems));
+        RRF_TRY(dgemm(st, false, false, p, kbi, p, 1.0, k.TG, width, k.Sx, p, 0.0, k.Sy, p,
+                      nullptr, 0));
+        RRF_TRY(dgemm(st, false, false, p, kbi, kbi, -1.0, k.Sy, p, Ti, bb, 0.0,
+                      k.TG + p * width, width, nullptr, 0));
+      }
+      RRF_TRY(copy_matrix(st, kbi, kbi, Ti, bb, k.TG + p + p * width, width));
+      p += kbi;
+    }
+    // Q(ca:, ca:) <- (I - W_G T_G W_G^T) Q(ca:, ca:)
+    double* Qb = Q + ca + ca * ldq;
+    RRF_TRY(dgemm(st, true, false, width, Nq, Nq, 1.0, WG, ldw, Qb, ldq, 0.0, k.Z, width, k.split,
+                  split_elems));
+    RRF_TRY(dgemm(st, false, false, width, Nq, width, 1.0, k.TG, width, k.Z, width, 0.0, k.Z2,
+                  width, nullptr, 0));
+    RRF_TRY(dgemm(st, false, false, Nq, Nq, width, -1.0, WG, ldw, k.Z2, width, 1.0, Qb, ldq,
+                  nullptr, 0));
+    i1 = i0;
+  }
+  return RRF_OK;
+}
+
 // The sketch of the mixed mode into Y (Ni x kb, FP64): bfloat16 copies of
 // the scaled T22 and of G, products with FP32 accumulation, each
 // intermediate column renormalised by a power of two; the last product is
@@ -164,7 +245,7 @@ int sketch_mixed(hipStream_t st, int64_t Mi, int64_t Ni, int64_t kb, int q, cons
 }
 
 // Event slots of the device context.
-enum { kEvStart = 0, kEvV = 1, kEvU = 3, kEvVdone = 5, kEvUdone = 7, kEvS1 = 9, kEvSvd = 10 };
+enum { kEvLoop = 0, kEvSvd = 1, kEvU = 2, kEvV = 3 };
 
 }  // namespace
 
@@ -194,7 +275,6 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   DeviceContext* ctx = nullptr;
   RRF_TRY(device_context(&ctx));
   std::lock_guard<std::mutex> lk(ctx->mu);
-  hipStream_t s1 = ctx->side[0];
   hipEvent_t* ev = ctx->ev;
   const size_t SE = B.split_elems;
 
@@ -202,131 +282,104 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   if (check_input) RRF_TRY(check_finite(st, m, n, A, lda, B.status + 1));
   const int64_t ldt = m, ldu = m, ldv = n;
   if (T != A) RRF_TRY(copy_matrix(st, m, n, A, lda, T, ldt));
-  RRF_CHECK_HIP(hipEventRecord(ev[kEvStart], st));
-  RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvStart], 0));
-  if (U) RRF_TRY(set_identity(s1, m, m, U, ldu));
-  if (V) RRF_TRY(set_identity(s1, n, n, V, ldv));
+  // reflector stores: zero outside each step's block
+  if (U) RRF_TRY(fill_matrix(st, m, n, 0.0, B.WU, m));
+  if (V) RRF_TRY(fill_matrix(st, n, n, 0.0, B.WV, n));
 
   const int64_t s = ceil_div(n, b);
-  const int64_t bb = std::min(b, n);  // block slot size of R, Us, Vs, d
+  const int64_t bb = std::min(b, n);  // block slot size of R, Us, Vs, d, TU, TV
+  std::vector<int64_t> ku(s, 0), kv(s, 0);  // reflector columns per step
   for (int64_t i = 0; i < s; ++i) {
     const int64_t c0 = i * b;
     const int64_t c2 = std::min(c0 + b, n);
     const int64_t r2 = std::min(c0 + b, m);
     const int64_t Mi = m - c0, Ni = n - c0;
-    const int r = (int)(i & 1);
     double* T22 = T + c0 + c0 * ldt;
     double* Tc = T + c0 * ldt;  // T(:, J2uJ3)
     double* Ri = B.R + i * bb * bb;  // ld bb
+    double* Tu = B.TU + i * bb * bb;  // ld bb
+    double* Wu = B.WU + c0 + c0 * m;  // ld m
     if (r2 < m && c2 < n) {
       const int64_t kb = b;
       const int64_t N3 = n - c2;
-      // ---- critical stream: sketch and V_i
-      if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvVdone + r], 0));
+      double* Tv = B.TV + i * bb * bb;
+      double* Wv = B.WV + c0 + c0 * n;  // ld n
+      double* Wr = B.WZ;                // W_v Tf_v^T, Ni x b, ld n
+      double* Zt = B.WZ + n * kb;       // Z^T on rows [b, Ni), ld n
+      double* X = B.XW;                 // m x b, ld m
+      double* Wl = B.XW + m * kb;       // W_u Tf_u^T on rows I2uI3, ld m
+      ku[i] = kb;
+      kv[i] = kb;
+      // ---- sketch and V_i
       RRF_TRY(gaussian(st, seed, (uint64_t)(i + 1), Mi, kb, B.G, Mi));
       if (precision == RRF_PREC_BF16_SKETCH) {
-        RRF_TRY(sketch_mixed(st, Mi, Ni, kb, q, T22, ldt, B, B.Y[r]));
+        RRF_TRY(sketch_mixed(st, Mi, Ni, kb, q, T22, ldt, B, B.Y));
       } else {
-        RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.G, Mi, 0.0, B.Y[r], Ni,
-                      B.split[0], SE));
+        RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.G, Mi, 0.0, B.Y, Ni,
+                      B.split, SE));
         for (int it = 0; it < q; ++it) {
-          RRF_TRY(dgemm(st, false, false, Mi, kb, Ni, 1.0, T22, ldt, B.Y[r], Ni, 0.0, B.Z, Mi,
-                        B.split[0], SE));
-          RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.Z, Mi, 0.0, B.Y[r], Ni,
-                        B.split[0], SE));
+          RRF_TRY(dgemm(st, false, false, Mi, kb, Ni, 1.0, T22, ldt, B.Y, Ni, 0.0, B.Z, Mi,
+                        B.split, SE));
+          RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.Z, Mi, 0.0, B.Y, Ni,
+                        B.split, SE));
         }
       }
-      RRF_TRY(householder_panel(st, Ni, (int)kb, B.Y[r], Ni, B.Y[r], Ni, nullptr, 0, B.Tv, kb,
-                                B.tau, nullptr, 0, B.panel, B.panel_bytes, B.status));
-      double* Wr = B.WZ[r];          // W_v Tf_v^T, Ni x b, ld n
-      double* Zt = B.WZ[r] + n * kb;  // Z^T on rows [b, Ni), ld n
-      double* X = B.XW[r];            // m x b, ld m
-      double* Wl = B.XW[r] + m * kb;  // W_u Tf_u^T on rows I2uI3, ld m
-      RRF_TRY(dgemm(st, false, true, Ni, kb, kb, 1.0, B.Y[r], Ni, B.Tv, kb, 0.0, Wr, n, nullptr,
-                    0));
-      RRF_CHECK_HIP(hipEventRecord(ev[kEvV + r], st));
+      RRF_TRY(householder_panel(st, Ni, (int)kb, B.Y, Ni, Wv, n, nullptr, 0, Tv, bb, B.tau,
+                                nullptr, 0, B.panel, B.panel_bytes, B.status));
+      RRF_TRY(dgemm(st, false, true, Ni, kb, kb, 1.0, Wv, n, Tv, bb, 0.0, Wr, n, nullptr, 0));
       // X = T(:, J2uJ3) W_v; columns J2 of T V_i
-      if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvUdone + r], 0));
-      RRF_TRY(dgemm(st, false, false, m, kb, Ni, 1.0, Tc, ldt, B.Y[r], Ni, 0.0, X, m,
-                    B.split[0], SE));
+      RRF_TRY(dgemm(st, false, false, m, kb, Ni, 1.0, Tc, ldt, Wv, n, 0.0, X, m, B.split, SE));
       RRF_TRY(dgemm(st, false, true, m, kb, kb, -1.0, X, m, Wr, n, 1.0, Tc, ldt, nullptr, 0));
-      // ---- critical stream: U_i and R from the panel T(I2uI3, J2)
-      RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, B.Wu[r], Mi, Ri, bb, B.Tu, kb, B.tau,
-                                T22, ldt, B.panel, B.panel_bytes, B.status));
-      // W_u Tf_u^T on rows I2uI3, zero on rows I1 (the rows this slot held
-      // two steps earlier are cleared)
-      const int64_t z0 = std::max<int64_t>(0, c0 - 2 * b);
+      // ---- U_i and R from the panel T(I2uI3, J2)
+      RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, Wu, m, Ri, bb, Tu, bb, B.tau, T22, ldt,
+                                B.panel, B.panel_bytes, B.status));
+      // W_u Tf_u^T on rows I2uI3, zero on rows I1 (clear the rows the
+      // previous step held)
+      const int64_t z0 = std::max<int64_t>(0, c0 - b);
       RRF_TRY(fill_matrix(st, c0 - z0, kb, 0.0, Wl + z0, m));
-      RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, Wl + c0, m,
-                    nullptr, 0));
-      RRF_CHECK_HIP(hipEventRecord(ev[kEvU + r], st));
+      RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, Wu, m, Tu, bb, 0.0, Wl + c0, m, nullptr, 0));
       // Z^T = T(I2uI3, J3)^T W_u - Wr(J3, :) (X(I2uI3, :)^T W_u)
       double* T23 = T + c0 + c2 * ldt;
-      RRF_TRY(dgemm(st, true, false, N3, kb, Mi, 1.0, T23, ldt, B.Wu[r], Mi, 0.0, Zt + kb, n,
-                    B.split[0], SE));
-      RRF_TRY(dgemm(st, true, false, kb, kb, Mi, 1.0, X + c0, m, B.Wu[r], Mi, 0.0, B.S, kb,
-                    B.split[0], SE));
+      RRF_TRY(dgemm(st, true, false, N3, kb, Mi, 1.0, T23, ldt, Wu, m, 0.0, Zt + kb, n, B.split,
+                    SE));
+      RRF_TRY(dgemm(st, true, false, kb, kb, Mi, 1.0, X + c0, m, Wu, m, 0.0, B.S, kb, B.split,
+                    SE));
       RRF_TRY(dgemm(st, false, false, N3, kb, kb, -1.0, Wr + kb, n, B.S, kb, 1.0, Zt + kb, n,
                     nullptr, 0));
       // T(:, J3) -= [X, W_u Tf_u^T] [Wr(J3, :), Z^T]^T
-      RRF_TRY(dgemm(st, false, true, m, N3, 2 * kb, -1.0, X, m, B.WZ[r] + kb, n, 1.0,
-                    T + c2 * ldt, ldt, nullptr, 0));
-
-      // ---- side stream: V V_i and U U_i
-      RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvV + r], 0));
-      if (V) {
-        double* Vc = V + c0 * ldv;
-        RRF_TRY(dgemm(s1, false, false, n, kb, Ni, 1.0, Vc, ldv, B.Y[r], Ni, 0.0, B.X1, n,
-                      B.split[1], SE));
-        RRF_TRY(dgemm(s1, false, true, n, Ni, kb, -1.0, B.X1, n, Wr, n, 1.0, Vc, ldv, nullptr,
-                      0));
-      }
-      RRF_CHECK_HIP(hipEventRecord(ev[kEvVdone + r], s1));
-      RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvU + r], 0));
-      if (U) {
-        double* Uc = U + c0 * ldu;
-        RRF_TRY(dgemm(s1, false, false, m, kb, Mi, 1.0, Uc, ldu, B.Wu[r], Mi, 0.0, B.X1, m,
-                      B.split[1], SE));
-        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, Wl + c0, m, 1.0, Uc, ldu,
-                      nullptr, 0));
-      }
-      RRF_CHECK_HIP(hipEventRecord(ev[kEvUdone + r], s1));
-
+      RRF_TRY(dgemm(st, false, true, m, N3, 2 * kb, -1.0, X, m, B.WZ + kb, n, 1.0, T + c2 * ldt,
+                    ldt, nullptr, 0));
     } else {
       // Last block: its SVD is of T(I2uI3, J2uJ3), Mi x Ni with Mi >= Ni;
       // a tall block is first reduced by a Householder QR.
       const int64_t kb = Ni;
-      if (i >= 2) RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvUdone + r], 0));
-      double* Wl = B.XW[r] + m * bb;  // W_u Tf_u^T, Mi x kb, ld m
       if (Mi > Ni) {
-        RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, B.Wu[r], Mi, Ri, bb, B.Tu, kb,
-                                  B.tau, nullptr, 0, B.panel, B.panel_bytes, B.status));
-        RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, B.Wu[r], Mi, B.Tu, kb, 0.0, Wl, m,
-                      nullptr, 0));
+        RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, Wu, m, Ri, bb, Tu, bb, B.tau,
+                                  nullptr, 0, B.panel, B.panel_bytes, B.status));
+        ku[i] = kb;
       } else {
         RRF_TRY(copy_matrix(st, kb, kb, T22, ldt, Ri, bb));
       }
-      RRF_CHECK_HIP(hipEventRecord(ev[kEvU + r], st));
-      RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvU + r], 0));
-      if (U && Mi > Ni) {
-        double* Uc = U + c0 * ldu;
-        RRF_TRY(dgemm(s1, false, false, m, kb, Mi, 1.0, Uc, ldu, B.Wu[r], Mi, 0.0, B.X1, m,
-                      B.split[1], SE));
-        RRF_TRY(dgemm(s1, false, true, m, Mi, kb, -1.0, B.X1, m, Wl, m, 1.0, Uc, ldu, nullptr,
-                      0));
-      }
-      RRF_CHECK_HIP(hipEventRecord(ev[kEvUdone + r], s1));
     }
   }
-  // ---- after the loop: all block SVDs in one launch, then the updates
-  // of the processed columns they feed.
-  RRF_CHECK_HIP(hipEventRecord(ev[kEvS1], s1));
-  RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvS1], 0));
+  RRF_CHECK_HIP(hipEventRecord(ev[kEvLoop], st));
+  // ---- U and V from the kept reflectors, on the side streams, while the
+  // small SVDs run
   const int64_t k_last = n - (s - 1) * b;
+  hipStream_t su = ctx->side[0], sv = ctx->side[1];
+  if (U) {
+    RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvLoop], 0));
+    RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE));
+  }
+  if (V) {
+    RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvLoop], 0));
+    RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE));
+  }
   RRF_TRY(block_svd_batched(st, (int)s, (int)bb, (int)k_last, B.R, bb, bb * bb, B.Us, B.d, bb,
                             B.Vs, B.svd, B.svd_bytes, B.status));
   RRF_CHECK_HIP(hipEventRecord(ev[kEvSvd], st));
-  RRF_CHECK_HIP(hipStreamWaitEvent(s1, ev[kEvSvd], 0));
+  if (U) RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvSvd], 0));
+  if (V) RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvSvd], 0));
   for (int64_t i = 0; i < s; ++i) {
     const int64_t c0 = i * b;
     const int64_t kb = std::min(b, n - c0);
@@ -338,7 +391,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
     // T(I2uI3, J2) = [D; 0] (the panel already cleared it; the last block is
     // written whole)
     RRF_TRY(set_diag(st, last ? m - c0 : kb, kb, B.d + i * bb, T22, ldt));
-    RRF_TRY(right_mult(st, c0, kb, T + c0 * ldt, ldt, Vsi, B.X0, B.split[0], SE));  // T(I1, J2)
+    RRF_TRY(right_mult(st, c0, kb, T + c0 * ldt, ldt, Vsi, B.X0, B.split, SE));  // T(I1, J2)
     if (!last) {
       const int64_t N3 = n - c2;
       double* T2r = T + c0 + c2 * ldt;  // T(I2, J3) <- Us^T T(I2, J3)
@@ -346,11 +399,19 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
                     0));
       RRF_TRY(copy_matrix(st, kb, N3, B.Zl, kb, T2r, ldt));
     }
-    if (U) RRF_TRY(right_mult(s1, m, kb, U + c0 * ldu, ldu, Usi, B.X1, B.split[1], SE));
-    if (V) RRF_TRY(right_mult(s1, n, kb, V + c0 * ldv, ldv, Vsi, B.X1, B.split[1], SE));
+    if (U)
+      RRF_TRY(right_mult(su, m, kb, U + c0 * ldu, ldu, Usi, B.back[0].tmp, B.back[0].split, SE));
+    if (V)
+      RRF_TRY(right_mult(sv, n, kb, V + c0 * ldv, ldv, Vsi, B.back[1].tmp, B.back[1].split, SE));
   }
-  RRF_CHECK_HIP(hipEventRecord(ev[kEvS1], s1));
-  RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvS1], 0));
+  if (U) {
+    RRF_CHECK_HIP(hipEventRecord(ev[kEvU], su));
+    RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvU], 0));
+  }
+  if (V) {
+    RRF_CHECK_HIP(hipEventRecord(ev[kEvV], sv));
+    RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvV], 0));
+  }
   *status_out = 0;
   return RRF_OK;
 }

@@ -3,7 +3,7 @@
 // or torch runtime in the process (rocprofv3 --kernel-trace / --pmc).
 //
 //   rrf_bench [--alg randutv|powerurv] [--m M] [--n N] [--b B] [--q Q] [--reps R] [--trace]
-//             [--copy-bytes BYTES] [--precision 0|1]
+//             [--copy-bytes BYTES] [--precision 0|1] [--no-uv]
 //
 // --copy-bytes first runs one device-to-device copy of BYTES bytes: a plain
 // copy kernel of known traffic, against which the HBM byte counters of a
@@ -26,7 +26,7 @@ static int fail(const char* what, int st) {
 int main(int argc, char** argv) {
   std::string alg = "randutv";
   long m = 0, n = 16384, b = 128, q = 2, reps = 1, copy_bytes = 0, precision = RRF_PREC_FP64;
-  bool trace = false;
+  bool trace = false, no_uv = false;
   for (int i = 1; i < argc; ++i) {
     std::string a = argv[i];
     auto next = [&](long& v) { if (i + 1 < argc) v = atol(argv[++i]); };
@@ -37,6 +37,7 @@ int main(int argc, char** argv) {
     else if (a == "--q") next(q);
     else if (a == "--reps") next(reps);
     else if (a == "--trace") trace = true;
+    else if (a == "--no-uv") no_uv = true;
     else if (a == "--copy-bytes") next(copy_bytes);
     else if (a == "--precision") next(precision);
     else { fprintf(stderr, "unknown argument %s\n", a.c_str()); return 2; }
@@ -74,8 +75,10 @@ int main(int argc, char** argv) {
   double best = 1e30, total = 0.0;
   for (long r = 0; r < reps; ++r) {
     auto t0 = std::chrono::steady_clock::now();
-    st = code == RRF_ALG_RANDUTV ? rrf_randutv_ex(m, n, A, m, b, (int)q, 1, U, T, V, &o)
-                                 : rrf_powerurv_ex(m, n, A, m, b, (int)q, 1, U, T, V, &o);
+    double* Uo = no_uv ? nullptr : U;
+    double* Vo = no_uv ? nullptr : V;
+    st = code == RRF_ALG_RANDUTV ? rrf_randutv_ex(m, n, A, m, b, (int)q, 1, Uo, T, Vo, &o)
+                                 : rrf_powerurv_ex(m, n, A, m, b, (int)q, 1, Uo, T, Vo, &o);
     if (st) return fail(alg.c_str(), st);
     double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     best = s < best ? s : best;

@@ -74,8 +74,13 @@ def test_workspace_size(lib):
     assert f(_lib.RRF_ALG_RANDUTV, 512, 600, 32, 1, 0) == 0     # m < n
     assert f(_lib.RRF_ALG_RANDUTV, 512, 512, 300, 1, 0) == 0    # b > 256
     assert f(7, 512, 512, 32, 1, 0) == 0
-    big = f(_lib.RRF_ALG_RANDUTV, 16384, 16384, 128, 2, 0)
-    assert 0 < big < 2 ** 31  # the FP64 path keeps its scratch small (O(n b))
+    # the reflectors of every step are kept (m x n for U, n x n for V) so that
+    # U and V can be formed backward after the loop; the rest is O(max(m,n) b)
+    n = 16384
+    big = f(_lib.RRF_ALG_RANDUTV, n, n, 128, 2, 0)
+    assert 8 * 2 * n * n < big < 8 * 2 * n * n + 2 ** 31
+    mixed = f(_lib.RRF_ALG_RANDUTV, n, n, 128, 2, 1)
+    assert big < mixed < big + 2 * 2 * n * n + 2 ** 30  # + two bfloat16 copies of T22
 
 
 def test_component_argument_errors(lib):
