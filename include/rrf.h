@@ -202,7 +202,10 @@ const char* rrf_last_error(void);
  * read and the reflectors written; generator: the matrix written).
  * rrf_trace_enable(on) clears the totals and switches recording on or off.
  * rrf_trace_read() waits for the recorded events and fills up to
- * max_entries totals, one per kernel class that ran; returns how many. */
+ * max_entries totals, one per kernel class that ran; returns how many.
+ * Kernels that form U and V after the randUTV loop run concurrently on two
+ * streams of their own; they are reported as separate classes whose names
+ * end in ":UV". */
 typedef struct rrf_trace_entry {
   char name[48];     /* kernel class, e.g. "dgemm_mfma_128x128_NT"          */
   int64_t launches;  /* launches recorded                                  */

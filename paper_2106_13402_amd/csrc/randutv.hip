@@ -49,6 +49,7 @@
 #include "context.hpp"
 #include "driver.hpp"
 #include "kernels.hpp"
+#include "trace.hpp"
 
 namespace rrf {
 
@@ -367,6 +368,8 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   // small SVDs run
   const int64_t k_last = n - (s - 1) * b;
   hipStream_t su = ctx->side[0], sv = ctx->side[1];
+  trace_mark_stream(su);
+  trace_mark_stream(sv);
   if (U) {
     RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvLoop], 0));
     RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE));

@@ -1,6 +1,9 @@
 // Optional per-kernel timing: a pair of HIP events around each launch of a
 // kernel class, on the stream the kernel runs on, plus the algorithmic flop
 // and byte counts of that launch. Off by default (one branch per launch).
+// Launches on streams marked with trace_mark_stream (the streams that form
+// U and V after the randUTV loop, where kernels run concurrently) are kept
+// as separate classes, named with a ":UV" suffix.
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -27,7 +30,8 @@ std::mutex g_mu;
 bool g_on = false;
 std::vector<Record> g_pending;
 std::vector<hipEvent_t> g_free;
-Totals g_tot[kTraceClasses];
+Totals g_tot[2 * kTraceClasses];
+std::vector<hipStream_t> g_marked;
 
 const char* kNames[kTraceClasses] = {
     "dgemm_mfma_128x128_NN", "dgemm_mfma_128x128_TN", "dgemm_mfma_128x128_NT",
@@ -69,9 +73,18 @@ void drain_locked() {
 
 bool trace_on() { return g_on; }
 
+void trace_mark_stream(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (hipStream_t m : g_marked)
+    if (m == st) return;
+  g_marked.push_back(st);
+}
+
 int trace_begin(hipStream_t st, int cls, double flops, double bytes) {
   if (!g_on) return -1;
   std::lock_guard<std::mutex> lk(g_mu);
+  for (hipStream_t m : g_marked)
+    if (m == st) cls += kTraceClasses;
   Record r{cls, flops, bytes, get_event(), get_event()};
   if (r.e0) (void)hipEventRecord(r.e0, st);
   g_pending.push_back(r);
@@ -108,11 +121,12 @@ int rrf_trace_read(rrf_trace_entry* out, int max_entries) {
   std::lock_guard<std::mutex> lk(g_mu);
   drain_locked();
   int n = 0;
-  for (int c = 0; c < kTraceClasses && n < max_entries; ++c) {
+  for (int c = 0; c < 2 * kTraceClasses && n < max_entries; ++c) {
     if (g_tot[c].launches == 0) continue;
     rrf_trace_entry& e = out[n++];
     memset(&e, 0, sizeof e);
-    strncpy(e.name, kNames[c], sizeof e.name - 1);
+    strncpy(e.name, kNames[c % kTraceClasses], sizeof e.name - 4);
+    if (c >= kTraceClasses) strncat(e.name, ":UV", sizeof e.name - 1 - strlen(e.name));
     e.launches = g_tot[c].launches;
     e.ms = g_tot[c].ms;
     e.flops = g_tot[c].flops;

@@ -16,6 +16,8 @@ bool trace_on();
 // Returns a token for trace_end (-1 when tracing is off).
 int trace_begin(hipStream_t st, int cls, double flops, double bytes);
 void trace_end(hipStream_t st, int token);
+// Launches on `st` are traced as separate ":UV" classes from now on.
+void trace_mark_stream(hipStream_t st);
 int gemm_trace_class(int tile, bool ta, bool tb);
 
 }  // namespace rrf
