@@ -127,7 +127,44 @@ int rrf_powerurv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t 
 size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
                           int precision);
 
-/* Release the library-managed workspace cache of the current device. */
+/*
+ * Batched randUTV -- Alg. 3 on `count` independent matrices in one call, for
+ * workloads of many small matrices (one kernel launch serves the same stage of
+ * every matrix). Matrix j is factored as rrf_randutv_ex would factor it with
+ * the sketch key seed + j (same arithmetic, same generator streams; results
+ * agree to rounding, as the products are summed in another order).
+ *
+ *  count  : number of matrices, >= 0 (0: nothing to do)              (arg 1)
+ *  m, n   : host arrays of count sizes, 1 <= n[j] <= m[j] <= 4096   (args 2, 3)
+ *  A      : host array of count device pointers, read only unless T[j] == A[j]
+ *                                                                     (arg 4)
+ *  lda    : host array, lda[j] >= m[j]                                (arg 5)
+ *  b      : block size for every matrix, 1 <= b <= 64; 0 = chosen per matrix
+ *           from n[j] (16 for n <= 128, 32 for n <= 320, else 64)    (arg 6)
+ *  q      : power iterations, >= 0                                    (arg 7)
+ *  seed   : generator key of matrix 0                                 (arg 8)
+ *  U      : host array of count device pointers to m[j] x m[j] outputs
+ *           (ld m[j]), or NULL for no U                               (arg 9)
+ *  T      : host array of device pointers to m[j] x n[j] outputs (ld m[j]);
+ *           T[j] may be A[j] when lda[j] == m[j]                      (arg 10)
+ *  V      : as U with n[j] x n[j] outputs (ld n[j]), or NULL          (arg 11)
+ *  opts   : as for rrf_randutv_ex; only RRF_PREC_FP64; the workspace must
+ *           hold rrf_randutv_batched_workspace_size(count, m, n, b) bytes
+ * The output of every matrix has the form rrf_randutv documents. The host
+ * arrays are read during the call only. The call keeps a small pinned host
+ * staging ring per device (freed by rrf_release_workspace) and may wait for
+ * earlier work on `stream` while it enqueues.
+ */
+int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
+                        const double* const* A, const int64_t* lda, int64_t b,
+                        int32_t q, uint64_t seed, double* const* U, double* const* T,
+                        double* const* V, const rrf_opts* opts);
+/* Bytes of device workspace for rrf_randutv_batched; 0 for invalid sizes. */
+size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m,
+                                          const int64_t* n, int64_t b);
+
+/* Release the library-managed workspace cache of the current device and the
+ * batched call's staging rings of every device. */
 int rrf_release_workspace(void);
 
 /* ---- building blocks, exported for component tests ------------------------

@@ -18,7 +18,8 @@ from ._lib import RRFError
 __all__ = [
     "RRFError", "randutv", "powerurv", "gaussian", "dgemm", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
-    "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS",
+    "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
+    "batched_workspace_size",
 ]
 
 # precision names of rrf_opts.precision
@@ -132,6 +133,65 @@ def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool =
     FP32 accumulation (RRF_PREC_BF16_SKETCH); everything else stays FP64."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
                    inplace, precision)
+
+
+def _i64_array(vals):
+    return (C.c_int64 * max(len(vals), 1))(*vals)
+
+
+def _ptr_array(vals):
+    return (C.c_void_p * max(len(vals), 1))(*vals)
+
+
+def batched_workspace_size(ms, ns, b: int) -> int:
+    """Bytes of workspace rrf_randutv_batched needs for these sizes (0: invalid)."""
+    return int(lib.rrf_randutv_batched_workspace_size(len(ms), _i64_array(ms), _i64_array(ns), b))
+
+
+def randutv_batched(As, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
+                    check_finite: bool = False, out=None):
+    """Batched randUTV (Alg. 3) of the matrices in the list ``As``; matrix j is
+    keyed by ``seed + j``; ``b = 0`` picks the block size per matrix.
+
+    Returns three lists (Us, Ts, Vs) (Us / Vs None when not wanted). ``out``
+    may pass such lists (tight column-major tensors of the right shapes) to be
+    written instead of new ones."""
+    count = len(As)
+    for j, A in enumerate(As):
+        _require(A, f"As[{j}]")
+    ms = [int(A.shape[0]) for A in As]
+    ns = [int(A.shape[1]) for A in As]
+    if count == 0:
+        return ([] if want_u else None), [], ([] if want_v else None)
+    dev = As[0].device
+    if out is not None:
+        Us, Ts, Vs = out
+        for j in range(count):
+            _require(Ts[j], f"Ts[{j}]", ms[j])
+            if _ld(Ts[j]) != ms[j]:
+                raise ValueError("outputs must be tight column-major tensors")
+    else:
+        Us = [empty_colmajor(m, m, dev) for m in ms] if want_u else None
+        Ts = [empty_colmajor(m, n, dev) for m, n in zip(ms, ns)]
+        Vs = [empty_colmajor(n, n, dev) for n in ns] if want_v else None
+    nbytes = batched_workspace_size(ms, ns, b)
+    if nbytes == 0:
+        raise RRFError(_lib.RRF_E_NOTSUP, "rrf_randutv_batched", "no workspace size for these sizes")
+    ws = _workspace(dev, nbytes)
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.stream = _stream_ptr(dev)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = ws.numel()
+    opts.check_finite = 1 if check_finite else 0
+    st = lib.rrf_randutv_batched(
+        count, _i64_array(ms), _i64_array(ns), _ptr_array([A.data_ptr() for A in As]),
+        _i64_array([_ld(A) for A in As]), b, q, seed,
+        _ptr_array([U.data_ptr() for U in Us]) if Us is not None else None,
+        _ptr_array([T.data_ptr() for T in Ts]),
+        _ptr_array([V.data_ptr() for V in Vs]) if Vs is not None else None, C.byref(opts))
+    _check(st, "rrf_randutv_batched")
+    return Us, Ts, Vs
 
 
 def powerurv(A, q: int, seed: int, *, b: int = 128, want_u: bool = True, want_v: bool = True,

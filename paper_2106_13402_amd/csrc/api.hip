@@ -5,6 +5,7 @@
 #include <mutex>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "common.hpp"
 #include "driver.hpp"
@@ -14,6 +15,8 @@ namespace rrf {
 
 namespace {
 thread_local std::string g_last_error;
+constexpr int64_t kBatchedMaxB = 64;      // one-workgroup panel width
+constexpr int64_t kBatchedMaxDim = 4096;  // panel rows reachable by column splits
 
 struct DeviceCache {
   void* ptr = nullptr;
@@ -198,6 +201,118 @@ int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, i
   return rrf_randutv_ex(m, n, A, lda, b, q, seed, U, T, V, nullptr);
 }
 
+size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m, const int64_t* n,
+                                          int64_t b) {
+  if (count < 0 || (count > 0 && (m == nullptr || n == nullptr)) || b < 0 || b > kBatchedMaxB)
+    return 0;
+  for (int64_t j = 0; j < count; ++j)
+    if (n[j] < 1 || m[j] < n[j] || m[j] > kBatchedMaxDim) return 0;
+  if (b > 0) return count > 0 ? randutv_batched_workspace(count, m, n, b) : 0;
+  // automatic block size: the groups run one after another in one workspace
+  size_t need = 0;
+  for (int64_t bg : {16, 32, 64}) {
+    std::vector<int64_t> gm, gn;
+    for (int64_t j = 0; j < count; ++j)
+      if (randutv_batched_block(m[j], n[j]) == bg) {
+        gm.push_back(m[j]);
+        gn.push_back(n[j]);
+      }
+    if (!gm.empty())
+      need = std::max(need, randutv_batched_workspace((int64_t)gm.size(), gm.data(), gn.data(), bg));
+  }
+  return need;
+}
+
+int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
+                        const double* const* A, const int64_t* lda, int64_t b, int32_t q,
+                        uint64_t seed, double* const* U, double* const* T, double* const* V,
+                        const rrf_opts* opts) {
+  if (count < 0) return set_error(-1, "count must be >= 0"), -1;
+  if (count == 0) return RRF_OK;
+  if (m == nullptr) return set_error(-2, "m is NULL"), -2;
+  if (n == nullptr) return set_error(-3, "n is NULL"), -3;
+  if (A == nullptr) return set_error(-4, "A is NULL"), -4;
+  if (lda == nullptr) return set_error(-5, "lda is NULL"), -5;
+  if (b < 0 || b > kBatchedMaxB) return set_error(-6, "b must be 0 or in [1, 64]"), -6;
+  if (q < 0) return set_error(-7, "q must be >= 0"), -7;
+  if (T == nullptr) return set_error(-10, "T is NULL"), -10;
+  for (int64_t j = 0; j < count; ++j) {
+    if (m[j] < 1) return set_error(-2, "m[j] must be >= 1"), -2;
+    if (n[j] < 1) return set_error(-3, "n[j] must be >= 1"), -3;
+    if (A[j] == nullptr) return set_error(-4, "A[j] is NULL"), -4;
+    if (lda[j] < m[j]) return set_error(-5, "lda[j] must be >= m[j]"), -5;
+    if (U && U[j] == nullptr) return set_error(-9, "U[j] is NULL"), -9;
+    if (T[j] == nullptr) return set_error(-10, "T[j] is NULL"), -10;
+    if (V && V[j] == nullptr) return set_error(-11, "V[j] is NULL"), -11;
+    if (T[j] == A[j] && lda[j] != m[j])
+      return set_error(-5, "T[j] may alias A[j] only when lda[j] == m[j]"), -5;
+    if (m[j] < n[j]) return set_error(RRF_E_NOTSUP, "m < n is not supported (factor A^T instead)");
+    if (m[j] > kBatchedMaxDim)
+      return set_error(RRF_E_NOTSUP, "batched randutv: m above 4096 (use rrf_randutv)");
+  }
+  rrf_opts o;
+  rrf_opts_init(&o);
+  if (opts) o = *opts;
+  if (o.precision != RRF_PREC_FP64)
+    return set_error(RRF_E_NOTSUP, "batched randutv: only RRF_PREC_FP64");
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  for (int64_t j = 0; j < count; ++j) {
+    RRF_TRY(check_device_ptr(A[j], 4));
+    if (U) RRF_TRY(check_device_ptr(U[j], 9));
+    RRF_TRY(check_device_ptr(T[j], 10));
+    if (V) RRF_TRY(check_device_ptr(V[j], 11));
+  }
+  const size_t need = rrf_randutv_batched_workspace_size(count, m, n, b);
+  void* ws = o.workspace;
+  size_t ws_bytes = o.workspace_bytes;
+  if (ws == nullptr) {
+    RRF_TRY(cached_workspace(dev, need, &ws));
+    ws_bytes = need;
+  } else if (ws_bytes < need) {
+    return set_error(RRF_E_NOMEM, "workspace smaller than rrf_randutv_batched_workspace_size()");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
+  int* status = reinterpret_cast<int*>(ws);
+  RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(status), 2, 0u));
+  if (o.check_finite) {
+    for (int64_t j = 0; j < count; ++j) RRF_TRY(check_finite(st, m[j], n[j], A[j], lda[j], status + 1));
+    int h = 0;
+    RRF_CHECK_HIP(hipMemcpyAsync(&h, status + 1, sizeof h, hipMemcpyDeviceToHost, st));
+    RRF_CHECK_HIP(hipStreamSynchronize(st));
+    if (h) return set_error(RRF_E_NUMERIC, "input holds NaN or infinity");
+  }
+  std::vector<uint64_t> seeds(count);
+  for (int64_t j = 0; j < count; ++j) seeds[j] = seed + (uint64_t)j;
+  if (b > 0) {
+    RRF_TRY(randutv_batched_run(st, count, m, n, A, lda, b, q, seeds.data(), U, T, V, ws, ws_bytes));
+  } else {
+    for (int64_t bg : {16, 32, 64}) {
+      std::vector<int64_t> gm, gn, gl;
+      std::vector<const double*> gA;
+      std::vector<double*> gU, gT, gV;
+      std::vector<uint64_t> gs;
+      for (int64_t j = 0; j < count; ++j) {
+        if (randutv_batched_block(m[j], n[j]) != bg) continue;
+        gm.push_back(m[j]);
+        gn.push_back(n[j]);
+        gl.push_back(lda[j]);
+        gA.push_back(A[j]);
+        gT.push_back(T[j]);
+        if (U) gU.push_back(U[j]);
+        if (V) gV.push_back(V[j]);
+        gs.push_back(seeds[j]);
+      }
+      if (gm.empty()) continue;
+      RRF_TRY(randutv_batched_run(st, (int64_t)gm.size(), gm.data(), gn.data(), gA.data(),
+                                  gl.data(), bg, q, gs.data(), U ? gU.data() : nullptr, gT.data(),
+                                  V ? gV.data() : nullptr, ws, ws_bytes));
+    }
+  }
+  if (o.async) return RRF_OK;
+  return finish(st, status);
+}
+
 int rrf_powerurv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                     uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
   return run_alg(RRF_ALG_POWERURV, m, n, A, lda, b, q, U, T, V, opts,
@@ -214,6 +329,7 @@ int rrf_powerurv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, 
 int rrf_release_workspace(void) {
   int dev = 0;
   RRF_TRY(device_ready(&dev));
+  RRF_TRY(randutv_batched_release());
   std::lock_guard<std::mutex> lk(g_cache_mu);
   auto it = g_cache.find(dev);
   if (it != g_cache.end() && it->second.ptr) {

@@ -20,4 +20,16 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
                  int q, uint64_t seed, double* U, double* T, double* V, void* ws, size_t ws_bytes,
                  bool check_input);
 
+// Batched Alg. 3 (one block size b for the whole call; matrix j keyed by
+// seeds[j]); outputs packed column-major (ld m, m, n). The status words of
+// `ws` (word 0: device-side failure bits) are not cleared here.
+int64_t randutv_batched_block(int64_t m, int64_t n);
+size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t* n, int64_t b);
+int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const int64_t* n,
+                        const double* const* A, const int64_t* lda, int64_t b, int q,
+                        const uint64_t* seeds, double* const* U, double* const* T,
+                        double* const* V, void* ws, size_t ws_bytes);
+// Free the descriptor rings of every device.
+int randutv_batched_release();
+
 }  // namespace rrf

@@ -54,6 +54,7 @@ struct SvdArgs {
   double* gA;  // global scratch: per block 2 k^2 doubles when not in LDS
   int use_lds;
   int* status;
+  const int* sizes;  // per-block sizes (device), or null
 };
 
 __device__ inline double wave_sum(double v) {
@@ -71,7 +72,7 @@ __global__ __launch_bounds__(kThreads) void jacobi_svd_kernel(SvdArgs a) {
   __shared__ int pick;
 
   const int blk = blockIdx.x;
-  const int k = (blk == a.count - 1) ? a.k_last : a.k;
+  const int k = a.sizes ? a.sizes[blk] : ((blk == a.count - 1) ? a.k_last : a.k);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* gbase = a.use_lds ? nullptr : a.gA + (size_t)blk * 2 * a.k * a.k;
   double* Aw = a.use_lds ? lds : gbase;
@@ -305,6 +306,43 @@ int block_svd_batched(hipStream_t st, int count, int k, int k_last, const double
   a.use_lds = in_lds ? 1 : 0;
   a.status = status;
   int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * k * k * count);
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(count), dim3(kThreads), in_lds ? need : 0, st, a);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int block_svd_sized(hipStream_t st, int count, int kmax, const int* d_sizes, const double* B,
+                    int64_t ldb, int64_t stride, double* Us, double* d, int64_t dstride,
+                    double* Vs, void* work, size_t work_bytes, int* status) {
+  if (count < 1) return RRF_OK;
+  if (kmax < 1 || kmax > kMaxK) return set_error(RRF_E_NOTSUP, "block svd: need k <= 256");
+  const size_t need = (size_t)2 * kmax * kmax * 8;
+  const bool in_lds = need <= kLdsBudget;
+  if (!in_lds && (work == nullptr || work_bytes < need * count))
+    return set_error(RRF_E_NOMEM, "block svd: workspace too small");
+  if (!g_attr_set) {
+    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)kLdsBudget));
+    g_attr_set = true;
+  }
+  SvdArgs a{};
+  a.k = kmax;
+  a.k_last = kmax;
+  a.count = count;
+  a.stride = stride;
+  a.dstride = dstride;
+  a.B = B;
+  a.ldb = ldb;
+  a.Us = Us;
+  a.d = d;
+  a.Vs = Vs;
+  a.gA = in_lds ? nullptr : reinterpret_cast<double*>(work);
+  a.use_lds = in_lds ? 1 : 0;
+  a.status = status;
+  a.sizes = d_sizes;
+  int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * kmax * kmax * count);
   hipLaunchKernelGGL(jacobi_svd_kernel, dim3(count), dim3(kThreads), in_lds ? need : 0, st, a);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());

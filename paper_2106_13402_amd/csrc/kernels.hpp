@@ -71,6 +71,11 @@ int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t
 
 // ---- jacobi_svd.hip ------------------------------------------------------
 size_t block_svd_work_bytes(int k);
+// As block_svd_batched with the size of every block in d_sizes (device ints,
+// each <= kmax; blocks laid out with stride elements between them).
+int block_svd_sized(hipStream_t st, int count, int kmax, const int* d_sizes, const double* B,
+                    int64_t ldb, int64_t stride, double* Us, double* d, int64_t dstride,
+                    double* Vs, void* work, size_t work_bytes, int* status);
 int block_svd(hipStream_t st, int k, const double* B, int64_t ldb, double* Us, double* d,
               double* Vs, void* work, size_t work_bytes, int* status);
 // `count` independent SVDs in one launch (one workgroup each): blocks 0..count-2

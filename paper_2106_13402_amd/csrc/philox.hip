@@ -13,36 +13,12 @@
 // bytes), so a wavefront writes 2 KiB of one column.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "philox.hpp"
 #include "trace.hpp"
 
 namespace rrf {
 
 namespace {
-
-constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull;
-constexpr uint64_t kM1 = 0xCA5A826395121157ull;
-constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull;
-constexpr uint64_t kW1 = 0xBB67AE8584CAA73Bull;
-constexpr double kTwoPi = 6.283185307179586;  // nearest double to 2 pi
-
-__device__ inline void philox4x64_10(uint64_t& x0, uint64_t& x1, uint64_t& x2, uint64_t& x3,
-                                     uint64_t k0, uint64_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += kW0;
-      k1 += kW1;
-    }
-    const uint64_t hi0 = __umul64hi(kM0, x0), lo0 = kM0 * x0;
-    const uint64_t hi1 = __umul64hi(kM1, x2), lo1 = kM1 * x2;
-    const uint64_t y0 = hi1 ^ x1 ^ k0;
-    const uint64_t y2 = hi0 ^ x3 ^ k1;
-    x0 = y0;
-    x1 = lo1;
-    x2 = y2;
-    x3 = lo0;
-  }
-}
 
 __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t sid, int64_t rows,
                                                        int64_t cols, double* __restrict__ out,
@@ -53,20 +29,8 @@ __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t s
        t += (int64_t)gridDim.x * 256) {
     const int64_t gr = t % groups;
     const int64_t c = t / groups;
-    uint64_t x0 = (uint64_t)gr, x1 = (uint64_t)c, x2 = 0, x3 = 0;
-    philox4x64_10(x0, x1, x2, x3, seed, sid);
-    const double ua = ((double)(x0 >> 11) + 1.0) * 0x1p-53;
-    const double va = (double)(x1 >> 11) * 0x1p-53;
-    const double ub = ((double)(x2 >> 11) + 1.0) * 0x1p-53;
-    const double vb = (double)(x3 >> 11) * 0x1p-53;
-    const double rho_a = sqrt(-2.0 * log(ua));
-    const double rho_b = sqrt(-2.0 * log(ub));
-    const double ta = kTwoPi * va, tb = kTwoPi * vb;
     double v[4];
-    v[0] = rho_a * cos(ta);
-    v[1] = rho_a * sin(ta);
-    v[2] = rho_b * cos(tb);
-    v[3] = rho_b * sin(tb);
+    gaussian4(seed, sid, (uint64_t)gr, (uint64_t)c, v);
     double* col = out + c * ld;
     const int64_t r0 = gr * 4;
 #pragma unroll

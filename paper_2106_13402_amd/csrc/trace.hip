@@ -38,7 +38,7 @@ const char* kNames[kTraceClasses] = {
     "dgemm_mfma_128x128_TT", "dgemm_mfma_64x64_NN",   "dgemm_mfma_64x64_TN",
     "dgemm_mfma_64x64_NT",   "dgemm_mfma_64x64_TT",   "splitk_reduce",
     "householder_panel",     "jacobi_svd",            "gaussian",
-    "elementwise",           "gemm_bf16_mfma_TN",
+    "elementwise",           "gemm_bf16_mfma_TN",     "dgemm_grouped_64x64",
 };
 
 hipEvent_t get_event() {

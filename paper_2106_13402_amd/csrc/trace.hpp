@@ -9,7 +9,7 @@ enum TraceClass {
   kTrGemm128NN = 0, kTrGemm128TN, kTrGemm128NT, kTrGemm128TT,
   kTrGemm64NN, kTrGemm64TN, kTrGemm64NT, kTrGemm64TT,
   kTrSplitReduce, kTrPanel, kTrJacobi, kTrGaussian, kTrElementwise, kTrGemmBf16,
-  kTraceClasses
+  kTrGemmGrouped, kTraceClasses
 };
 
 bool trace_on();

@@ -5,10 +5,12 @@ orthogonal factors, Sec. 5.2 "fast decay" construction).
 """
 from .matrices import (
     SPECTRA,
+    batch_gaussians,
+    batch_shapes,
     gaussian_matrix,
     haar,
     spectral_matrix,
     spectrum,
 )
 
-__all__ = ["SPECTRA", "gaussian_matrix", "haar", "spectral_matrix", "spectrum"]
+__all__ = ["SPECTRA", "batch_gaussians", "batch_shapes", "gaussian_matrix", "haar", "spectral_matrix", "spectrum"]

@@ -111,5 +111,31 @@ def spectral_matrix(m: int, n: int, s, seed: int = 0, noise: float = 0.0, device
     return A.t().contiguous().t()
 
 
+def batch_shapes(count: int, seed: int = 0, nmin: int = 64, nmax: int = 512):
+    """Shapes of a batch of small matrices: n ~ U{nmin..nmax}, m ~ U{n..2n}
+    (integers, inclusive), drawn from numpy's PCG64 seeded with [seed, 4]."""
+    rng = _np_rng(seed, 4)
+    ns = rng.integers(nmin, nmax + 1, size=count)
+    ms = [int(rng.integers(n, 2 * n + 1)) for n in ns]
+    return [(m, int(n)) for m, n in zip(ms, ns)]
+
+
+def batch_gaussians(shapes, seed: int = 0, device=None):
+    """One i.i.d. N(0,1) matrix per shape, column-major with ld = m. On a
+    GPU the matrices are views into one buffer (stream 5 of the seed)."""
+    if _is_cpu(device):
+        rng = _np_rng(seed, 5)
+        return [np.asfortranarray(rng.standard_normal((m, n))) for m, n in shapes]
+    import torch
+    total = sum(m * n for m, n in shapes)
+    buf = torch.randn(total, generator=_torch_gen(device, seed, 5), dtype=torch.float64,
+                      device=device)
+    out, off = [], 0
+    for m, n in shapes:
+        out.append(buf[off:off + m * n].view(n, m).t())
+        off += m * n
+    return out
+
+
 def describe(kind: str, **kw) -> str:
     return kind + "(" + ",".join(f"{k}={v}" for k, v in sorted(kw.items())) + ")"

@@ -106,3 +106,49 @@ def test_opts_init(lib):
     o.async_ = 1
     lib.rrf_opts_init(C.byref(o))
     assert o.precision == 0 and o.async_ == 0 and o.workspace is None
+
+
+def _arr(t, vals):
+    return (t * len(vals))(*vals)
+
+
+def test_batched_argument_errors(lib):
+    f = lib.rrf_randutv_batched
+    m, n, lda = _arr(C.c_int64, [8, 6]), _arr(C.c_int64, [6, 6]), _arr(C.c_int64, [8, 6])
+    A = _arr(C.c_void_p, [0x1000, 0x2000])
+    T = _arr(C.c_void_p, [0x3000, 0x4000])
+    assert f(-1, m, n, A, lda, 4, 1, 1, NULL, T, NULL, NULL) == -1
+    assert f(0, NULL, NULL, NULL, NULL, 4, 1, 1, NULL, NULL, NULL, NULL) == 0  # nothing to do
+    assert f(2, NULL, n, A, lda, 4, 1, 1, NULL, T, NULL, NULL) == -2
+    assert f(2, m, n, A, lda, 65, 1, 1, NULL, T, NULL, NULL) == -6
+    assert f(2, m, n, A, lda, -1, 1, 1, NULL, T, NULL, NULL) == -6
+    assert f(2, m, n, A, lda, 4, -1, 1, NULL, T, NULL, NULL) == -7
+    assert f(2, m, n, A, lda, 4, 1, 1, NULL, NULL, NULL, NULL) == -10
+    bad_lda = _arr(C.c_int64, [8, 5])
+    assert f(2, m, n, A, bad_lda, 4, 1, 1, NULL, T, NULL, NULL) == -5
+    alias = _arr(C.c_void_p, [0x1000, 0x4000])
+    assert f(2, m, n, A, _arr(C.c_int64, [9, 6]), 4, 1, 1, NULL, alias, NULL, NULL) == -5
+    one_null = _arr(C.c_void_p, [0x5000, 0])
+    assert f(2, m, n, A, lda, 4, 1, 1, one_null, T, NULL, NULL) == -9
+    wide = _arr(C.c_int64, [8, 7])
+    assert f(2, m, wide, A, lda, 4, 1, 1, NULL, T, NULL, NULL) == _lib.RRF_E_NOTSUP
+    huge = _arr(C.c_int64, [8, 5000])
+    assert f(2, huge, n, A, _arr(C.c_int64, [8, 5000]), 4, 1, 1, NULL, T, NULL,
+             NULL) == _lib.RRF_E_NOTSUP
+
+
+def test_batched_workspace_size(lib):
+    f = lib.rrf_randutv_batched_workspace_size
+    ms, ns = [100, 300, 512], [64, 200, 512]
+    m, n = _arr(C.c_int64, ms), _arr(C.c_int64, ns)
+    w16, w64, wauto = f(3, m, n, 16), f(3, m, n, 64), f(3, m, n, 0)
+    assert w16 > 0 and w64 > 0 and wauto > 0
+    # at least the kept reflectors (m n + n^2 doubles per matrix), and the
+    # automatic choice needs no more than the largest single group would
+    refl = sum(8 * (a * c + c * c) for a, c in zip(ms, ns))
+    assert refl < w16 and refl < w64
+    assert wauto <= max(w16, w64)
+    assert f(3, m, n, 65) == 0
+    assert f(3, m, _arr(C.c_int64, [64, 301, 512]), 16) == 0   # n > m
+    assert f(1, _arr(C.c_int64, [4097]), _arr(C.c_int64, [4]), 16) == 0
+    assert f(2, m, n, 16) < w16

@@ -1,0 +1,181 @@
+"""GPU parity of rrf_randutv_batched (Alg. 3 on many small matrices in one
+call) against the FP64 oracle, matrix by matrix on the same input and the
+same sketch seed (matrix j uses seed + j).
+
+Per matrix the gates are those of the single-matrix tests: U and V
+orthogonal and A = U T V^T to 1e-13 (2-norms), T exactly upper trapezoidal,
+each b x b diagonal block diagonal, non-negative and descending, and |T_kk|
+equal to the oracle's where that value is well posed (1e-10 relative plus
+10 n u ||A||), of the same magnitude where the sketch is numerically rank
+deficient. At the full batch size (4096 matrices, n ~ U[64, 512],
+m ~ U[n, 2n], q = 1, automatic b) every matrix is checked for orthogonality
+and reconstruction on the GPU, and a sample against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import metrics as M
+from synthetic import batch_gaussians, batch_shapes, gaussian_matrix, spectral_matrix, spectrum
+
+from test_gpu_factorizations import (_check_blocks, _check_factorization, _diag_parity_derived,
+                                     _host, _to_dev, U64)
+
+pytestmark = pytest.mark.gpu
+
+
+def _auto_b(n):
+    return 16 if n <= 128 else (32 if n <= 320 else 64)
+
+
+def _run(As_host, b, q, seed, gpu, **kw):
+    from paper_2106_13402_amd import randutv_batched
+    As = [_to_dev(A, gpu) for A in As_host]
+    Us, Ts, Vs = randutv_batched(As, b, q, seed, **kw)
+    return ([_host(U) for U in Us] if Us is not None else None, [_host(T) for T in Ts],
+            [_host(V) for V in Vs] if Vs is not None else None)
+
+
+def _check_against_oracle(As, Us, Ts, Vs, b, q, seed):
+    for j, A in enumerate(As):
+        bj = b if b > 0 else _auto_b(A.shape[1])
+        print(f"  matrix {j}: {A.shape[0]}x{A.shape[1]} b={bj}", flush=True)
+        _check_factorization(A, Us[j], Ts[j], Vs[j])
+        _check_blocks(Ts[j], bj)
+        To, rel = _diag_parity_derived(Ts[j], A, bj, q, seed + j)
+        if rel < 1e-12:
+            np.testing.assert_allclose(np.abs(Ts[j]), np.abs(To), atol=1e-9 * M.spec(A))
+
+
+MIXED = [(40, 30), (64, 64), (33, 17), (100, 64), (9, 4), (70, 70), (1, 1), (5, 1), (130, 129),
+         (250, 90)]
+
+
+@pytest.mark.parametrize("b", [8, 16, 32, 64])
+@pytest.mark.parametrize("q", [0, 1])
+def test_batched_mixed_shapes(gpu, b, q):
+    """Ragged batch: square, tall, n < b, n = 1, a tail block of every width,
+    and (b = 64) panels taller than one workgroup holds."""
+    print(f"case: batched mixed shapes b={b} q={q}", flush=True)
+    As = [gaussian_matrix(m, n, seed=100 + j) for j, (m, n) in enumerate(MIXED)]
+    Us, Ts, Vs = _run(As, b, q, 3, gpu)
+    _check_against_oracle(As, Us, Ts, Vs, b, q, 3)
+
+
+@pytest.mark.parametrize("shapes,b", [([(600, 100), (520, 64), (300, 200)], 64),
+                                      ([(1100, 40), (1030, 33)], 32)])
+def test_batched_split_panels(gpu, shapes, b):
+    """Panels split by columns once or twice (rows beyond one workgroup's LDS)."""
+    print(f"case: batched split panels {shapes} b={b}", flush=True)
+    As = [gaussian_matrix(m, n, seed=200 + j) for j, (m, n) in enumerate(shapes)]
+    Us, Ts, Vs = _run(As, b, 1, 11, gpu)
+    _check_against_oracle(As, Us, Ts, Vs, b, 1, 11)
+
+
+def test_batched_decaying_spectra(gpu):
+    """Rank-revealing quality on graded spectra: the trailing norms on the
+    block grid match the oracle's."""
+    print("case: batched decaying spectra", flush=True)
+    shapes = [(200, 160), (256, 256), (300, 150)]
+    As = [spectral_matrix(m, n, spectrum("geometric", n, decades=10.0), seed=j)
+          for j, (m, n) in enumerate(shapes)]
+    Us, Ts, Vs = _run(As, 16, 1, 21, gpu)
+    for j, A in enumerate(As):
+        n = A.shape[1]
+        _check_factorization(A, Us[j], Ts[j], Vs[j])
+        _check_blocks(Ts[j], 16)
+        _, To, _ = oracle.randutv(A, 16, 1, 21 + j, want_u=False, want_v=False)
+        ks = np.arange(0, n, 16)
+        eg, eo = M.trailing_norms(Ts[j], ks), M.trailing_norms(To, ks)
+        assert np.all(np.abs(eg - eo) <= 1e-10 * eo + 10 * n * U64 * M.spec(A))
+
+
+def test_batched_matches_single_calls(gpu):
+    """Matrix j of a batch equals rrf_randutv with seed + j (to rounding)."""
+    from paper_2106_13402_amd import randutv
+    print("case: batched vs single calls", flush=True)
+    shapes = [(120, 96), (96, 96), (200, 64), (64, 50)]
+    As = [gaussian_matrix(m, n, seed=300 + j) for j, (m, n) in enumerate(shapes)]
+    Us, Ts, Vs = _run(As, 16, 2, 40, gpu)
+    for j, A in enumerate(As):
+        _, T1, _ = randutv(_to_dev(A, gpu), 16, 2, 40 + j)
+        np.testing.assert_allclose(np.abs(Ts[j]), np.abs(_host(T1)), atol=1e-9 * M.spec(A))
+
+
+def test_batched_auto_block(gpu):
+    """b = 0: block size 16 / 32 / 64 chosen from n, one group per size."""
+    print("case: batched automatic block size", flush=True)
+    shapes = [(150, 100), (240, 200), (400, 330), (128, 128), (90, 70)]
+    As = [gaussian_matrix(m, n, seed=400 + j) for j, (m, n) in enumerate(shapes)]
+    Us, Ts, Vs = _run(As, 0, 1, 50, gpu)
+    _check_against_oracle(As, Us, Ts, Vs, 0, 1, 50)
+
+
+def test_batched_options_and_edges(gpu):
+    import torch
+    from paper_2106_13402_amd import RRFError, colmajor, randutv_batched
+    print("case: batched options and edges", flush=True)
+    # no U / no V; padded leading dimension; zero and identity matrices
+    A0 = gaussian_matrix(80, 60, seed=5)
+    big = torch.zeros((97, 60), dtype=torch.float64, device=gpu).t().contiguous().t()
+    big[:80] = torch.as_tensor(A0, device=gpu)
+    Z = torch.zeros((50, 40), dtype=torch.float64, device=gpu).t().contiguous().t()
+    I = colmajor(torch.eye(64, dtype=torch.float64, device=gpu))
+    Us, Ts, Vs = randutv_batched([big[:80], Z, I], 16, 1, 7, want_u=False)
+    assert Us is None and len(Vs) == 3
+    _, To, _ = oracle.randutv(A0, 16, 1, 7, want_u=False, want_v=False)
+    np.testing.assert_allclose(np.abs(_host(Ts[0])), np.abs(To), atol=1e-9 * M.spec(A0))
+    assert np.all(_host(Ts[1]) == 0.0) and M.orth_error(_host(Vs[1])) < 1e-13
+    np.testing.assert_allclose(_host(Ts[2]), np.eye(64), atol=1e-13)
+    _, Ts2, Vs2 = randutv_batched([big[:80]], 16, 1, 7, want_u=False, want_v=False)
+    assert Vs2 is None
+    np.testing.assert_allclose(_host(Ts2[0]), _host(Ts[0]), rtol=0, atol=0)  # deterministic
+    # in place: T[j] is A[j]
+    from paper_2106_13402_amd import empty_colmajor
+    A1 = colmajor(_to_dev(gaussian_matrix(70, 50, seed=6), gpu).clone())
+    ref = _host(A1).copy()
+    out = ([empty_colmajor(70, 70, gpu)], [A1], [empty_colmajor(50, 50, gpu)])
+    Us3, Ts3, Vs3 = randutv_batched([A1], 16, 0, 9, out=out)
+    assert Ts3[0].data_ptr() == A1.data_ptr()
+    _check_factorization(ref, _host(Us3[0]), _host(A1), _host(Vs3[0]))
+    # non-finite input is rejected when asked
+    bad = _to_dev(gaussian_matrix(20, 10, seed=8), gpu).clone()
+    bad[3, 4] = float("nan")
+    with pytest.raises(RRFError) as e:
+        randutv_batched([_to_dev(A0, gpu), bad], 8, 1, 1, check_finite=True)
+    assert e.value.status == 4
+
+
+def test_batched_full_size(gpu):
+    """4096 matrices, n ~ U[64, 512], m ~ U[n, 2n], q = 1, automatic b:
+    every matrix checked on the GPU (Frobenius-norm bounds, which imply the
+    2-norm ones), six of them against the oracle."""
+    import torch
+    from paper_2106_13402_amd import randutv_batched
+    shapes = batch_shapes(4096, seed=0)
+    print(f"case: batched full size, {len(shapes)} matrices", flush=True)
+    As = batch_gaussians(shapes, seed=0, device=gpu)
+    Us, Ts, Vs = randutv_batched(As, 0, 1, 1000)
+    torch.cuda.synchronize()
+    print("  factored", flush=True)
+    worst_o, worst_r = 0.0, 0.0
+    for j, (m, n) in enumerate(shapes):
+        U, T, V, A = Us[j], Ts[j], Vs[j], As[j]
+        eo = max(float(torch.linalg.norm(U.t() @ U - torch.eye(m, dtype=U.dtype, device=gpu))),
+                 float(torch.linalg.norm(V.t() @ V - torch.eye(n, dtype=V.dtype, device=gpu))))
+        er = float(torch.linalg.norm(A - U @ T @ V.t()) / torch.linalg.norm(A))
+        worst_o, worst_r = max(worst_o, eo), max(worst_r, er)
+        if n > 1:
+            assert float(torch.tril(T, -1).abs().max()) == 0.0
+    print(f"  worst ||U^T U - I||_F, ||V^T V - I||_F = {worst_o:.2e}, "
+          f"||A - U T V^T||_F / ||A||_F = {worst_r:.2e}", flush=True)
+    assert worst_o <= 1e-12 and worst_r <= 1e-13
+    rng = np.random.default_rng(1)
+    small = [j for j, (m, n) in enumerate(shapes) if n <= 200]
+    for j in list(rng.choice(small, size=6, replace=False)):
+        A = _host(As[j]).copy(order="F")
+        bj = _auto_b(A.shape[1])
+        T = _host(Ts[j])
+        _check_blocks(T, bj)
+        _, To, _ = oracle.randutv(A, bj, 1, 1000 + int(j), want_u=False, want_v=False)
+        np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * M.spec(A))
