@@ -63,6 +63,134 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Singular values, descending order, outputs, completion of Us and the sign
+// rule, for a converged block: Aw = A V and Vw = V, columns ldw apart, in
+// LDS or global memory; NT threads; the small shared arrays come from the
+// kernel.
+template <int NT>
+__device__ void finish_block(int k, const double* Aw, const double* Vw, int ldw, double* sig,
+                             int* perm, double* coef, int& pick, double* Usb, double* Vsb,
+                             double* db) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // Column norms = singular values.
+  for (int c = wave; c < k; c += (NT / 64)) {
+    double s = 0.0;
+    for (int r = lane; r < k; r += 64) {
+      const double x = Aw[(size_t)c * ldw + r];
+      s += x * x;
+    }
+    s = wave_sum(s);
+    if (lane == 0) sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  // Descending order, ties broken by column index. The sort key maps NaN
+  // (non-finite input) below every norm, so (key, index) is a strict total
+  // order and the ranks always form a permutation of 0..k-1.
+  for (int c = tid; c < k; c += NT) {
+    int rank = 0;
+    const double sc = (sig[c] == sig[c]) ? sig[c] : -1.0;
+    for (int i = 0; i < k; ++i) {
+      const double si = (sig[i] == sig[i]) ? sig[i] : -1.0;
+      rank += (si > sc) || (si == sc && i < c);
+    }
+    perm[rank] = c;
+  }
+  __syncthreads();
+  const double tiny = DBL_MIN * (double)k;
+  for (int idx = tid; idx < k * k; idx += NT) {
+    const int r = idx % k, pos = idx / k;
+    const int c = perm[pos];
+    const double sc = sig[c];
+    Vsb[(size_t)pos * k + r] = Vw[(size_t)c * ldw + r];
+    Usb[(size_t)pos * k + r] = (sc > tiny) ? Aw[(size_t)c * ldw + r] / sc : 0.0;
+  }
+  for (int pos = tid; pos < k; pos += NT) db[pos] = sig[perm[pos]];
+  __syncthreads();
+
+  // Complete Us where d = 0 (these positions come last in the sorted order).
+  for (int pos = 0; pos < k; ++pos) {
+    if (sig[perm[pos]] > tiny) continue;
+    double* U = Usb;
+    // coverage of coordinate i by the columns 0..pos-1
+    for (int i = tid; i < k; i += NT) {
+      double s = 0.0;
+      for (int c = 0; c < pos; ++c) {
+        const double x = U[(size_t)c * k + i];
+        s += x * x;
+      }
+      coef[i] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int best = 0;
+      for (int i = 1; i < k; ++i)
+        if (coef[i] < coef[best]) best = i;
+      pick = best;
+    }
+    __syncthreads();
+    const int ip = pick;
+    // u = e_ip - U U(ip,:)^T, then one re-orthogonalization pass.
+    double* u = U + (size_t)pos * k;
+    for (int r = tid; r < k; r += NT) {
+      double s = (r == ip) ? 1.0 : 0.0;
+      for (int c = 0; c < pos; ++c) s -= U[(size_t)c * k + r] * U[(size_t)c * k + ip];
+      u[r] = s;
+    }
+    __syncthreads();
+    for (int c = tid; c < pos; c += NT) {
+      double s = 0.0;
+      for (int r = 0; r < k; ++r) s += U[(size_t)c * k + r] * u[r];
+      coef[c] = s;
+    }
+    __syncthreads();
+    for (int r = tid; r < k; r += NT) {
+      double s = u[r];
+      for (int c = 0; c < pos; ++c) s -= U[(size_t)c * k + r] * coef[c];
+      u[r] = s;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      double s = 0.0;
+      for (int r = lane; r < k; r += 64) s += u[r] * u[r];
+      s = wave_sum(s);
+      if (lane == 0) coef[0] = 1.0 / sqrt(s);
+    }
+    __syncthreads();
+    const double inv = coef[0];
+    for (int r = tid; r < k; r += NT) u[r] *= inv;
+    __syncthreads();
+  }
+
+  // Sign rule: the entry of v_j of largest magnitude is positive.
+  for (int pos = wave; pos < k; pos += (NT / 64)) {
+    double best = -1.0;
+    int bi = 0;  // stays a valid row even if every entry is NaN
+    for (int r = lane; r < k; r += 64) {
+      const double x = fabs(Vsb[(size_t)pos * k + r]);
+      if (x > best || (x == best && r < bi)) {
+        best = x;
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    const bool flip = Vsb[(size_t)pos * k + bi] < 0.0;
+    if (flip) {
+      for (int r = lane; r < k; r += 64) {
+        Vsb[(size_t)pos * k + r] = -Vsb[(size_t)pos * k + r];
+        Usb[(size_t)pos * k + r] = -Usb[(size_t)pos * k + r];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void jacobi_svd_kernel(SvdArgs a) {
   extern __shared__ double lds[];
   __shared__ double sig[kMaxK];
@@ -150,126 +278,129 @@ __global__ __launch_bounds__(kThreads) void jacobi_svd_kernel(SvdArgs a) {
   }
   if (!converged && tid == 0) atomicOr(a.status, 2);
 
-  // Column norms = singular values.
-  for (int c = wave; c < k; c += kWaves) {
-    double s = 0.0;
-    for (int r = lane; r < k; r += 64) {
-      const double x = Aw[(size_t)c * k + r];
-      s += x * x;
-    }
-    s = wave_sum(s);
-    if (lane == 0) sig[c] = sqrt(s);
+  finish_block<kThreads>(k, Aw, Vw, k, sig, perm, coef, pick, Usb, Vsb, db);
+}
+
+// Blocks of k <= 64 on one wave each: the k/2 disjoint pairs of a round are
+// spread over the wave, L = 64 / P lanes per pair (P = k/2 rounded up to a
+// power of two), the lanes of a pair striding over the rows and reducing
+// their three inner products among themselves. Same rotation, threshold,
+// ordering and post-processing as jacobi_svd_kernel; A V and V in LDS with
+// columns k + 1 apart (distinct pairs fall on distinct banks).
+constexpr int kSmallK = 64;
+
+__global__ __launch_bounds__(64) void jacobi_small_kernel(SvdArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double sig[kSmallK];
+  __shared__ int perm[kSmallK];
+  __shared__ double coef[kSmallK];
+  __shared__ int pick;
+
+  const int blk = blockIdx.x;
+  const int k = a.sizes ? a.sizes[blk] : ((blk == a.count - 1) ? a.k_last : a.k);
+  const int lane = threadIdx.x;
+  const int ld = k + 1;
+  double* Aw = lds;
+  double* Vw = lds + (size_t)k * ld;
+  const double* Bb = a.B + (int64_t)blk * a.stride;
+  double* Usb = a.Us + (int64_t)blk * a.stride;
+  double* Vsb = a.Vs + (int64_t)blk * a.stride;
+  double* db = a.d + (int64_t)blk * a.dstride;
+
+  for (int idx = lane; idx < k * k; idx += 64) {
+    const int i = idx % k, j = idx / k;
+    Aw[i + j * ld] = Bb[i + (int64_t)j * a.ldb];
+    Vw[i + j * ld] = (i == j) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  // Descending order, ties broken by column index. The sort key maps NaN
-  // (non-finite input) below every norm, so (key, index) is a strict total
-  // order and the ranks always form a permutation of 0..k-1.
-  for (int c = tid; c < k; c += kThreads) {
-    int rank = 0;
-    const double sc = (sig[c] == sig[c]) ? sig[c] : -1.0;
-    for (int i = 0; i < k; ++i) {
-      const double si = (sig[i] == sig[i]) ? sig[i] : -1.0;
-      rank += (si > sc) || (si == sc && i < c);
-    }
-    perm[rank] = c;
-  }
-  __syncthreads();
-  const double tiny = DBL_MIN * (double)k;
-  for (int idx = tid; idx < k * k; idx += kThreads) {
-    const int r = idx % k, pos = idx / k;
-    const int c = perm[pos];
-    const double sc = sig[c];
-    Vsb[(size_t)pos * k + r] = Vw[(size_t)c * k + r];
-    Usb[(size_t)pos * k + r] = (sc > tiny) ? Aw[(size_t)c * k + r] / sc : 0.0;
-  }
-  for (int pos = tid; pos < k; pos += kThreads) db[pos] = sig[perm[pos]];
   __syncthreads();
 
-  // Complete Us where d = 0 (these positions come last in the sorted order).
-  for (int pos = 0; pos < k; ++pos) {
-    if (sig[perm[pos]] > tiny) continue;
-    double* U = Usb;
-    // coverage of coordinate i by the columns 0..pos-1
-    for (int i = tid; i < k; i += kThreads) {
-      double s = 0.0;
-      for (int c = 0; c < pos; ++c) {
-        const double x = U[(size_t)c * k + i];
-        s += x * x;
+  const int kk = k + (k & 1);
+  const int npairs = kk / 2;
+  int P = 1;
+  while (P < npairs) P <<= 1;
+  const int L = 64 / P;
+  const int pi = lane / L, sub = lane % L;
+  const double tol = DBL_EPSILON * fmax(sqrt((double)k), 8.0);
+  bool converged = (k == 1);
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    int rot = 0;
+    for (int round = 0; round < kk - 1; ++round) {
+      int p, q;
+      if (pi == 0) {
+        p = round;
+        q = kk - 1;
+      } else {
+        p = (round + pi) % (kk - 1);
+        q = (round - pi + kk - 1) % (kk - 1);
       }
-      coef[i] = s;
+      if (p > q) {
+        const int t = p;
+        p = q;
+        q = t;
+      }
+      const bool active = pi < npairs && q < k;
+      double* ap = Aw + (size_t)p * ld;
+      double* aq = Aw + (size_t)q * ld;
+      double app = 0.0, aqq = 0.0, apq = 0.0;
+      if (active)
+        for (int r = sub; r < k; r += L) {
+          const double x = ap[r], y = aq[r];
+          app += x * x;
+          aqq += y * y;
+          apq += x * y;
+        }
+      for (int off = L / 2; off > 0; off >>= 1) {
+        app += __shfl_xor(app, off, 64);
+        aqq += __shfl_xor(aqq, off, 64);
+        apq += __shfl_xor(apq, off, 64);
+      }
+      if (active && apq != 0.0 && fabs(apq) > tol * sqrt(app) * sqrt(aqq)) {
+        const double zeta = (aqq - app) / (2.0 * apq);
+        double t;
+        if (fabs(zeta) > 1e150) t = 0.5 / zeta;
+        else t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t);
+        const double s = c * t;
+        double* vp = Vw + (size_t)p * ld;
+        double* vq = Vw + (size_t)q * ld;
+        for (int r = sub; r < k; r += L) {
+          const double x = ap[r], y = aq[r];
+          ap[r] = c * x - s * y;
+          aq[r] = s * x + c * y;
+          const double u = vp[r], w = vq[r];
+          vp[r] = c * u - s * w;
+          vq[r] = s * u + c * w;
+        }
+        rot = 1;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    if (tid == 0) {
-      int best = 0;
-      for (int i = 1; i < k; ++i)
-        if (coef[i] < coef[best]) best = i;
-      pick = best;
-    }
-    __syncthreads();
-    const int ip = pick;
-    // u = e_ip - U U(ip,:)^T, then one re-orthogonalization pass.
-    double* u = U + (size_t)pos * k;
-    for (int r = tid; r < k; r += kThreads) {
-      double s = (r == ip) ? 1.0 : 0.0;
-      for (int c = 0; c < pos; ++c) s -= U[(size_t)c * k + r] * U[(size_t)c * k + ip];
-      u[r] = s;
-    }
-    __syncthreads();
-    for (int c = tid; c < pos; c += kThreads) {
-      double s = 0.0;
-      for (int r = 0; r < k; ++r) s += U[(size_t)c * k + r] * u[r];
-      coef[c] = s;
-    }
-    __syncthreads();
-    for (int r = tid; r < k; r += kThreads) {
-      double s = u[r];
-      for (int c = 0; c < pos; ++c) s -= U[(size_t)c * k + r] * coef[c];
-      u[r] = s;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double s = 0.0;
-      for (int r = lane; r < k; r += 64) s += u[r] * u[r];
-      s = wave_sum(s);
-      if (lane == 0) coef[0] = 1.0 / sqrt(s);
-    }
-    __syncthreads();
-    const double inv = coef[0];
-    for (int r = tid; r < k; r += kThreads) u[r] *= inv;
-    __syncthreads();
+    converged = !__any(rot);
   }
-
-  // Sign rule: the entry of v_j of largest magnitude is positive.
-  for (int pos = wave; pos < k; pos += kWaves) {
-    double best = -1.0;
-    int bi = 0;  // stays a valid row even if every entry is NaN
-    for (int r = lane; r < k; r += 64) {
-      const double x = fabs(Vsb[(size_t)pos * k + r]);
-      if (x > best || (x == best && r < bi)) {
-        best = x;
-        bi = r;
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    const bool flip = Vsb[(size_t)pos * k + bi] < 0.0;
-    if (flip) {
-      for (int r = lane; r < k; r += 64) {
-        Vsb[(size_t)pos * k + r] = -Vsb[(size_t)pos * k + r];
-        Usb[(size_t)pos * k + r] = -Usb[(size_t)pos * k + r];
-      }
-    }
-  }
+  if (!converged && lane == 0) atomicOr(a.status, 2);
+  finish_block<64>(k, Aw, Vw, ld, sig, perm, coef, pick, Usb, Vsb, db);
 }
 
 bool g_attr_set = false;
+bool g_small_attr_set = false;
+
+// LDS of the one-wave kernel for blocks up to k.
+size_t small_lds(int k) { return (size_t)2 * k * (k + 1) * 8; }
+
+int launch_small(hipStream_t st, const SvdArgs& a, int kmax) {
+  if (!g_small_attr_set) {
+    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_small_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)small_lds(kSmallK)));
+    g_small_attr_set = true;
+  }
+  int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * kmax * kmax * a.count);
+  hipLaunchKernelGGL(jacobi_small_kernel, dim3(a.count), dim3(64), small_lds(kmax), st, a);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
 
 }  // namespace
 
@@ -281,6 +412,21 @@ int block_svd_batched(hipStream_t st, int count, int k, int k_last, const double
   if (count < 1) return RRF_OK;
   if (k < 1 || k > kMaxK || k_last < 1 || k_last > k)
     return set_error(RRF_E_NOTSUP, "block svd: need 1 <= k_last <= k <= 256");
+  if (k <= kSmallK) {
+    SvdArgs a{};
+    a.k = k;
+    a.k_last = k_last;
+    a.count = count;
+    a.stride = stride;
+    a.dstride = dstride;
+    a.B = B;
+    a.ldb = ldb;
+    a.Us = Us;
+    a.d = d;
+    a.Vs = Vs;
+    a.status = status;
+    return launch_small(st, a, k);
+  }
   const size_t need = (size_t)2 * k * k * 8;
   const bool in_lds = need <= kLdsBudget;
   if (!in_lds && (work == nullptr || work_bytes < need * count))
@@ -317,6 +463,22 @@ int block_svd_sized(hipStream_t st, int count, int kmax, const int* d_sizes, con
                     double* Vs, void* work, size_t work_bytes, int* status) {
   if (count < 1) return RRF_OK;
   if (kmax < 1 || kmax > kMaxK) return set_error(RRF_E_NOTSUP, "block svd: need k <= 256");
+  if (kmax <= kSmallK) {
+    SvdArgs a{};
+    a.k = kmax;
+    a.k_last = kmax;
+    a.count = count;
+    a.stride = stride;
+    a.dstride = dstride;
+    a.B = B;
+    a.ldb = ldb;
+    a.Us = Us;
+    a.d = d;
+    a.Vs = Vs;
+    a.status = status;
+    a.sizes = d_sizes;
+    return launch_small(st, a, kmax);
+  }
   const size_t need = (size_t)2 * kmax * kmax * 8;
   const bool in_lds = need <= kLdsBudget;
   if (!in_lds && (work == nullptr || work_bytes < need * count))

@@ -159,7 +159,7 @@ def test_householder_panel_inplace(gpu):
 
 
 # ------------------------------------------------------------- block SVD
-@pytest.mark.parametrize("k", [1, 2, 7, 32, 64, 100, 128, 256])
+@pytest.mark.parametrize("k", [1, 2, 7, 16, 32, 33, 63, 64, 65, 100, 128, 256])
 def test_block_svd(gpu, k):
     from paper_2106_13402_amd import block_svd
     rng = np.random.default_rng(k)
