@@ -11,8 +11,10 @@ seconds, lower is better), the roofline entry of the dominant kernel measured
 live with HIP events on the library's stream, the accuracy of the result
 against the known spectrum, the same factorization with the bfloat16 sketch
 (RRF_PREC_BF16_SKETCH) timed the same way and held to e_k <= max(1.5
-sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), the FP64 CPU oracle
+timed on a bounded sample of the same workload, and ("batched") the batched
+call on 4096 small matrices (n ~ U{64..512}, m ~ U{n..2n}, graded spectrum,
+q = 1, automatic b) in matrices per second with every matrix's residual.
 
     python bench.py [--steps K] [--warmup W] [--n N] [--b B] [--q Q]
 """
@@ -181,6 +183,97 @@ def cpu_baseline(A_host, b, q, seed, budget_s):
     }
 
 
+# ------------------------------------------------------------- batched leg
+def auto_block(n: int) -> int:
+    """Block size the batched call picks for b = 0."""
+    return 16 if n <= 128 else (32 if n <= 320 else 64)
+
+
+def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seconds: float,
+                cpu: bool) -> dict:
+    """rrf_randutv_batched on `count` matrices, n ~ U{64..512}, m ~ U{n..2n},
+    A_j = Q1 diag(10^(-8 (i-1)/(n-1))) Q2^T, automatic b, U and V accumulated;
+    matrices per second over `steps` timed calls, the relative residual of
+    every matrix, and the oracle timed on a bounded sample."""
+    import numpy as np
+    import torch
+
+    import paper_2106_13402_amd as rrf
+    from synthetic import batch_shapes, batch_spectral
+
+    dev = torch.device("cuda:0")
+    shapes = batch_shapes(count, seed=0)
+    t0 = time.perf_counter()
+    As = batch_spectral(shapes, seed=0, decades=8.0, device=dev)
+    torch.cuda.synchronize()
+    log(f"batched: {count} matrices generated in {time.perf_counter() - t0:.1f} s")
+    out = ([rrf.empty_colmajor(m, m, dev) for m, n in shapes],
+           [rrf.empty_colmajor(m, n, dev) for m, n in shapes],
+           [rrf.empty_colmajor(n, n, dev) for m, n in shapes])
+    for _ in range(max(warmup, 1)):
+        rrf.randutv_batched(As, 0, q, seed, out=out)
+    torch.cuda.synchronize()
+    rrf.trace_enable(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        rrf.randutv_batched(As, 0, q, seed, out=out)
+    torch.cuda.synchronize()
+    per = (time.perf_counter() - t0) / steps
+    kern = rrf.trace_read()
+    rrf.trace_enable(False)
+    log(f"batched: {per * 1e3:.1f} ms per call, {count / per:.0f} matrices/s")
+    flops = sum(total_flops(m, n, auto_block(n), q) for m, n in shapes)
+    Us, Ts, Vs = out
+    res = torch.empty(count, dtype=torch.float64, device=dev)
+    orth = torch.empty(count, dtype=torch.float64, device=dev)
+    for j, (m, n) in enumerate(shapes):
+        A = As[j]
+        res[j] = torch.linalg.norm(A - Us[j] @ Ts[j] @ Vs[j].t()) / torch.linalg.norm(A)
+        eu = torch.linalg.norm(Us[j].t() @ Us[j] - torch.eye(m, dtype=A.dtype, device=dev))
+        ev = torch.linalg.norm(Vs[j].t() @ Vs[j] - torch.eye(n, dtype=A.dtype, device=dev))
+        orth[j] = torch.maximum(eu, ev)
+    res, orth = res.cpu().numpy(), orth.cpu().numpy()
+    kernels = {e["name"]: {"launches": e["launches"] // steps, "ms_per_call": e["ms"] / steps,
+                           "tflops": (e["flops"] / (e["ms"] * 1e-3) / 1e12) if e["flops"] else None}
+               for e in kern}
+    leg = {
+        "workload": (f"randUTV of {count} matrices, n ~ U{{64..512}}, m ~ U{{n..2n}}, "
+                     f"A = Q1 diag(10^(-8(i-1)/(n-1))) Q2^T, q={q}, b chosen per matrix "
+                     f"(16 / 32 / 64 for n <= 128 / 320 / 512), U and V accumulated, FP64"),
+        "value": count / per, "unit": "matrices/s", "ms_per_call": per * 1e3,
+        "model_flops": flops, "model_tflops": flops / per / 1e12,
+        "residual_fro_rel": {"max": float(res.max()), "median": float(np.median(res)),
+                             "p99": float(np.quantile(res, 0.99))},
+        "orth_fro_max": float(orth.max()),
+        "kernels": kernels,
+    }
+    if cpu:
+        import oracle
+        done, fl, t0 = 0, 0.0, time.perf_counter()
+        for j, (m, n) in enumerate(shapes):
+            oracle.randutv(As[j].cpu().numpy().copy(order="F"), auto_block(n), q, seed + j)
+            done += 1
+            fl += total_flops(m, n, auto_block(n), q)
+            if time.perf_counter() - t0 >= cpu_seconds:
+                break
+        el = time.perf_counter() - t0
+        rate = fl / el
+        cores = len(os.sched_getaffinity(0))
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max(int(p.get("num_threads", 0)) for p in threadpool_info()) or cores
+        except Exception:
+            pass
+        leg["cpu_baseline"] = {
+            "value": count / (flops / rate), "unit": "matrices/s", "cores": cores,
+            "kind": "oracle",
+            "sample": (f"the first {done} matrices of the batch, one after another, in "
+                       f"{el:.1f} s ({rate / 1e9:.1f} GFLOP/s); matrices/s for the whole batch "
+                       f"by the algorithmic flop model"),
+        }
+    return leg
+
+
 # ---------------------------------------------------------------------- main
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
@@ -195,6 +288,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch", type=int, default=4096, help="matrices in the batched leg")
+    ap.add_argument("--batch-q", type=int, default=1)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -334,6 +430,9 @@ def main() -> int:
         A_host = A.cpu().numpy()
         del U, T, V
         out["cpu_baseline"] = cpu_baseline(A_host, b, q, args.seed, args.cpu_seconds)
+    if not args.no_batched:
+        out["batched"] = batched_leg(args.batch, args.batch_q, args.steps, args.warmup, args.seed,
+                                     args.cpu_seconds / 2, not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
     return 0
 

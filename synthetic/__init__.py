@@ -7,10 +7,11 @@ from .matrices import (
     SPECTRA,
     batch_gaussians,
     batch_shapes,
+    batch_spectral,
     gaussian_matrix,
     haar,
     spectral_matrix,
     spectrum,
 )
 
-__all__ = ["SPECTRA", "batch_gaussians", "batch_shapes", "gaussian_matrix", "haar", "spectral_matrix", "spectrum"]
+__all__ = ["SPECTRA", "batch_gaussians", "batch_shapes", "batch_spectral", "gaussian_matrix", "haar", "spectral_matrix", "spectrum"]

@@ -137,5 +137,49 @@ def batch_gaussians(shapes, seed: int = 0, device=None):
     return out
 
 
+def _spectral_one(m: int, n: int, seed: int, j: int, decades: float) -> np.ndarray:
+    rng = np.random.default_rng([int(seed), 6, int(j)])
+    q = []
+    for r, c in ((m, n), (n, n)):
+        Q, R = np.linalg.qr(rng.standard_normal((r, c)))
+        d = np.sign(np.diag(R))
+        d[d == 0] = 1.0
+        q.append(Q * d[None, :])
+    s = 10.0 ** (-decades * np.arange(n, dtype=np.float64) / max(n - 1, 1))
+    return np.asfortranarray((q[0] * s[None, :]) @ q[1].T)
+
+
+def batch_spectral(shapes, seed: int = 0, decades: float = 8.0, device=None,
+                   workers: int | None = None):
+    """A_j = Q1_j diag(s_j) Q2_j^T for each shape (m, n), s_j,i =
+    10^(-decades (i-1)/(n-1)), Q1_j (m x n) and Q2_j (n x n) Haar with the
+    sign fix of ``haar``, drawn from numpy stream [seed, 6, j]; column-major,
+    ld = m. Made on the host (a thread pool, one BLAS thread each) on every
+    device, so CPU and GPU get the same matrices; on a GPU they are views
+    into one device buffer."""
+    import concurrent.futures as cf
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import contextlib
+    workers = workers or min(16, len(__import__("os").sched_getaffinity(0)))
+    ctx = threadpool_limits(1) if threadpool_limits else contextlib.nullcontext()
+    with ctx, cf.ThreadPoolExecutor(workers) as ex:
+        mats = list(ex.map(lambda a: _spectral_one(a[1][0], a[1][1], seed, a[0], decades),
+                           enumerate(shapes)))
+    if _is_cpu(device):
+        return mats
+    import torch
+    flat = np.concatenate([a.ravel(order="F") for a in mats])
+    del mats
+    buf = torch.from_numpy(flat).to(device)
+    out, off = [], 0
+    for m, n in shapes:
+        out.append(buf[off:off + m * n].view(n, m).t())
+        off += m * n
+    return out
+
+
 def describe(kind: str, **kw) -> str:
     return kind + "(" + ",".join(f"{k}={v}" for k, v in sorted(kw.items())) + ")"
