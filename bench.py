@@ -184,9 +184,10 @@ def cpu_baseline(A_host, b, q, seed, budget_s):
 
 
 # ------------------------------------------------------------- batched leg
-def auto_block(n: int) -> int:
+def auto_block(n: int, m: int = 0) -> int:
     """Block size the batched call picks for b = 0."""
-    return 16 if n <= 128 else (32 if n <= 320 else 64)
+    import paper_2106_13402_amd as rrf
+    return rrf.batched_block(max(m, n), n)
 
 
 def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seconds: float,
@@ -239,7 +240,7 @@ def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seco
     leg = {
         "workload": (f"randUTV of {count} matrices, n ~ U{{64..512}}, m ~ U{{n..2n}}, "
                      f"A = Q1 diag(10^(-8(i-1)/(n-1))) Q2^T, q={q}, b chosen per matrix "
-                     f"(16 / 32 / 64 for n <= 128 / 320 / 512), U and V accumulated, FP64"),
+                     f"(16 for n <= 256, else 32), U and V accumulated, FP64"),
         "value": count / per, "unit": "matrices/s", "ms_per_call": per * 1e3,
         "model_flops": flops, "model_tflops": flops / per / 1e12,
         "residual_fro_rel": {"max": float(res.max()), "median": float(np.median(res)),

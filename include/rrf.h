@@ -140,7 +140,7 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
  *                                                                     (arg 4)
  *  lda    : host array, lda[j] >= m[j]                                (arg 5)
  *  b      : block size for every matrix, 1 <= b <= 64; 0 = chosen per matrix
- *           from n[j] (16 for n <= 128, 32 for n <= 320, else 64)    (arg 6)
+ *           by rrf_randutv_batched_block(m[j], n[j])                 (arg 6)
  *  q      : power iterations, >= 0                                    (arg 7)
  *  seed   : generator key of matrix 0                                 (arg 8)
  *  U      : host array of count device pointers to m[j] x m[j] outputs
@@ -159,6 +159,9 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
                         const double* const* A, const int64_t* lda, int64_t b,
                         int32_t q, uint64_t seed, double* const* U, double* const* T,
                         double* const* V, const rrf_opts* opts);
+/* The block size rrf_randutv_batched uses for an m x n matrix when called
+ * with b = 0 (16 for n <= 256, else 32); 0 for invalid sizes. */
+int64_t rrf_randutv_batched_block(int64_t m, int64_t n);
 /* Bytes of device workspace for rrf_randutv_batched; 0 for invalid sizes. */
 size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m,
                                           const int64_t* n, int64_t b);

@@ -19,7 +19,7 @@ __all__ = [
     "RRFError", "randutv", "powerurv", "gaussian", "dgemm", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
-    "batched_workspace_size",
+    "batched_workspace_size", "batched_block",
 ]
 
 # precision names of rrf_opts.precision
@@ -141,6 +141,11 @@ def _i64_array(vals):
 
 def _ptr_array(vals):
     return (C.c_void_p * max(len(vals), 1))(*vals)
+
+
+def batched_block(m: int, n: int) -> int:
+    """Block size the batched call uses for an m x n matrix when b = 0."""
+    return int(lib.rrf_randutv_batched_block(m, n))
 
 
 def batched_workspace_size(ms, ns, b: int) -> int:

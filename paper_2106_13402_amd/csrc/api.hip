@@ -201,6 +201,11 @@ int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, i
   return rrf_randutv_ex(m, n, A, lda, b, q, seed, U, T, V, nullptr);
 }
 
+int64_t rrf_randutv_batched_block(int64_t m, int64_t n) {
+  if (n < 1 || m < n) return 0;
+  return randutv_batched_block(m, n);
+}
+
 size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m, const int64_t* n,
                                           int64_t b) {
   if (count < 0 || (count > 0 && (m == nullptr || n == nullptr)) || b < 0 || b > kBatchedMaxB)
@@ -210,7 +215,7 @@ size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m, const
   if (b > 0) return count > 0 ? randutv_batched_workspace(count, m, n, b) : 0;
   // automatic block size: the groups run one after another in one workspace
   size_t need = 0;
-  for (int64_t bg : {16, 32, 64}) {
+  for (int64_t bg : {16, 32}) {
     std::vector<int64_t> gm, gn;
     for (int64_t j = 0; j < count; ++j)
       if (randutv_batched_block(m[j], n[j]) == bg) {
@@ -287,7 +292,7 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
   if (b > 0) {
     RRF_TRY(randutv_batched_run(st, count, m, n, A, lda, b, q, seeds.data(), U, T, V, ws, ws_bytes));
   } else {
-    for (int64_t bg : {16, 32, 64}) {
+    for (int64_t bg : {16, 32}) {
       std::vector<int64_t> gm, gn, gl;
       std::vector<const double*> gA;
       std::vector<double*> gU, gT, gV;

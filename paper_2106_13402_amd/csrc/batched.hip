@@ -6,8 +6,8 @@
 // and handles every problem in one launch (grid.y or grid.x = problem), so a
 // round costs a fixed number of launches whatever the batch size:
 //  * gemm_grouped_kernel: C = alpha op(A) op(B) + beta C per problem on the
-//    FP64 matrix cores, 64 x 64 tiles (small problems), workgroups beyond a
-//    problem's tile count exit at once;
+//    FP64 matrix cores, one workgroup per tile of every problem (a flat grid
+//    over all tiles), tile shape chosen per launch by the outputs' width;
 //  * elem_kernel: fill / copy / diagonal / identity per problem;
 //  * gauss_kernel: the sketch Gaussian of each problem (its own key);
 //  * panel_wg_kernel: Householder QR with compact-WY output (Sec. 2.3, the
@@ -15,10 +15,12 @@
 //    The arithmetic is that of the grid-wide panel kernel with every sum
 //    taken inside the workgroup.
 #include <algorithm>
+#include <climits>
 #include <vector>
 
 #include "batched.hpp"
 #include "common.hpp"
+#include "gemm_tile.hpp"
 #include "kernels.hpp"
 #include "philox.hpp"
 #include "trace.hpp"
@@ -29,96 +31,77 @@ namespace {
 
 // --- grouped GEMM ----------------------------------------------------------
 
-constexpr int kGT = 256;       // threads
-constexpr int kGB = 64;        // tile edge
-constexpr int kGK = 16;        // K slice
-constexpr int kGLD = kGB + 1;  // LDS row stride of a [k][mn] slice
-
-template <bool TA, bool TB>
-__global__ __launch_bounds__(kGT) void gemm_grouped_kernel(const GemmDesc* __restrict__ descs) {
-  const GemmDesc g = descs[blockIdx.y];
-  const int64_t tiles_m = (g.M + kGB - 1) / kGB;
-  if ((int64_t)blockIdx.x >= tiles_m * ((g.N + kGB - 1) / kGB)) return;
-  __shared__ double la[2][kGK * kGLD], lb[2][kGK * kGLD];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;  // 2 x 2 waves of 32 x 32
-  const int64_t i0 = (int64_t)(blockIdx.x % tiles_m) * kGB;
-  const int64_t j0 = (int64_t)(blockIdx.x / tiles_m) * kGB;
-  const int lr = lane & 15, lk = lane >> 4;
-
-  f64x4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-
-  // element e of the 64 x 16 slice: the operand's contiguous dimension first
-  auto load = [&](double (&ra)[4], double (&rb)[4], int64_t k0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + kGT * i;
-      int mm, kk, nn, k2;
-      if (TA) { kk = e % kGK; mm = e / kGK; } else { mm = e % kGB; kk = e / kGB; }
-      if (TB) { nn = e % kGB; k2 = e / kGB; } else { k2 = e % kGK; nn = e / kGK; }
-      const int64_t gm = i0 + mm, ga = k0 + kk, gn = j0 + nn, gb = k0 + k2;
-      ra[i] = (gm < g.M && ga < g.K) ? (TA ? g.A[ga + gm * g.lda] : g.A[gm + ga * g.lda]) : 0.0;
-      rb[i] = (gn < g.N && gb < g.K) ? (TB ? g.B[gn + gb * g.ldb] : g.B[gb + gn * g.ldb]) : 0.0;
-    }
-  };
-  auto store = [&](int buf, const double (&ra)[4], const double (&rb)[4]) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + kGT * i;
-      int mm, kk, nn, k2;
-      if (TA) { kk = e % kGK; mm = e / kGK; } else { mm = e % kGB; kk = e / kGB; }
-      if (TB) { nn = e % kGB; k2 = e / kGB; } else { k2 = e % kGK; nn = e / kGK; }
-      la[buf][kk * kGLD + mm] = ra[i];
-      lb[buf][k2 * kGLD + nn] = rb[i];
-    }
-  };
-
-  if (g.K > 0) {
-    double ra[4], rb[4];
-    load(ra, rb, 0);
-    store(0, ra, rb);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
-      const bool more = k0 + kGK < g.K;
-      if (more) load(ra, rb, k0 + kGK);
-#pragma unroll
-      for (int kk = 0; kk < kGK; kk += 4) {
-        double af[2], bf[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) af[a] = la[buf][(kk + lk) * kGLD + wm * 32 + a * 16 + lr];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) bf[b] = lb[buf][(kk + lk) * kGLD + wn * 32 + b * 16 + lr];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[b], af[a], acc[a][b], 0, 0, 0);
-      }
-      if (more) store(buf ^ 1, ra, rb);
-      __syncthreads();
-      buf ^= 1;
-    }
+// One BM x BN tile of one problem per workgroup (the MFMA tile loop of
+// gemm_tile.hpp); the workgroup finds its problem by binary search of the
+// running tile counts.
+template <bool TA, bool TB, int BM, int BN, int GM, int GN, bool VEC>
+__global__ __launch_bounds__(tile::kThreads, 2) void gemm_grouped_kernel(
+    const GemmDesc* __restrict__ descs, const int* __restrict__ prefix, int count) {
+  using TL = tile::Tile<BM, BN, TA, TB, VEC, GM, GN>;
+  __shared__ double lds[TL::LDS];
+  const int bid = blockIdx.x;
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= bid) lo = mid;
+    else hi = mid;
   }
-  // lane l, register r: C(row l % 16, column 4 r + l / 16) of a sub-tile
+  const GemmDesc g = descs[lo];
+  const int t = bid - prefix[lo];
+  const int64_t tiles_m = (g.M + BM - 1) / BM;
+  const int64_t i0 = (int64_t)(t % tiles_m) * BM;
+  const int64_t j0 = (int64_t)(t / tiles_m) * BN;
+
+  f64x4 acc[TL::MI][TL::NI];
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int64_t gi = i0 + wm * 32 + a * 16 + lr;
+  for (int a = 0; a < TL::MI; ++a)
+#pragma unroll
+    for (int b = 0; b < TL::NI; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  TL::run(acc, lds, g.A, g.lda, g.B, g.ldb, g.M, g.N, i0, j0, 0, g.K);
+#pragma unroll
+  for (int a = 0; a < TL::MI; ++a) {
+    const int64_t gi = TL::row(i0, a);
     if (gi >= g.M) continue;
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < TL::NI; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gj = j0 + wn * 32 + b * 16 + 4 * r + lk;
+        const int64_t gj = TL::col(j0, b, r);
         if (gj >= g.N) continue;
         double c = g.alpha * acc[a][b][r];
         if (g.beta != 0.0) c += g.beta * g.C[gi + gj * g.ldc];
         g.C[gi + gj * g.ldc] = c;
       }
+  }
+}
+
+template <int BM, int BN, int GM, int GN, bool VEC>
+void launch_grouped(hipStream_t st, bool ta, bool tb, dim3 grid, const GemmDesc* d,
+                    const int* prefix, int count) {
+  const dim3 block(tile::kThreads);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<false, false, BM, BN, GM, GN, VEC>), grid, block, 0,
+                       st, d, prefix, count);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<true, false, BM, BN, GM, GN, VEC>), grid, block, 0,
+                       st, d, prefix, count);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((gemm_grouped_kernel<false, true, BM, BN, GM, GN, VEC>), grid, block, 0,
+                       st, d, prefix, count);
+  else
+    hipLaunchKernelGGL((gemm_grouped_kernel<true, true, BM, BN, GM, GN, VEC>), grid, block, 0,
+                       st, d, prefix, count);
+}
+
+template <bool VEC>
+void launch_grouped_tile(hipStream_t st, bool ta, bool tb, int tile, dim3 grid,
+                         const GemmDesc* d, const int* prefix, int count) {
+  switch (tile) {
+    case kTile128x128: launch_grouped<128, 128, 2, 2, VEC>(st, ta, tb, grid, d, prefix, count); break;
+    case kTile128x64: launch_grouped<128, 64, 2, 2, VEC>(st, ta, tb, grid, d, prefix, count); break;
+    case kTile64x64: launch_grouped<64, 64, 2, 2, VEC>(st, ta, tb, grid, d, prefix, count); break;
+    case kTile128x32: launch_grouped<128, 32, 4, 1, VEC>(st, ta, tb, grid, d, prefix, count); break;
+    default: launch_grouped<128, 16, 4, 1, VEC>(st, ta, tb, grid, d, prefix, count);
   }
 }
 
@@ -307,18 +290,17 @@ int64_t panel_wg_max_rows(int k) {
   return avail / (k + 1) - 1;
 }
 
-int gemm_grouped(hipStream_t st, bool ta, bool tb, const GemmDesc* d_descs, int count,
-                 int64_t max_tiles, double flops) {
-  if (count <= 0 || max_tiles <= 0) return RRF_OK;
-  int tok = trace_begin(st, kTrGemmGrouped, flops, 0.0);
-  for (int c0 = 0; c0 < count; c0 += 65535) {
-    const dim3 grid((unsigned)max_tiles, (unsigned)std::min(count - c0, 65535));
-    const GemmDesc* d = d_descs + c0;
-    if (!ta && !tb) hipLaunchKernelGGL((gemm_grouped_kernel<false, false>), grid, dim3(kGT), 0, st, d);
-    else if (ta && !tb) hipLaunchKernelGGL((gemm_grouped_kernel<true, false>), grid, dim3(kGT), 0, st, d);
-    else if (!ta && tb) hipLaunchKernelGGL((gemm_grouped_kernel<false, true>), grid, dim3(kGT), 0, st, d);
-    else hipLaunchKernelGGL((gemm_grouped_kernel<true, true>), grid, dim3(kGT), 0, st, d);
-  }
+int gemm_grouped(hipStream_t st, bool ta, bool tb, int tile, bool vec, const GemmDesc* d_descs,
+                 const int* d_prefix, int count, int64_t total_tiles, double flops) {
+  if (count <= 0 || total_tiles <= 0) return RRF_OK;
+  if (tile < 0 || tile >= kGemmTiles) return set_error(RRF_E_INTERNAL, "grouped gemm: tile shape");
+  if (total_tiles > INT32_MAX) return set_error(RRF_E_NOTSUP, "grouped gemm: too many tiles");
+  const dim3 grid((unsigned)total_tiles);
+  static const int cls[kGemmTiles] = {kTrGemmGrouped, kTrGemmGrouped128x64, kTrGemmGrouped128x32,
+                                      kTrGemmGrouped128x16, kTrGemmGrouped128x128};
+  int tok = trace_begin(st, cls[tile], flops, 0.0);
+  if (vec) launch_grouped_tile<true>(st, ta, tb, tile, grid, d_descs, d_prefix, count);
+  else launch_grouped_tile<false>(st, ta, tb, tile, grid, d_descs, d_prefix, count);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;

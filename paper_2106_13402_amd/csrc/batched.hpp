@@ -56,19 +56,31 @@ struct PanelDesc {
   int64_t ldz;
 };
 
-// Device-resident descriptor arrays; one launch each.
-int gemm_grouped(hipStream_t st, bool ta, bool tb, const GemmDesc* d_descs, int count,
-                 int64_t max_tiles, double flops);
+// Tile shapes of the grouped GEMM: rows x columns of C per workgroup.
+enum GemmTile { kTile64x64 = 0, kTile128x64 = 1, kTile128x32 = 2, kTile128x16 = 3,
+                kTile128x128 = 4, kGemmTiles = 5 };
+inline int64_t tile_rows(int tile) { return tile == kTile64x64 ? 64 : 128; }
+inline int64_t tile_cols(int tile) {
+  return tile == kTile128x32 ? 32 : (tile == kTile128x16 ? 16 : (tile == kTile128x128 ? 128 : 64));
+}
+inline int64_t tile_count(int tile, int64_t M, int64_t N) {
+  const int64_t r = tile_rows(tile), c = tile_cols(tile);
+  return ((M + r - 1) / r) * ((N + c - 1) / c);
+}
+
+// Device-resident descriptor arrays; one launch each. The grouped GEMM runs
+// total_tiles workgroups: d_prefix (count + 1 ints, d_prefix[0] = 0) holds
+// the running tile counts, problem p owning workgroups [d_prefix[p],
+// d_prefix[p+1]).
+// vec: every A and B starts 16-byte aligned with even leading dimensions
+// (16-byte loads).
+int gemm_grouped(hipStream_t st, bool ta, bool tb, int tile, bool vec, const GemmDesc* d_descs,
+                 const int* d_prefix, int count, int64_t total_tiles, double flops);
 int elem_batched(hipStream_t st, const ElemDesc* d_descs, int count, int64_t max_cols);
 int gauss_batched(hipStream_t st, const GaussDesc* d_descs, int count, int64_t max_elems);
 // All panels must have at most panel_wg_max_rows(k) rows (k <= 64).
 int panel_wg_batched(hipStream_t st, const PanelDesc* d_descs, int count, int k,
                      int64_t max_rows);
 int64_t panel_wg_max_rows(int k);
-
-// 64 x 64 tiles of the grouped GEMM.
-inline int64_t grouped_tiles(int64_t M, int64_t N) {
-  return ((M + 63) / 64) * ((N + 63) / 64);
-}
 
 }  // namespace rrf

@@ -28,6 +28,7 @@
 //    partial-sum buffer that a second kernel reduces in a fixed order, so
 //    results are bitwise reproducible (no floating-point atomics).
 #include "common.hpp"
+#include "gemm_tile.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
 
@@ -35,8 +36,8 @@ namespace rrf {
 
 namespace {
 
-constexpr int kBK = 16;
-constexpr int kThreads = 256;
+using tile::kBK;
+using tile::kThreads;
 
 struct GemmF64Args {
   int64_t M, N, K;
@@ -52,158 +53,34 @@ struct GemmF64Args {
   int tiles_m;
 };
 
-// One operand tile (MN x kBK of op(X)) in LDS, with its copy from HBM.
-// KMAJOR: the operand is contiguous along k in HBM (A for op=T, B for op=N).
-template <int MN, bool KMAJOR, bool VEC>
-struct Operand {
-  static constexpr int LD = KMAJOR ? (kBK + 1) : (MN + 16);  // LDS row stride
-  static constexpr int SIZE = KMAJOR ? MN * LD : kBK * LD;    // doubles per buffer
-  static constexpr int ELEMS = MN * kBK;
-  static constexpr int PER_T = ELEMS / kThreads;              // doubles per thread
-  static constexpr int VW = VEC ? 2 : 1;                      // doubles per load
-  static constexpr int LOADS = PER_T / VW;
-
-  // Element (mn, k) of the tile for load slot (tid, r): consecutive threads
-  // walk the operand's contiguous dimension in HBM.
-  __device__ static inline void coord(int tid, int r, int& mn, int& k) {
-    const int e = (tid + kThreads * r) * VW;
-    if (KMAJOR) {
-      k = e % kBK;
-      mn = e / kBK;
-    } else {
-      mn = e % MN;
-      k = e / MN;
-    }
-  }
-  // Load the slice [k0, k0 + kBK) into registers. X is op(X)'s storage with
-  // leading dimension ld; the tile starts at row/column mn0.
-  __device__ static inline void load(double (&reg)[PER_T], const double* X, int64_t ld,
-                                     int64_t mn0, int64_t mn_end, int64_t k0, int64_t k_end,
-                                     int tid) {
-#pragma unroll
-    for (int r = 0; r < LOADS; ++r) {
-      int mn, k;
-      coord(tid, r, mn, k);
-      const int64_t gm = mn0 + mn, gk = k0 + k;
-      const double* p = KMAJOR ? X + gk + gm * ld : X + gm + gk * ld;
-      if (VEC) {
-        // the pair runs along the contiguous dimension
-        const bool in0 = gm < mn_end && gk < k_end;
-        const bool in1 = KMAJOR ? (gm < mn_end && gk + 1 < k_end) : (gm + 1 < mn_end && gk < k_end);
-        if (in0 && in1) {
-          const double2 v = *reinterpret_cast<const double2*>(p);
-          reg[2 * r] = v.x;
-          reg[2 * r + 1] = v.y;
-        } else {
-          reg[2 * r] = in0 ? p[0] : 0.0;
-          reg[2 * r + 1] = in1 ? p[1] : 0.0;
-        }
-      } else {
-        reg[r] = (gm < mn_end && gk < k_end) ? *p : 0.0;
-      }
-    }
-  }
-  __device__ static inline void store(double* lds, const double (&reg)[PER_T], int tid) {
-#pragma unroll
-    for (int r = 0; r < LOADS; ++r) {
-      int mn, k;
-      coord(tid, r, mn, k);
-#pragma unroll
-      for (int v = 0; v < VW; ++v) {
-        const int mm = KMAJOR ? mn : mn + v;
-        const int kk = KMAJOR ? k + v : k;
-        lds[KMAJOR ? mm * LD + kk : kk * LD + mm] = reg[VW * r + v];
-      }
-    }
-  }
-  // MFMA operand: element (mn, k) of the tile.
-  __device__ static inline double frag(const double* lds, int mn, int k) {
-    return lds[KMAJOR ? mn * LD + k : k * LD + mn];
-  }
-};
-
 template <int BM, int BN, bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(kThreads, 2) void dgemm_mfma_kernel(GemmF64Args g) {
-  // op(A) is k-major in HBM when A is transposed; op(B) when B is not.
-  using OA = Operand<BM, TA, VEC>;
-  using OB = Operand<BN, !TB, VEC>;
-  constexpr int WM = BM / 2, WN = BN / 2;
-  constexpr int MI = WM / 16, NI = WN / 16;
-  __shared__ double lds[2 * (OA::SIZE + OB::SIZE)];
+  using TL = tile::Tile<BM, BN, TA, TB, VEC>;
+  __shared__ double lds[TL::LDS];
 
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-
-  const int tile = blockIdx.x;
-  const int tm = tile % g.tiles_m;
-  const int tn = tile / g.tiles_m;
-  const int64_t i0 = (int64_t)tm * BM;
-  const int64_t j0 = (int64_t)tn * BN;
+  const int t = blockIdx.x;
+  const int64_t i0 = (int64_t)(t % g.tiles_m) * BM;
+  const int64_t j0 = (int64_t)(t / g.tiles_m) * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
   const int64_t kend = (kbeg + g.kchunk < g.K) ? kbeg + g.kchunk : g.K;
 
-  f64x4 acc[MI][NI];
+  f64x4 acc[TL::MI][TL::NI];
 #pragma unroll
-  for (int mi = 0; mi < MI; ++mi)
+  for (int mi = 0; mi < TL::MI; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int ni = 0; ni < TL::NI; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
+  TL::run(acc, lds, g.A, g.lda, g.B, g.ldb, g.M, g.N, i0, j0, kbeg, kend);
 
-  double ra[OA::PER_T];
-  double rb[OB::PER_T];
-  const int lr = lane & 15;  // row (mn) of the operand fragment
-  const int lk = lane >> 4;  // k of the operand fragment
-
-  if (kbeg < kend) {
-    OA::load(ra, g.A, g.lda, i0, g.M, kbeg, kend, tid);
-    OB::load(rb, g.B, g.ldb, j0, g.N, kbeg, kend, tid);
-    OA::store(lds, ra, tid);
-    OB::store(lds + OA::SIZE, rb, tid);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
-      const bool more = k0 + kBK < kend;
-      if (more) {
-        OA::load(ra, g.A, g.lda, i0, g.M, k0 + kBK, kend, tid);
-        OB::load(rb, g.B, g.ldb, j0, g.N, k0 + kBK, kend, tid);
-      }
-      const double* la = lds + buf * (OA::SIZE + OB::SIZE);
-      const double* lb = la + OA::SIZE;
-#pragma unroll
-      for (int kk = 0; kk < kBK; kk += 4) {
-        double af[MI], bf[NI];
-#pragma unroll
-        for (int mi = 0; mi < MI; ++mi) af[mi] = OA::frag(la, wm * WM + mi * 16 + lr, kk + lk);
-#pragma unroll
-        for (int ni = 0; ni < NI; ++ni) bf[ni] = OB::frag(lb, wn * WN + ni * 16 + lr, kk + lk);
-#pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < NI; ++ni)
-            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ni], af[mi], acc[mi][ni], 0, 0, 0);
-      }
-      if (more) {
-        double* na = lds + (buf ^ 1) * (OA::SIZE + OB::SIZE);
-        OA::store(na, ra, tid);
-        OB::store(na + OA::SIZE, rb, tid);
-      }
-      __syncthreads();
-      buf ^= 1;
-    }
-  }
-
-  // Epilogue: lane l, register r holds C(row l%16, col 4r + l/16) of a sub-tile.
   const int64_t MN = g.M * g.N;
 #pragma unroll
-  for (int mi = 0; mi < MI; ++mi) {
-    const int64_t gi = i0 + wm * WM + mi * 16 + lr;
+  for (int mi = 0; mi < TL::MI; ++mi) {
+    const int64_t gi = TL::row(i0, mi);
     if (gi >= g.M) continue;
 #pragma unroll
-    for (int ni = 0; ni < NI; ++ni) {
+    for (int ni = 0; ni < TL::NI; ++ni) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gj = j0 + wn * WN + ni * 16 + 4 * r + lk;
+        const int64_t gj = TL::col(j0, ni, r);
         if (gj >= g.N) continue;
         const double v = acc[mi][ni][r];
         if (g.P) {

@@ -14,11 +14,18 @@
 // merge of two compact-WY factors, as in householder_panel).
 //
 // Descriptors of a round are built on the host in pinned memory and copied
-// to the device on the caller's stream; a ring of slots lets the host build
-// the next rounds while the device runs the earlier ones.
+// to the device on the stream that runs the round; a ring of slots lets the
+// host build the next rounds while the device runs the earlier ones. Large
+// batches are cut into up to four slices of about equal work, each driven by
+// its own host thread on its own stream, ordered after the caller's stream
+// and before its later work: one slice's latency-bound launches (panels,
+// small SVDs) overlap another's GEMMs.
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <mutex>
+#include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -56,8 +63,10 @@ struct Plan {
     size_t off;
     int count;
     int64_t aux;
-    int k;
+    int k;  // panel width, or the GEMM tile shape
     double flops;
+    size_t off2;  // GEMM: running tile counts
+    bool vec;     // GEMM: 16-byte loads
   };
   std::vector<unsigned char> bytes;
   std::vector<Op> ops;
@@ -69,33 +78,63 @@ struct Plan {
     memcpy(bytes.data() + off, v.data(), v.size() * sizeof(D));
     return off;
   }
+  // The tile shape with the least padded work, weighted by how well each
+  // shape keeps the matrix cores fed (wider tiles reuse each loaded slice
+  // more often).
+  static int pick_tile(const std::vector<GemmDesc>& v) {
+    static const int order[5] = {kTile128x128, kTile128x64, kTile64x64, kTile128x32, kTile128x16};
+    static const double weight[5] = {1.0, 1.1, 1.3, 1.25, 1.5};
+    int best = kTile64x64;
+    double best_cost = 0.0;
+    for (int c = 0; c < 5; ++c) {
+      const int t = order[c];
+      double area = 0.0;
+      for (const auto& g : v)
+        area += (double)tile_count(t, g.M, g.N) * tile_rows(t) * tile_cols(t) * (double)g.K;
+      const double cost = area * weight[c];
+      if (c == 0 || cost < best_cost) {
+        best = t;
+        best_cost = cost;
+      }
+    }
+    return best;
+  }
   void gemm(bool ta, bool tb, const std::vector<GemmDesc>& v) {
     if (v.empty()) return;
-    int64_t tiles = 0;
+    const int tile = pick_tile(v);
+    std::vector<int> prefix(v.size() + 1, 0);
     double fl = 0.0;
-    for (const auto& g : v) {
-      tiles = std::max(tiles, grouped_tiles(g.M, g.N));
-      fl += 2.0 * g.M * g.N * g.K;
+    int64_t total = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+      total += tile_count(tile, v[i].M, v[i].N);
+      prefix[i + 1] = (int)std::min<int64_t>(total, INT32_MAX);
+      fl += 2.0 * v[i].M * v[i].N * v[i].K;
     }
-    ops.push_back({kGemm, ta, tb, put(v), (int)v.size(), tiles, 0, fl});
+    // 16-byte loads when every operand column starts 16-byte aligned
+    bool vec = true;
+    for (const auto& g : v)
+      vec = vec && ((uintptr_t)g.A % 16 == 0) && ((uintptr_t)g.B % 16 == 0) && g.lda % 2 == 0 &&
+            g.ldb % 2 == 0;
+    const size_t off = put(v);
+    ops.push_back({kGemm, ta, tb, off, (int)v.size(), total, tile, fl, put(prefix), vec});
   }
   void elem(const std::vector<ElemDesc>& v) {
     if (v.empty()) return;
     int64_t cols = 0;
     for (const auto& e : v) cols = std::max(cols, e.cols);
-    ops.push_back({kElem, false, false, put(v), (int)v.size(), cols, 0, 0.0});
+    ops.push_back({kElem, false, false, put(v), (int)v.size(), cols, 0, 0.0, 0, false});
   }
   void gauss(const std::vector<GaussDesc>& v) {
     if (v.empty()) return;
     int64_t el = 0;
     for (const auto& e : v) el = std::max(el, e.rows * e.cols);
-    ops.push_back({kGauss, false, false, put(v), (int)v.size(), el, 0, 0.0});
+    ops.push_back({kGauss, false, false, put(v), (int)v.size(), el, 0, 0.0, 0, false});
   }
   void panel(const std::vector<PanelDesc>& v, int k) {
     if (v.empty()) return;
     int64_t rows = 0;
     for (const auto& e : v) rows = std::max(rows, e.M);
-    ops.push_back({kPanel, false, false, put(v), (int)v.size(), rows, k, 0.0});
+    ops.push_back({kPanel, false, false, put(v), (int)v.size(), rows, k, 0.0, 0, false});
   }
 };
 
@@ -109,8 +148,7 @@ struct Ring {
   bool pending[kSlots] = {};
   int slot = 0;
 };
-std::mutex g_ring_mu;
-std::unordered_map<int, Ring> g_rings;
+std::mutex g_ring_mu;  // one batched call at a time per process
 
 int ring_reserve(Ring& r, size_t cap) {
   if (r.cap >= cap) return RRF_OK;
@@ -152,7 +190,8 @@ int run_plan(hipStream_t st, Ring& r, const Plan& p) {
     const void* dd = d + op.off;
     switch (op.kind) {
       case Plan::kGemm:
-        RRF_TRY(gemm_grouped(st, op.ta, op.tb, static_cast<const GemmDesc*>(dd), op.count, op.aux,
+        RRF_TRY(gemm_grouped(st, op.ta, op.tb, op.k, op.vec, static_cast<const GemmDesc*>(dd),
+                             reinterpret_cast<const int*>(d + op.off2), op.count, op.aux,
                              op.flops));
         break;
       case Plan::kElem:
@@ -202,6 +241,9 @@ ElemDesc copy(int64_t rows, int64_t cols, const double* S, int64_t lds, double* 
 bool plan_panel(std::vector<Plan>& rounds, const std::vector<PanelDesc>& P,
                 const std::vector<double*>& pt, int k) {
   if (P.empty()) return true;
+  // one launch holds every panel (each is a chain of k latency-bound column
+  // steps, so the launch takes as long as its slowest panel); when any is
+  // too tall for one workgroup, all are split
   int64_t maxM = 0;
   for (const auto& p : P) maxM = std::max(maxM, p.M);
   if (maxM <= panel_wg_max_rows(k)) {
@@ -694,13 +736,75 @@ int run_backward(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Share
 
 int64_t randutv_batched_block(int64_t m, int64_t n) {
   (void)m;
-  // wider blocks once n is large enough that the panels stop dominating
-  return n <= 128 ? 16 : (n <= 320 ? 32 : 64);
+  // measured per n bucket of the 4096-matrix workload (n in [64, 512],
+  // m in [n, 2n], q = 1): 16 is fastest up to n = 256, 32 above; 64 never
+  // wins (its panels need column splits and its block SVDs are 8x dearer)
+  return n <= 256 ? 16 : 32;
 }
 
 size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t* n, int64_t b) {
   return layout(count, m, n, b, nullptr, nullptr, nullptr);
 }
+
+namespace {
+
+// One slice of the batch on its own stream: set-up, the loop, the block
+// SVDs and updates, and U and V. mats[j].blk0 and sh index the slice's own
+// blocks.
+int run_slice(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh, int64_t b,
+              int q) {
+  RRF_TRY(ring_reserve(ring, std::max(mats.size() * kDescPerMat, (size_t)sh.nblocks * 4) +
+                                 (1 << 16)));
+  {
+    Plan p;
+    std::vector<ElemDesc> e;
+    for (auto& x : mats) {
+      if (x.T != x.A) e.push_back(copy(x.m, x.n, x.A, x.lda, x.T, x.m));
+      if (x.U) e.push_back(fill(x.m, x.n, 0.0, x.WU, x.m));  // reflector stores
+      if (x.V) e.push_back(fill(x.n, x.n, 0.0, x.WV, x.n));
+    }
+    p.elem(e);
+    RRF_TRY(run_plan(st, ring, p));
+  }
+  {
+    std::vector<int> hs((size_t)sh.nblocks);
+    for (auto& x : mats)
+      for (int64_t i = 0; i < x.s; ++i) hs[x.blk0 + i] = (int)std::min(b, x.n - i * b);
+    RRF_TRY(upload(st, ring, hs.data(), hs.size() * sizeof(int), sh.sizes));
+  }
+  std::vector<std::vector<int64_t>> ku(mats.size()), kv(mats.size());
+  for (size_t j = 0; j < mats.size(); ++j) {
+    ku[j].assign(mats[j].s, 0);
+    kv[j].assign(mats[j].s, 0);
+  }
+  RRF_TRY(run_loop(st, ring, mats, sh, b, q, ku, kv));
+  RRF_TRY(run_blocks(st, ring, mats, sh, b));
+  RRF_TRY(run_backward(st, ring, mats, sh, b, ku, kv));
+  return RRF_OK;
+}
+
+// Per-device resources kept between calls: the slices' streams (default
+// priority), their descriptor rings, and the events that order them after
+// and before the caller's stream.
+constexpr int kMaxSlices = 4;
+struct DeviceRes {
+  Ring rings[kMaxSlices];
+  hipStream_t streams[kMaxSlices] = {};
+  hipEvent_t done[kMaxSlices] = {};
+  hipEvent_t start = nullptr;
+};
+std::unordered_map<int, DeviceRes> g_res;
+
+int slice_resources(DeviceRes& r, int S) {
+  if (!r.start) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.start, hipEventDisableTiming));
+  for (int i = 0; i < S; ++i) {
+    if (!r.streams[i]) RRF_CHECK_HIP(hipStreamCreateWithFlags(&r.streams[i], hipStreamNonBlocking));
+    if (!r.done[i]) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.done[i], hipEventDisableTiming));
+  }
+  return RRF_OK;
+}
+
+}  // namespace
 
 int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const int64_t* n,
                         const double* const* A, const int64_t* lda, int64_t b, int q,
@@ -722,35 +826,76 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
   int dev = 0;
   RRF_CHECK_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ring_mu);
-  Ring& ring = g_rings[dev];
-  RRF_TRY(ring_reserve(ring, std::max((size_t)count * kDescPerMat, (size_t)sh.nblocks * 4) +
-                                 (1 << 16)));
+  DeviceRes& res = g_res[dev];
 
+  // Contiguous slices of about equal work (m n^2 per matrix): the lockstep
+  // rounds of one slice leave the chip partly idle in their latency-bound
+  // launches (panels, small SVDs), which the other slices' GEMMs fill.
+  const int S = (int)std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, count / 256));
+  if (S == 1) return run_slice(st, res.rings[0], mats, sh, b, q);
+  RRF_TRY(slice_resources(res, S));
+  double total = 0.0;
+  for (auto& x : mats) total += (double)x.m * x.n * x.n;
+  std::vector<int64_t> cut(S + 1, count);
+  cut[0] = 0;
   {
-    Plan p;
-    std::vector<ElemDesc> e;
-    for (auto& x : mats) {
-      if (x.T != x.A) e.push_back(copy(x.m, x.n, x.A, x.lda, x.T, x.m));
-      if (x.U) e.push_back(fill(x.m, x.n, 0.0, x.WU, x.m));  // reflector stores
-      if (x.V) e.push_back(fill(x.n, x.n, 0.0, x.WV, x.n));
+    double acc = 0.0;
+    int c = 1;
+    for (int64_t j = 0; j < count && c < S; ++j) {
+      acc += (double)mats[j].m * mats[j].n * mats[j].n;
+      if (acc >= total * c / S) cut[c++] = j + 1;
     }
-    p.elem(e);
-    RRF_TRY(run_plan(st, ring, p));
   }
-  {
-    std::vector<int> hs((size_t)sh.nblocks);
-    for (auto& x : mats)
-      for (int64_t i = 0; i < x.s; ++i) hs[x.blk0 + i] = (int)std::min(b, x.n - i * b);
-    RRF_TRY(upload(st, ring, hs.data(), hs.size() * sizeof(int), sh.sizes));
+  struct Work {
+    std::vector<Mat> mats;
+    Shared sh;
+    int rc = RRF_OK;
+    std::string msg;
+  };
+  std::vector<Work> work(S);
+  const size_t svd_per_block = sh.nblocks ? sh.svd_bytes / (size_t)sh.nblocks : 0;
+  for (int i = 0; i < S; ++i) {
+    Work& w = work[i];
+    w.mats.assign(mats.begin() + cut[i], mats.begin() + cut[i + 1]);
+    const int64_t off = w.mats.empty() ? 0 : w.mats.front().blk0;
+    int64_t nb = 0;
+    for (auto& x : w.mats) {
+      x.blk0 -= off;
+      nb += x.s;
+    }
+    w.sh = sh;
+    w.sh.nblocks = nb;
+    w.sh.R = sh.R + off * b * b;
+    w.sh.Us = sh.Us + off * b * b;
+    w.sh.Vs = sh.Vs + off * b * b;
+    w.sh.d = sh.d + off * b;
+    w.sh.sizes = sh.sizes + off;
+    w.sh.svd = static_cast<char*>(sh.svd) + off * svd_per_block;
+    w.sh.svd_bytes = nb * svd_per_block;
   }
-  std::vector<std::vector<int64_t>> ku(count), kv(count);
-  for (int64_t j = 0; j < count; ++j) {
-    ku[j].assign(mats[j].s, 0);
-    kv[j].assign(mats[j].s, 0);
+  RRF_CHECK_HIP(hipEventRecord(res.start, st));
+  for (int i = 0; i < S; ++i) RRF_CHECK_HIP(hipStreamWaitEvent(res.streams[i], res.start, 0));
+  std::vector<std::thread> threads;
+  for (int i = 0; i < S; ++i) {
+    threads.emplace_back([&, i]() {
+      Work& w = work[i];
+      hipError_t e = hipSetDevice(dev);  // the current device is per thread
+      if (e != hipSuccess) {
+        w.rc = set_hip_error(e, "hipSetDevice", __FILE__, __LINE__);
+      } else if (!w.mats.empty()) {
+        w.rc = run_slice(res.streams[i], res.rings[i], w.mats, w.sh, b, q);
+      }
+      if (w.rc != RRF_OK) w.msg = rrf_last_error();
+    });
   }
-  RRF_TRY(run_loop(st, ring, mats, sh, b, q, ku, kv));
-  RRF_TRY(run_blocks(st, ring, mats, sh, b));
-  RRF_TRY(run_backward(st, ring, mats, sh, b, ku, kv));
+  for (auto& t : threads) t.join();
+  // the caller's stream waits for every slice, also after a failure
+  for (int i = 0; i < S; ++i) {
+    RRF_CHECK_HIP(hipEventRecord(res.done[i], res.streams[i]));
+    RRF_CHECK_HIP(hipStreamWaitEvent(st, res.done[i], 0));
+  }
+  for (auto& w : work)
+    if (w.rc != RRF_OK) return set_error(w.rc, w.msg.c_str());
   return RRF_OK;
 }
 
@@ -758,16 +903,23 @@ int randutv_batched_release() {
   std::lock_guard<std::mutex> lk(g_ring_mu);
   int cur = 0;
   RRF_CHECK_HIP(hipGetDevice(&cur));
-  for (auto& kvp : g_rings) {
-    Ring& r = kvp.second;
+  for (auto& kvp : g_res) {
+    DeviceRes& r = kvp.second;
     RRF_CHECK_HIP(hipSetDevice(kvp.first));
     RRF_CHECK_HIP(hipDeviceSynchronize());
-    for (int s = 0; s < kSlots; ++s)
-      if (r.copied[s]) RRF_CHECK_HIP(hipEventDestroy(r.copied[s]));
-    if (r.host) RRF_CHECK_HIP(hipHostFree(r.host));
-    if (r.dev) RRF_CHECK_HIP(hipFree(r.dev));
+    for (auto& ring : r.rings) {
+      for (int s = 0; s < kSlots; ++s)
+        if (ring.copied[s]) RRF_CHECK_HIP(hipEventDestroy(ring.copied[s]));
+      if (ring.host) RRF_CHECK_HIP(hipHostFree(ring.host));
+      if (ring.dev) RRF_CHECK_HIP(hipFree(ring.dev));
+    }
+    for (int i = 0; i < kMaxSlices; ++i) {
+      if (r.streams[i]) RRF_CHECK_HIP(hipStreamDestroy(r.streams[i]));
+      if (r.done[i]) RRF_CHECK_HIP(hipEventDestroy(r.done[i]));
+    }
+    if (r.start) RRF_CHECK_HIP(hipEventDestroy(r.start));
   }
-  g_rings.clear();
+  g_res.clear();
   RRF_CHECK_HIP(hipSetDevice(cur));
   return RRF_OK;
 }

@@ -6,6 +6,7 @@
 // as separate classes, named with a ":UV" suffix.
 #include <cstring>
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
@@ -19,6 +20,7 @@ struct Record {
   int cls;
   double flops, bytes;
   hipEvent_t e0, e1;
+  bool ended;  // e1 recorded (only ended records are drained)
 };
 
 struct Totals {
@@ -28,7 +30,8 @@ struct Totals {
 
 std::mutex g_mu;
 bool g_on = false;
-std::vector<Record> g_pending;
+std::unordered_map<int, Record> g_pending;  // by token
+int g_next = 0;
 std::vector<hipEvent_t> g_free;
 Totals g_tot[2 * kTraceClasses];
 std::vector<hipStream_t> g_marked;
@@ -39,6 +42,8 @@ const char* kNames[kTraceClasses] = {
     "dgemm_mfma_64x64_NT",   "dgemm_mfma_64x64_TT",   "splitk_reduce",
     "householder_panel",     "jacobi_svd",            "gaussian",
     "elementwise",           "gemm_bf16_mfma_TN",     "dgemm_grouped_64x64",
+    "dgemm_grouped_128x64",  "dgemm_grouped_128x32",  "dgemm_grouped_128x16",
+    "dgemm_grouped_128x128",
 };
 
 hipEvent_t get_event() {
@@ -52,8 +57,15 @@ hipEvent_t get_event() {
   return e;
 }
 
+// Fold the ended records into the totals; records whose launch is still
+// being enqueued by another thread stay pending.
 void drain_locked() {
-  for (Record& r : g_pending) {
+  for (auto it = g_pending.begin(); it != g_pending.end();) {
+    Record& r = it->second;
+    if (!r.ended) {
+      ++it;
+      continue;
+    }
     float ms = 0.f;
     if (r.e0 && r.e1 && hipEventSynchronize(r.e1) == hipSuccess &&
         hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
@@ -65,8 +77,8 @@ void drain_locked() {
     }
     if (r.e0) g_free.push_back(r.e0);
     if (r.e1) g_free.push_back(r.e1);
+    it = g_pending.erase(it);
   }
-  g_pending.clear();
 }
 
 }  // namespace
@@ -85,17 +97,21 @@ int trace_begin(hipStream_t st, int cls, double flops, double bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (hipStream_t m : g_marked)
     if (m == st) cls += kTraceClasses;
-  Record r{cls, flops, bytes, get_event(), get_event()};
+  Record r{cls, flops, bytes, get_event(), get_event(), false};
   if (r.e0) (void)hipEventRecord(r.e0, st);
-  g_pending.push_back(r);
-  return (int)g_pending.size() - 1;
+  const int token = g_next;
+  g_next = (g_next + 1) & 0x3fffffff;
+  g_pending[token] = r;
+  return token;
 }
 
 void trace_end(hipStream_t st, int token) {
   if (token < 0) return;
   std::lock_guard<std::mutex> lk(g_mu);
-  if (token < (int)g_pending.size() && g_pending[token].e1)
-    (void)hipEventRecord(g_pending[token].e1, st);
+  auto it = g_pending.find(token);
+  if (it == g_pending.end()) return;
+  if (it->second.e1) (void)hipEventRecord(it->second.e1, st);
+  it->second.ended = true;
   if (g_pending.size() > 4096) drain_locked();
 }
 

@@ -9,7 +9,8 @@ enum TraceClass {
   kTrGemm128NN = 0, kTrGemm128TN, kTrGemm128NT, kTrGemm128TT,
   kTrGemm64NN, kTrGemm64TN, kTrGemm64NT, kTrGemm64TT,
   kTrSplitReduce, kTrPanel, kTrJacobi, kTrGaussian, kTrElementwise, kTrGemmBf16,
-  kTrGemmGrouped, kTraceClasses
+  kTrGemmGrouped, kTrGemmGrouped128x64, kTrGemmGrouped128x32, kTrGemmGrouped128x16,
+  kTrGemmGrouped128x128, kTraceClasses
 };
 
 bool trace_on();

@@ -152,3 +152,9 @@ def test_batched_workspace_size(lib):
     assert f(3, m, _arr(C.c_int64, [64, 301, 512]), 16) == 0   # n > m
     assert f(1, _arr(C.c_int64, [4097]), _arr(C.c_int64, [4]), 16) == 0
     assert f(2, m, n, 16) < w16
+
+
+def test_batched_block_rule(lib):
+    f = lib.rrf_randutv_batched_block
+    assert f(100, 64) == 16 and f(512, 256) == 16 and f(300, 257) == 32 and f(1024, 512) == 32
+    assert f(10, 11) == 0 and f(5, 0) == 0

@@ -25,7 +25,8 @@ pytestmark = pytest.mark.gpu
 
 
 def _auto_b(n):
-    return 16 if n <= 128 else (32 if n <= 320 else 64)
+    from paper_2106_13402_amd import batched_block
+    return batched_block(n, n)
 
 
 def _run(As_host, b, q, seed, gpu, **kw):
@@ -103,7 +104,7 @@ def test_batched_matches_single_calls(gpu):
 
 
 def test_batched_auto_block(gpu):
-    """b = 0: block size 16 / 32 / 64 chosen from n, one group per size."""
+    """b = 0: block size chosen from n (16 up to 256, else 32), one group per size."""
     print("case: batched automatic block size", flush=True)
     shapes = [(150, 100), (240, 200), (400, 330), (128, 128), (90, 70)]
     As = [gaussian_matrix(m, n, seed=400 + j) for j, (m, n) in enumerate(shapes)]
@@ -179,3 +180,17 @@ def test_batched_full_size(gpu):
         _check_blocks(T, bj)
         _, To, _ = oracle.randutv(A, bj, 1, 1000 + int(j), want_u=False, want_v=False)
         np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * M.spec(A))
+
+
+def test_batched_slices(gpu):
+    """A batch large enough to be cut into slices on separate streams (640
+    small matrices: two slices): every matrix checked against the oracle."""
+    print("case: batched slices, 640 matrices", flush=True)
+    shapes = batch_shapes(640, seed=5, nmin=4, nmax=40)
+    As = [gaussian_matrix(m, n, seed=500 + j) for j, (m, n) in enumerate(shapes)]
+    Us, Ts, Vs = _run(As, 8, 1, 60, gpu)
+    for j, A in enumerate(As):
+        _check_factorization(A, Us[j], Ts[j], Vs[j])
+        _check_blocks(Ts[j], 8)
+        _, To, _ = oracle.randutv(A, 8, 1, 60 + j, want_u=False, want_v=False)
+        np.testing.assert_allclose(np.abs(Ts[j]), np.abs(To), atol=1e-9 * M.spec(A))
