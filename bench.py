@@ -38,15 +38,16 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # HBM bytes per launch of each FP64 GEMM class on the default workload, from
 # rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs scaled by the counters' reading
 # for a 1 GiB device copy (profiles/randutv_n16384_b128_q2_fp64_hbm_traffic.md).
-# They describe the GEMM source with this SHA-256 prefix only.
-TRAFFIC_SOURCE = "paper_2106_13402_amd/csrc/gemm_f64.hip"
-TRAFFIC_SHA256_16 = "f14d76753d43c389"
+# They describe the GEMM sources whose concatenation has this SHA-256 prefix.
+TRAFFIC_SOURCES = ("paper_2106_13402_amd/csrc/gemm_f64.hip",
+                   "paper_2106_13402_amd/csrc/gemm_tile.hpp")
+TRAFFIC_SHA256_16 = "d7b78f80d6b254c1"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "dgemm_mfma_128x128_NN": 609247578,
-    "dgemm_mfma_128x128_TN": 595826607,
-    "dgemm_mfma_128x128_NT": 923792113,
-    "dgemm_mfma_128x128_NN:UV": 427799858,
-    "dgemm_mfma_128x128_TN:UV": 856924490,
+    "dgemm_mfma_128x128_NN": 608591690,
+    "dgemm_mfma_128x128_TN": 595814424,
+    "dgemm_mfma_128x128_NT": 917414241,
+    "dgemm_mfma_128x128_NN:UV": 427685111,
+    "dgemm_mfma_128x128_TN:UV": 857058180,
 }
 
 
@@ -56,9 +57,12 @@ def measured_traffic(kernel: str, n: int, b: int, q: int):
     import hashlib
     if (n, b, q) != (16384, 128, 2):
         return None
-    with open(os.path.join(ROOT, TRAFFIC_SOURCE), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != TRAFFIC_SHA256_16:
-            return None
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != TRAFFIC_SHA256_16:
+        return None
     return TRAFFIC_BYTES_PER_LAUNCH.get(kernel)
 
 

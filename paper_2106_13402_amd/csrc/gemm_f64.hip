@@ -55,32 +55,86 @@ struct GemmF64Args {
 
 template <int BM, int BN, bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(kThreads, 2) void dgemm_mfma_kernel(GemmF64Args g) {
-  using TL = tile::Tile<BM, BN, TA, TB, VEC>;
-  __shared__ double lds[TL::LDS];
+  // op(A) is k-major in HBM when A is transposed; op(B) when B is not.
+  using OA = tile::Operand<BM, TA, VEC>;
+  using OB = tile::Operand<BN, !TB, VEC>;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MI = WM / 16, NI = WN / 16;
+  __shared__ double lds[2 * (OA::SIZE + OB::SIZE)];
 
-  const int t = blockIdx.x;
-  const int64_t i0 = (int64_t)(t % g.tiles_m) * BM;
-  const int64_t j0 = (int64_t)(t / g.tiles_m) * BN;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int tile = blockIdx.x;
+  const int tm = tile % g.tiles_m;
+  const int tn = tile / g.tiles_m;
+  const int64_t i0 = (int64_t)tm * BM;
+  const int64_t j0 = (int64_t)tn * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
   const int64_t kend = (kbeg + g.kchunk < g.K) ? kbeg + g.kchunk : g.K;
 
-  f64x4 acc[TL::MI][TL::NI];
+  f64x4 acc[MI][NI];
 #pragma unroll
-  for (int mi = 0; mi < TL::MI; ++mi)
+  for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < TL::NI; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
-  TL::run(acc, lds, g.A, g.lda, g.B, g.ldb, g.M, g.N, i0, j0, kbeg, kend);
+    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
 
+  double ra[OA::PER_T];
+  double rb[OB::PER_T];
+  const int lr = lane & 15;  // row (mn) of the operand fragment
+  const int lk = lane >> 4;  // k of the operand fragment
+
+  if (kbeg < kend) {
+    OA::load(ra, g.A, g.lda, i0, g.M, kbeg, kend, tid);
+    OB::load(rb, g.B, g.ldb, j0, g.N, kbeg, kend, tid);
+    OA::store(lds, ra, tid);
+    OB::store(lds + OA::SIZE, rb, tid);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kBK) {
+      const bool more = k0 + kBK < kend;
+      if (more) {
+        OA::load(ra, g.A, g.lda, i0, g.M, k0 + kBK, kend, tid);
+        OB::load(rb, g.B, g.ldb, j0, g.N, k0 + kBK, kend, tid);
+      }
+      const double* la = lds + buf * (OA::SIZE + OB::SIZE);
+      const double* lb = la + OA::SIZE;
+#pragma unroll
+      for (int kk = 0; kk < kBK; kk += 4) {
+        double af[MI], bf[NI];
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi) af[mi] = OA::frag(la, wm * WM + mi * 16 + lr, kk + lk);
+#pragma unroll
+        for (int ni = 0; ni < NI; ++ni) bf[ni] = OB::frag(lb, wn * WN + ni * 16 + lr, kk + lk);
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < NI; ++ni)
+            acc[mi][ni] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[ni], af[mi], acc[mi][ni], 0, 0, 0);
+      }
+      if (more) {
+        double* na = lds + (buf ^ 1) * (OA::SIZE + OB::SIZE);
+        OA::store(na, ra, tid);
+        OB::store(na + OA::SIZE, rb, tid);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  // Epilogue: lane l, register r holds C(row l%16, col 4r + l/16) of a sub-tile.
   const int64_t MN = g.M * g.N;
 #pragma unroll
-  for (int mi = 0; mi < TL::MI; ++mi) {
-    const int64_t gi = TL::row(i0, mi);
+  for (int mi = 0; mi < MI; ++mi) {
+    const int64_t gi = i0 + wm * WM + mi * 16 + lr;
     if (gi >= g.M) continue;
 #pragma unroll
-    for (int ni = 0; ni < TL::NI; ++ni) {
+    for (int ni = 0; ni < NI; ++ni) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gj = TL::col(j0, ni, r);
+        const int64_t gj = j0 + wn * WN + ni * 16 + 4 * r + lk;
         if (gj >= g.N) continue;
         const double v = acc[mi][ni][r];
         if (g.P) {

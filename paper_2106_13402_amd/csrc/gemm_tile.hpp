@@ -1,5 +1,7 @@
-// The FP64 MFMA tile loop shared by the single GEMM (gemm_f64.hip) and the
-// grouped GEMM of the batched path (batched.hip).
+// FP64 MFMA tiles: the operand staging shared by the single GEMM
+// (gemm_f64.hip) and the grouped GEMM of the batched path (batched.hip), and
+// the tile loop of the grouped GEMM (the single GEMM keeps its own copy of
+// the loop, which compiles to fewer instructions for its fixed 2 x 2 grid).
 //
 // A workgroup of 256 threads (four wave64s in a GM x GN grid) computes a
 // BM x BN tile of op(A) op(B) over a K range; each wave owns (BM/GM) x
