@@ -143,103 +143,113 @@ __global__ __launch_bounds__(256) void gauss_kernel(const GaussDesc* __restrict_
 
 // --- Householder panel, one workgroup --------------------------------------
 
-constexpr int kPT = 512;
-constexpr int kPMaxK = 64;
+constexpr int kRT = 512;    // most threads of a panel workgroup
+constexpr int kPMaxK = 64;  // widest panel
 
-__device__ inline int pow2_at_least(int n) {
-  int p = 1;
-  while (p < n) p <<= 1;
-  return p;
+// One halving exchange of the reduce-scatter below (offset O, H values kept),
+// then the next; the steps are unrolled at compile time so that every
+// register index is static.
+template <int H, int O, int K>
+__device__ inline void halve(double (&s)[K], int lane) {
+  if constexpr (H >= 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const double keep = up ? s[i + H] : s[i];
+      const double send = up ? s[i] : s[i + H];
+      s[i] = keep + __shfl_xor(send, O, 64);
+    }
+    halve<H / 2, O / 2, K>(s, lane);
+  }
 }
 
-// Rows of the panel live in LDS (row-major, stride k + 1, one zero row
-// after them, the spare column k absorbing the diagonal lane's stores), Tf
-// after them. Round j applies H_{j-1} and forms, in the same pass, the Gram
-// row of column j with the later columns and the dots v_{j-1}^T v_l for
-// column j-1 of Tf; the sums are reduced across the workgroup in LDS.
-__global__ __launch_bounds__(kPT) void panel_wg_kernel(const PanelDesc* __restrict__ descs,
+// Sum over the 64 lanes of each of K values (K a power of two <= 64):
+// halving exchanges leave lane l holding value l / (64 / K).
+template <int K>
+__device__ inline double wave_reduce_scatter(double (&s)[K], int lane) {
+  halve<K / 2, 32, K>(s, lane);
+  double v = s[0];
+#pragma unroll
+  for (int o = 32 / K; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Householder QR of an M x k panel (k <= K) with compact-WY output (Sec. 2.3,
+// the dlarfg rule), the panel held in registers: thread t owns rows t,
+// t + 512, ... (RPT of them), all K columns. Column j takes one reduction
+// of K inner products with the current column j over the rows below j,
+//   s_c = sum_{r > j} x_rc x_rj,
+// which give at once the norm (c = j), v_j^T A_c for the update of the
+// later columns (c > j, with row j published through LDS) and the dots
+// v_c^T v_j that extend T_f (c < j). Two barriers per column.
+template <int K, int RPT, int NT>
+__global__ __launch_bounds__(NT) void panel_reg_kernel(const PanelDesc* __restrict__ descs,
                                                        int k) {
-  extern __shared__ double smem[];
-  __shared__ double red_s[3 * kPMaxK];
-  __shared__ double w_s[kPMaxK];
-  __shared__ double part[kPT];
+  constexpr int kRW = NT / 64;
+  __shared__ double part[kRW][K];
+  __shared__ double red[K];
+  __shared__ double rowj[2][K];
+  __shared__ double Tl[K][K + 1];  // Tl[i][c] = T_f(i, c)
+  __shared__ double taus[K];
   const PanelDesc a = descs[blockIdx.x];
-  const int tid = threadIdx.x;
-  const int rows = (int)a.M;
-  const int L = k + 1;
-  double* Ls = smem;
-  double* Tl = smem + (size_t)(rows + 1) * L;  // k x k, ld k
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t M = a.M;
 
-  for (int idx = tid; idx < rows * k; idx += kPT) {
-    const int r = idx % rows, c = idx / rows;
-    Ls[r * L + c] = a.P[r + (int64_t)c * a.ldp];
+  double x[RPT][K];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int64_t r = tid + (int64_t)t * NT;
+#pragma unroll
+    for (int c = 0; c < K; ++c) x[t][c] = (r < M && c < k) ? a.P[r + (int64_t)c * a.ldp] : 0.0;
   }
-  for (int c = tid; c < L; c += kPT) Ls[rows * L + c] = 0.0;
-  __syncthreads();
   if (a.zero)
-    for (int idx = tid; idx < rows * k; idx += kPT) {
-      const int r = idx % rows, c = idx / rows;
-      a.zero[r + (int64_t)c * a.ldz] = 0.0;
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int64_t r = tid + (int64_t)t * NT;
+      if (r < M)
+        for (int c = 0; c < k; ++c) a.zero[r + (int64_t)c * a.ldz] = 0.0;
     }
 
-  double tau_prev = 0.0;
-  for (int j = 0; j <= k; ++j) {
-    const int ns = (j < k) ? (k - j) : 0;
-    const int nt = (j >= 2) ? (j - 1) : 0;
-    const double twj = (j >= 1 && j < k) ? tau_prev * w_s[j] : 0.0;
-    const int nc = ns + nt;
-    const int ncp = pow2_at_least(nc);
-    const int tpc = kPT / ncp;
-    const int ci = tid % ncp, sub = tid / ncp;
-    const int jm = (j >= 1) ? j - 1 : 0;
-    double acc = 0.0;
-    if (ci < nc) {
-      const bool gram = ci < ns;
-      const int col = gram ? j + ci : ci - ns;
-      const int cst = (gram && col == j) ? k : col;
-      const double tw = (gram && j >= 1) ? tau_prev * w_s[col] : 0.0;
-      if (!gram && sub == 0) acc = Ls[(j - 1) * L + col];  // row j-1 of v_{j-1} is 1
-      for (int r = j + sub; r < rows; r += tpc) {
-        const double vv = Ls[r * L + jm];
-        const double y = Ls[r * L + col] - tw * vv;
-        Ls[r * L + cst] = y;
-        const double xj = (r == j) ? 0.0 : Ls[r * L + j] - twj * vv;
-        acc += (gram ? xj : vv) * y;
-      }
+  for (int j = 0; j < k; ++j) {
+    double xj[RPT];
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      double v = 0.0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) v = (c == j) ? x[t][c] : v;
+      xj[t] = v;
     }
-    part[tid] = acc;
-    __syncthreads();
-    if (tid < nc) {
-      double s = 0.0;
-      for (int u = 0; u < tpc; ++u) s += part[tid + u * ncp];
-      if (tid < ns) red_s[j + tid] = s;
-      else red_s[2 * k + (tid - ns)] = s;
-    }
-    if (j < k) {
-      for (int c = j + 1 + tid; c < k; c += kPT) red_s[k + c] = Ls[j * L + c];
-      for (int r = j + tid; r < rows; r += kPT) {
-        double x = Ls[r * L + j];
-        if (j >= 1) {
-          x -= twj * Ls[r * L + j - 1];
-          Ls[r * L + j] = x;
-        }
-        if (r == j) red_s[k + j] = x;
+    if (tid == j)
+#pragma unroll
+      for (int c = 0; c < K; ++c) rowj[j & 1][c] = x[0][c];
+    // partial sums over this thread's rows, reduced in chunks of at most 32
+    // values (fewer live registers)
+    constexpr int CH = K < 32 ? K : 32;
+#pragma unroll
+    for (int c0 = 0; c0 < K; c0 += CH) {
+      double s[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) s[c] = 0.0;
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int64_t r = tid + (int64_t)t * NT;
+        const double w = (r > j) ? xj[t] : 0.0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) s[c] += x[t][c0 + c] * w;
       }
+      const double v = wave_reduce_scatter<CH>(s, lane);
+      if (lane % (64 / CH) == 0) part[wave][c0 + lane / (64 / CH)] = v;
     }
     __syncthreads();
-    // column j-1 of Tf: Tf(i, j-1) = -tau_{j-1} sum_{c=i}^{j-2} Tf(i, c) dots_c
-    if (j >= 1) {
-      const int jj = j - 1;
-      for (int i = tid; i < jj; i += kPT) {
-        double s = 0.0;
-        for (int c = i; c < jj; ++c) s += Tl[i + c * k] * red_s[2 * k + c];
-        Tl[i + jj * k] = -tau_prev * s;
-      }
-      if (tid == 0) Tl[jj + jj * k] = tau_prev;
+    if (tid < K) {
+      double acc = 0.0;
+#pragma unroll
+      for (int w = 0; w < kRW; ++w) acc += part[w][tid];
+      red[tid] = acc;
     }
-    if (j == k) break;
-    const double alpha = red_s[k + j];
-    const double xn2 = red_s[j];
+    __syncthreads();
+    const double* rj = rowj[j & 1];
+    const double alpha = rj[j], xn2 = red[j];
     double tau, beta, scal;
     if (xn2 == 0.0) {
       tau = 0.0;
@@ -251,34 +261,52 @@ __global__ __launch_bounds__(kPT) void panel_wg_kernel(const PanelDesc* __restri
       tau = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    for (int c = j + 1 + tid; c < k; c += kPT) {
-      const double w = red_s[k + c] + scal * red_s[c];
-      w_s[c] = w;
-      if (a.R) a.R[j + (int64_t)c * a.ldr] = red_s[k + c] - tau * w;
+    // d_c = v_c^T v_j (c < j) and w_c = v_j^T A_c (c > j), one column at a time
+    double vr[RPT];
+#pragma unroll
+    for (int t = 0; t < RPT; ++t) {
+      const int64_t r = tid + (int64_t)t * NT;
+      vr[t] = (r > j) ? scal * xj[t] : (r == j ? 1.0 : 0.0);
     }
-    if (tid == 0) {
-      a.tau[j] = tau;
-      if (a.R) a.R[j + (int64_t)j * a.ldr] = beta;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const double dwc = rj[c] + scal * red[c];
+#pragma unroll
+      for (int t = 0; t < RPT; ++t) {
+        const int64_t r = tid + (int64_t)t * NT;
+        const double upd = x[t][c] - tau * vr[t] * dwc;
+        x[t][c] = (c > j) ? upd : (c == j ? ((r > j) ? vr[t] : (r == j ? beta : x[t][c])) : x[t][c]);
+      }
     }
-    if (a.R)
-      for (int i = j + 1 + tid; i < k; i += kPT) a.R[i + (int64_t)j * a.ldr] = 0.0;
-    for (int r = j + 1 + tid; r < rows; r += kPT) Ls[r * L + j] *= scal;
-    tau_prev = tau;
-    __syncthreads();
+    // column j of T_f: T(i, j) = -tau_j sum_{c=i}^{j-1} T(i, c) d_c
+    if (tid < j) {
+      double acc = 0.0;
+      for (int c = tid; c < j; ++c) acc += Tl[tid][c] * (rj[c] + scal * red[c]);
+      Tl[tid][j] = -tau * acc;
+    } else if (tid == j) {
+      Tl[j][j] = tau;
+      taus[j] = tau;
+    }
   }
   __syncthreads();
-  for (int idx = tid; idx < k * k; idx += kPT) {
+  for (int idx = tid; idx < k * k; idx += NT) {
     const int i = idx % k, c = idx / k;
-    a.Tf[i + (int64_t)c * a.ldt] = (i <= c) ? Tl[i + c * k] : 0.0;
+    a.Tf[i + (int64_t)c * a.ldt] = (i <= c) ? Tl[i][c] : 0.0;
   }
-  for (int idx = tid; idx < rows * k; idx += kPT) {
-    const int r = idx % rows, c = idx / rows;
-    a.W[r + (int64_t)c * a.ldw] = (r < c) ? 0.0 : (r == c ? 1.0 : Ls[r * L + c]);
+  for (int j = tid; j < k; j += NT) a.tau[j] = taus[j];
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int64_t r = tid + (int64_t)t * NT;
+    if (r >= M) continue;
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      if (c < k) a.W[r + (int64_t)c * a.ldw] = (r < c) ? 0.0 : (r == c ? 1.0 : x[t][c]);
+    if (a.R && r < k)
+#pragma unroll
+      for (int c = 0; c < K; ++c)
+        if (c < k) a.R[r + (int64_t)c * a.ldr] = (c >= r) ? x[t][c] : 0.0;
   }
 }
-
-constexpr int64_t kPanelLds = 140 * 1024;
-bool g_panel_attr = false;
 
 }  // namespace
 
@@ -286,8 +314,9 @@ bool g_panel_attr = false;
 
 int64_t panel_wg_max_rows(int k) {
   if (k < 1 || k > kPMaxK) return 0;
-  const int64_t avail = kPanelLds / 8 - (int64_t)k * k;
-  return avail / (k + 1) - 1;
+  int K = 1;
+  while (K < k) K <<= 1;
+  return (int64_t)kRT * std::min(64 / K, 8);  // at most 64 register doubles per row slot
 }
 
 int gemm_grouped(hipStream_t st, bool ta, bool tb, int tile, bool vec, const GemmDesc* d_descs,
@@ -331,20 +360,52 @@ int gauss_batched(hipStream_t st, const GaussDesc* d_descs, int count, int64_t m
   return RRF_OK;
 }
 
+template <int K, int RPT>
+void launch_panel(hipStream_t st, const PanelDesc* d, int count, int k, int nt) {
+  if (nt == 256)
+    hipLaunchKernelGGL((panel_reg_kernel<K, RPT, 256>), dim3((unsigned)count), dim3(256), 0, st, d,
+                       k);
+  else
+    hipLaunchKernelGGL((panel_reg_kernel<K, RPT, kRT>), dim3((unsigned)count), dim3(kRT), 0, st, d,
+                       k);
+}
+
+template <int K>
+void launch_panel_rows(hipStream_t st, const PanelDesc* d, int count, int k, int rpt, int nt) {
+  if constexpr (K <= 64) {
+    if (rpt == 1) launch_panel<K, 1>(st, d, count, k, nt);
+    if constexpr (2 * K <= 64) if (rpt == 2) launch_panel<K, 2>(st, d, count, k, nt);
+    if constexpr (4 * K <= 64) if (rpt == 4) launch_panel<K, 4>(st, d, count, k, nt);
+    if constexpr (8 * K <= 64) if (rpt == 8) launch_panel<K, 8>(st, d, count, k, nt);
+  }
+}
+
 int panel_wg_batched(hipStream_t st, const PanelDesc* d_descs, int count, int k,
                      int64_t max_rows) {
   if (count <= 0) return RRF_OK;
   if (k < 1 || k > kPMaxK || max_rows > panel_wg_max_rows(k))
-    return set_error(RRF_E_INTERNAL, "batched panel: shape beyond one workgroup's LDS");
-  if (!g_panel_attr) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)panel_wg_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)kPanelLds));
-    g_panel_attr = true;
+    return set_error(RRF_E_INTERNAL, "batched panel: shape beyond one workgroup's registers");
+  int K = 1;
+  while (K < k) K <<= 1;
+  // 256 threads when their rows fit in at most 32 register doubles per
+  // thread (several panels per CU), else 512
+  int nt = 256, rpt = 1;
+  while ((int64_t)nt * rpt < max_rows) rpt <<= 1;
+  if (K * rpt > 32) {
+    nt = kRT;
+    rpt = 1;
+    while ((int64_t)nt * rpt < max_rows) rpt <<= 1;
   }
-  const size_t lds = ((size_t)(max_rows + 1) * (k + 1) + (size_t)k * k) * 8;
   int tok = trace_begin(st, kTrPanel, 0.0, 0.0);
-  hipLaunchKernelGGL(panel_wg_kernel, dim3((unsigned)count), dim3(kPT), lds, st, d_descs, k);
+  switch (K) {
+    case 1: launch_panel_rows<1>(st, d_descs, count, k, rpt, nt); break;
+    case 2: launch_panel_rows<2>(st, d_descs, count, k, rpt, nt); break;
+    case 4: launch_panel_rows<4>(st, d_descs, count, k, rpt, nt); break;
+    case 8: launch_panel_rows<8>(st, d_descs, count, k, rpt, nt); break;
+    case 16: launch_panel_rows<16>(st, d_descs, count, k, rpt, nt); break;
+    case 32: launch_panel_rows<32>(st, d_descs, count, k, rpt, nt); break;
+    default: launch_panel_rows<64>(st, d_descs, count, k, rpt, nt);
+  }
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;
