@@ -316,7 +316,9 @@ int64_t panel_wg_max_rows(int k) {
   if (k < 1 || k > kPMaxK) return 0;
   int K = 1;
   while (K < k) K <<= 1;
-  return (int64_t)kRT * std::min(64 / K, 8);  // at most 64 register doubles per row slot
+  // at most 32 register doubles of panel per thread: taller panels are
+  // faster split by columns than held at 64 doubles per thread
+  return (int64_t)kRT * std::max(1, std::min(32 / K, 8));
 }
 
 int gemm_grouped(hipStream_t st, bool ta, bool tb, int tile, bool vec, const GemmDesc* d_descs,
