@@ -50,12 +50,18 @@ extern "C" {
 
 /* ---- precision modes -------------------------------------------------- */
 #define RRF_PREC_FP64   0  /* every step in binary64                           */
-/* randUTV only: the sketch Y = (T22^T T22)^q T22^T G of each step is formed
- * from bfloat16 copies of T22 (scaled by a power of two) and G with binary32
- * accumulation, each intermediate column rescaled by a power of two and
- * rounded to bfloat16 (round to nearest even); the QR of Y and every update
- * of T, U and V stay in binary64. The sketch only has to capture the
- * dominant subspace of T22 (Alg. 3; the paper itself is binary64 throughout). */
+/* The products that only have to capture a dominant singular subspace are
+ * formed from bfloat16 values (round to nearest even) with binary32
+ * accumulation; everything else stays binary64 (the paper itself is binary64
+ * throughout).
+ *  randUTV (Alg. 3): the sketch Y = (T22^T T22)^q T22^T G of each step, from
+ *    bfloat16 copies of T22 (scaled by a power of two) and G, each
+ *    intermediate column rescaled by a power of two before rounding; the QR
+ *    of Y and every update of T, U and V in binary64.
+ *  powerURV (Alg. 1): the 2q power products A V and A^T V_hat, from a
+ *    bfloat16 copy of A (scaled by a power of two) and V, V_hat rounded as
+ *    they are; the QRs, the Q factors and the final A V in binary64 (q = 0
+ *    has no power products and is binary64). */
 #define RRF_PREC_BF16_SKETCH 1
 
 /* ---- algorithms (for rrf_workspace_size) -------------------------------- */

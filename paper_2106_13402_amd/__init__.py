@@ -200,11 +200,14 @@ def randutv_batched(As, b: int, q: int, seed: int, *, want_u: bool = True, want_
 
 
 def powerurv(A, q: int, seed: int, *, b: int = 128, want_u: bool = True, want_v: bool = True,
-             check_finite: bool = False, inplace: bool = False):
-    """powerURV (Alg. 1): returns (U, T, V); b is the QR panel width."""
+             check_finite: bool = False, inplace: bool = False, precision: str = "fp64"):
+    """powerURV (Alg. 1): returns (U, T, V); b is the QR panel width.
+
+    precision "bf16_sketch" forms the 2q power products from bfloat16 values
+    with FP32 accumulation (RRF_PREC_BF16_SKETCH); everything else stays FP64."""
     n = int(A.shape[1])
     return _factor("rrf_powerurv_ex", "powerurv", A, min(b, max(n, 1)), q, seed, want_u, want_v,
-                   check_finite, inplace)
+                   check_finite, inplace, precision)
 
 
 def gaussian(seed: int, stream_id: int, rows: int, cols: int, device="cuda"):

@@ -124,9 +124,8 @@ int run_alg(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t
   rrf_opts o;
   rrf_opts_init(&o);
   if (opts) o = *opts;
-  if (o.precision != RRF_PREC_FP64 &&
-      !(alg == RRF_ALG_RANDUTV && o.precision == RRF_PREC_BF16_SKETCH))
-    return set_error(RRF_E_NOTSUP, "precision mode not implemented for this algorithm");
+  if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH)
+    return set_error(RRF_E_NOTSUP, "precision mode not implemented");
   const bool ok = alg == RRF_ALG_RANDUTV ? randutv_supported(m, n, b) : powerurv_supported(m, n, b);
   if (!ok) return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
   int dev = 0;
@@ -180,9 +179,9 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q, i
     if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
     return randutv_supported(m, n, b) ? randutv_workspace(m, n, b, precision) : 0;
   }
-  if (precision != RRF_PREC_FP64) return 0;
+  if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
   if (alg == RRF_ALG_POWERURV)
-    return powerurv_supported(m, n, b) ? powerurv_workspace(m, n, b, q) : 0;
+    return powerurv_supported(m, n, b) ? powerurv_workspace(m, n, b, q, precision) : 0;
   return 0;
 }
 
@@ -322,7 +321,8 @@ int rrf_powerurv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t 
                     uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
   return run_alg(RRF_ALG_POWERURV, m, n, A, lda, b, q, U, T, V, opts,
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
-                   return powerurv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk);
+                   return powerurv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
+                                       opts ? opts->precision : RRF_PREC_FP64);
                  });
 }
 

@@ -15,10 +15,10 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
 
 // Alg. 1, same status layout.
 bool powerurv_supported(int64_t m, int64_t n, int64_t b);
-size_t powerurv_workspace(int64_t m, int64_t n, int64_t b, int q);
+size_t powerurv_workspace(int64_t m, int64_t n, int64_t b, int q, int precision);
 int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                  int q, uint64_t seed, double* U, double* T, double* V, void* ws, size_t ws_bytes,
-                 bool check_input);
+                 bool check_input, int precision);
 
 // Batched Alg. 3 (one block size b for the whole call; matrix j keyed by
 // seeds[j]); outputs packed column-major (ld m, m, n). The status words of

@@ -60,7 +60,9 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
 int to_bf16(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
             const unsigned long long* word, uint16_t* out, int64_t ldo, uint16_t* outT,
             int64_t ldot);
+// Workspace of gemm_bf16_tn for any K (16 split-K partials), and for one K.
 size_t gemm_bf16_work_bytes(int64_t M, int64_t N);
+size_t gemm_bf16_work_bytes_k(int64_t M, int64_t N, int64_t K);
 // A^T B (A: K x M, B: K x N, bfloat16, ld multiples of 8, rows past K zero)
 // with FP32 accumulation; the M x N result goes either to out16 as bfloat16
 // with each column scaled by its own power of two (rows [M, ld16) zero), or to

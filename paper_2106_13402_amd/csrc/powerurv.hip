@@ -7,6 +7,14 @@
 //     Y = A^T V_hat; V = Q of HQR_thin(Y)           (n x n)
 //   A_hat = A V;  [U, R] = HQR_full(A_hat);  T = [R; 0]
 //
+// Mixed mode (RRF_PREC_BF16_SKETCH): the 2q power products Y_hat = A V and
+// Y = A^T V_hat are formed from bfloat16 values with FP32 accumulation (A
+// scaled by a power of two and copied once, with and without transpose, so
+// both products read their operands along K; V and V_hat rounded each
+// round), widened to FP64 for the QRs. A positive scale of a product leaves
+// its Householder Q unchanged. The QRs, the explicit Q factors and the final
+// A_hat = A V stay FP64.
+//
 // The QRs are blocked Householder factorizations: the panel kernel factors
 // nb columns at a time (compact WY, Sec. 2.3) and the trailing columns are
 // updated with two GEMMs, A <- A - (W Tf^T)(W^T A). Explicit Q factors are
@@ -36,9 +44,14 @@ struct PBufs {
   size_t split_elems = 0;
   void* panel = nullptr;
   size_t panel_bytes = 0;
+  // mixed mode: bfloat16 copies (ld a multiple of 8) and the bf16 GEMM scratch
+  uint16_t *Ab = nullptr, *Abt = nullptr, *Vb = nullptr, *Vhb = nullptr;
+  unsigned long long* word = nullptr;
+  void* bwork = nullptr;
+  size_t bwork_bytes = 0;
 };
 
-bool plan(Arena& ar, int64_t m, int64_t n, int64_t nb, bool need_v, PBufs* B) {
+bool plan(Arena& ar, int64_t m, int64_t n, int64_t nb, bool need_v, int precision, PBufs* B) {
   const int64_t mx = std::max(m, n);
   B->status = ar.take<int>(64);
   B->Yh = ar.take<double>((size_t)m * n);
@@ -54,6 +67,16 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t nb, bool need_v, PBufs* B) {
   B->panel_bytes = panel_work_bytes(mx, (int)nb);
   if (B->panel_bytes == 0) return false;
   B->panel = ar.take<char>(B->panel_bytes);
+  if (precision == RRF_PREC_BF16_SKETCH) {
+    const int64_t lm = bf16_ld(m), ln = bf16_ld(n);
+    B->Ab = ar.take<uint16_t>((size_t)lm * n);
+    B->Abt = ar.take<uint16_t>((size_t)ln * m);
+    B->Vb = ar.take<uint16_t>((size_t)ln * n);
+    B->Vhb = ar.take<uint16_t>((size_t)lm * n);
+    B->word = ar.take<unsigned long long>(1);
+    B->bwork_bytes = std::max(gemm_bf16_work_bytes_k(m, n, n), gemm_bf16_work_bytes_k(n, n, m));
+    B->bwork = ar.take<char>(B->bwork_bytes);
+  }
   return true;
 }
 
@@ -112,25 +135,27 @@ bool powerurv_supported(int64_t m, int64_t n, int64_t b) {
   return panel_work_bytes(std::max(m, n), (int)std::min(b, n)) > 0;
 }
 
-size_t powerurv_workspace(int64_t m, int64_t n, int64_t b, int q) {
-  (void)q;
+size_t powerurv_workspace(int64_t m, int64_t n, int64_t b, int q, int precision) {
   Arena ar;
   ar.counting = true;
   PBufs B;
-  if (!plan(ar, m, n, std::min(b, n), true, &B)) return 0;
+  if (!plan(ar, m, n, std::min(b, n), true, q > 0 ? precision : RRF_PREC_FP64, &B)) return 0;
   return ar.used;
 }
 
 int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                  int q, uint64_t seed, double* U, double* T, double* V, void* ws, size_t ws_bytes,
-                 bool check_input) {
+                 bool check_input, int precision) {
   const int64_t nb = std::min(b, n);
+  if (q == 0) precision = RRF_PREC_FP64;  // no power products to round
   Arena ar;
   ar.base = reinterpret_cast<char*>(ws);
   ar.cap = ws_bytes;
   PBufs B;
-  if (!plan(ar, m, n, nb, V == nullptr, &B) || ar.used > ws_bytes)
+  if (!plan(ar, m, n, nb, V == nullptr, precision, &B) || ar.used > ws_bytes)
     return set_error(RRF_E_NOMEM, "powerurv: workspace too small");
+  const bool mixed = precision == RRF_PREC_BF16_SKETCH;
+  const int64_t lm = bf16_ld(m), ln = bf16_ld(n);
   RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(B.status), 64, 0u));
   if (check_input) RRF_TRY(check_finite(st, m, n, A, lda, B.status + 1));
   double* Vm = V ? V : B.Vw;
@@ -140,13 +165,30 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
     RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R));
     RRF_TRY(form_q(st, n, n, nb, n, B, Vm));
   }
+  if (mixed) {
+    RRF_TRY(maxabs(st, m, n, A, lda, B.word));
+    RRF_TRY(to_bf16(st, m, n, A, lda, B.word, B.Ab, lm, B.Abt, ln));
+  }
   for (int it = 0; it < q; ++it) {
-    RRF_TRY(dgemm(st, false, false, m, n, n, 1.0, A, lda, Vm, n, 0.0, B.Yh, m, B.split,
-                  B.split_elems));
+    if (mixed) {
+      // Y_hat = A V = (A^T)^T V
+      RRF_TRY(to_bf16(st, n, n, Vm, n, nullptr, B.Vb, ln, nullptr, 0));
+      RRF_TRY(gemm_bf16_tn(st, m, n, n, B.Abt, ln, B.Vb, ln, nullptr, 0, B.Yh, m, B.bwork,
+                           B.bwork_bytes));
+    } else {
+      RRF_TRY(dgemm(st, false, false, m, n, n, 1.0, A, lda, Vm, n, 0.0, B.Yh, m, B.split,
+                    B.split_elems));
+    }
     RRF_TRY(hqr_blocked(st, m, n, nb, B.Yh, m, B, B.R));
     RRF_TRY(form_q(st, m, n, nb, n, B, B.Yh));  // V_hat in Yh
-    RRF_TRY(dgemm(st, true, false, n, n, m, 1.0, A, lda, B.Yh, m, 0.0, Vm, n, B.split,
-                  B.split_elems));
+    if (mixed) {
+      RRF_TRY(to_bf16(st, m, n, B.Yh, m, nullptr, B.Vhb, lm, nullptr, 0));
+      RRF_TRY(gemm_bf16_tn(st, n, n, m, B.Ab, lm, B.Vhb, lm, nullptr, 0, Vm, n, B.bwork,
+                           B.bwork_bytes));
+    } else {
+      RRF_TRY(dgemm(st, true, false, n, n, m, 1.0, A, lda, B.Yh, m, 0.0, Vm, n, B.split,
+                    B.split_elems));
+    }
     RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R));
     RRF_TRY(form_q(st, n, n, nb, n, B, Vm));
   }

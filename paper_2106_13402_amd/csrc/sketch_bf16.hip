@@ -324,18 +324,11 @@ size_t gemm_bf16_work_bytes(int64_t M, int64_t N) {
   return (size_t)16 * M * N * sizeof(float) + (size_t)M * N * sizeof(float) + 256;
 }
 
-int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t* A,
-                 int64_t lda, const uint16_t* B, int64_t ldb, uint16_t* out16, int64_t ld16,
-                 double* out64, int64_t ld64, void* work, size_t work_bytes) {
-  if (M <= 0 || N <= 0) return RRF_OK;
-  if ((lda & 7) || (ldb & 7) || (reinterpret_cast<uintptr_t>(A) & 15) ||
-      (reinterpret_cast<uintptr_t>(B) & 15))
-    return set_error(RRF_E_INTERNAL, "bf16 gemm: operands must be 16-byte aligned");
-  if (work_bytes < gemm_bf16_work_bytes(M, N) || work == nullptr)
-    return set_error(RRF_E_NOMEM, "bf16 gemm: workspace too small");
-  const int64_t tiles_m = ceil_div(M, kBM), tiles = tiles_m * ceil_div(N, kBN);
-  // split K as for the FP64 GEMM: fill the 512 resident slots, at least 256
-  // of K per split, at most 16 splits
+namespace {
+// Split of K as for the FP64 GEMM: fill the 512 resident slots, at least 256
+// of K per split, at most 16 splits.
+int bf16_splits(int64_t M, int64_t N, int64_t K) {
+  const int64_t tiles = ceil_div(M, kBM) * ceil_div(N, kBN);
   int splits = 1;
   if (tiles < 512 && K >= 512) {
     double best = 1.0;
@@ -347,6 +340,27 @@ int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t
       }
     }
   }
+  const int64_t kchunk = round_up(ceil_div(std::max<int64_t>(K, 1), splits), kBK);
+  return (int)std::max<int64_t>(1, ceil_div(K, kchunk));
+}
+}  // namespace
+
+size_t gemm_bf16_work_bytes_k(int64_t M, int64_t N, int64_t K) {
+  return (size_t)bf16_splits(M, N, K) * M * N * sizeof(float) +
+         (M > kColLds ? (size_t)M * N * sizeof(float) : 0) + 256;
+}
+
+int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t* A,
+                 int64_t lda, const uint16_t* B, int64_t ldb, uint16_t* out16, int64_t ld16,
+                 double* out64, int64_t ld64, void* work, size_t work_bytes) {
+  if (M <= 0 || N <= 0) return RRF_OK;
+  if ((lda & 7) || (ldb & 7) || (reinterpret_cast<uintptr_t>(A) & 15) ||
+      (reinterpret_cast<uintptr_t>(B) & 15))
+    return set_error(RRF_E_INTERNAL, "bf16 gemm: operands must be 16-byte aligned");
+  if (work_bytes < gemm_bf16_work_bytes_k(M, N, K) || work == nullptr)
+    return set_error(RRF_E_NOMEM, "bf16 gemm: workspace too small");
+  const int64_t tiles_m = ceil_div(M, kBM), tiles = tiles_m * ceil_div(N, kBN);
+  int splits = bf16_splits(M, N, K);
   GemmBf16Args g{};
   g.M = M; g.N = N; g.K = K;
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb;
@@ -354,7 +368,7 @@ int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t
   splits = (int)std::max<int64_t>(1, ceil_div(K, g.kchunk));
   g.tiles_m = (int)tiles_m;
   float* P = reinterpret_cast<float*>(work);
-  float* col = P + (size_t)16 * M * N;
+  float* col = P + (size_t)splits * M * N;
   g.P = P;
   int tok = trace_begin(st, kTrGemmBf16, 2.0 * M * N * K, 2.0 * ((double)M * K + (double)K * N) +
                                                              4.0 * splits * M * N);

@@ -71,6 +71,13 @@ def test_workspace_size(lib):
     f = lib.rrf_workspace_size
     assert f(_lib.RRF_ALG_RANDUTV, 512, 512, 32, 1, 0) > 0
     assert f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 1, 0) > 0
+    # powerURV's mixed mode adds bfloat16 copies of A (both layouts), V and
+    # V_hat and the bfloat16 GEMM's partial sums; q = 0 has no power products
+    pw = f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 1, 0)
+    pm = f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 1, 1)
+    assert pw + 4 * 2 * 512 * 512 <= pm <= pw + 4 * 2 * 512 * 512 + 16 * 4 * 512 * 512 + 2 ** 20
+    assert f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 0, 1) == f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 0, 0)
+    assert f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 1, 2) == 0
     assert f(_lib.RRF_ALG_RANDUTV, 512, 600, 32, 1, 0) == 0     # m < n
     assert f(_lib.RRF_ALG_RANDUTV, 512, 512, 300, 1, 0) == 0    # b > 256
     assert f(7, 512, 512, 32, 1, 0) == 0

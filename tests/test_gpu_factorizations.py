@@ -288,6 +288,55 @@ def test_powerurv_parity(gpu, m, n, b, q):
     np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * 2.0)
 
 
+# ------------------------------------------------ powerURV, bfloat16 power products
+POWER_MIXED = [(300, 256, 32, 1, 64.0), (400, 256, 64, 2, 40.0), (256, 256, 16, 2, 1e9),
+               (520, 300, 128, 1, 75.0)]
+
+
+@pytest.mark.parametrize("m,n,b,q,scale", POWER_MIXED)
+def test_powerurv_bf16_parity(gpu, m, n, b, q, scale):
+    """GPU against the oracle's mixed mode (same rounded operands; the GPU
+    accumulates in FP32, the oracle in FP64): |T_kk| agree to a median of
+    1e-5 ||A|| and at most 2e-4 ||A|| (FP32 accumulation over K <= 520
+    terms: ~K 2^-24 relative in the worst case, far less typically; an FP32
+    emulation on the CPU gives medians 3e-8 to 2.4e-6), while the FP64 path
+    sits 6e-5 to 7e-5 away in the median, which the first bound excludes. U, V orthogonal and A = U T V^T to FP64 accuracy (the QRs,
+    the Q factors and A V are FP64). scale = 1e9 is the linear spectrum."""
+    from paper_2106_13402_amd import powerurv
+    print(f"case: powerurv bf16 m={m} n={n} b={b} q={q}", flush=True)
+    j = np.arange(n, dtype=float)
+    s = 1.0 - j / (2 * n) if scale > 1e8 else np.exp(-j / scale)
+    A = spectral_matrix(m, n, s, seed=m + n + q)
+    U, T, V = (_host(x) for x in powerurv(_to_dev(A, gpu), q, 1, b=b, precision="bf16_sketch"))
+    _check_factorization(A, U, T, V)
+    _, To, _ = oracle.powerurv(A, q, 1, precision="bf16")
+    _, T64, _ = oracle.powerurv(A, q, 1)
+    d = np.abs(np.abs(np.diag(T)) - np.abs(np.diag(To))) / s[0]
+    d64 = np.abs(np.abs(np.diag(T64)) - np.abs(np.diag(To))) / s[0]
+    assert np.median(d) <= 1e-5 and d.max() <= 2e-4, (np.median(d), d.max())
+    assert np.median(d64) > 4 * np.median(d)  # the bound tells the modes apart
+
+
+def test_powerurv_bf16_gate_1024(gpu):
+    """1024 x 1024, s_j = exp(-j/200), q = 2: e_k of the mixed mode within
+    max(1.5 sigma_{k+1}, 1.1 x the FP64 oracle envelope over 5 sketch seeds)."""
+    from paper_2106_13402_amd import powerurv
+    n = 1024
+    s = np.exp(-np.arange(n) / 200.0)
+    A = spectral_matrix(n, n, s, seed=9)
+    U, T, V = (_host(x) for x in powerurv(_to_dev(A, gpu), 2, 1, b=128,
+                                          precision="bf16_sketch"))
+    _check_factorization(A, U, T, V)
+    ks = list(range(0, n, 64))
+    env = np.zeros(len(ks))
+    for seed in range(5):
+        _, To, _ = oracle.powerurv(A, 2, 100 + seed)
+        env = np.maximum(env, [M.spec(To[k:, k:]) for k in ks])
+    ek = [M.spec(T[k:, k:]) for k in ks]
+    bad = [k for i, k in enumerate(ks) if ek[i] > max(1.5 * s[k], 1.1 * env[i])]
+    assert not bad, bad
+
+
 # ------------------------------------------------------- mixed-precision sketch
 def _oracle_envelope(A, b, q, seeds, ks):
     """Largest e_k = ||T(k:, k:)||_2 over FP64 oracle runs with several sketch

@@ -103,7 +103,7 @@ def test_r_diagonal_is_gram_schmidt_of_AV():
 
 MUTANTS = {
     "no_rurv_qr_for_q0": ("        V = form_q(W, tau, n)\n    else:", "        V = G\n    else:"),
-    "A_instead_of_AT": ("Y = A.T @ V_hat", "Y = A @ V_hat"),
+    "A_instead_of_AT": ("Y = Ap.T @ rnd(V_hat)", "Y = Ap @ rnd(V_hat)"),
     "skip_final_product": ("A_hat = A @ V\n", "A_hat = A @ G\n"),
     "one_round_less": ("for j in range(q):", "for j in range(max(q - 1, 0)):"),
 }
@@ -124,3 +124,68 @@ def test_pins_catch_planted_mistake(name):
     A = _well_conditioned(24, 24, seed=5)
     q = 0 if name == "no_rurv_qr_for_q0" else 2
     assert pin_failures(_mutant(name), A, q) != [], name
+
+
+# ------------------------------------------------ mixed mode (bfloat16 power)
+def _spectral(m, n, s, seed=0):
+    from synthetic import spectral_matrix
+    return spectral_matrix(m, n, s, seed=seed)
+
+
+def test_mixed_q0_is_fp64():
+    """q = 0 has no power products: the mixed mode is the FP64 RURV."""
+    A = np.random.default_rng(3).standard_normal((40, 30))
+    U1, T1, V1 = oracle.powerurv(A, 0, 5)
+    U2, T2, V2 = oracle.powerurv(A, 0, 5, precision="bf16")
+    assert np.array_equal(T1, T2) and np.array_equal(V1, V2) and np.array_equal(U1, U2)
+
+
+def test_mixed_power_of_two_invariance():
+    """Scaling A by 2^k leaves the rounded power products' column spaces,
+    hence V, unchanged bit for bit, and scales T exactly."""
+    A = _spectral(60, 48, np.exp(-np.arange(48) / 6.0))
+    U1, T1, V1 = oracle.powerurv(A, 2, 7, precision="bf16")
+    U2, T2, V2 = oracle.powerurv(A * 2.0 ** 37, 2, 7, precision="bf16")
+    assert np.array_equal(V1, V2) and np.array_equal(U1, U2)
+    assert np.array_equal(T2, T1 * 2.0 ** 37)
+
+
+def test_mixed_rounds_and_keeps_the_subspace():
+    """The bfloat16 products move the dominant subspace of V (a gap of 10^3
+    after k = 8) by the rounding level, not by zero (the rounding is applied)
+    and not by more (it is still captured); the factorization stays exact.
+    The trailing columns span singular values below bfloat16's resolution
+    relative to the leading ones and may rotate freely."""
+    n = 64
+    s = np.r_[np.linspace(1.0, 0.5, 8), 1e-3 * np.linspace(1.0, 0.5, n - 8)]
+    A = _spectral(80, n, s, seed=2)
+    _, _, V64 = oracle.powerurv(A, 1, 3)
+    U, T, V = oracle.powerurv(A, 1, 3, precision="bf16")
+    assert M.orth_error(U) < 1e-13 and M.orth_error(V) < 1e-13
+    assert M.recon_error(A, U, T, V) < 1e-13
+    P, P64 = V[:, :8] @ V[:, :8].T, V64[:, :8] @ V64[:, :8].T
+    d = np.linalg.norm(P - P64, 2)
+    assert 1e-7 < d < 2e-2, d
+    _, _, Vt = np.linalg.svd(A)
+    Pd = Vt[:8].T
+    sin_b = np.linalg.norm(Pd - V[:, :8] @ (V[:, :8].T @ Pd), 2)
+    assert sin_b < 2e-2, sin_b
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_mixed_rank_revealing_gate(q):
+    """e_k of the mixed mode within max(1.5 sigma_{k+1}, 1.1 x the FP64
+    envelope over 5 sketch seeds) where sigma_{k+1} is well above rounding."""
+    n = 160
+    s = np.exp(-np.arange(n) / 40.0)
+    A = _spectral(n, n, s, seed=4)
+    ks = list(range(0, n, 8))
+    env = np.zeros(len(ks))
+    for seed in range(5):
+        _, T, _ = oracle.powerurv(A, q, 100 + seed)
+        env = np.maximum(env, [M.spec(T[k:, k:]) for k in ks])
+    _, Tb, _ = oracle.powerurv(A, q, 1, precision="bf16")
+    ek = np.array([M.spec(Tb[k:, k:]) for k in ks])
+    ok = [i for i, k in enumerate(ks) if s[k] >= 1e-10]
+    bad = [ks[i] for i in ok if ek[i] > max(1.5 * s[ks[i]], 1.1 * env[i])]
+    assert not bad, bad
