@@ -187,6 +187,78 @@ def cpu_baseline(A_host, b, q, seed, budget_s):
     }
 
 
+# ------------------------------------------------------------ powerURV leg
+def powerurv_flops(m: int, n: int, q: int) -> float:
+    """Algorithmic flops of Alg. 1 with explicit Q factors (U formed), with
+    LAPACK's counts: QR of m x n 2 m n^2 - 2/3 n^3, its thin Q the same, a
+    full m x m Q 4 m^2 n - 4 m n^2 + 4/3 n^3. Per power round A V and
+    A^T V_hat (2 m n^2 each), QR + thin Q of the m x n product, QR + Q of the
+    n x n one (8/3 n^3); then A V, its QR and the m x m U. For m = n this is
+    (28 q / 3 + 14 / 3) n^3 (q = 0: the RURV start QR adds 8/3 n^3)."""
+    per_round = 4 * m * n * n + (4 * m * n * n - 4 / 3 * n ** 3) + 8 / 3 * n ** 3
+    tail = 2 * m * n * n + (2 * m * n * n - 2 / 3 * n ** 3) + (4 * m * m * n - 4 * m * n * n
+                                                               + 4 / 3 * n ** 3)
+    start = 8 / 3 * n ** 3 if q == 0 else 0.0
+    return q * per_round + tail + start
+
+
+def powerurv_leg(A, U, T, V, s, kgrid, b, q, args, dev, fp64_acc):
+    """powerURV (Alg. 1) on the same matrix, FP64 and with the bfloat16 power
+    products, timed like the randUTV legs (U and V formed)."""
+    import ctypes as C
+    import torch
+    import paper_2106_13402_amd as rrf
+    from paper_2106_13402_amd import _lib
+    n = A.shape[1]
+
+    def factor(precision):
+        nbytes = rrf.workspace_size("powerurv", n, n, b, q, precision)
+        ws = rrf._workspace(dev, nbytes)
+        opts = _lib.rrf_opts()
+        rrf.lib.rrf_opts_init(C.byref(opts))
+        opts.precision = rrf.PRECISIONS[precision]
+        opts.stream = torch.cuda.current_stream(dev).cuda_stream
+        opts.workspace = ws.data_ptr()
+        opts.workspace_bytes = ws.numel()
+        st = rrf.lib.rrf_powerurv_ex(n, n, A.data_ptr(), n, b, q, args.seed, U.data_ptr(),
+                                     T.data_ptr(), V.data_ptr(), C.byref(opts))
+        if st != 0:
+            raise RuntimeError(f"rrf_powerurv_ex failed: {st} {rrf.lib.rrf_last_error().decode()}")
+
+    leg = {"workload": f"powerURV n={n} b={b} q={q}, same matrix, U and V formed",
+           "model_flops": powerurv_flops(n, n, q)}
+    ref = None
+    for precision in ("fp64", "bf16_sketch"):
+        for _ in range(args.warmup):
+            factor(precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            factor(precision)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / args.steps
+        log(f"powerURV {precision}: {per:.3f} s per factorization")
+        r = {"value": per, "unit": "s", "model_tflops": leg["model_flops"] / per / 1e12}
+        if fp64_acc is not None:
+            acc = accuracy(A, U, T, V, s, kgrid)
+            r["accuracy"] = acc
+            if ref is None:
+                ref = acc["e_k"]
+            else:
+                # the bfloat16 power products act on the whole of A, so they
+                # resolve directions down to about 1e-3 sigma_1 only
+                ks = [i for i, k in enumerate(kgrid) if s[k] >= 1e-3 * s[0]]
+                r["ek_over_fp64_max"] = max(acc["e_k"][i] / ref[i] for i in ks)
+                r["ek_gate"] = ("e_k <= max(1.5 sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid where "
+                                "sigma_{k+1} >= 1e-3 sigma_1")
+                r["ek_gate_pass"] = all(acc["e_k"][i] <= max(1.5 * s[kgrid[i]], 1.1 * ref[i])
+                                        for i in ks)
+                r["ek_over_fp64_max_all_k"] = max(a / f for a, f in zip(acc["e_k"], ref))
+        leg[precision] = r
+    leg["speedup_mixed"] = leg["fp64"]["value"] / leg["bf16_sketch"]["value"]
+    return leg
+
+
 # ------------------------------------------------------------- batched leg
 def auto_block(n: int, m: int = 0) -> int:
     """Block size the batched call picks for b = 0."""
@@ -319,6 +391,7 @@ def main() -> int:
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-powerurv", action="store_true")
     ap.add_argument("--batch", type=int, default=4096, help="matrices in the batched leg")
     ap.add_argument("--batch-q", type=int, default=1)
     args = ap.parse_args()
@@ -455,6 +528,9 @@ def main() -> int:
                                         for i in ks)
             log(f"mixed accuracy: {acc}")
         out["mixed"] = mixed
+    if not args.no_powerurv:
+        out["powerurv"] = powerurv_leg(A, U, T, V, s, kgrid, b, q, args, dev,
+                                       None if args.no_accuracy else out["accuracy"])
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         A_host = A.cpu().numpy()

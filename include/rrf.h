@@ -61,7 +61,10 @@ extern "C" {
  *  powerURV (Alg. 1): the 2q power products A V and A^T V_hat, from a
  *    bfloat16 copy of A (scaled by a power of two) and V, V_hat rounded as
  *    they are; the QRs, the Q factors and the final A V in binary64 (q = 0
- *    has no power products and is binary64). */
+ *    has no power products and is binary64). These products are rounded
+ *    relative to ||A||, so directions below about 1e-3 of the largest
+ *    singular value are not separated (e_k there exceeds the binary64
+ *    value). */
 #define RRF_PREC_BF16_SKETCH 1
 
 /* ---- algorithms (for rrf_workspace_size) -------------------------------- */

@@ -337,6 +337,29 @@ def test_powerurv_bf16_gate_1024(gpu):
     assert not bad, bad
 
 
+def test_powerurv_bf16_resolution_limit(gpu):
+    """1024 x 1024, s_j = exp(-j/80) (down to 3e-6), q = 2: the gate holds
+    where sigma_{k+1} >= 1e-3 sigma_1; below, where the bfloat16 power
+    products no longer separate directions, e_k stays within 10x the FP64
+    envelope (a bounded, documented limit, not a pass of the gate)."""
+    from paper_2106_13402_amd import powerurv
+    n = 1024
+    s = np.exp(-np.arange(n) / 80.0)
+    A = spectral_matrix(n, n, s, seed=10)
+    U, T, V = (_host(x) for x in powerurv(_to_dev(A, gpu), 2, 1, b=128,
+                                          precision="bf16_sketch"))
+    _check_factorization(A, U, T, V)
+    ks = list(range(0, n, 64))
+    env = np.zeros(len(ks))
+    for seed in range(3):
+        _, To, _ = oracle.powerurv(A, 2, 100 + seed)
+        env = np.maximum(env, [M.spec(To[k:, k:]) for k in ks])
+    ek = np.array([M.spec(T[k:, k:]) for k in ks])
+    hi = [i for i, k in enumerate(ks) if s[k] >= 1e-3]
+    assert all(ek[i] <= max(1.5 * s[ks[i]], 1.1 * env[i]) for i in hi)
+    assert np.all(ek <= 10 * env), (ek / env).max()
+
+
 # ------------------------------------------------------- mixed-precision sketch
 def _oracle_envelope(A, b, q, seeds, ks):
     """Largest e_k = ||T(k:, k:)||_2 over FP64 oracle runs with several sketch

@@ -189,3 +189,25 @@ def test_mixed_rank_revealing_gate(q):
     ok = [i for i, k in enumerate(ks) if s[k] >= 1e-10]
     bad = [ks[i] for i in ok if ek[i] > max(1.5 * s[ks[i]], 1.1 * env[i])]
     assert not bad, bad
+
+
+def test_mixed_resolution_limit():
+    """Below about 1e-3 sigma_1 the bfloat16 power products (rounded relative
+    to ||A||) no longer separate directions: e_k there exceeds the FP64
+    value, by a bounded factor (here spectrum exp(-j/40), q = 2, e_k at
+    sigma ~ 1e-5 is 2-3x the FP64 envelope), while above it the gate holds."""
+    n = 512
+    s = np.exp(-np.arange(n) / 40.0)
+    A = _spectral(n, n, s, seed=3)
+    ks = list(range(0, n, 32))
+    env = np.zeros(len(ks))
+    for seed in range(3):
+        _, T, _ = oracle.powerurv(A, 2, 100 + seed)
+        env = np.maximum(env, [M.spec(T[k:, k:]) for k in ks])
+    _, Tb, _ = oracle.powerurv(A, 2, 1, precision="bf16")
+    ek = np.array([M.spec(Tb[k:, k:]) for k in ks])
+    hi = [i for i, k in enumerate(ks) if s[k] >= 1e-3]
+    lo = [i for i, k in enumerate(ks) if s[k] < 1e-4]
+    assert all(ek[i] <= max(1.5 * s[ks[i]], 1.1 * env[i]) for i in hi)
+    r = ek[lo] / env[lo]
+    assert 1.2 < r.max() < 6.0, r
