@@ -298,7 +298,7 @@ def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seco
     ms, ns = i64([m for m, n in shapes]), i64([n for m, n in shapes])
     pa, pu, pt, pv = ptrs(As), ptrs(out[0]), ptrs(out[1]), ptrs(out[2])
     ldas = i64([int(A.stride(1)) for A in As])
-    nbytes = rrf.batched_workspace_size([m for m, n in shapes], [n for m, n in shapes], 0)
+    nbytes = rrf.batched_workspace_size([m for m, n in shapes], [n for m, n in shapes], 0, "fp64")
     ws = rrf._workspace(dev, nbytes)
     opts = _lib.rrf_opts()
     rrf.lib.rrf_opts_init(C.byref(opts))

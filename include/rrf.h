@@ -157,8 +157,9 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
  *  T      : host array of device pointers to m[j] x n[j] outputs (ld m[j]);
  *           T[j] may be A[j] when lda[j] == m[j]                      (arg 10)
  *  V      : as U with n[j] x n[j] outputs (ld n[j]), or NULL          (arg 11)
- *  opts   : as for rrf_randutv_ex; only RRF_PREC_FP64; the workspace must
- *           hold rrf_randutv_batched_workspace_size(count, m, n, b) bytes
+ *  opts   : as for rrf_randutv_ex (RRF_PREC_FP64, or RRF_PREC_BF16_SKETCH for
+ *           the bfloat16 sketch of every step); the workspace must hold
+ *           rrf_randutv_batched_workspace_size(count, m, n, b, precision) bytes
  * The output of every matrix has the form rrf_randutv documents. The host
  * arrays are read during the call only. The call keeps a small pinned host
  * staging ring per device (freed by rrf_release_workspace) and may wait for
@@ -171,9 +172,10 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
 /* The block size rrf_randutv_batched uses for an m x n matrix when called
  * with b = 0 (16 for n <= 256, else 32); 0 for invalid sizes. */
 int64_t rrf_randutv_batched_block(int64_t m, int64_t n);
-/* Bytes of device workspace for rrf_randutv_batched; 0 for invalid sizes. */
+/* Bytes of device workspace for rrf_randutv_batched; 0 for invalid sizes or
+ * precision. */
 size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m,
-                                          const int64_t* n, int64_t b);
+                                          const int64_t* n, int64_t b, int precision);
 
 /* Release the library-managed workspace cache of the current device and the
  * batched call's staging rings of every device. */

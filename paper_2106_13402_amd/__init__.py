@@ -148,15 +148,17 @@ def batched_block(m: int, n: int) -> int:
     return int(lib.rrf_randutv_batched_block(m, n))
 
 
-def batched_workspace_size(ms, ns, b: int) -> int:
+def batched_workspace_size(ms, ns, b: int, precision: str = "fp64") -> int:
     """Bytes of workspace rrf_randutv_batched needs for these sizes (0: invalid)."""
-    return int(lib.rrf_randutv_batched_workspace_size(len(ms), _i64_array(ms), _i64_array(ns), b))
+    return int(lib.rrf_randutv_batched_workspace_size(len(ms), _i64_array(ms), _i64_array(ns), b,
+                                                      PRECISIONS[precision]))
 
 
 def randutv_batched(As, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
-                    check_finite: bool = False, out=None):
+                    check_finite: bool = False, out=None, precision: str = "fp64"):
     """Batched randUTV (Alg. 3) of the matrices in the list ``As``; matrix j is
-    keyed by ``seed + j``; ``b = 0`` picks the block size per matrix.
+    keyed by ``seed + j``; ``b = 0`` picks the block size per matrix;
+    precision "bf16_sketch" forms every step's sketch from bfloat16 copies.
 
     Returns three lists (Us, Ts, Vs) (Us / Vs None when not wanted). ``out``
     may pass such lists (tight column-major tensors of the right shapes) to be
@@ -179,12 +181,13 @@ def randutv_batched(As, b: int, q: int, seed: int, *, want_u: bool = True, want_
         Us = [empty_colmajor(m, m, dev) for m in ms] if want_u else None
         Ts = [empty_colmajor(m, n, dev) for m, n in zip(ms, ns)]
         Vs = [empty_colmajor(n, n, dev) for n in ns] if want_v else None
-    nbytes = batched_workspace_size(ms, ns, b)
+    nbytes = batched_workspace_size(ms, ns, b, precision)
     if nbytes == 0:
         raise RRFError(_lib.RRF_E_NOTSUP, "rrf_randutv_batched", "no workspace size for these sizes")
     ws = _workspace(dev, nbytes)
     opts = _lib.rrf_opts()
     lib.rrf_opts_init(C.byref(opts))
+    opts.precision = PRECISIONS[precision]
     opts.stream = _stream_ptr(dev)
     opts.workspace = ws.data_ptr()
     opts.workspace_bytes = ws.numel()

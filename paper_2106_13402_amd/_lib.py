@@ -59,7 +59,7 @@ PROTOTYPES = {
     "rrf_workspace_size": (_sz, [C.c_int, _i64, _i64, _i64, _i32, C.c_int]),
     "rrf_randutv_batched": (C.c_int, [_i64, _vp, _vp, _vp, _vp, _i64, _i32, _u64, _vp, _vp, _vp,
                                       C.POINTER(rrf_opts)]),
-    "rrf_randutv_batched_workspace_size": (_sz, [_i64, _vp, _vp, _i64]),
+    "rrf_randutv_batched_workspace_size": (_sz, [_i64, _vp, _vp, _i64, C.c_int]),
     "rrf_randutv_batched_block": (_i64, [_i64, _i64]),
     "rrf_release_workspace": (C.c_int, []),
     "rrf_gaussian": (C.c_int, [_u64, _u64, _i64, _i64, _dp, _i64, _vp]),

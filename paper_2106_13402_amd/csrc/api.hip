@@ -206,12 +206,13 @@ int64_t rrf_randutv_batched_block(int64_t m, int64_t n) {
 }
 
 size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m, const int64_t* n,
-                                          int64_t b) {
+                                          int64_t b, int precision) {
   if (count < 0 || (count > 0 && (m == nullptr || n == nullptr)) || b < 0 || b > kBatchedMaxB)
     return 0;
+  if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
   for (int64_t j = 0; j < count; ++j)
     if (n[j] < 1 || m[j] < n[j] || m[j] > kBatchedMaxDim) return 0;
-  if (b > 0) return count > 0 ? randutv_batched_workspace(count, m, n, b) : 0;
+  if (b > 0) return count > 0 ? randutv_batched_workspace(count, m, n, b, precision) : 0;
   // automatic block size: the groups run one after another in one workspace
   size_t need = 0;
   for (int64_t bg : {16, 32}) {
@@ -222,7 +223,8 @@ size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m, const
         gn.push_back(n[j]);
       }
     if (!gm.empty())
-      need = std::max(need, randutv_batched_workspace((int64_t)gm.size(), gm.data(), gn.data(), bg));
+      need = std::max(need, randutv_batched_workspace((int64_t)gm.size(), gm.data(), gn.data(), bg,
+                                                      precision));
   }
   return need;
 }
@@ -257,8 +259,8 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
   rrf_opts o;
   rrf_opts_init(&o);
   if (opts) o = *opts;
-  if (o.precision != RRF_PREC_FP64)
-    return set_error(RRF_E_NOTSUP, "batched randutv: only RRF_PREC_FP64");
+  if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH)
+    return set_error(RRF_E_NOTSUP, "batched randutv: precision mode not implemented");
   int dev = 0;
   RRF_TRY(device_ready(&dev));
   for (int64_t j = 0; j < count; ++j) {
@@ -267,7 +269,7 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
     RRF_TRY(check_device_ptr(T[j], 10));
     if (V) RRF_TRY(check_device_ptr(V[j], 11));
   }
-  const size_t need = rrf_randutv_batched_workspace_size(count, m, n, b);
+  const size_t need = rrf_randutv_batched_workspace_size(count, m, n, b, o.precision);
   void* ws = o.workspace;
   size_t ws_bytes = o.workspace_bytes;
   if (ws == nullptr) {
@@ -289,7 +291,8 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
   std::vector<uint64_t> seeds(count);
   for (int64_t j = 0; j < count; ++j) seeds[j] = seed + (uint64_t)j;
   if (b > 0) {
-    RRF_TRY(randutv_batched_run(st, count, m, n, A, lda, b, q, seeds.data(), U, T, V, ws, ws_bytes));
+    RRF_TRY(randutv_batched_run(st, count, m, n, A, lda, b, q, seeds.data(), U, T, V, ws, ws_bytes,
+                                o.precision));
   } else {
     for (int64_t bg : {16, 32}) {
       std::vector<int64_t> gm, gn, gl;
@@ -310,7 +313,7 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
       if (gm.empty()) continue;
       RRF_TRY(randutv_batched_run(st, (int64_t)gm.size(), gm.data(), gn.data(), gA.data(),
                                   gl.data(), bg, q, gs.data(), U ? gU.data() : nullptr, gT.data(),
-                                  V ? gV.data() : nullptr, ws, ws_bytes));
+                                  V ? gV.data() : nullptr, ws, ws_bytes, o.precision));
     }
   }
   if (o.async) return RRF_OK;

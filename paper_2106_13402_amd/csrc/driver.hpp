@@ -24,11 +24,12 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
 // seeds[j]); outputs packed column-major (ld m, m, n). The status words of
 // `ws` (word 0: device-side failure bits) are not cleared here.
 int64_t randutv_batched_block(int64_t m, int64_t n);
-size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t* n, int64_t b);
+size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t* n, int64_t b,
+                                 int precision);
 int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const int64_t* n,
                         const double* const* A, const int64_t* lda, int64_t b, int q,
                         const uint64_t* seeds, double* const* U, double* const* T,
-                        double* const* V, void* ws, size_t ws_bytes);
+                        double* const* V, void* ws, size_t ws_bytes, int precision);
 // Free the descriptor rings of every device.
 int randutv_batched_release();
 

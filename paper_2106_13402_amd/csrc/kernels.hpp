@@ -50,7 +50,7 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
 
 // ---- sketch_bf16.hip ------------------------------------------------------
 // Leading dimension of a bfloat16 copy with `rows` rows (a multiple of 8).
-int64_t bf16_ld(int64_t rows);
+inline int64_t bf16_ld(int64_t rows) { return (rows + 7) & ~(int64_t)7; }
 // *word = max|X| as binary64 bits (word zeroed first).
 int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
            unsigned long long* word);

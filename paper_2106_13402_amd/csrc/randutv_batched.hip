@@ -52,11 +52,16 @@ struct Mat {
   double *G, *Y, *Z, *XW, *WZ, *S, *X0, *Zl, *WU, *WV, *TU, *TV, *tau, *pt;
   double *TG, *Sx, *Sy, *Zg, *Z2;
   int64_t blk0;  // index of this matrix's first block in the shared R/Us/Vs/d
+  // mixed sketch: bfloat16 copies of T22 (and transposed), G, Y, Z (ld a
+  // multiple of 8), FP32 products, the max|T22| word
+  uint16_t *Tb, *Tbt, *Gb, *Yb, *Zb;
+  float* Pf;
+  unsigned long long* word;
 };
 
 // One round: descriptors packed in `bytes`, launches in `ops` order.
 struct Plan {
-  enum { kGemm, kElem, kGauss, kPanel };
+  enum { kGemm, kElem, kGauss, kPanel, kMax, kBf16, kGemm16, kRound };
   struct Op {
     int kind;
     bool ta, tb;
@@ -130,6 +135,38 @@ struct Plan {
     for (const auto& e : v) el = std::max(el, e.rows * e.cols);
     ops.push_back({kGauss, false, false, put(v), (int)v.size(), el, 0, 0.0, 0, false});
   }
+  void maxabs(const std::vector<MaxDesc>& v) {
+    if (v.empty()) return;
+    int64_t rows = 0;
+    for (const auto& e : v) rows = std::max(rows, e.rows);
+    ops.push_back({kMax, false, false, put(v), (int)v.size(), rows, 0, 0.0, 0, false});
+  }
+  void bf16(const std::vector<Bf16Desc>& v) {
+    if (v.empty()) return;
+    int64_t tiles = 0;
+    for (const auto& e : v)
+      tiles = std::max(tiles, bf16_conv_tiles(e.rows, e.cols, e.ldo, e.outT ? e.ldot : 0));
+    ops.push_back({kBf16, false, false, put(v), (int)v.size(), tiles, 0, 0.0, 0, false});
+  }
+  void gemm16(const std::vector<Bf16GemmDesc>& v) {
+    if (v.empty()) return;
+    std::vector<int> prefix(v.size() + 1, 0);
+    double fl = 0.0;
+    int64_t total = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+      total += bf16_group_tiles(v[i].M, v[i].N);
+      prefix[i + 1] = (int)std::min<int64_t>(total, INT32_MAX);
+      fl += 2.0 * v[i].M * v[i].N * v[i].K;
+    }
+    const size_t off = put(v);
+    ops.push_back({kGemm16, false, false, off, (int)v.size(), total, 0, fl, put(prefix), false});
+  }
+  void round(const std::vector<RoundDesc>& v) {
+    if (v.empty()) return;
+    int64_t cols = 0;
+    for (const auto& e : v) cols = std::max(cols, e.N);
+    ops.push_back({kRound, false, false, put(v), (int)v.size(), cols, 0, 0.0, 0, false});
+  }
   void panel(const std::vector<PanelDesc>& v, int k) {
     if (v.empty()) return;
     int64_t rows = 0;
@@ -199,6 +236,20 @@ int run_plan(hipStream_t st, Ring& r, const Plan& p) {
         break;
       case Plan::kGauss:
         RRF_TRY(gauss_batched(st, static_cast<const GaussDesc*>(dd), op.count, op.aux));
+        break;
+      case Plan::kMax:
+        RRF_TRY(maxabs_batched(st, static_cast<const MaxDesc*>(dd), op.count, op.aux));
+        break;
+      case Plan::kBf16:
+        RRF_TRY(to_bf16_batched(st, static_cast<const Bf16Desc*>(dd), op.count, op.aux));
+        break;
+      case Plan::kGemm16:
+        RRF_TRY(gemm_bf16_grouped(st, static_cast<const Bf16GemmDesc*>(dd),
+                                  reinterpret_cast<const int*>(d + op.off2), op.count, op.aux,
+                                  op.flops));
+        break;
+      case Plan::kRound:
+        RRF_TRY(round_columns_batched(st, static_cast<const RoundDesc*>(dd), op.count, op.aux));
         break;
       default:
         RRF_TRY(panel_wg_batched(st, static_cast<const PanelDesc*>(dd), op.count, op.k, op.aux));
@@ -333,8 +384,8 @@ struct Shared {
 };
 
 // Carve the workspace (or only count its bytes when base is null).
-size_t layout(int64_t count, const int64_t* m, const int64_t* n, int64_t b, char* base,
-              Shared* sh, std::vector<Mat>* mats) {
+size_t layout(int64_t count, const int64_t* m, const int64_t* n, int64_t b, int precision,
+              char* base, Shared* sh, std::vector<Mat>* mats) {
   Arena ar;
   ar.base = base;
   ar.counting = base == nullptr;
@@ -380,14 +431,94 @@ size_t layout(int64_t count, const int64_t* m, const int64_t* n, int64_t b, char
     x.Sy = ar.take<double>((size_t)2 * gk * kb);
     x.Zg = ar.take<double>((size_t)2 * gk * mx);
     x.Z2 = ar.take<double>((size_t)2 * gk * mx);
+    if (precision == RRF_PREC_BF16_SKETCH) {
+      const int64_t lm = bf16_ld(mj), ln = bf16_ld(nj);
+      x.Tb = ar.take<uint16_t>((size_t)lm * nj);
+      x.Tbt = ar.take<uint16_t>((size_t)ln * mj);
+      x.Gb = ar.take<uint16_t>((size_t)lm * kb);
+      x.Yb = ar.take<uint16_t>((size_t)ln * kb);
+      x.Zb = ar.take<uint16_t>((size_t)lm * kb);
+      x.Pf = ar.take<float>((size_t)mx * kb);
+      x.word = ar.take<unsigned long long>(1);
+    }
     if (mats) (*mats)[j] = x;
   }
   return ar.used;
 }
 
+// The mixed sketch of step i for the matrices in `js` (as sketch_mixed of
+// randutv.hip): T22 scaled by the power of two of its max|.| and rounded to
+// bfloat16 with its transpose, G rounded as it is, every product accumulated
+// in FP32; the intermediate columns are rescaled by powers of two and
+// rounded, the last product is widened to FP64 into Y.
+void plan_sketch_bf16(std::vector<Plan>& rounds, std::vector<Mat>& mats,
+                      const std::vector<int64_t>& js, int64_t c0, int64_t b, int q) {
+  if (js.empty()) return;
+  rounds.emplace_back();
+  Plan& p = rounds.back();
+  std::vector<GaussDesc> g;
+  std::vector<ElemDesc> zw;
+  std::vector<MaxDesc> mx;
+  std::vector<Bf16Desc> cv;
+  for (int64_t j : js) {
+    Mat& x = mats[j];
+    const int64_t Mi = x.m - c0, Ni = x.n - c0;
+    const double* T22 = x.T + c0 + c0 * x.m;
+    g.push_back(GaussDesc{x.seed, (uint64_t)(c0 / b + 1), Mi, b, x.G, Mi});
+    zw.push_back(fill(1, 1, 0.0, reinterpret_cast<double*>(x.word), 1));  // 0.0 has all-zero bits
+    mx.push_back(MaxDesc{Mi, Ni, T22, x.m, x.word});
+    cv.push_back(Bf16Desc{Mi, Ni, T22, x.m, x.word, x.Tb, bf16_ld(Mi), x.Tbt, bf16_ld(Ni)});
+  }
+  p.gauss(g);
+  p.elem(zw);
+  p.maxabs(mx);
+  std::vector<Bf16Desc> gc;
+  for (int64_t j : js) {
+    Mat& x = mats[j];
+    const int64_t Mi = x.m - c0;
+    gc.push_back(Bf16Desc{Mi, b, x.G, Mi, nullptr, x.Gb, bf16_ld(Mi), nullptr, 0});
+  }
+  cv.insert(cv.end(), gc.begin(), gc.end());
+  p.bf16(cv);
+  // Y = T22^T G
+  {
+    std::vector<Bf16GemmDesc> gm;
+    std::vector<RoundDesc> rd;
+    for (int64_t j : js) {
+      Mat& x = mats[j];
+      const int64_t Mi = x.m - c0, Ni = x.n - c0, lm = bf16_ld(Mi), ln = bf16_ld(Ni);
+      const bool last = q == 0;
+      gm.push_back(Bf16GemmDesc{Ni, b, Mi, x.Tb, lm, x.Gb, lm, last ? nullptr : x.Pf, Ni,
+                                last ? x.Y : nullptr, Ni});
+      if (!last) rd.push_back(RoundDesc{Ni, b, x.Pf, Ni, x.Yb, ln});
+    }
+    p.gemm16(gm);
+    p.round(rd);
+  }
+  for (int it = 0; it < q; ++it) {
+    const bool last = it == q - 1;
+    std::vector<Bf16GemmDesc> gz, gy;
+    std::vector<RoundDesc> rz, ry;
+    for (int64_t j : js) {
+      Mat& x = mats[j];
+      const int64_t Mi = x.m - c0, Ni = x.n - c0, lm = bf16_ld(Mi), ln = bf16_ld(Ni);
+      // Z = T22 Y = Tbt^T Y, then Y = T22^T Z = Tb^T Z
+      gz.push_back(Bf16GemmDesc{Mi, b, Ni, x.Tbt, ln, x.Yb, ln, x.Pf, Mi, nullptr, 0});
+      rz.push_back(RoundDesc{Mi, b, x.Pf, Mi, x.Zb, lm});
+      gy.push_back(Bf16GemmDesc{Ni, b, Mi, x.Tb, lm, x.Zb, lm, last ? nullptr : x.Pf, Ni,
+                                last ? x.Y : nullptr, Ni});
+      if (!last) ry.push_back(RoundDesc{Ni, b, x.Pf, Ni, x.Yb, ln});
+    }
+    p.gemm16(gz);
+    p.round(rz);
+    p.gemm16(gy);
+    p.round(ry);
+  }
+}
+
 // The loop of Alg. 3 for every matrix, step i of all together.
 int run_loop(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh, int64_t b,
-             int q, std::vector<std::vector<int64_t>>& ku,
+             int q, int precision, std::vector<std::vector<int64_t>>& ku,
              std::vector<std::vector<int64_t>>& kv) {
   const int64_t bb = b;
   const int64_t count = (int64_t)mats.size();
@@ -402,7 +533,9 @@ int run_loop(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& s
       (i < mats[j].s - 1 ? norm : last).push_back(j);
     }
     // sketch: Y = T22^T G_i, then q times Z = T22 Y, Y = T22^T Z
-    {
+    if (precision == RRF_PREC_BF16_SKETCH) {
+      plan_sketch_bf16(rounds, mats, norm, c0, b, q);
+    } else {
       rounds.emplace_back();
       std::vector<GaussDesc> g;
       std::vector<GemmDesc> y;
@@ -742,8 +875,9 @@ int64_t randutv_batched_block(int64_t m, int64_t n) {
   return n <= 256 ? 16 : 32;
 }
 
-size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t* n, int64_t b) {
-  return layout(count, m, n, b, nullptr, nullptr, nullptr);
+size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t* n, int64_t b,
+                                 int precision) {
+  return layout(count, m, n, b, precision, nullptr, nullptr, nullptr);
 }
 
 namespace {
@@ -752,7 +886,7 @@ namespace {
 // SVDs and updates, and U and V. mats[j].blk0 and sh index the slice's own
 // blocks.
 int run_slice(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh, int64_t b,
-              int q) {
+              int q, int precision) {
   RRF_TRY(ring_reserve(ring, std::max(mats.size() * kDescPerMat, (size_t)sh.nblocks * 4) +
                                  (1 << 16)));
   {
@@ -777,7 +911,7 @@ int run_slice(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& 
     ku[j].assign(mats[j].s, 0);
     kv[j].assign(mats[j].s, 0);
   }
-  RRF_TRY(run_loop(st, ring, mats, sh, b, q, ku, kv));
+  RRF_TRY(run_loop(st, ring, mats, sh, b, q, precision, ku, kv));
   RRF_TRY(run_blocks(st, ring, mats, sh, b));
   RRF_TRY(run_backward(st, ring, mats, sh, b, ku, kv));
   return RRF_OK;
@@ -809,11 +943,12 @@ int slice_resources(DeviceRes& r, int S) {
 int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const int64_t* n,
                         const double* const* A, const int64_t* lda, int64_t b, int q,
                         const uint64_t* seeds, double* const* U, double* const* T,
-                        double* const* V, void* ws, size_t ws_bytes) {
+                        double* const* V, void* ws, size_t ws_bytes, int precision) {
   if (count < 1) return RRF_OK;
   std::vector<Mat> mats;
   Shared sh;
-  const size_t need = layout(count, m, n, b, reinterpret_cast<char*>(ws), &sh, &mats);
+  const size_t need =
+      layout(count, m, n, b, precision, reinterpret_cast<char*>(ws), &sh, &mats);
   if (need > ws_bytes) return set_error(RRF_E_NOMEM, "batched randutv: workspace too small");
   for (int64_t j = 0; j < count; ++j) {
     mats[j].A = A[j];
@@ -832,7 +967,7 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
   // rounds of one slice leave the chip partly idle in their latency-bound
   // launches (panels, small SVDs), which the other slices' GEMMs fill.
   const int S = (int)std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, count / 256));
-  if (S == 1) return run_slice(st, res.rings[0], mats, sh, b, q);
+  if (S == 1) return run_slice(st, res.rings[0], mats, sh, b, q, precision);
   RRF_TRY(slice_resources(res, S));
   double total = 0.0;
   for (auto& x : mats) total += (double)x.m * x.n * x.n;
@@ -883,7 +1018,7 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
       if (e != hipSuccess) {
         w.rc = set_hip_error(e, "hipSetDevice", __FILE__, __LINE__);
       } else if (!w.mats.empty()) {
-        w.rc = run_slice(res.streams[i], res.rings[i], w.mats, w.sh, b, q);
+        w.rc = run_slice(res.streams[i], res.rings[i], w.mats, w.sh, b, q, precision);
       }
       if (w.rc != RRF_OK) w.msg = rrf_last_error();
     });

@@ -23,8 +23,10 @@
 // instead of FP64 (8 bytes, and FP64 matrix-core rates), so the sketch is
 // HBM-bound at b <= 256.
 #include <algorithm>
+#include <climits>
 #include <cfloat>
 
+#include "batched.hpp"
 #include "common.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
@@ -288,11 +290,170 @@ __global__ __launch_bounds__(kColThreads) void reduce_columns_kernel(
     out16[i + n * ld16] = (i < M) ? bf16_from_f32(c[i] * s) : (uint16_t)0;
 }
 
+// --- batched forms (the mixed sketch of the batched randUTV) ---------------
+
+// One workgroup per (problem, 256-row block): max over its rows and all
+// columns, one atomic per workgroup.
+__global__ __launch_bounds__(256) void maxabs_batched_kernel(const MaxDesc* __restrict__ descs) {
+  __shared__ double red[4];
+  const MaxDesc d = descs[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if ((int64_t)blockIdx.x * 256 >= d.rows) return;
+  double m = 0.0;
+  if (i < d.rows)
+    for (int64_t j = 0; j < d.cols; ++j) m = fmax(m, fabs(d.X[i + j * d.ld]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (m > 0.0) atomicMax(d.word, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// to_bf16_kernel per problem: blockIdx.x walks the problem's 64 x 64 tiles
+// (rows up to max(rows, ldo), columns up to max(cols, ldot)).
+__global__ __launch_bounds__(256) void to_bf16_batched_kernel(const Bf16Desc* __restrict__ descs) {
+  __shared__ uint16_t tile[64][65];
+  const Bf16Desc d = descs[blockIdx.y];
+  const int64_t R = d.rows > d.ldo ? d.rows : d.ldo;
+  const int64_t C = d.outT ? (d.cols > d.ldot ? d.cols : d.ldot) : d.cols;
+  const int64_t tr = (R + 63) / 64;
+  if ((int64_t)blockIdx.x >= tr * ((C + 63) / 64)) return;
+  const double s = d.word ? pow2_scale(__longlong_as_double((long long)*d.word)) : 1.0;
+  const int64_t r0 = (int64_t)(blockIdx.x % tr) * 64, c0 = (int64_t)(blockIdx.x / tr) * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t r = r0 + tx, c = c0 + cc;
+    uint16_t v = 0;
+    if (r < d.rows && c < d.cols) v = bf16_from_f64(d.X[r + c * d.ld] * s);
+    if (r < d.ldo && c < d.cols) d.out[r + c * d.ldo] = v;
+    tile[cc][tx] = v;
+  }
+  if (!d.outT) return;
+  __syncthreads();
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t c = c0 + tx, r = r0 + rr;
+    if (c < d.ldot && r < d.rows) d.outT[c + r * d.ldot] = (c < d.cols) ? tile[tx][rr] : (uint16_t)0;
+  }
+}
+
+// 128 x 32 output tiles of every problem (4 waves of 32 x 32, 2 x 2 blocks of
+// v_mfma_f32_16x16x32_bf16), K in slices of 64 through double-buffered LDS;
+// the workgroup finds its problem by binary search of the running tile counts.
+constexpr int kGBM = 128, kGBN = 32;
+
+__global__ __launch_bounds__(kThreads) void gemm_bf16_grouped_kernel(
+    const Bf16GemmDesc* __restrict__ descs, const int* __restrict__ prefix, int count) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[2][(kGBM + kGBN) * kLK];
+  const int bid = blockIdx.x;
+  int lo = 0, hi = count;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= bid) lo = mid;
+    else hi = mid;
+  }
+  const Bf16GemmDesc g = descs[lo];
+  const int t = bid - prefix[lo];
+  const int64_t tiles_m = (g.M + kGBM - 1) / kGBM;
+  const int64_t m0 = (int64_t)(t % tiles_m) * kGBM, n0 = (int64_t)(t / tiles_m) * kGBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;  // 4 x 1 waves
+  const int64_t kpad = (g.K + 7) & ~(int64_t)7;
+
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // A: 128 x 64 slice = 1024 chunks of 16 bytes (four per thread); B: 32 x 64
+  // = 256 chunks (one per thread)
+  auto load = [&](uint4 (&ra)[4], uint4& rb, int64_t k0) {
+    load_slice(ra, g.A, g.lda, m0, g.M, k0, kpad, tid);
+    const int row = tid >> 3, part = tid & 7;
+    const int64_t n = n0 + row, k = k0 + part * 8;
+    rb = (n < g.N && k < kpad) ? *reinterpret_cast<const uint4*>(g.B + k + n * g.ldb)
+                               : make_uint4(0, 0, 0, 0);
+  };
+  auto store = [&](int buf, const uint4 (&ra)[4], const uint4& rb) {
+    store_slice(lds[buf], ra, tid);
+    const int row = tid >> 3, part = tid & 7;
+    *reinterpret_cast<uint4*>(lds[buf] + kGBM * kLK + row * kLK + part * 8) = rb;
+  };
+  if (g.K > 0) {
+    uint4 ra[4], rb;
+    load(ra, rb, 0);
+    store(0, ra, rb);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < g.K; k0 += kBK) {
+      const bool more = k0 + kBK < g.K;
+      if (more) load(ra, rb, k0 + kBK);
+      const uint16_t* la = lds[buf];
+      const uint16_t* lb = lds[buf] + kGBM * kLK;
+#pragma unroll
+      for (int ks = 0; ks < kBK; ks += 32) {
+        bf16x8 af[2], bfr[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          af[i] = *reinterpret_cast<const bf16x8*>(
+              la + (wave * 32 + i * 16 + (lane & 15)) * kLK + ks + 8 * (lane >> 4));
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          bfr[j] = *reinterpret_cast<const bf16x8*>(
+              lb + (j * 16 + (lane & 15)) * kLK + ks + 8 * (lane >> 4));
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      }
+      if (more) store(buf ^ 1, ra, rb);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  // lane l, register r holds D(row 4 (l / 16) + r, column l % 16) of a sub-tile
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t n = n0 + j * 16 + (lane & 15);
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wave * 32 + i * 16 + 4 * (lane >> 4) + r;
+        if (m >= g.M) continue;
+        if (g.out64) g.out64[m + n * g.ld64] = (double)acc[i][j][r];
+        else g.P[m + n * g.ldp] = acc[i][j][r];
+      }
+    }
+}
+
+// One workgroup per (problem, column): the column's max, its power of two,
+// the scaled bfloat16 column with rows [M, ld16) zero.
+__global__ __launch_bounds__(256) void round_columns_batched_kernel(
+    const RoundDesc* __restrict__ descs) {
+  __shared__ float red[4];
+  const RoundDesc d = descs[blockIdx.y];
+  const int64_t n = blockIdx.x;
+  if (n >= d.N) return;
+  const float* c = d.P + n * d.ldp;
+  float m = 0.f;
+  for (int64_t i = threadIdx.x; i < d.M; i += 256) m = fmaxf(m, fabsf(c[i]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  const float s = (float)pow2_scale((double)fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+  for (int64_t i = threadIdx.x; i < d.ld16; i += 256)
+    d.out16[i + n * d.ld16] = (i < d.M) ? bf16_from_f32(c[i] * s) : (uint16_t)0;
+}
+
 bool g_col_attr = false;
 
 }  // namespace
-
-int64_t bf16_ld(int64_t rows) { return (rows + 7) & ~(int64_t)7; }
 
 int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
            unsigned long long* word) {
@@ -387,6 +548,54 @@ int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t
                     4.0 * splits * M * N + (out64 ? 8.0 : 2.0) * M * N);
   hipLaunchKernelGGL(reduce_columns_kernel, dim3((unsigned)N), dim3(kColThreads), lds, st, M, N,
                      splits, P, out16, ld16, out64, ld64, col);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int maxabs_batched(hipStream_t st, const MaxDesc* d, int count, int64_t max_rows) {
+  if (count <= 0 || max_rows <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrElementwise, 0.0, 0.0);
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const dim3 grid((unsigned)ceil_div(max_rows, 256), (unsigned)std::min(count - c0, 65535));
+    hipLaunchKernelGGL(maxabs_batched_kernel, grid, dim3(256), 0, st, d + c0);
+  }
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int to_bf16_batched(hipStream_t st, const Bf16Desc* d, int count, int64_t max_tiles) {
+  if (count <= 0 || max_tiles <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrElementwise, 0.0, 0.0);
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const dim3 grid((unsigned)max_tiles, (unsigned)std::min(count - c0, 65535));
+    hipLaunchKernelGGL(to_bf16_batched_kernel, grid, dim3(256), 0, st, d + c0);
+  }
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int gemm_bf16_grouped(hipStream_t st, const Bf16GemmDesc* d, const int* d_prefix, int count,
+                      int64_t total_tiles, double flops) {
+  if (count <= 0 || total_tiles <= 0) return RRF_OK;
+  if (total_tiles > INT32_MAX) return set_error(RRF_E_NOTSUP, "bf16 grouped gemm: too many tiles");
+  int tok = trace_begin(st, kTrGemmBf16, flops, 0.0);
+  hipLaunchKernelGGL(gemm_bf16_grouped_kernel, dim3((unsigned)total_tiles), dim3(kThreads), 0, st,
+                     d, d_prefix, count);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int round_columns_batched(hipStream_t st, const RoundDesc* d, int count, int64_t max_cols) {
+  if (count <= 0 || max_cols <= 0) return RRF_OK;
+  int tok = trace_begin(st, kTrSplitReduce, 0.0, 0.0);
+  for (int c0 = 0; c0 < count; c0 += 65535) {
+    const dim3 grid((unsigned)max_cols, (unsigned)std::min(count - c0, 65535));
+    hipLaunchKernelGGL(round_columns_batched_kernel, grid, dim3(256), 0, st, d + c0);
+  }
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;

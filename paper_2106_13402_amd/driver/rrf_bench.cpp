@@ -4,7 +4,7 @@
 //
 //   rrf_bench [--alg randutv|powerurv] [--m M] [--n N] [--b B] [--q Q] [--reps R] [--trace]
 //             [--copy-bytes BYTES] [--precision 0|1] [--no-uv]
-//   rrf_bench --alg batched [--count C] [--b B] [--q Q] [--reps R] [--trace]
+//   rrf_bench --alg batched [--count C] [--b B] [--q Q] [--reps R] [--trace] [--precision 0|1]
 //
 // The batched form factors C Gaussian matrices (default 4096) with n drawn
 // uniformly from [64, 512] and m from [n, 2n] by a fixed xorshift sequence
@@ -39,7 +39,7 @@ static void print_trace() {
            e[i].bytes / (e[i].ms * 1e-3) / 1e9);
 }
 
-static int run_batched(long count, long b, long q, long reps, bool trace) {
+static int run_batched(long count, long b, long q, long reps, bool trace, long precision) {
   std::vector<int64_t> m(count), n(count), ld(count);
   uint64_t x = 0x9E3779B97F4A7C15ull;
   auto next = [&]() {
@@ -59,7 +59,8 @@ static int run_batched(long count, long b, long q, long reps, bool trace) {
   }
   double *A = nullptr, *T = nullptr, *U = nullptr, *V = nullptr;
   void* ws = nullptr;
-  const size_t wsb = rrf_randutv_batched_workspace_size(count, m.data(), n.data(), b);
+  const size_t wsb =
+      rrf_randutv_batched_workspace_size(count, m.data(), n.data(), b, (int)precision);
   if (wsb == 0) return fail("rrf_randutv_batched_workspace_size", -1);
   if (hipMalloc(&A, a_el * 8) != hipSuccess || hipMalloc(&T, a_el * 8) != hipSuccess ||
       hipMalloc(&U, u_el * 8) != hipSuccess || hipMalloc(&V, v_el * 8) != hipSuccess ||
@@ -85,6 +86,7 @@ static int run_batched(long count, long b, long q, long reps, bool trace) {
   rrf_opts_init(&o);
   o.workspace = ws;
   o.workspace_bytes = wsb;
+  o.precision = (int)precision;
   if (trace) rrf_trace_enable(1);
   double best = 1e30, total = 0.0;
   for (long r = 0; r < reps; ++r) {
@@ -127,7 +129,8 @@ int main(int argc, char** argv) {
     else if (a == "--precision") next(precision);
     else { fprintf(stderr, "unknown argument %s\n", a.c_str()); return 2; }
   }
-  if (alg == "batched") return run_batched(count, b_given ? b : 0, q_given ? q : 1, reps, trace);
+  if (alg == "batched")
+    return run_batched(count, b_given ? b : 0, q_given ? q : 1, reps, trace, precision);
   if (m < n) m = n;
   const size_t bytes = (size_t)m * n * sizeof(double);
   double *A = nullptr, *U = nullptr, *T = nullptr, *V = nullptr;

@@ -11,11 +11,12 @@ extern "C" long mock_errors();
 extern "C" void* mock_malloc(size_t);
 int main(int argc, char** argv) {
   FILE* f = fopen(argv[1], "rb");
-  int64_t hdr[7];
-  if (fread(hdr, 8, 7, f) != 7) return 2;
+  int64_t hdr[8];
+  if (fread(hdr, 8, 8, f) != 8) return 2;
   const int64_t count = hdr[0], b = hdr[1], q = hdr[2];
   const uint64_t seed = hdr[3];
   const bool wu = hdr[4], wv = hdr[5], inplace = hdr[6];
+  const int precision = (int)hdr[7];
   std::vector<int64_t> m(count), n(count), lda(count);
   std::vector<const double*> A(count);
   std::vector<double*> U(count), T(count), V(count);
@@ -33,12 +34,12 @@ int main(int argc, char** argv) {
     seeds[j] = seed + j;
   }
   fclose(f);
-  size_t ws = rrf::randutv_batched_workspace(count, m.data(), n.data(), b);
+  size_t ws = rrf::randutv_batched_workspace(count, m.data(), n.data(), b, precision);
   void* w = mock_malloc(ws);
   ((int*)w)[0] = 0; ((int*)w)[1] = 0;
   int rc = rrf::randutv_batched_run(nullptr, count, m.data(), n.data(), A.data(), lda.data(), b, (int)q,
                                     seeds.data(), wu ? U.data() : nullptr, T.data(),
-                                    wv ? V.data() : nullptr, w, ws);
+                                    wv ? V.data() : nullptr, w, ws, precision);
   printf("rc=%d mock_errors=%ld ws=%zu\n", rc, mock_errors(), ws);
   FILE* o = fopen(argv[2], "wb");
   for (int64_t j = 0; j < count; ++j) {

@@ -224,6 +224,128 @@ int gauss_batched(hipStream_t, const GaussDesc* d, int count, int64_t max_elems)
   return RRF_OK;
 }
 
+// --- the mixed sketch's batched kernels ------------------------------------
+
+static void chk(const void* p, size_t bytes) {
+  if (!inb(p, bytes)) fail("access out of bounds", p);
+}
+static uint16_t bf16_of_f64(double x) {
+  if (x == 0.0) return 0;
+  int lead = ilogb(x);
+  if (lead < -126) lead = -126;
+  const double q = rint(scalbn(x, 7 - lead));
+  float r = (float)scalbn(q, lead - 7);
+  uint32_t u;
+  memcpy(&u, &r, 4);
+  return (uint16_t)(u >> 16);
+}
+static uint16_t bf16_of_f32(float x) {
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+static float f32_of_bf16(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+static double pow2s(double m) {
+  if (!(m > 0.0)) return 1.0;
+  int e;
+  frexp(m, &e);
+  return ldexp(1.0, -e);
+}
+
+int maxabs_batched(hipStream_t, const MaxDesc* d, int count, int64_t max_rows) {
+  std::lock_guard<std::recursive_mutex> lk_(g_kmu);
+  begin_launch("maxabs_batched");
+  for (int p = 0; p < count; ++p) {
+    if (d[p].rows > max_rows) fail("rows beyond grid", nullptr);
+    double m = 0.0;
+    for (int64_t c = 0; c < d[p].cols; ++c)
+      for (int64_t r = 0; r < d[p].rows; ++r) m = std::max(m, fabs(rd(d[p].X + r + c * d[p].ld, p)));
+    chk(d[p].word, 8);
+    unsigned long long bits;
+    memcpy(&bits, &m, 8);
+    if (bits > *d[p].word) *d[p].word = bits;
+  }
+  return RRF_OK;
+}
+
+int to_bf16_batched(hipStream_t, const Bf16Desc* d, int count, int64_t max_tiles) {
+  std::lock_guard<std::recursive_mutex> lk_(g_kmu);
+  begin_launch("to_bf16_batched");
+  for (int p = 0; p < count; ++p) {
+    const Bf16Desc e = d[p];
+    if (bf16_conv_tiles(e.rows, e.cols, e.ldo, e.outT ? e.ldot : 0) > max_tiles)
+      fail("tiles beyond grid", nullptr);
+    double s = 1.0;
+    if (e.word) {
+      chk(e.word, 8);
+      double m;
+      memcpy(&m, e.word, 8);
+      s = pow2s(m);
+    }
+    for (int64_t c = 0; c < e.cols; ++c)
+      for (int64_t r = 0; r < std::max(e.rows, e.ldo); ++r) {
+        const uint16_t v = r < e.rows ? bf16_of_f64(rd(e.X + r + c * e.ld, p) * s) : 0;
+        if (r < e.ldo) { chk(e.out + r + c * e.ldo, 2); e.out[r + c * e.ldo] = v; }
+        if (e.outT && r < e.rows) { chk(e.outT + c + r * e.ldot, 2); e.outT[c + r * e.ldot] = v; }
+      }
+    if (e.outT)
+      for (int64_t r = 0; r < e.rows; ++r)
+        for (int64_t c = e.cols; c < e.ldot; ++c) { chk(e.outT + c + r * e.ldot, 2); e.outT[c + r * e.ldot] = 0; }
+  }
+  return RRF_OK;
+}
+
+int gemm_bf16_grouped(hipStream_t, const Bf16GemmDesc* d, const int* prefix, int count,
+                      int64_t total_tiles, double) {
+  std::lock_guard<std::recursive_mutex> lk_(g_kmu);
+  begin_launch("gemm_bf16_grouped");
+  if (prefix[0] != 0 || prefix[count] != total_tiles) fail("prefix ends", nullptr);
+  for (int p = 0; p < count; ++p) {
+    const Bf16GemmDesc g = d[p];
+    if (prefix[p + 1] - prefix[p] != bf16_group_tiles(g.M, g.N)) fail("prefix count", nullptr);
+    if (g.lda % 8 || g.ldb % 8 || (uintptr_t)g.A % 16 || (uintptr_t)g.B % 16)
+      fail("bf16 operand alignment", nullptr);
+    const int64_t kpad = (g.K + 7) / 8 * 8;
+    for (int64_t i = 0; i < g.M; ++i)
+      for (int64_t j = 0; j < g.N; ++j) {
+        float acc = 0.f;
+        for (int64_t k = 0; k < kpad; ++k) {  // the kernel reads the zero padding too
+          chk(g.A + k + i * g.lda, 2);
+          chk(g.B + k + j * g.ldb, 2);
+          acc += f32_of_bf16(g.A[k + i * g.lda]) * f32_of_bf16(g.B[k + j * g.ldb]);
+        }
+        if (g.out64) wr(g.out64 + i + j * g.ld64, (double)acc, p);
+        else { chk(g.P + i + j * g.ldp, 4); g.P[i + j * g.ldp] = acc; }
+      }
+  }
+  return RRF_OK;
+}
+
+int round_columns_batched(hipStream_t, const RoundDesc* d, int count, int64_t max_cols) {
+  std::lock_guard<std::recursive_mutex> lk_(g_kmu);
+  begin_launch("round_columns_batched");
+  for (int p = 0; p < count; ++p) {
+    const RoundDesc e = d[p];
+    if (e.N > max_cols) fail("cols beyond grid", nullptr);
+    for (int64_t n = 0; n < e.N; ++n) {
+      float m = 0.f;
+      for (int64_t i = 0; i < e.M; ++i) { chk(e.P + i + n * e.ldp, 4); m = std::max(m, fabsf(e.P[i + n * e.ldp])); }
+      const float s = (float)pow2s((double)m);
+      for (int64_t i = 0; i < e.ld16; ++i) {
+        chk(e.out16 + i + n * e.ld16, 2);
+        e.out16[i + n * e.ld16] = i < e.M ? bf16_of_f32(e.P[i + n * e.ldp] * s) : 0;
+      }
+    }
+  }
+  return RRF_OK;
+}
+
 int64_t panel_wg_max_rows(int k) {
   if (k < 1 || k > 64) return 0;
   int K = 1;

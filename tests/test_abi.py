@@ -148,17 +148,21 @@ def test_batched_workspace_size(lib):
     f = lib.rrf_randutv_batched_workspace_size
     ms, ns = [100, 300, 512], [64, 200, 512]
     m, n = _arr(C.c_int64, ms), _arr(C.c_int64, ns)
-    w16, w64, wauto = f(3, m, n, 16), f(3, m, n, 64), f(3, m, n, 0)
+    w16, w64, wauto = f(3, m, n, 16, 0), f(3, m, n, 64, 0), f(3, m, n, 0, 0)
     assert w16 > 0 and w64 > 0 and wauto > 0
     # at least the kept reflectors (m n + n^2 doubles per matrix), and the
     # automatic choice needs no more than the largest single group would
     refl = sum(8 * (a * c + c * c) for a, c in zip(ms, ns))
     assert refl < w16 and refl < w64
     assert wauto <= max(w16, w64)
-    assert f(3, m, n, 65) == 0
-    assert f(3, m, _arr(C.c_int64, [64, 301, 512]), 16) == 0   # n > m
-    assert f(1, _arr(C.c_int64, [4097]), _arr(C.c_int64, [4]), 16) == 0
-    assert f(2, m, n, 16) < w16
+    assert f(3, m, n, 65, 0) == 0
+    assert f(3, m, _arr(C.c_int64, [64, 301, 512]), 16, 0) == 0   # n > m
+    assert f(1, _arr(C.c_int64, [4097]), _arr(C.c_int64, [4]), 16, 0) == 0
+    assert f(2, m, n, 16, 0) < w16
+    # the mixed sketch adds bfloat16 copies of T22 (both layouts), G, Y, Z and FP32 products
+    wm = f(3, m, n, 16, 1)
+    assert w16 + sum(4 * a * c for a, c in zip(ms, ns)) <= wm
+    assert f(3, m, n, 16, 7) == 0
 
 
 def test_batched_block_rule(lib):

@@ -47,13 +47,14 @@ def harness(tmp_path_factory):
     return exe, out
 
 
-def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0):
+def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0, precision=0):
     exe, out = harness
     rng = np.random.default_rng(len(shapes) * 7 + b + q)
     As = []
     fin, fout = str(out / "in.bin"), str(out / "out.bin")
     with open(fin, "wb") as f:
-        f.write(struct.pack("<7q", len(shapes), b, q, seed, int(wu), int(wv), int(inplace)))
+        f.write(struct.pack("<8q", len(shapes), b, q, seed, int(wu), int(wv), int(inplace),
+                            precision))
         for m, n in shapes:
             A = rng.standard_normal((m, n))
             As.append(A)
@@ -88,7 +89,12 @@ def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0):
             c1 = min(c0 + b, n)
             blk = T[c0:c1, c0:c1]
             assert np.all(blk - np.diag(np.diag(blk)) == 0.0)
-        np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * nA)
+        if precision == 0:
+            np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * nA)
+        else:  # the bfloat16 sketch changes the trajectory; e_k stays comparable
+            ks = list(range(0, n, b))
+            eg, eo = M.trailing_norms(T, ks), M.trailing_norms(To, ks)
+            assert np.all(eg <= 1.5 * eo + 1e-12 * nA), (eg, eo)
 
 
 def test_planner_ragged_batch(harness):
@@ -118,3 +124,11 @@ def test_planner_slices(harness):
     ns = rng.integers(1, 7, size=520)
     shapes = [(int(rng.integers(n, 2 * n + 1)), int(n)) for n in ns]
     _run(harness, shapes, 4, 1, 13)
+
+
+def test_planner_mixed_sketch(harness):
+    # the bfloat16 sketch: its conversions, grouped products and column
+    # roundings go through the same bounds, race and padding checks
+    _run(harness, [(40, 30), (64, 64), (33, 17), (100, 64), (9, 4), (70, 70)], 8, 1, 5,
+         precision=1)
+    _run(harness, [(300, 200), (64, 10)], 32, 2, 11, precision=1)
