@@ -11,7 +11,10 @@ seconds, lower is better), the roofline entry of the dominant kernel measured
 live with HIP events on the library's stream, the accuracy of the result
 against the known spectrum, the same factorization with the bfloat16 sketch
 (RRF_PREC_BF16_SKETCH) timed the same way and held to e_k <= max(1.5
-sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), the FP64 CPU oracle
+sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), the same with the
+split-bfloat16 three-pass updates (RRF_PREC_BF16_X3, "mixed_x3"; results
+accurate to about 1e-5, so the gate covers sigma_{k+1} >= 100 x that), the
+powerURV leg, the FP64 CPU oracle
 timed on a bounded sample of the same workload, and ("batched") the batched
 call on 4096 small matrices (n ~ U{64..512}, m ~ U{n..2n}, graded spectrum,
 q = 1, automatic b) in matrices per second with every matrix's residual.
@@ -501,33 +504,48 @@ def main() -> int:
     if not args.no_accuracy:
         out["accuracy"] = accuracy(A, U, T, V, s, kgrid)
         log(f"accuracy: {out['accuracy']}")
-    if not args.no_mixed:
-        # the same factorization with the bfloat16 sketch, timed the same way
+    def mixed_leg(precision):
+        # the same factorization in a mixed mode, timed the same way, with the
+        # kernel breakdown of the timed steps
         for w in range(args.warmup):
-            factor("bf16_sketch")
+            factor(precision)
+        rrf.trace_enable(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
-            factor("bf16_sketch")
+            factor(precision)
         torch.cuda.synchronize()
-        per_mixed = (time.perf_counter() - t0) / args.steps
-        log(f"mixed sketch: {per_mixed:.3f} s per factorization")
-        mixed = {"precision": "bf16_sketch", "value": per_mixed, "unit": "s",
-                 "ms_per_step": per_mixed * 1e3, "speedup_vs_fp64": per / per_mixed,
-                 "model_tflops": model_flops / per_mixed / 1e12}
+        per_m = (time.perf_counter() - t0) / args.steps
+        kern_m = rrf.trace_read()
+        rrf.trace_enable(False)
+        log(f"{precision}: {per_m:.3f} s per factorization")
+        leg = {"precision": precision, "value": per_m, "unit": "s",
+               "ms_per_step": per_m * 1e3, "speedup_vs_fp64": per / per_m,
+               "model_tflops": model_flops / per_m / 1e12,
+               "kernels": {e["name"]: {
+                   "launches": e["launches"] // args.steps, "ms_per_step": e["ms"] / args.steps,
+                   "tflops": (e["flops"] / (e["ms"] * 1e-3) / 1e12) if e["flops"] else None,
+                   "gbs": (e["bytes"] / (e["ms"] * 1e-3) / 1e9) if e["bytes"] else None}
+                   for e in kern_m}}
         if not args.no_accuracy:
             acc = accuracy(A, U, T, V, s, kgrid)
             ref = out["accuracy"]["e_k"]
             # gate on the k with sigma_{k+1} well above the reconstruction error
             ks = [i for i, k in enumerate(kgrid) if s[k] >= 100 * acc["recon"] * s[0]]
             ratio = [acc["e_k"][i] / ref[i] for i in ks]
-            mixed["accuracy"] = acc
-            mixed["ek_over_fp64_max"] = max(ratio)
-            mixed["ek_gate"] = "e_k <= max(1.5 sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid"
-            mixed["ek_gate_pass"] = all(acc["e_k"][i] <= max(1.5 * s[kgrid[i]], 1.1 * ref[i])
-                                        for i in ks)
-            log(f"mixed accuracy: {acc}")
-        out["mixed"] = mixed
+            leg["accuracy"] = acc
+            leg["ek_over_fp64_max"] = max(ratio)
+            leg["ek_gate"] = "e_k <= max(1.5 sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid"
+            leg["ek_gate_k"] = [kgrid[i] for i in ks]
+            leg["ek_gate_pass"] = all(acc["e_k"][i] <= max(1.5 * s[kgrid[i]], 1.1 * ref[i])
+                                      for i in ks)
+            leg["recon_le_1e-6"] = acc["recon"] <= 1e-6
+            log(f"{precision} accuracy: {acc}")
+        return leg
+
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg("bf16_sketch")
+        out["mixed_x3"] = mixed_leg("bf16_x3")
     if not args.no_powerurv:
         out["powerurv"] = powerurv_leg(A, U, T, V, s, kgrid, b, q, args, dev,
                                        None if args.no_accuracy else out["accuracy"])

@@ -66,6 +66,17 @@ extern "C" {
  *    singular value are not separated (e_k there exceeds the binary64
  *    value). */
 #define RRF_PREC_BF16_SKETCH 1
+/* randUTV only: the bfloat16 sketch of RRF_PREC_BF16_SKETCH, and every
+ * update of T, U and V by a product of Householder transforms (the right
+ * update of Alg. 3 with V_i, the left update with U_i, the accumulation of U
+ * and V) formed by the split-bfloat16 three-pass product of rrf_gemm_x3
+ * (error per term at most about 2^-15 |a| |b|). T keeps binary64 storage and is
+ * scaled by the power of two of max|A| for the run (exact, undone at the
+ * end). The panels, the b x b SVDs and the small products among the
+ * compact-WY factors stay binary64. ||A - U T V^T|| / ||A|| and the
+ * orthogonality of U and V are then about 1e-5, not binary64 level; e_k is
+ * resolved down to about 1e-5 of each step's trailing norm. */
+#define RRF_PREC_BF16_X3 2
 
 /* ---- algorithms (for rrf_workspace_size) -------------------------------- */
 #define RRF_ALG_RANDUTV  0
@@ -184,6 +195,17 @@ int rrf_release_workspace(void);
 /* ---- building blocks, exported for component tests ------------------------
  * Each runs on `stream` (hipStream_t, NULL = null stream) and returns after
  * the work is enqueued; device memory and ownership as above. */
+
+/* As rrf_dgemm, with each element x of A and B split as x32 = x rounded to
+ * binary32, hi = x32 rounded to bfloat16, lo = (x32 - hi) rounded to
+ * bfloat16 (all to nearest even), and op(A) op(B) formed as the three-pass
+ * sum hi_a hi_b + hi_a lo_b + lo_a hi_b on the bfloat16 matrix cores with
+ * binary32 accumulation, widened to binary64 for alpha, beta and C. This is
+ * the product of the RRF_PREC_BF16_X3 updates (a mixed-precision extension;
+ * the paper computes in binary64). Errors and arguments as rrf_dgemm. */
+int rrf_gemm_x3(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                double* C, int64_t ldc, void* work, size_t work_bytes, void* stream);
 
 /* The sketch generator: out(r, c) = N(0,1) entry (r, c) of (seed, stream),
  * 0 <= r < rows, 0 <= c < cols, column-major with leading dimension ld. */

@@ -16,6 +16,14 @@ FP64. The definitions the GPU path follows:
   value the result is +-inf.
 * ``pow2_scale(x)``: the power of two 2^-e with max|x| 2^-e in [0.5, 1),
   e from frexp of max|x| (1 when x is all zero). Multiplying by it is exact.
+* ``split_x3(x)`` and ``gemm_x3(A, B)``: the product of the x3 updates.
+  x32 = x rounded to binary32 (nearest even), hi = x32 rounded to bfloat16,
+  lo = (x32 - hi) rounded to bfloat16 (the subtraction is exact); the
+  product keeps the three leading terms of (hi_a + lo_a)(hi_b + lo_b),
+  hi_a hi_b + hi_a lo_b + lo_a hi_b, each exact, summed here in FP64 (the
+  GPU sums them in FP32: ``fp32_x3_bound``). The split keeps about 17
+  bits (|x - hi - lo| <= (2^-17 + 2^-24) |x|); per term the dropped part,
+  mostly lo_a lo_b, is at most about 2^-15 |a| |b|.
 * ``sketch_bf16(T22, G, q)``: T22 is scaled by its pow2_scale and rounded
   to bfloat16, G (standard normal, in range) is rounded as it is;
   Y = T^T G; then q times: round Y column by column
@@ -94,3 +102,29 @@ def sketch_bf16(T22: np.ndarray, G: np.ndarray, q: int) -> np.ndarray:
         Z = Tb @ _round_columns(Y)
         Y = Tb.T @ _round_columns(Z)
     return Y
+
+
+def split_x3(x: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """(hi, lo) of the x3 split (module docstring), as binary64 arrays."""
+    x32 = np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+    hi = bf16_round(x32)
+    lo = bf16_round(x32 - hi)
+    return hi, lo
+
+
+def gemm_x3(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """A B (A: M x K, B: K x N) by the three-pass split product, in FP64."""
+    Ah, Al = split_x3(A)
+    Bh, Bl = split_x3(B)
+    return Ah @ Bh + Ah @ Bl + Al @ Bh
+
+
+def fp32_x3_bound(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Elementwise bound on |GPU - gemm_x3(A, B)|: the 3K exact terms summed
+    in binary32 in any order (gamma_{3K}) plus the final binary32 rounding."""
+    Ah, Al = split_x3(A)
+    Bh, Bl = split_x3(B)
+    K3 = 3 * A.shape[1]
+    g = K3 * U32 / (1.0 - K3 * U32)
+    absprod = np.abs(Ah) @ np.abs(Bh) + np.abs(Ah) @ np.abs(Bl) + np.abs(Al) @ np.abs(Bh)
+    return (g + U32) * absprod

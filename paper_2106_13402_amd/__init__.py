@@ -16,14 +16,15 @@ from . import _lib
 from ._lib import RRFError
 
 __all__ = [
-    "RRFError", "randutv", "powerurv", "gaussian", "dgemm", "householder_panel",
+    "RRFError", "randutv", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
     "batched_workspace_size", "batched_block",
 ]
 
 # precision names of rrf_opts.precision
-PRECISIONS = {"fp64": _lib.RRF_PREC_FP64, "bf16_sketch": _lib.RRF_PREC_BF16_SKETCH}
+PRECISIONS = {"fp64": _lib.RRF_PREC_FP64, "bf16_sketch": _lib.RRF_PREC_BF16_SKETCH,
+              "bf16_x3": _lib.RRF_PREC_BF16_X3}
 
 lib = _lib.load()
 
@@ -130,7 +131,9 @@ def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool =
     """randUTV (Alg. 3): returns (U, T, V) with A = U T V^T (U/V None if not wanted).
 
     precision "bf16_sketch" forms each step's sketch from bfloat16 copies with
-    FP32 accumulation (RRF_PREC_BF16_SKETCH); everything else stays FP64."""
+    FP32 accumulation (RRF_PREC_BF16_SKETCH); everything else stays FP64.
+    "bf16_x3" adds the split-bfloat16 three-pass product to every update of
+    T, U and V (RRF_PREC_BF16_X3; results accurate to about 1e-5)."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
                    inplace, precision)
 
@@ -224,6 +227,16 @@ def gaussian(seed: int, stream_id: int, rows: int, cols: int, device="cuda"):
 def dgemm(A, B, *, transa: bool = False, transb: bool = False, alpha: float = 1.0,
           beta: float = 0.0, C_out=None, split_work: bool = True):
     """C = alpha op(A) op(B) + beta C on the FP64 MFMA kernel."""
+    return _gemm("rrf_dgemm", A, B, transa, transb, alpha, beta, C_out, split_work)
+
+
+def gemm_x3(A, B, *, transa: bool = False, transb: bool = False, alpha: float = 1.0,
+            beta: float = 0.0, C_out=None, split_work: bool = True):
+    """C = alpha op(A) op(B) + beta C by the split-bfloat16 three-pass product."""
+    return _gemm("rrf_gemm_x3", A, B, transa, transb, alpha, beta, C_out, split_work)
+
+
+def _gemm(name, A, B, transa, transb, alpha, beta, C_out, split_work):
     torch = _torch()
     _require(A, "A")
     _require(B, "B")
@@ -239,10 +252,10 @@ def dgemm(A, B, *, transa: bool = False, transb: bool = False, alpha: float = 1.
             raise ValueError("beta != 0 needs C_out")
     _require(C_out, "C", rows=M)
     work = torch.empty(8 * M * N * 8 if split_work else 0, dtype=torch.uint8, device=A.device)
-    _check(lib.rrf_dgemm(int(transa), int(transb), M, N, K, alpha, A.data_ptr(), _ld(A),
-                         B.data_ptr(), _ld(B), beta, C_out.data_ptr(), _ld(C_out),
-                         work.data_ptr() if work.numel() else None, work.numel(),
-                         _stream_ptr(A.device)), "rrf_dgemm")
+    _check(getattr(lib, name)(int(transa), int(transb), M, N, K, alpha, A.data_ptr(), _ld(A),
+                              B.data_ptr(), _ld(B), beta, C_out.data_ptr(), _ld(C_out),
+                              work.data_ptr() if work.numel() else None, work.numel(),
+                              _stream_ptr(A.device)), name)
     return C_out
 
 

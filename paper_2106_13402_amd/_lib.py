@@ -19,6 +19,7 @@ RRF_E_NUMERIC = 4
 RRF_E_INTERNAL = 5
 RRF_PREC_FP64 = 0
 RRF_PREC_BF16_SKETCH = 1
+RRF_PREC_BF16_X3 = 2
 RRF_ALG_RANDUTV = 0
 RRF_ALG_POWERURV = 1
 
@@ -65,6 +66,8 @@ PROTOTYPES = {
     "rrf_gaussian": (C.c_int, [_u64, _u64, _i64, _i64, _dp, _i64, _vp]),
     "rrf_dgemm": (C.c_int, [C.c_int, C.c_int, _i64, _i64, _i64, _d, _dp, _i64, _dp, _i64, _d,
                             _dp, _i64, _vp, _sz, _vp]),
+    "rrf_gemm_x3": (C.c_int, [C.c_int, C.c_int, _i64, _i64, _i64, _d, _dp, _i64, _dp, _i64, _d,
+                              _dp, _i64, _vp, _sz, _vp]),
     "rrf_panel_workspace_size": (_sz, [_i64, _i64]),
     "rrf_householder_panel": (C.c_int, [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64,
                                         _dp, _vp, _sz, _vp]),

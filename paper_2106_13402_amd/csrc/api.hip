@@ -124,8 +124,9 @@ int run_alg(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t
   rrf_opts o;
   rrf_opts_init(&o);
   if (opts) o = *opts;
-  if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH)
-    return set_error(RRF_E_NOTSUP, "precision mode not implemented");
+  if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH &&
+      !(alg == RRF_ALG_RANDUTV && o.precision == RRF_PREC_BF16_X3))
+    return set_error(RRF_E_NOTSUP, "precision mode not implemented for this algorithm");
   const bool ok = alg == RRF_ALG_RANDUTV ? randutv_supported(m, n, b) : powerurv_supported(m, n, b);
   if (!ok) return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
   int dev = 0;
@@ -176,7 +177,9 @@ void rrf_opts_init(rrf_opts* opts) {
 size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q, int precision) {
   if (m < 1 || n < 1 || b < 1 || q < 0 || m < n) return 0;
   if (alg == RRF_ALG_RANDUTV) {
-    if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
+    if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH &&
+        precision != RRF_PREC_BF16_X3)
+      return 0;
     return randutv_supported(m, n, b) ? randutv_workspace(m, n, b, precision) : 0;
   }
   if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
@@ -359,9 +362,10 @@ int rrf_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, 
   return gaussian(reinterpret_cast<hipStream_t>(stream), seed, stream_id, rows, cols, out, ld);
 }
 
-int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
-              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-              int64_t ldc, void* work, size_t work_bytes, void* stream) {
+static int gemm_entry(GemmFn fn, int transa, int transb, int64_t M, int64_t N, int64_t K,
+                      double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
+                      void* stream) {
   if (transa != 0 && transa != 1) return set_error(-1, "transa must be 0 or 1"), -1;
   if (transb != 0 && transb != 1) return set_error(-2, "transb must be 0 or 1"), -2;
   if (M < 0) return set_error(-3, "M must be >= 0"), -3;
@@ -376,8 +380,22 @@ int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double al
   if (ldc < (M > 1 ? M : 1)) return set_error(-13, "ldc too small"), -13;
   int dev = 0;
   RRF_TRY(device_ready(&dev));
-  return dgemm(reinterpret_cast<hipStream_t>(stream), transa != 0, transb != 0, M, N, K, alpha, A,
-               lda, B, ldb, beta, C, ldc, reinterpret_cast<double*>(work), work_bytes / 8);
+  return fn(reinterpret_cast<hipStream_t>(stream), transa != 0, transb != 0, M, N, K, alpha, A, lda,
+            B, ldb, beta, C, ldc, reinterpret_cast<double*>(work), work_bytes / 8);
+}
+
+int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+              int64_t ldc, void* work, size_t work_bytes, void* stream) {
+  return gemm_entry(dgemm, transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
+                    work_bytes, stream);
+}
+
+int rrf_gemm_x3(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                double* C, int64_t ldc, void* work, size_t work_bytes, void* stream) {
+  return gemm_entry(gemm_x3, transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
+                    work_bytes, stream);
 }
 
 size_t rrf_panel_workspace_size(int64_t M, int64_t k) {

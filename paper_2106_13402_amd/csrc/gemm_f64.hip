@@ -253,14 +253,18 @@ int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
                : launch_tile<64, 64, false>(st, ta, tb, g, splits);
   trace_end(st, tok);
   if (e != hipSuccess) return set_hip_error(e, "dgemm launch", __FILE__, __LINE__);
-  if (splits > 1) {
-    tok = trace_begin(st, kTrSplitReduce, (double)splits * M * N,
-                      8.0 * (splits + (beta != 0.0 ? 2.0 : 1.0)) * M * N);
-    hipLaunchKernelGGL(splitk_reduce_kernel, grid_2d(M, N), dim3(256), 0, st, M, N,
-                       splits, (const double*)work, alpha, beta, C, ldc);
-    trace_end(st, tok);
-    RRF_CHECK_HIP(hipGetLastError());
-  }
+  if (splits > 1) return splitk_reduce(st, M, N, splits, work, alpha, beta, C, ldc);
+  return RRF_OK;
+}
+
+int splitk_reduce(hipStream_t st, int64_t M, int64_t N, int splits, const double* P, double alpha,
+                  double beta, double* C, int64_t ldc) {
+  int tok = trace_begin(st, kTrSplitReduce, (double)splits * M * N,
+                        8.0 * (splits + (beta != 0.0 ? 2.0 : 1.0)) * M * N);
+  hipLaunchKernelGGL(splitk_reduce_kernel, grid_2d(M, N), dim3(256), 0, st, M, N, splits, P,
+                     alpha, beta, C, ldc);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;
 }
 

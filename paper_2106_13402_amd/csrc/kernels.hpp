@@ -11,6 +11,21 @@ namespace rrf {
 int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
           int64_t ldc, double* work, size_t work_elems);
+// C = alpha sum_z P_z + beta C for split-K partials P_z = P + z M N (ld M),
+// summed in split order.
+int splitk_reduce(hipStream_t st, int64_t M, int64_t N, int splits, const double* P, double alpha,
+                  double beta, double* C, int64_t ldc);
+
+// The signature shared by dgemm and gemm_x3.
+typedef int (*GemmFn)(hipStream_t, bool, bool, int64_t, int64_t, int64_t, double, const double*,
+                      int64_t, const double*, int64_t, double, double*, int64_t, double*, size_t);
+
+// ---- gemm_x3.hip -----------------------------------------------------------
+// As dgemm, with every operand split into bfloat16 hi + lo (from its binary32
+// rounding) and the product hi hi + hi lo + lo hi accumulated in binary32.
+int gemm_x3(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+            const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+            int64_t ldc, double* work, size_t work_elems);
 
 // ---- philox.hip ----------------------------------------------------------
 int gaussian(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
@@ -57,6 +72,10 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
 // out = bf16(X s) (rows x cols, ld ldo, rows [rows, ldo) zero) and, when
 // outT is non-null, its transpose (ld ldot, rows [cols, ldot) zero); s is the
 // power of two putting max|X| (from *word) in [0.5, 1), or 1 when word is null.
+// X *= s (inverse: X /= s), s the power of two putting max|X| from *word in
+// [0.5, 1) (1 when the max is 0); exact.
+int scale_pow2(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld,
+               const unsigned long long* word, bool inverse);
 int to_bf16(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
             const unsigned long long* word, uint16_t* out, int64_t ldo, uint16_t* outT,
             int64_t ldot);

@@ -49,6 +49,13 @@ namespace {
 
 constexpr int kThreads = 512;
 constexpr int kMaxCols = 256;
+// Widest panel one cooperative launch takes; wider ones are split by columns.
+// Each column costs one grid-wide exchange whose partial sums grow with k and
+// whose workgroup count grows as the LDS rows per workgroup shrink: at
+// M = 16384 a 256-column launch takes 4.9 ms, two 128-column halves with the
+// split's GEMMs about 3 ms, while 128 columns in one launch (1.2 ms) beat two
+// halves of 64 (1.3 ms).
+constexpr int kLaunchCols = 128;
 constexpr int64_t kLdsBudget = 140 * 1024;  // dynamic LDS bytes per workgroup
 constexpr int kMaxGroups = 256;
 constexpr int kRing = 4;                     // slot buffers in flight
@@ -487,7 +494,7 @@ size_t split_temp_bytes(int k1, int k2) { return (size_t)(3 + kSplitParts) * k1 
 
 size_t panel_work_bytes(int64_t Mmax, int k) {
   if (k < 1 || k > kMaxCols || Mmax < k) return 0;
-  const int64_t fit = fit_rows(k);
+  const int64_t fit = k <= kLaunchCols ? fit_rows(k) : 0;
   size_t need = 0;
   if (fit >= k) {
     PanelPlan p;
@@ -513,7 +520,7 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                       int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
                       double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
   PanelPlan plan;
-  if (panel_plan(M, k, &plan))
+  if (k <= kLaunchCols && panel_plan(M, k, &plan))
     return panel_launch(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
                         work_bytes, status);
   if (k < 2 || M < k)

@@ -145,7 +145,7 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B) {
   B->panel = ar.take<char>(B->panel_bytes);
   B->svd_bytes = (size_t)s * block_svd_work_bytes((int)kb);
   B->svd = ar.take<char>(B->svd_bytes);
-  if (precision == RRF_PREC_BF16_SKETCH) {
+  if (precision == RRF_PREC_BF16_SKETCH || precision == RRF_PREC_BF16_X3) {
     B->Tb = ar.take<uint16_t>((size_t)bf16_ld(m) * n);
     B->Tbt = ar.take<uint16_t>((size_t)bf16_ld(n) * m);
     B->Gb = ar.take<uint16_t>((size_t)bf16_ld(m) * kb);
@@ -176,7 +176,8 @@ int right_mult(hipStream_t st, int64_t rows, int64_t k, double* X, int64_t ldx, 
 // trailing block Q(ca:, ca:) as three GEMMs.
 int accumulate_backward(hipStream_t st, int64_t N, double* Q, int64_t ldq, const double* Wall,
                         int64_t ldw, const double* Tall, int64_t bb, int64_t b,
-                        const std::vector<int64_t>& kbs, const Back& k, size_t split_elems) {
+                        const std::vector<int64_t>& kbs, const Back& k, size_t split_elems,
+                        GemmFn upd) {
   RRF_TRY(set_identity(st, N, N, Q, ldq));
   int64_t i1 = (int64_t)kbs.size();
   while (i1 > 0) {
@@ -210,12 +211,12 @@ int accumulate_backward(hipStream_t st, int64_t N, double* Q, int64_t ldq, const
     }
     // Q(ca:, ca:) <- (I - W_G T_G W_G^T) Q(ca:, ca:)
     double* Qb = Q + ca + ca * ldq;
-    RRF_TRY(dgemm(st, true, false, width, Nq, Nq, 1.0, WG, ldw, Qb, ldq, 0.0, k.Z, width, k.split,
-                  split_elems));
+    RRF_TRY(upd(st, true, false, width, Nq, Nq, 1.0, WG, ldw, Qb, ldq, 0.0, k.Z, width, k.split,
+                split_elems));
     RRF_TRY(dgemm(st, false, false, width, Nq, width, 1.0, k.TG, width, k.Z, width, 0.0, k.Z2,
                   width, nullptr, 0));
-    RRF_TRY(dgemm(st, false, false, Nq, Nq, width, -1.0, WG, ldw, k.Z2, width, 1.0, Qb, ldq,
-                  nullptr, 0));
+    RRF_TRY(upd(st, false, false, Nq, Nq, width, -1.0, WG, ldw, k.Z2, width, 1.0, Qb, ldq,
+                nullptr, 0));
     i1 = i0;
   }
   return RRF_OK;
@@ -278,11 +279,23 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipEvent_t* ev = ctx->ev;
   const size_t SE = B.split_elems;
+  const bool mixed_sketch = precision == RRF_PREC_BF16_SKETCH || precision == RRF_PREC_BF16_X3;
+  const bool x3 = precision == RRF_PREC_BF16_X3;
+  // the products that update T, U and V
+  const GemmFn upd = x3 ? gemm_x3 : dgemm;
+  unsigned long long* scale_word = B.word + 8;  // max|A| of the x3 mode
 
   RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(B.status), 64, 0u));
   if (check_input) RRF_TRY(check_finite(st, m, n, A, lda, B.status + 1));
   const int64_t ldt = m, ldu = m, ldv = n;
   if (T != A) RRF_TRY(copy_matrix(st, m, n, A, lda, T, ldt));
+  if (x3) {
+    // T = 2^-e A with max|T| in [0.5, 1): every entry of T, and of the
+    // products formed from it, stays inside the binary32 range of the split
+    // (the scaling is exact and undone at the end)
+    RRF_TRY(maxabs(st, m, n, T, ldt, scale_word));
+    RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, false));
+  }
   // reflector stores: zero outside each step's block
   if (U) RRF_TRY(fill_matrix(st, m, n, 0.0, B.WU, m));
   if (V) RRF_TRY(fill_matrix(st, n, n, 0.0, B.WV, n));
@@ -313,7 +326,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
       kv[i] = kb;
       // ---- sketch and V_i
       RRF_TRY(gaussian(st, seed, (uint64_t)(i + 1), Mi, kb, B.G, Mi));
-      if (precision == RRF_PREC_BF16_SKETCH) {
+      if (mixed_sketch) {
         RRF_TRY(sketch_mixed(st, Mi, Ni, kb, q, T22, ldt, B, B.Y));
       } else {
         RRF_TRY(dgemm(st, true, false, Ni, kb, Mi, 1.0, T22, ldt, B.G, Mi, 0.0, B.Y, Ni,
@@ -329,8 +342,8 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
                                 nullptr, 0, B.panel, B.panel_bytes, B.status));
       RRF_TRY(dgemm(st, false, true, Ni, kb, kb, 1.0, Wv, n, Tv, bb, 0.0, Wr, n, nullptr, 0));
       // X = T(:, J2uJ3) W_v; columns J2 of T V_i
-      RRF_TRY(dgemm(st, false, false, m, kb, Ni, 1.0, Tc, ldt, Wv, n, 0.0, X, m, B.split, SE));
-      RRF_TRY(dgemm(st, false, true, m, kb, kb, -1.0, X, m, Wr, n, 1.0, Tc, ldt, nullptr, 0));
+      RRF_TRY(upd(st, false, false, m, kb, Ni, 1.0, Tc, ldt, Wv, n, 0.0, X, m, B.split, SE));
+      RRF_TRY(upd(st, false, true, m, kb, kb, -1.0, X, m, Wr, n, 1.0, Tc, ldt, nullptr, 0));
       // ---- U_i and R from the panel T(I2uI3, J2)
       RRF_TRY(householder_panel(st, Mi, (int)kb, T22, ldt, Wu, m, Ri, bb, Tu, bb, B.tau, T22, ldt,
                                 B.panel, B.panel_bytes, B.status));
@@ -341,15 +354,15 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
       RRF_TRY(dgemm(st, false, true, Mi, kb, kb, 1.0, Wu, m, Tu, bb, 0.0, Wl + c0, m, nullptr, 0));
       // Z^T = T(I2uI3, J3)^T W_u - Wr(J3, :) (X(I2uI3, :)^T W_u)
       double* T23 = T + c0 + c2 * ldt;
-      RRF_TRY(dgemm(st, true, false, N3, kb, Mi, 1.0, T23, ldt, Wu, m, 0.0, Zt + kb, n, B.split,
-                    SE));
+      RRF_TRY(upd(st, true, false, N3, kb, Mi, 1.0, T23, ldt, Wu, m, 0.0, Zt + kb, n, B.split,
+                  SE));
       RRF_TRY(dgemm(st, true, false, kb, kb, Mi, 1.0, X + c0, m, Wu, m, 0.0, B.S, kb, B.split,
                     SE));
-      RRF_TRY(dgemm(st, false, false, N3, kb, kb, -1.0, Wr + kb, n, B.S, kb, 1.0, Zt + kb, n,
-                    nullptr, 0));
+      RRF_TRY(upd(st, false, false, N3, kb, kb, -1.0, Wr + kb, n, B.S, kb, 1.0, Zt + kb, n,
+                  nullptr, 0));
       // T(:, J3) -= [X, W_u Tf_u^T] [Wr(J3, :), Z^T]^T
-      RRF_TRY(dgemm(st, false, true, m, N3, 2 * kb, -1.0, X, m, B.WZ + kb, n, 1.0, T + c2 * ldt,
-                    ldt, nullptr, 0));
+      RRF_TRY(upd(st, false, true, m, N3, 2 * kb, -1.0, X, m, B.WZ + kb, n, 1.0, T + c2 * ldt,
+                  ldt, nullptr, 0));
     } else {
       // Last block: its SVD is of T(I2uI3, J2uJ3), Mi x Ni with Mi >= Ni;
       // a tall block is first reduced by a Householder QR.
@@ -372,11 +385,11 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   trace_mark_stream(sv);
   if (U) {
     RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvLoop], 0));
-    RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE));
+    RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE, upd));
   }
   if (V) {
     RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvLoop], 0));
-    RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE));
+    RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE, upd));
   }
   RRF_TRY(block_svd_batched(st, (int)s, (int)bb, (int)k_last, B.R, bb, bb * bb, B.Us, B.d, bb,
                             B.Vs, B.svd, B.svd_bytes, B.status));
@@ -415,6 +428,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
     RRF_CHECK_HIP(hipEventRecord(ev[kEvV], sv));
     RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvV], 0));
   }
+  if (x3) RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, true));
   *status_out = 0;
   return RRF_OK;
 }

@@ -100,6 +100,19 @@ __global__ __launch_bounds__(256) void maxabs_kernel(int64_t rows, int64_t cols,
   }
 }
 
+// X *= s or X /= s with s = pow2_scale(max|X|) from `word`: multiplication
+// by a power of two, exact for every entry in the normal range.
+__global__ __launch_bounds__(256) void scale_pow2_kernel(int64_t rows, int64_t cols, double* X,
+                                                         int64_t ld,
+                                                         const unsigned long long* word,
+                                                         bool inverse) {
+  const double s0 = pow2_scale(__longlong_as_double((long long)*word));
+  const double s = inverse ? 1.0 / s0 : s0;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows) return;
+  for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) X[i + j * ld] *= s;
+}
+
 // --- binary64 -> bfloat16, optionally scaled and transposed ----------------
 
 // out (rows x cols, ld ldo) = bf16(X * s), outT (cols x rows, ld ldot) its
@@ -462,6 +475,17 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
   dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 32));
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
   hipLaunchKernelGGL(maxabs_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int scale_pow2(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld,
+               const unsigned long long* word, bool inverse) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  const dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 65535));
+  int tok = trace_begin(st, kTrElementwise, 0.0, 16.0 * rows * cols);
+  hipLaunchKernelGGL(scale_pow2_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word, inverse);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;

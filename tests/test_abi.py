@@ -88,11 +88,18 @@ def test_workspace_size(lib):
     assert 8 * 2 * n * n < big < 8 * 2 * n * n + 2 ** 31
     mixed = f(_lib.RRF_ALG_RANDUTV, n, n, 128, 2, 1)
     assert big < mixed < big + 2 * 2 * n * n + 2 ** 30  # + two bfloat16 copies of T22
+    # the x3 updates need no buffers beyond the bfloat16 sketch's
+    assert f(_lib.RRF_ALG_RANDUTV, n, n, 128, 2, _lib.RRF_PREC_BF16_X3) == mixed
+    # powerURV has no x3 mode
+    assert f(_lib.RRF_ALG_POWERURV, n, n, 128, 2, _lib.RRF_PREC_BF16_X3) == 0
 
 
 def test_component_argument_errors(lib):
     assert lib.rrf_dgemm(2, 0, 1, 1, 1, 1.0, DUMMY, 1, DUMMY, 1, 0.0, DUMMY, 1, NULL, 0, NULL) == -1
     assert lib.rrf_dgemm(0, 0, 4, 4, 4, 1.0, DUMMY, 3, DUMMY, 4, 0.0, DUMMY, 4, NULL, 0, NULL) == -8
+    assert lib.rrf_gemm_x3(0, 3, 1, 1, 1, 1.0, DUMMY, 1, DUMMY, 1, 0.0, DUMMY, 1, NULL, 0, NULL) == -2
+    assert lib.rrf_gemm_x3(0, 1, 4, 4, 4, 1.0, DUMMY, 4, DUMMY, 3, 0.0, DUMMY, 4, NULL, 0, NULL) == -10
+    assert lib.rrf_gemm_x3(0, 0, 4, 4, 4, 1.0, DUMMY, 4, DUMMY, 4, 0.0, DUMMY, 3, NULL, 0, NULL) == -13
     assert lib.rrf_householder_panel(3, 4, DUMMY, 3, DUMMY, 3, NULL, 4, DUMMY, 4, DUMMY, NULL, 0,
                                      NULL) == -1
     assert lib.rrf_block_svd(0, DUMMY, 1, DUMMY, DUMMY, DUMMY, NULL, 0, NULL) == -1
@@ -113,6 +120,22 @@ def test_opts_init(lib):
     o.async_ = 1
     lib.rrf_opts_init(C.byref(o))
     assert o.precision == 0 and o.async_ == 0 and o.workspace is None
+
+
+def test_x3_mode_is_randutv_only(lib):
+    # rejected before any device work: powerURV and the batched call have no
+    # x3 updates
+    o = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(o))
+    o.precision = _lib.RRF_PREC_BF16_X3
+    assert lib.rrf_powerurv_ex(8, 8, DUMMY, 8, 4, 1, 1, NULL, DUMMY, NULL,
+                               C.byref(o)) == _lib.RRF_E_NOTSUP
+    m = (C.c_int64 * 1)(8)
+    A = (C.c_void_p * 1)(0x1000)
+    T = (C.c_void_p * 1)(0x3000)
+    assert lib.rrf_randutv_batched(1, m, m, A, m, 4, 1, 1, NULL, T, NULL,
+                                   C.byref(o)) == _lib.RRF_E_NOTSUP
+    assert lib.rrf_randutv_batched_workspace_size(1, m, m, 4, _lib.RRF_PREC_BF16_X3) == 0
 
 
 def _arr(t, vals):

@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.bf16 import bf16_round, fp32_gemm_bound, gemm_tn_reference, pow2_scale, sketch_bf16
+from oracle.bf16 import (bf16_round, fp32_gemm_bound, fp32_x3_bound, gemm_tn_reference, gemm_x3,
+                         pow2_scale, sketch_bf16, split_x3)
 
 
 def _torch_bf16(x32):
@@ -131,3 +132,94 @@ def test_sketch_bf16_power_of_two_invariance():
     # renormalisation, the sketch stays finite and non-zero
     Y = sketch_bf16(T * 1e-30, G, 2)
     assert np.all(np.isfinite(Y)) and np.all(np.linalg.norm(Y, axis=0) > 0.1)
+
+
+# --------------------------------------------------------- x3 split product
+def test_split_x3_matches_torch_roundings():
+    # hi is torch's bfloat16 of the binary32 value, lo torch's bfloat16 of the
+    # (exact) binary32 remainder
+    rng = np.random.default_rng(10)
+    x = np.concatenate([rng.standard_normal(20000),
+                        rng.standard_normal(5000) * 2.0 ** rng.integers(-100, 100, 5000)])
+    hi, lo = split_x3(x)
+    x32 = torch.from_numpy(x).to(torch.float32)
+    hi_t = x32.to(torch.bfloat16).to(torch.float32)
+    lo_t = (x32 - hi_t).to(torch.bfloat16).to(torch.float64)
+    np.testing.assert_array_equal(hi, hi_t.to(torch.float64).numpy())
+    np.testing.assert_array_equal(lo, lo_t.numpy())
+
+
+def test_split_x3_hand_cases():
+    # x32 keeps 2^-20 and drops 2^-30; hi rounds the 2^-10 tail away (below
+    # half an ulp of 1, 2^-8); lo rounds 2^-10 + 2^-20 to 2^-10 (2^-20 is
+    # below half an ulp of 2^-10, 2^-18)
+    hi, lo = split_x3(np.array([1.0 + 2.0 ** -10 + 2.0 ** -20 + 2.0 ** -30]))
+    assert hi[0] == 1.0 and lo[0] == 2.0 ** -10
+    # a binary32 tie of hi goes to the even neighbour, lo takes the rest
+    hi, lo = split_x3(np.array([1.0 + 2.0 ** -8]))
+    assert hi[0] == 1.0 and lo[0] == 2.0 ** -8
+    hi, lo = split_x3(np.array([1.0 + 3 * 2.0 ** -8]))
+    assert hi[0] == 1.0 + 2.0 ** -6 and lo[0] == -(2.0 ** -8)
+
+
+def test_split_x3_error_bound_is_sharp():
+    # x in [2^e, 2^(e+1)): |x32 - hi| < 2^(e-8) (half an ulp of hi), so the
+    # remainder's leading exponent is at most e - 9 and lo is within half its
+    # ulp, 2^(e-9-8): |x - hi - lo| <= (2^-24 + 2^-17) |x|, reached to within
+    # a factor of 2 (the split keeps about 17 bits, not 24)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(200000) * 2.0 ** rng.integers(-30, 30, 200000)
+    hi, lo = split_x3(x)
+    rel = np.abs(x - hi - lo) / np.abs(x)
+    assert rel.max() <= 2.0 ** -24 + 2.0 ** -17
+    assert rel.max() >= 2.0 ** -18
+
+
+def test_gemm_x3_drops_exactly_the_lo_lo_term():
+    # a = b = 1 + 2^-10 split exactly as hi = 1, lo = 2^-10: the exact
+    # product is 1 + 2^-9 + 2^-20, the three-pass sum misses lo lo = 2^-20
+    a = np.array([[1.0 + 2.0 ** -10]])
+    assert gemm_x3(a, a)[0, 0] == 1.0 + 2.0 ** -9
+    assert (a @ a)[0, 0] == 1.0 + 2.0 ** -9 + 2.0 ** -20
+    # inner dimension: sums of such terms, with signs
+    A = np.array([[1.0 + 2.0 ** -10, -(1.0 + 2.0 ** -10), 2.0]])
+    B = np.array([[1.0 + 2.0 ** -10], [1.0 - 2.0 ** -10], [3.0]])
+    # (1 + e)^2 - lo lo, -(1 + e)(1 - e) - (lo (-lo)), 6 with e = 2^-10
+    assert gemm_x3(A, B)[0, 0] == (1 + 2.0 ** -9) - (1 - 2.0 ** -20) - 2.0 ** -20 + 6.0
+
+
+def test_gemm_x3_error_bound():
+    # per term, with r = x - hi - lo (<= 2^-17 (1 + 2^-7) |x|) and
+    # |lo| <= 2^-8 (1 + 2^-8) |x|: ab - x3(a, b) = a r_b + r_a b - r_a r_b
+    # + lo_a lo_b, at most 2^-15 (1 + 2^-6) |a| |b|
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((40, 300)) * 2.0 ** rng.integers(-8, 8, (40, 300))
+    B = rng.standard_normal((300, 30))
+    err = np.abs(gemm_x3(A, B) - A @ B)
+    scale = np.abs(A) @ np.abs(B)
+    bound = (2.0 ** -15 * (1 + 2.0 ** -6) + 1e-15) * scale
+    assert np.all(err <= bound)
+    # far from binary64 exactness, and far better than one bfloat16 pass
+    assert np.max(err / scale) > 2.0 ** -26
+    one_pass = np.abs(split_x3(A)[0] @ split_x3(B)[0] - A @ B)
+    assert np.max(one_pass / scale) > 2.0 ** 6 * np.max(err / scale)
+
+
+def test_fp32_x3_bound_covers_binary32_sums():
+    # the 3K exact terms summed in binary32 in a random order
+    rng = np.random.default_rng(13)
+    for K in (8, 500, 4000):
+        A = rng.standard_normal((5, K))
+        B = rng.standard_normal((K, 4))
+        Ah, Al = split_x3(A)
+        Bh, Bl = split_x3(B)
+        ref = gemm_x3(A, B)
+        bound = fp32_x3_bound(A, B)
+        for i in range(5):
+            for j in range(4):
+                terms = np.concatenate([Ah[i] * Bh[:, j], Ah[i] * Bl[:, j], Al[i] * Bh[:, j]])
+                s = np.float32(0.0)
+                for t in rng.permutation(terms).astype(np.float32):
+                    s = np.float32(s + t)
+                assert abs(float(s) - ref[i, j]) <= bound[i, j]
+        assert np.max(bound / (np.abs(A) @ np.abs(B))) < 1e-3
