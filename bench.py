@@ -15,7 +15,9 @@ sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), the same with the
 split-bfloat16 three-pass updates (RRF_PREC_BF16_X3, "mixed_x3"; results
 accurate to about 1e-5, so the gate covers sigma_{k+1} >= 100 x that), the
 powerURV leg, the FP64 CPU oracle
-timed on a bounded sample of the same workload, and ("batched") the batched
+timed on a bounded sample of the same workload, ("gap") the 32768 x 8192
+sharp-gap workload in the three precision modes with e_k around k = 1000,
+and ("batched") the batched
 call on 4096 small matrices (n ~ U{64..512}, m ~ U{n..2n}, graded spectrum,
 q = 1, automatic b) in matrices per second with every matrix's residual.
 
@@ -44,13 +46,13 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # They describe the GEMM sources whose concatenation has this SHA-256 prefix.
 TRAFFIC_SOURCES = ("paper_2106_13402_amd/csrc/gemm_f64.hip",
                    "paper_2106_13402_amd/csrc/gemm_tile.hpp")
-TRAFFIC_SHA256_16 = "d7b78f80d6b254c1"
+TRAFFIC_SHA256_16 = "8dab7403c870db34"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "dgemm_mfma_128x128_NN": 608591690,
-    "dgemm_mfma_128x128_TN": 595814424,
-    "dgemm_mfma_128x128_NT": 917414241,
-    "dgemm_mfma_128x128_NN:UV": 427685111,
-    "dgemm_mfma_128x128_TN:UV": 857058180,
+    "dgemm_mfma_128x128_NN": 608648606,
+    "dgemm_mfma_128x128_TN": 595841394,
+    "dgemm_mfma_128x128_NT": 931093346,
+    "dgemm_mfma_128x128_NN:UV": 427565173,
+    "dgemm_mfma_128x128_TN:UV": 856814214,
 }
 
 
@@ -263,6 +265,87 @@ def powerurv_leg(A, U, T, V, s, kgrid, b, q, args, dev, fp64_acc):
 
 
 # ------------------------------------------------------------- batched leg
+def gap_leg(args, dev):
+    """The rectangular sharp-gap workload: m = 32768, n = 8192,
+    A = Q1 diag(s) Q2^T + 1e-12 N(0,1) with s_j = 1 for j <= 1000 and 1e-10
+    after, b = 256, q = 2, U and V formed, in FP64, with the bfloat16 sketch
+    and with the x3 updates. e_k on k = 900, 904, ..., 1100. Below the gap
+    sigma_{k+1} = 1 to within ||E||_2; above it Weyl's bound only brackets it,
+    sigma_{k+1} <= 1e-10 + ||E||_2, so e_k / (s_{k+1} + ||E||_2) is reported
+    (a lower bound of e_k / sigma_{k+1}) with the FP64 run's e_k beside it."""
+    import numpy as np
+    import torch
+
+    import paper_2106_13402_amd as rrf
+    from synthetic import gaussian_matrix, spectral_matrix
+
+    m, n, b, q = 32768, 8192, 256, 2
+    j = np.arange(1, n + 1)
+    s = np.where(j <= 1000, 1.0, 1e-10)
+    log(f"gap: generating A, {m} x {n}")
+    E = gaussian_matrix(m, n, 0, 3, dev)
+    e_norm = 1e-12 * _power_norm(lambda x: E @ x, lambda y: E.t() @ y, n, dev, iters=40)
+    del E
+    A = spectral_matrix(m, n, s, seed=0, noise=1e-12, device=dev)
+    U = rrf.empty_colmajor(m, m, dev)
+    T = rrf.empty_colmajor(m, n, dev)
+    V = rrf.empty_colmajor(n, n, dev)
+    kgrid = list(range(900, 1101, 4))
+
+    def factor(precision):
+        import ctypes as C
+        from paper_2106_13402_amd import _lib
+        ws = rrf._workspace(dev, rrf.workspace_size("randutv", m, n, b, q, precision))
+        opts = _lib.rrf_opts()
+        rrf.lib.rrf_opts_init(C.byref(opts))
+        opts.precision = rrf.PRECISIONS[precision]
+        opts.stream = torch.cuda.current_stream(dev).cuda_stream
+        opts.workspace = ws.data_ptr()
+        opts.workspace_bytes = ws.numel()
+        st = rrf.lib.rrf_randutv_ex(m, n, A.data_ptr(), m, b, q, args.seed, U.data_ptr(),
+                                    T.data_ptr(), V.data_ptr(), C.byref(opts))
+        if st != 0:
+            raise RuntimeError(f"rrf_randutv_ex failed: {st} {rrf.lib.rrf_last_error().decode()}")
+
+    leg = {"workload": f"randUTV m={m} n={n} b={b} q={q}, A=Q1 diag(s) Q2^T + 1e-12 N(0,1), "
+                       "s_j = 1 (j <= 1000), 1e-10 after; U and V accumulated",
+           "noise_norm": e_norm, "k_grid": kgrid, "modes": {}}
+    ek64 = None
+    for precision in ("fp64", "bf16_sketch", "bf16_x3"):
+        factor(precision)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        factor(precision)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        acc = accuracy(A, U, T, V, s, [0])
+        eks = []
+        for k in kgrid:
+            Tk = T[k:, k:]
+            eks.append(_power_norm(lambda x: Tk @ x, lambda y: Tk.t() @ y, n - k, dev, iters=60))
+        if ek64 is None:
+            ek64 = eks
+        lo = [e / (float(s[k]) + e_norm) for e, k in zip(eks, kgrid)]
+        below = [i for i, k in enumerate(kgrid) if k < 1000]
+        above = [i for i, k in enumerate(kgrid) if k >= 1000]
+        leg["modes"][precision] = {
+            "value": sec, "unit": "s", "speedup_vs_fp64": None,
+            "recon": acc["recon"], "orth_U": acc["orth_U"], "orth_V": acc["orth_V"],
+            "e_k": eks, "ek_over_fp64": [e / r for e, r in zip(eks, ek64)],
+            "ek_over_sigma_below_gap_max": max(lo[i] for i in below),
+            "ek_over_sigma_bound_above_gap_max": max(lo[i] for i in above),
+            "e_1000": eks[kgrid.index(1000)], "e_1024": eks[kgrid.index(1024)],
+        }
+        log(f"gap {precision}: {sec:.3f} s, recon {acc['recon']:.2e}, "
+            f"e_1000 {eks[kgrid.index(1000)]:.3e} (FP64 {ek64[kgrid.index(1000)]:.3e})")
+    t64 = leg["modes"]["fp64"]["value"]
+    for v in leg["modes"].values():
+        v["speedup_vs_fp64"] = t64 / v["value"]
+    del A, U, T, V
+    torch.cuda.empty_cache()
+    return leg
+
+
 def auto_block(n: int, m: int = 0) -> int:
     """Block size the batched call picks for b = 0."""
     import paper_2106_13402_amd as rrf
@@ -395,6 +478,7 @@ def main() -> int:
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-powerurv", action="store_true")
+    ap.add_argument("--no-gap", action="store_true", help="skip the 32768 x 8192 gap workload")
     ap.add_argument("--batch", type=int, default=4096, help="matrices in the batched leg")
     ap.add_argument("--batch-q", type=int, default=1)
     args = ap.parse_args()
@@ -549,6 +633,11 @@ def main() -> int:
     if not args.no_powerurv:
         out["powerurv"] = powerurv_leg(A, U, T, V, s, kgrid, b, q, args, dev,
                                        None if args.no_accuracy else out["accuracy"])
+    if not args.no_gap:
+        del U, T, V
+        torch.cuda.empty_cache()
+        out["gap"] = gap_leg(args, dev)
+        U = T = V = None
     if not args.no_cpu_baseline:
         log(f"timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         A_host = A.cpu().numpy()
