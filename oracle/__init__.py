@@ -1,4 +1,5 @@
-"""Plain FP64 CPU oracle for randUTV (Alg. 3) and powerURV (Alg. 1).
+"""Plain FP64 CPU oracle for randUTV (Alg. 3), randUTV_boosted (Alg. 2) and
+powerURV (Alg. 1).
 
 TEST INFRASTRUCTURE, not product code. Only ``tests/``,
 ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may
@@ -9,10 +10,11 @@ from .philox import gaussian, philox4x64_10
 from .hqr import apply_q, form_q, hqr
 from .small_svd import canonical_signs, small_svd
 from .randutv import randutv
+from .randutv_boosted import randutv_boosted
 from .powerurv import powerurv
 from . import metrics
 
 __all__ = [
     "gaussian", "philox4x64_10", "hqr", "apply_q", "form_q",
-    "small_svd", "canonical_signs", "randutv", "powerurv", "metrics",
+    "small_svd", "canonical_signs", "randutv", "randutv_boosted", "powerurv", "metrics",
 ]
