@@ -125,6 +125,38 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
                    const rrf_opts* opts);
 
 /*
+ * randUTV_boosted -- Alg. 2 (Sec. 4.2-4.3): randUTV with oversampling.
+ *
+ * Each step samples the trailing block with b + p_i columns,
+ * p_i = min(p, N_i - b) (N_i = n - i b), and takes V_i from an unpivoted
+ * Householder QR of the leading b left singular vectors W_Y(:, 1:b) of the
+ * sample matrix Y (QR of Y, SVD of its R factor). The first step draws all
+ * b + p_1 Gaussian columns (stream 1) through q power steps; each later step
+ * draws b (stream i), applies q - 1 power steps and one more product to
+ * them (q = 0: the Gaussian itself), projects them off W_l, orthonormalises
+ * them and samples Y = T22^T [Q, W_l], where W_l is the orthonormalised
+ * image T22 W_next of the previous step's extra vectors
+ * W_next = V_i(:, b+1:N_i)^T W_Y(:, b+1:b+p_i) (the paper's listing applies
+ * W_next on the left of T22, which only types for square blocks; this
+ * library maps it through T22 first). The rest of each step, the last step
+ * and the output form are those of rrf_randutv. FP64 only.
+ *
+ *  m, n, A, lda, b, q : as for rrf_randutv                 (args 1-6)
+ *  p      : oversampling, p >= 0, with b + p <= 256        (arg 7)
+ *  seed, U, T, V      : as for rrf_randutv                 (args 8-11)
+ * opts: precision must be RRF_PREC_FP64; the workspace must hold
+ * rrf_randutv_boosted_workspace_size(m, n, b, q, p) bytes. b + p > 256
+ * returns RRF_E_NOTSUP.
+ */
+int rrf_randutv_boosted(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                        int32_t q, int64_t p, uint64_t seed, double* U, double* T, double* V);
+int rrf_randutv_boosted_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                           int32_t q, int64_t p, uint64_t seed, double* U, double* T,
+                           double* V, const rrf_opts* opts);
+size_t rrf_randutv_boosted_workspace_size(int64_t m, int64_t n, int64_t b, int32_t q,
+                                          int64_t p);
+
+/*
  * powerURV -- Alg. 1 (Sec. 3.2).
  *
  * V starts as an n x n Gaussian; q rounds of  Y_hat = A V,

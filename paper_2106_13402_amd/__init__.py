@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import RRFError
 
 __all__ = [
-    "RRFError", "randutv", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
+    "RRFError", "randutv", "randutv_boosted", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
     "batched_workspace_size", "batched_block",
@@ -94,7 +94,7 @@ def workspace_size(alg: str, m: int, n: int, b: int, q: int, precision: str = "f
 
 
 def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, want_v: bool,
-            check_finite: bool, inplace: bool, precision: str = "fp64"):
+            check_finite: bool, inplace: bool, precision: str = "fp64", p=None):
     _require(A, "A")
     m, n = int(A.shape[0]), int(A.shape[1])
     dev = A.device
@@ -106,7 +106,10 @@ def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, wa
         T = A
     else:
         T = empty_colmajor(m, n, dev)
-    nbytes = workspace_size(alg, m, n, b, q, precision)
+    if p is None:
+        nbytes = workspace_size(alg, m, n, b, q, precision)
+    else:
+        nbytes = int(lib.rrf_randutv_boosted_workspace_size(m, n, b, q, p))
     if nbytes == 0:
         raise RRFError(_lib.RRF_E_NOTSUP, fname, "no workspace size for these arguments")
     ws = _workspace(dev, nbytes)
@@ -119,7 +122,8 @@ def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, wa
     opts.async_ = 0
     opts.check_finite = 1 if check_finite else 0
     fn = getattr(lib, fname)
-    st = fn(m, n, A.data_ptr(), _ld(A), b, q, seed,
+    extra = () if p is None else (p,)
+    st = fn(m, n, A.data_ptr(), _ld(A), b, q, *extra, seed,
             U.data_ptr() if U is not None else None, T.data_ptr(),
             V.data_ptr() if V is not None else None, C.byref(opts))
     _check(st, fname)
@@ -136,6 +140,14 @@ def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool =
     T, U and V (RRF_PREC_BF16_X3; results accurate to about 1e-5)."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
                    inplace, precision)
+
+
+def randutv_boosted(A, b: int, q: int, p: int, seed: int, *, want_u: bool = True,
+                    want_v: bool = True, check_finite: bool = False, inplace: bool = False):
+    """randUTV_boosted (Alg. 2): randUTV with b + p samples per step and the
+    extra samples recycled into the next step; returns (U, T, V). FP64."""
+    return _factor("rrf_randutv_boosted_ex", "randutv", A, b, q, seed, want_u, want_v,
+                   check_finite, inplace, "fp64", p=int(p))
 
 
 def _i64_array(vals):

@@ -102,14 +102,14 @@ int finish(hipStream_t st, const int* status_dev) {
 
 // Shared argument checks of rrf_randutv / rrf_powerurv (LAPACK numbering).
 int check_args(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
-               const double* T) {
+               const double* T, int shift = 0) {
   if (m < 1) return set_error(-1, "m must be >= 1"), -1;
   if (n < 1) return set_error(-2, "n must be >= 1"), -2;
   if (A == nullptr) return set_error(-3, "A is NULL"), -3;
   if (lda < m) return set_error(-4, "lda must be >= m"), -4;
   if (b < 1) return set_error(-5, "b must be >= 1"), -5;
   if (q < 0) return set_error(-6, "q must be >= 0"), -6;
-  if (T == nullptr) return set_error(-9, "T is NULL"), -9;
+  if (T == nullptr) return set_error(-9 - shift, "T is NULL"), -9 - shift;
   if (T == A && lda != m) return set_error(-4, "T may alias A only when lda == m"), -4;
   if (m < n) return set_error(RRF_E_NOTSUP, "m < n is not supported (factor A^T instead)");
   return RRF_OK;
@@ -117,25 +117,37 @@ int check_args(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, in
 
 typedef bool (*SupportedFn)(int64_t, int64_t, int64_t);
 
+// boost_p >= 0: randUTV_boosted with that oversampling (its argument list has
+// p after q, so the pointer positions move by one).
 template <typename Run>
 int run_alg(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
-            double* U, double* T, double* V, const rrf_opts* opts, Run run) {
-  RRF_TRY(check_args(m, n, A, lda, b, q, T));
+            double* U, double* T, double* V, const rrf_opts* opts, Run run,
+            int64_t boost_p = -1) {
+  const int shift = boost_p >= 0 ? 1 : 0;
+  RRF_TRY(check_args(m, n, A, lda, b, q, T, shift));
   rrf_opts o;
   rrf_opts_init(&o);
   if (opts) o = *opts;
-  if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH &&
-      !(alg == RRF_ALG_RANDUTV && o.precision == RRF_PREC_BF16_X3))
+  if (boost_p >= 0) {
+    if (o.precision != RRF_PREC_FP64)
+      return set_error(RRF_E_NOTSUP, "randutv_boosted: only RRF_PREC_FP64");
+    if (std::min(b, n) + std::min(boost_p, std::max<int64_t>(n - b, 0)) > 256)
+      return set_error(RRF_E_NOTSUP, "randutv_boosted: needs b + p <= 256");
+  } else if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH &&
+             !(alg == RRF_ALG_RANDUTV && o.precision == RRF_PREC_BF16_X3)) {
     return set_error(RRF_E_NOTSUP, "precision mode not implemented for this algorithm");
+  }
   const bool ok = alg == RRF_ALG_RANDUTV ? randutv_supported(m, n, b) : powerurv_supported(m, n, b);
   if (!ok) return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
   int dev = 0;
   RRF_TRY(device_ready(&dev));
   RRF_TRY(check_device_ptr(A, 3));
-  RRF_TRY(check_device_ptr(U, 8));
-  RRF_TRY(check_device_ptr(T, 9));
-  RRF_TRY(check_device_ptr(V, 10));
-  const size_t need = rrf_workspace_size(alg, m, n, b, q, o.precision);
+  RRF_TRY(check_device_ptr(U, 8 + shift));
+  RRF_TRY(check_device_ptr(T, 9 + shift));
+  RRF_TRY(check_device_ptr(V, 10 + shift));
+  const size_t need = boost_p >= 0 ? randutv_workspace(m, n, b, RRF_PREC_FP64, boost_p)
+                                   : rrf_workspace_size(alg, m, n, b, q, o.precision);
+  if (need == 0) return set_error(RRF_E_NOTSUP, "shape outside the kernel limits");
   void* ws = o.workspace;
   size_t ws_bytes = o.workspace_bytes;
   if (ws == nullptr) {
@@ -196,6 +208,32 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
                    return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
                                       opts ? opts->precision : RRF_PREC_FP64, &dummy);
                  });
+}
+
+size_t rrf_randutv_boosted_workspace_size(int64_t m, int64_t n, int64_t b, int32_t q,
+                                          int64_t p) {
+  (void)q;
+  if (m < 1 || n < 1 || b < 1 || q < 0 || p < 0 || m < n) return 0;
+  if (std::min(b, n) + std::min(p, std::max<int64_t>(n - b, 0)) > 256) return 0;
+  return randutv_supported(m, n, b) ? randutv_workspace(m, n, b, RRF_PREC_FP64, p) : 0;
+}
+
+int rrf_randutv_boosted_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                           int32_t q, int64_t p, uint64_t seed, double* U, double* T, double* V,
+                           const rrf_opts* opts) {
+  if (p < 0) return set_error(-7, "p must be >= 0"), -7;
+  return run_alg(RRF_ALG_RANDUTV, m, n, A, lda, b, q, U, T, V, opts,
+                 [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
+                   int dummy = 0;
+                   return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
+                                      RRF_PREC_FP64, &dummy, p);
+                 },
+                 p);
+}
+
+int rrf_randutv_boosted(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                        int64_t p, uint64_t seed, double* U, double* T, double* V) {
+  return rrf_randutv_boosted_ex(m, n, A, lda, b, q, p, seed, U, T, V, nullptr);
 }
 
 int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,

@@ -1,4 +1,9 @@
-// randUTV_basic (Alg. 3) on one GPU.
+// randUTV_basic (Alg. 3) and randUTV_boosted (Alg. 2) on one GPU.
+//
+// Alg. 2 changes only how V_i is built (boosted_sample below): b + p samples,
+// V_i from the leading b left singular vectors of the sample matrix, and the
+// p extra vectors of one step recycled into the next; the rest of each step
+// is the Alg. 3 step described here.
 //
 // Per step i (0-based here, c0 = i b, J2 = [c0, c2), I2 = [c0, r2)):
 //   1. G_i = Gaussian(seed, stream i+1), (m-c0) x b, generated in HBM;
@@ -68,6 +73,29 @@ struct Back {
   double* split = nullptr;
 };
 
+// Alg. 2's sampling (b + p columns; kY = b + p).
+struct Boost {
+  double* G = nullptr;    // m x kY   Gaussian (b + p columns at the first step, b later)
+  double* Z = nullptr;    // m x kY   power-iteration products
+  double* Y = nullptr;    // n x kY   the sample matrix; its Householder QR in place
+  double* X = nullptr;    // m x b    left sample X, then its Householder QR in place
+  double* S = nullptr;    // m x kY   [Q_X(:, 1:b), W_l]
+  double* Zw = nullptr;   // m x p    T22 W_next, then its Householder QR in place
+  double* Qy = nullptr;   // n x kY   Q_Y(:, 1:kY)
+  double* WY = nullptr;   // n x kY   W_Y(:, 1:kY) = Q_Y(:, 1:kY) U_R
+  double* Wn = nullptr;   // n x p    W_next (rows: the next step's trailing columns)
+  double* Ry = nullptr;   // kY x kY  R factor of Y
+  double* Tf = nullptr;   // kY x kY  compact-WY factors of the three sample QRs
+  double* Us = nullptr;   // kY x kY  left singular vectors of R_Y
+  double* Vs = nullptr;   // kY x kY
+  double* d = nullptr;    // kY
+  double* C = nullptr;    // kY x kY  small products
+  double* C2 = nullptr;   // kY x kY
+  double* tau = nullptr;  // kY
+  void* svd = nullptr;
+  size_t svd_bytes = 0;
+};
+
 struct Bufs {
   int* status = nullptr;
   double* G = nullptr;      // m x b
@@ -103,9 +131,11 @@ struct Bufs {
   unsigned long long* word = nullptr;  // max|T22|
   void* bwork = nullptr;
   size_t bwork_bytes = 0;
+  Boost boost;  // Alg. 2 only
 };
 
-bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B) {
+// p < 0: Alg. 3; p >= 0: Alg. 2 with oversampling p.
+bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B, int64_t p = -1) {
   const int64_t mx = std::max(m, n);
   const int64_t kb = std::min(b, n);
   const int64_t s = ceil_div(n, b);
@@ -140,8 +170,19 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B) {
     k.tmp = ar.take<double>((size_t)mx * kb);
     k.split = ar.take<double>(B->split_elems);
   }
+  const int64_t pw = p > 0 ? std::min(p, std::max<int64_t>(n - kb, 0)) : 0;  // widest p_i
+  const int64_t ky = kb + pw;
   B->panel_bytes = panel_work_bytes(mx, (int)kb);
   if (B->panel_bytes == 0) return false;
+  if (p >= 0) {
+    // the sample QRs have widths b, p_i <= pw and b + p_i <= ky
+    for (int64_t w : {pw, ky}) {
+      if (w < 1) continue;
+      const size_t pb = panel_work_bytes(mx, (int)w);
+      if (pb == 0) return false;
+      B->panel_bytes = std::max(B->panel_bytes, pb);
+    }
+  }
   B->panel = ar.take<char>(B->panel_bytes);
   B->svd_bytes = (size_t)s * block_svd_work_bytes((int)kb);
   B->svd = ar.take<char>(B->svd_bytes);
@@ -155,7 +196,109 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B) {
     B->bwork_bytes = gemm_bf16_work_bytes(mx, kb);
     B->bwork = ar.take<char>(B->bwork_bytes);
   }
+  if (p >= 0) {
+    Boost& X = B->boost;
+    X.G = ar.take<double>((size_t)m * ky);
+    X.Z = ar.take<double>((size_t)m * ky);
+    X.Y = ar.take<double>((size_t)n * ky);
+    X.X = ar.take<double>((size_t)m * kb);
+    X.S = ar.take<double>((size_t)m * ky);
+    X.Zw = ar.take<double>((size_t)m * std::max<int64_t>(pw, 1));
+    X.Qy = ar.take<double>((size_t)n * ky);
+    X.WY = ar.take<double>((size_t)n * ky);
+    X.Wn = ar.take<double>((size_t)n * std::max<int64_t>(pw, 1));
+    X.Ry = ar.take<double>((size_t)ky * ky);
+    X.Tf = ar.take<double>((size_t)ky * ky);
+    X.Us = ar.take<double>((size_t)ky * ky);
+    X.Vs = ar.take<double>((size_t)ky * ky);
+    X.d = ar.take<double>((size_t)ky);
+    X.C = ar.take<double>((size_t)ky * ky);
+    X.C2 = ar.take<double>((size_t)ky * ky);
+    X.tau = ar.take<double>((size_t)ky);
+    X.svd_bytes = block_svd_work_bytes((int)ky);
+    X.svd = ar.take<char>(X.svd_bytes);
+  }
   return true;
+}
+
+// Q(:, 0:k) of the Householder QR (W unit lower trapezoidal M x k, Tf k x k):
+// (I - W Tf W^T)(:, 0:k) = [I; 0] - W (Tf W(0:k, :)^T).
+int thin_q(hipStream_t st, int64_t M, int64_t k, const double* W, int64_t ldw, const double* Tf,
+           int64_t ldt, double* Q, int64_t ldq, double* C) {
+  RRF_TRY(dgemm(st, false, true, k, k, k, 1.0, Tf, ldt, W, ldw, 0.0, C, k, nullptr, 0));
+  RRF_TRY(set_identity(st, M, k, Q, ldq));
+  return dgemm(st, false, false, M, k, k, -1.0, W, ldw, C, k, 1.0, Q, ldq, nullptr, 0);
+}
+
+// The sample and V_i of step i (0-based) of Alg. 2, for the trailing block
+// T22 (Mi x Ni) with b + pi samples: Y (Sec. 4.3: at the first step b + pi
+// fresh samples through q power steps; later b fresh ones through q - 1
+// power steps and one more product, projected off W_l = orth(T22 W_next),
+// orthonormalised and sampled together with W_l), then W_Y(:, 0:k) from the
+// tall-thin SVD of Y (Householder QR, SVD of R_Y, Q_Y U_R), the Householder
+// QR of W_Y(:, 0:b) into (Wv, Tv), and W_next = (V_i^T W_Y(:, b:k))(b:, :)
+// for the next step (its rows are the next trailing block's columns).
+int boosted_sample(hipStream_t st, int64_t i, int64_t Mi, int64_t Ni, int64_t b, int64_t pi,
+                   int q, uint64_t seed, const double* T22, int64_t ldt, const Bufs& B,
+                   double* Wv, int64_t ldwv, double* Tv, int64_t ldtv, size_t SE) {
+  const Boost& X = B.boost;
+  const int64_t k = b + pi;
+  double* Y = X.Y;  // Ni x k, ld Ni
+  if (i == 0) {
+    RRF_TRY(gaussian(st, seed, 1, Mi, k, X.G, Mi));
+    RRF_TRY(dgemm(st, true, false, Ni, k, Mi, 1.0, T22, ldt, X.G, Mi, 0.0, Y, Ni, B.split, SE));
+    for (int it = 0; it < q; ++it) {
+      RRF_TRY(dgemm(st, false, false, Mi, k, Ni, 1.0, T22, ldt, Y, Ni, 0.0, X.Z, Mi, B.split, SE));
+      RRF_TRY(dgemm(st, true, false, Ni, k, Mi, 1.0, T22, ldt, X.Z, Mi, 0.0, Y, Ni, B.split, SE));
+    }
+  } else {
+    RRF_TRY(gaussian(st, seed, (uint64_t)(i + 1), Mi, b, X.G, Mi));
+    if (q >= 1) {
+      RRF_TRY(dgemm(st, true, false, Ni, b, Mi, 1.0, T22, ldt, X.G, Mi, 0.0, Y, Ni, B.split, SE));
+      for (int it = 0; it + 1 < q; ++it) {
+        RRF_TRY(dgemm(st, false, false, Mi, b, Ni, 1.0, T22, ldt, Y, Ni, 0.0, X.Z, Mi, B.split,
+                      SE));
+        RRF_TRY(dgemm(st, true, false, Ni, b, Mi, 1.0, T22, ldt, X.Z, Mi, 0.0, Y, Ni, B.split,
+                      SE));
+      }
+      RRF_TRY(dgemm(st, false, false, Mi, b, Ni, 1.0, T22, ldt, Y, Ni, 0.0, X.X, Mi, B.split, SE));
+    } else {
+      RRF_TRY(copy_matrix(st, Mi, b, X.G, Mi, X.X, Mi));
+    }
+    double* Wl = X.S + b * Mi;  // S = [Q_X(:, 0:b), W_l], ld Mi
+    if (pi > 0) {
+      // W_l = orth(T22 W_next); X -= W_l (W_l^T X)
+      RRF_TRY(dgemm(st, false, false, Mi, pi, Ni, 1.0, T22, ldt, X.Wn, Ni, 0.0, X.Zw, Mi, B.split,
+                    SE));
+      RRF_TRY(householder_panel(st, Mi, (int)pi, X.Zw, Mi, X.Zw, Mi, nullptr, 0, X.Tf, pi, X.tau,
+                                nullptr, 0, B.panel, B.panel_bytes, B.status));
+      RRF_TRY(thin_q(st, Mi, pi, X.Zw, Mi, X.Tf, pi, Wl, Mi, X.C));
+      RRF_TRY(dgemm(st, true, false, pi, b, Mi, 1.0, Wl, Mi, X.X, Mi, 0.0, X.C, pi, B.split, SE));
+      RRF_TRY(dgemm(st, false, false, Mi, b, pi, -1.0, Wl, Mi, X.C, pi, 1.0, X.X, Mi, nullptr, 0));
+    }
+    RRF_TRY(householder_panel(st, Mi, (int)b, X.X, Mi, X.X, Mi, nullptr, 0, X.Tf, b, X.tau,
+                              nullptr, 0, B.panel, B.panel_bytes, B.status));
+    RRF_TRY(thin_q(st, Mi, b, X.X, Mi, X.Tf, b, X.S, Mi, X.C));
+    RRF_TRY(dgemm(st, true, false, Ni, k, Mi, 1.0, T22, ldt, X.S, Mi, 0.0, Y, Ni, B.split, SE));
+  }
+  // W_Y(:, 0:k) = Q_Y(:, 0:k) U_R with Y = Q_Y R_Y and R_Y = U_R D V_R^T
+  RRF_TRY(householder_panel(st, Ni, (int)k, Y, Ni, Y, Ni, X.Ry, k, X.Tf, k, X.tau, nullptr, 0,
+                            B.panel, B.panel_bytes, B.status));
+  RRF_TRY(block_svd(st, (int)k, X.Ry, k, X.Us, X.d, X.Vs, X.svd, X.svd_bytes, B.status));
+  RRF_TRY(thin_q(st, Ni, k, Y, Ni, X.Tf, k, X.Qy, Ni, X.C));
+  RRF_TRY(dgemm(st, false, false, Ni, k, k, 1.0, X.Qy, Ni, X.Us, k, 0.0, X.WY, Ni, nullptr, 0));
+  // [V_i, ~] = HQR_full(W_Y(:, 0:b))
+  RRF_TRY(householder_panel(st, Ni, (int)b, X.WY, Ni, Wv, ldwv, nullptr, 0, Tv, ldtv, X.tau,
+                            nullptr, 0, B.panel, B.panel_bytes, B.status));
+  if (pi > 0) {
+    // W_next = (W_Y2 - Wv Tv^T (Wv^T W_Y2))(b:, :), W_Y2 = W_Y(:, b:k)
+    double* WY2 = X.WY + b * Ni;
+    RRF_TRY(dgemm(st, true, false, b, pi, Ni, 1.0, Wv, ldwv, WY2, Ni, 0.0, X.C, b, B.split, SE));
+    RRF_TRY(dgemm(st, true, false, b, pi, b, 1.0, Tv, ldtv, X.C, b, 0.0, X.C2, b, nullptr, 0));
+    RRF_TRY(dgemm(st, false, false, Ni, pi, b, -1.0, Wv, ldwv, X.C2, b, 1.0, WY2, Ni, nullptr, 0));
+    RRF_TRY(copy_matrix(st, Ni - b, pi, WY2 + b, Ni, X.Wn, Ni - b));
+  }
+  return RRF_OK;
 }
 
 // X(:, 0:k) <- X(:, 0:k) S  (rows x k times k x k) through `tmp`.
@@ -256,23 +399,24 @@ bool randutv_supported(int64_t m, int64_t n, int64_t b) {
   return panel_work_bytes(std::max(m, n), (int)std::min(b, n)) > 0;
 }
 
-size_t randutv_workspace(int64_t m, int64_t n, int64_t b, int precision) {
+size_t randutv_workspace(int64_t m, int64_t n, int64_t b, int precision, int64_t p) {
   Arena ar;
   ar.counting = true;
   Bufs B;
-  if (!plan(ar, m, n, b, precision, &B)) return 0;
+  if (!plan(ar, m, n, b, precision, &B, p)) return 0;
   return ar.used;
 }
 
 int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                 int q, uint64_t seed, double* U, double* T, double* V, void* ws,
-                size_t ws_bytes, bool check_input, int precision, int* status_out) {
+                size_t ws_bytes, bool check_input, int precision, int* status_out, int64_t p) {
   Arena ar;
   ar.base = reinterpret_cast<char*>(ws);
   ar.cap = ws_bytes;
   Bufs B;
-  if (!plan(ar, m, n, b, precision, &B) || ar.used > ws_bytes)
+  if (!plan(ar, m, n, b, precision, &B, p) || ar.used > ws_bytes)
     return set_error(RRF_E_NOMEM, "randutv: workspace too small");
+  const bool boosted = p >= 0;
   *status_out = 0;
   DeviceContext* ctx = nullptr;
   RRF_TRY(device_context(&ctx));
@@ -325,6 +469,10 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
       ku[i] = kb;
       kv[i] = kb;
       // ---- sketch and V_i
+      if (boosted) {
+        const int64_t pi = std::min<int64_t>(p, Ni - kb);
+        RRF_TRY(boosted_sample(st, i, Mi, Ni, kb, pi, q, seed, T22, ldt, B, Wv, n, Tv, bb, SE));
+      } else {
       RRF_TRY(gaussian(st, seed, (uint64_t)(i + 1), Mi, kb, B.G, Mi));
       if (mixed_sketch) {
         RRF_TRY(sketch_mixed(st, Mi, Ni, kb, q, T22, ldt, B, B.Y));
@@ -340,6 +488,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
       }
       RRF_TRY(householder_panel(st, Ni, (int)kb, B.Y, Ni, Wv, n, nullptr, 0, Tv, bb, B.tau,
                                 nullptr, 0, B.panel, B.panel_bytes, B.status));
+      }
       RRF_TRY(dgemm(st, false, true, Ni, kb, kb, 1.0, Wv, n, Tv, bb, 0.0, Wr, n, nullptr, 0));
       // X = T(:, J2uJ3) W_v; columns J2 of T V_i
       RRF_TRY(upd(st, false, false, m, kb, Ni, 1.0, Tc, ldt, Wv, n, 0.0, X, m, B.split, SE));

@@ -138,6 +138,24 @@ def test_x3_mode_is_randutv_only(lib):
     assert lib.rrf_randutv_batched_workspace_size(1, m, m, 4, _lib.RRF_PREC_BF16_X3) == 0
 
 
+def test_boosted_argument_errors(lib):
+    f = lib.rrf_randutv_boosted
+    assert f(8, 8, DUMMY, 8, 4, 1, -1, 1, NULL, DUMMY, NULL) == -7
+    assert f(8, 8, DUMMY, 8, 4, -1, 2, 1, NULL, DUMMY, NULL) == -6
+    assert f(8, 8, DUMMY, 8, 4, 1, 2, 1, NULL, NULL, NULL) == -10
+    assert f(8, 9, DUMMY, 8, 4, 1, 2, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP  # m < n
+    assert f(400, 300, DUMMY, 400, 200, 1, 100, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP
+    o = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(o))
+    o.precision = _lib.RRF_PREC_BF16_SKETCH
+    assert lib.rrf_randutv_boosted_ex(8, 8, DUMMY, 8, 4, 1, 2, 1, NULL, DUMMY, NULL,
+                                      C.byref(o)) == _lib.RRF_E_NOTSUP
+    ws = lib.rrf_randutv_boosted_workspace_size
+    assert ws(16384, 16384, 128, 2, 128) > lib.rrf_workspace_size(0, 16384, 16384, 128, 2, 0)
+    assert ws(100, 50, 16, 1, 300) > 0  # p is clipped to n - b
+    assert ws(1000, 500, 200, 1, 100) == 0 and ws(10, 20, 4, 1, 2) == 0 and ws(10, 8, 4, 1, -1) == 0
+
+
 def _arr(t, vals):
     return (t * len(vals))(*vals)
 
