@@ -125,6 +125,32 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
                    const rrf_opts* opts);
 
 /*
+ * randUTV halted early -- Sec. 4.1 (error of the rank-k approximation).
+ *
+ * Runs the steps of rrf_randutv_ex and, before each step (c0 = i b columns
+ * reduced), stops when c0 >= kmax or when e = ||T(c0:m, c0:n)||_F, which is
+ * ||A - A_k||_F of the rank-c0 approximation, is <= tol ||A||_F. e is formed
+ * directly from the trailing block (one pass over it; the paper's update
+ * e_i^2 = e_{i-1}^2 - ||T(I2, J2 u J3)||_F^2 loses its relative accuracy
+ * once e_i falls below sqrt(eps) ||A||_F). On return *k_out = k, the
+ * columns reduced; A = U T V^T holds with T = [T11 T12; 0 T22], T11 (k x k)
+ * upper triangular with diagonal, non-negative, descending b x b blocks,
+ * and T22 = T(k:m, k:n) the unreduced remainder (U, V the product of the
+ * steps taken). tol = 0 and kmax >= n give rrf_randutv_ex's result.
+ *
+ *  m, n, A, lda, b, q, seed : as for rrf_randutv            (args 1-7)
+ *  tol    : relative Frobenius tolerance, tol >= 0         (arg 8)
+ *  kmax   : cap on the columns reduced, kmax >= 0          (arg 9)
+ *  U, T, V: as for rrf_randutv                             (args 10-12)
+ *  k_out  : host int64 receiving k                         (arg 13)
+ *  opts   : as for rrf_randutv_ex (any precision mode); the call always
+ *           synchronizes (the stopping test reads each step's norm)
+ */
+int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                        int32_t q, uint64_t seed, double tol, int64_t kmax, double* U, double* T,
+                        double* V, int64_t* k_out, const rrf_opts* opts);
+
+/*
  * randUTV_boosted -- Alg. 2 (Sec. 4.2-4.3): randUTV with oversampling.
  *
  * Each step samples the trailing block with b + p_i columns,

@@ -9,12 +9,12 @@ library in ``paper_2106_13402_amd`` and never imports it.
 from .philox import gaussian, philox4x64_10
 from .hqr import apply_q, form_q, hqr
 from .small_svd import canonical_signs, small_svd
-from .randutv import randutv
+from .randutv import randutv, randutv_partial
 from .randutv_boosted import randutv_boosted
 from .powerurv import powerurv
 from . import metrics
 
 __all__ = [
     "gaussian", "philox4x64_10", "hqr", "apply_q", "form_q",
-    "small_svd", "canonical_signs", "randutv", "randutv_boosted", "powerurv", "metrics",
+    "small_svd", "canonical_signs", "randutv", "randutv_partial", "randutv_boosted", "powerurv", "metrics",
 ]

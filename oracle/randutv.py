@@ -40,12 +40,14 @@ def randutv(
     want_v: bool = True,
     max_steps: Optional[int] = None,
     on_step: Optional[Callable[[int, np.ndarray], None]] = None,
+    stop_before: Optional[Callable[[int, np.ndarray], bool]] = None,
 ):
     """Compute ``A = U T V^T`` by Alg. 3.
 
     Returns ``(U, T, V)``; U (m x m) and V (n x n) are ``None`` when not
     requested. ``max_steps`` stops after that many loop iterations (used to
-    time a bounded sample); ``on_step(i, T)`` sees T after step i.
+    time a bounded sample); ``on_step(i, T)`` sees T after step i;
+    ``stop_before(i, T)`` returning True ends the loop before step i.
     """
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
@@ -59,6 +61,8 @@ def randutv(
     s = math.ceil(n / b)
     for i in range(1, s + 1):
         if max_steps is not None and i > max_steps:
+            break
+        if stop_before is not None and stop_before(i, T):
             break
         # Index sets (0-based, half-open): I1 = [0,c0), I2 = [c0,r2), I3 = [r2,m)
         c0 = b * (i - 1)
@@ -117,3 +121,24 @@ def randutv(
             on_step(i, T)
     return U, T, V
 
+
+
+def randutv_partial(A: np.ndarray, b: int, q: int, seed: int, tol: float, kmax: int, *,
+                    want_u: bool = True, want_v: bool = True):
+    """Alg. 3 halted early (Sec. 4.1, error of the rank-k approximation):
+    before step i (0-based, c0 = i b) the loop stops when c0 >= kmax or when
+    e_i = ||T(c0:, c0:)||_F <= tol ||A||_F. Returns ``(U, T, V, k)`` with
+    k = the columns already reduced (T(k:, k:) is the unreduced remainder
+    and A = U T V^T holds exactly as for the full factorization)."""
+    e0 = float(np.linalg.norm(A))
+    done = [0]
+
+    def stop_before(i, T):
+        c0 = b * (i - 1)
+        if c0 >= kmax or float(np.linalg.norm(T[c0:, c0:])) <= tol * e0:
+            return True
+        done[0] = i
+        return False
+
+    U, T, V = randutv(A, b, q, seed, want_u=want_u, want_v=want_v, stop_before=stop_before)
+    return U, T, V, min(b * done[0], A.shape[1])

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import RRFError
 
 __all__ = [
-    "RRFError", "randutv", "randutv_boosted", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
+    "RRFError", "randutv", "randutv_boosted", "randutv_partial", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
     "batched_workspace_size", "batched_block",
@@ -140,6 +140,36 @@ def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool =
     T, U and V (RRF_PREC_BF16_X3; results accurate to about 1e-5)."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
                    inplace, precision)
+
+
+def randutv_partial(A, b: int, q: int, seed: int, tol: float, kmax: int | None = None, *,
+                    want_u: bool = True, want_v: bool = True, precision: str = "fp64"):
+    """randUTV halted once ||T22||_F <= tol ||A||_F or kmax columns are
+    reduced (Sec. 4.1); returns (U, T, V, k) with T(k:, k:) unreduced."""
+    _require(A, "A")
+    m, n = int(A.shape[0]), int(A.shape[1])
+    dev = A.device
+    U = empty_colmajor(m, m, dev) if want_u else None
+    V = empty_colmajor(n, n, dev) if want_v else None
+    T = empty_colmajor(m, n, dev)
+    nbytes = workspace_size("randutv", m, n, b, q, precision)
+    if nbytes == 0:
+        raise RRFError(_lib.RRF_E_NOTSUP, "rrf_randutv_partial", "no workspace size")
+    ws = _workspace(dev, nbytes)
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.precision = PRECISIONS[precision]
+    opts.stream = _stream_ptr(dev)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = ws.numel()
+    k = C.c_int64(0)
+    st = lib.rrf_randutv_partial(m, n, A.data_ptr(), _ld(A), b, q, seed, float(tol),
+                                 n if kmax is None else int(kmax),
+                                 U.data_ptr() if U is not None else None, T.data_ptr(),
+                                 V.data_ptr() if V is not None else None, C.byref(k),
+                                 C.byref(opts))
+    _check(st, "rrf_randutv_partial")
+    return U, T, V, int(k.value)
 
 
 def randutv_boosted(A, b: int, q: int, p: int, seed: int, *, want_u: bool = True,

@@ -122,8 +122,8 @@ typedef bool (*SupportedFn)(int64_t, int64_t, int64_t);
 template <typename Run>
 int run_alg(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
             double* U, double* T, double* V, const rrf_opts* opts, Run run,
-            int64_t boost_p = -1) {
-  const int shift = boost_p >= 0 ? 1 : 0;
+            int64_t boost_p = -1, int ptr_shift = -1) {
+  const int shift = ptr_shift >= 0 ? ptr_shift : (boost_p >= 0 ? 1 : 0);
   RRF_TRY(check_args(m, n, A, lda, b, q, T, shift));
   rrf_opts o;
   rrf_opts_init(&o);
@@ -234,6 +234,27 @@ int rrf_randutv_boosted_ex(int64_t m, int64_t n, const double* A, int64_t lda, i
 int rrf_randutv_boosted(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                         int64_t p, uint64_t seed, double* U, double* T, double* V) {
   return rrf_randutv_boosted_ex(m, n, A, lda, b, q, p, seed, U, T, V, nullptr);
+}
+
+int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                        int32_t q, uint64_t seed, double tol, int64_t kmax, double* U, double* T,
+                        double* V, int64_t* k_out, const rrf_opts* opts) {
+  if (!(tol >= 0.0)) return set_error(-8, "tol must be >= 0"), -8;
+  if (kmax < 0) return set_error(-9, "kmax must be >= 0"), -9;
+  if (k_out == nullptr) return set_error(-13, "k_out is NULL"), -13;
+  *k_out = 0;
+  EarlyStop stop{tol, kmax, k_out};
+  rrf_opts o;
+  rrf_opts_init(&o);
+  if (opts) o = *opts;
+  o.async = 0;  // the stopping test reads each step's norm on the host
+  return run_alg(RRF_ALG_RANDUTV, m, n, A, lda, b, q, U, T, V, &o,
+                 [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
+                   int dummy = 0;
+                   return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
+                                      o.precision, &dummy, -1, &stop);
+                 },
+                 -1, 2);
 }
 
 int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,

@@ -7,13 +7,23 @@ namespace rrf {
 
 // Alg. 3. Status words (device ints) live at the start of `ws`: word 0
 // collects kernel failure bits, word 1 the input finiteness check.
+// Early stop of randUTV (Sec. 4.1): before each step the loop ends when the
+// reduced columns reach kmax or ||T22||_F <= tol ||A||_F (one host
+// synchronization per step); k_out receives the columns reduced.
+struct EarlyStop {
+  double tol;
+  int64_t kmax;
+  int64_t* k_out;
+};
+
 // p < 0 runs Alg. 3; p >= 0 runs Alg. 2 (randUTV_boosted) with oversampling p
-// (b + p <= 256, FP64 only).
+// (b + p <= 256, FP64 only). stop: early stop (null: the full factorization).
 bool randutv_supported(int64_t m, int64_t n, int64_t b);
 size_t randutv_workspace(int64_t m, int64_t n, int64_t b, int precision, int64_t p = -1);
 int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                 int q, uint64_t seed, double* U, double* T, double* V, void* ws, size_t ws_bytes,
-                bool check_input, int precision, int* status_out, int64_t p = -1);
+                bool check_input, int precision, int* status_out, int64_t p = -1,
+                const EarlyStop* stop = nullptr);
 
 // Alg. 1, same status layout.
 bool powerurv_supported(int64_t m, int64_t n, int64_t b);

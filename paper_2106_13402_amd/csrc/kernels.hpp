@@ -72,6 +72,11 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
 // out = bf16(X s) (rows x cols, ld ldo, rows [rows, ldo) zero) and, when
 // outT is non-null, its transpose (ld ldot, rows [cols, ldot) zero); s is the
 // power of two putting max|X| (from *word) in [0.5, 1), or 1 when word is null.
+// *out (device) = ||X||_F, summing the squares of X s with s the power of two
+// of the max in *word (a bound on |X|); parts: scratch of max_parts doubles,
+// at least ceil(rows / 256). Deterministic.
+int frob_norm(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+              const unsigned long long* word, double* parts, int max_parts, double* out);
 // X *= s (inverse: X /= s), s the power of two putting max|X| from *word in
 // [0.5, 1) (1 when the max is 0); exact.
 int scale_pow2(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld,

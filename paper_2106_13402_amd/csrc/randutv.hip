@@ -132,7 +132,13 @@ struct Bufs {
   void* bwork = nullptr;
   size_t bwork_bytes = 0;
   Boost boost;  // Alg. 2 only
+  // early stop: ||T22||_F of each step
+  unsigned long long* nword = nullptr;  // max|A|
+  double* nparts = nullptr;             // kNormParts partial sums
+  double* nout = nullptr;
 };
+
+constexpr int kNormParts = 1024;
 
 // p < 0: Alg. 3; p >= 0: Alg. 2 with oversampling p.
 bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B, int64_t p = -1) {
@@ -141,6 +147,9 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B, in
   const int64_t s = ceil_div(n, b);
   const int64_t gk = kGroup * kb;
   B->status = ar.take<int>(64);
+  B->nword = ar.take<unsigned long long>(4);
+  B->nparts = ar.take<double>(kNormParts);
+  B->nout = ar.take<double>(4);
   B->G = ar.take<double>((size_t)m * kb);
   B->Z = ar.take<double>((size_t)m * kb);
   B->Y = ar.take<double>((size_t)n * kb);
@@ -409,7 +418,10 @@ size_t randutv_workspace(int64_t m, int64_t n, int64_t b, int precision, int64_t
 
 int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                 int q, uint64_t seed, double* U, double* T, double* V, void* ws,
-                size_t ws_bytes, bool check_input, int precision, int* status_out, int64_t p) {
+                size_t ws_bytes, bool check_input, int precision, int* status_out, int64_t p,
+                const EarlyStop* stop) {
+  if (stop && ceil_div(m, 256) > kNormParts)
+    return set_error(RRF_E_NOTSUP, "randutv: early stop needs m <= 262144");
   Arena ar;
   ar.base = reinterpret_cast<char*>(ws);
   ar.cap = ws_bytes;
@@ -447,12 +459,27 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   const int64_t s = ceil_div(n, b);
   const int64_t bb = std::min(b, n);  // block slot size of R, Us, Vs, d, TU, TV
   std::vector<int64_t> ku(s, 0), kv(s, 0);  // reflector columns per step
+  int64_t s_done = 0;                        // steps carried out
+  double e0 = 0.0;
+  if (stop) RRF_TRY(maxabs(st, m, n, T, ldt, B.nword));
   for (int64_t i = 0; i < s; ++i) {
     const int64_t c0 = i * b;
     const int64_t c2 = std::min(c0 + b, n);
     const int64_t r2 = std::min(c0 + b, m);
     const int64_t Mi = m - c0, Ni = n - c0;
     double* T22 = T + c0 + c0 * ldt;
+    if (stop) {
+      // Sec. 4.1: ||A - A_k||_F = ||T22||_F after c0 = k columns; stop once it
+      // is within the tolerance, or at the rank cap
+      if (c0 >= stop->kmax) break;
+      RRF_TRY(frob_norm(st, Mi, Ni, T22, ldt, B.nword, B.nparts, kNormParts, B.nout));
+      double e = 0.0;
+      RRF_CHECK_HIP(hipMemcpyAsync(&e, B.nout, sizeof e, hipMemcpyDeviceToHost, st));
+      RRF_CHECK_HIP(hipStreamSynchronize(st));
+      if (i == 0) e0 = e;
+      if (e <= stop->tol * e0) break;
+    }
+    s_done = i + 1;
     double* Tc = T + c0 * ldt;  // T(:, J2uJ3)
     double* Ri = B.R + i * bb * bb;  // ld bb
     double* Tu = B.TU + i * bb * bb;  // ld bb
@@ -528,7 +555,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   RRF_CHECK_HIP(hipEventRecord(ev[kEvLoop], st));
   // ---- U and V from the kept reflectors, on the side streams, while the
   // small SVDs run
-  const int64_t k_last = n - (s - 1) * b;
+  const int64_t k_last = s_done == s ? n - (s - 1) * b : bb;
   hipStream_t su = ctx->side[0], sv = ctx->side[1];
   trace_mark_stream(su);
   trace_mark_stream(sv);
@@ -540,12 +567,13 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
     RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvLoop], 0));
     RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE, upd));
   }
-  RRF_TRY(block_svd_batched(st, (int)s, (int)bb, (int)k_last, B.R, bb, bb * bb, B.Us, B.d, bb,
-                            B.Vs, B.svd, B.svd_bytes, B.status));
+  if (s_done > 0)
+    RRF_TRY(block_svd_batched(st, (int)s_done, (int)bb, (int)k_last, B.R, bb, bb * bb, B.Us, B.d,
+                              bb, B.Vs, B.svd, B.svd_bytes, B.status));
   RRF_CHECK_HIP(hipEventRecord(ev[kEvSvd], st));
   if (U) RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvSvd], 0));
   if (V) RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvSvd], 0));
-  for (int64_t i = 0; i < s; ++i) {
+  for (int64_t i = 0; i < s_done; ++i) {
     const int64_t c0 = i * b;
     const int64_t kb = std::min(b, n - c0);
     const int64_t c2 = c0 + kb;
@@ -578,6 +606,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
     RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvV], 0));
   }
   if (x3) RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, true));
+  if (stop && stop->k_out) *stop->k_out = std::min(s_done * b, n);
   *status_out = 0;
   return RRF_OK;
 }

@@ -113,6 +113,48 @@ __global__ __launch_bounds__(256) void scale_pow2_kernel(int64_t rows, int64_t c
   for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) X[i + j * ld] *= s;
 }
 
+// --- ||X||_F for the early stop of randUTV ---------------------------------
+
+// parts[blockIdx] = sum of (s x)^2 over rows [256 bx, 256 bx + 256) and the
+// columns bx.y, bx.y + gridDim.y, ...; s = pow2_scale of the max in `word`
+// (a bound on |X|, so no square overflows). Fixed-order sums throughout.
+__global__ __launch_bounds__(256) void sumsq_kernel(int64_t rows, int64_t cols,
+                                                    const double* __restrict__ X, int64_t ld,
+                                                    const unsigned long long* word,
+                                                    double* __restrict__ parts) {
+  __shared__ double red[4];
+  const double s = pow2_scale(__longlong_as_double((long long)*word));
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double acc = 0.0;
+  if (i < rows)
+    for (int64_t j = blockIdx.y; j < cols; j += gridDim.y) {
+      const double v = X[i + j * ld] * s;
+      acc = fma(v, v, acc);
+    }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    parts[blockIdx.x + (int64_t)blockIdx.y * gridDim.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// out = sqrt(sum of parts) / s.
+__global__ __launch_bounds__(256) void sumsq_finish_kernel(const double* __restrict__ parts,
+                                                           int count,
+                                                           const unsigned long long* word,
+                                                           double* out) {
+  __shared__ double red[4];
+  const double s = pow2_scale(__longlong_as_double((long long)*word));
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < count; k += 256) acc += parts[k];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = sqrt((red[0] + red[1]) + (red[2] + red[3])) / s;
+}
+
 // --- binary64 -> bfloat16, optionally scaled and transposed ----------------
 
 // out (rows x cols, ld ldo) = bf16(X * s), outT (cols x rows, ld ldot) its
@@ -475,6 +517,22 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
   dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 32));
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
   hipLaunchKernelGGL(maxabs_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
+int frob_norm(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
+              const unsigned long long* word, double* parts, int max_parts, double* out) {
+  if (rows <= 0 || cols <= 0) return fill_matrix(st, 1, 1, 0.0, out, 1);
+  const int64_t gx = ceil_div(rows, 256);
+  if (gx > max_parts) return set_error(RRF_E_NOTSUP, "frob_norm: too many rows");
+  const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(cols, max_parts / gx));
+  int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
+  hipLaunchKernelGGL(sumsq_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, rows, cols,
+                     X, ld, word, parts);
+  hipLaunchKernelGGL(sumsq_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)parts,
+                     (int)(gx * gy), word, out);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;

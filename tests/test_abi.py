@@ -156,6 +156,17 @@ def test_boosted_argument_errors(lib):
     assert ws(1000, 500, 200, 1, 100) == 0 and ws(10, 20, 4, 1, 2) == 0 and ws(10, 8, 4, 1, -1) == 0
 
 
+def test_partial_argument_errors(lib):
+    f = lib.rrf_randutv_partial
+    k = C.c_int64(7)
+    assert f(8, 8, DUMMY, 8, 4, 1, 1, -1.0, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == -8
+    assert f(8, 8, DUMMY, 8, 4, 1, 1, float("nan"), 8, NULL, DUMMY, NULL, C.byref(k), NULL) == -8
+    assert f(8, 8, DUMMY, 8, 4, 1, 1, 1e-3, -1, NULL, DUMMY, NULL, C.byref(k), NULL) == -9
+    assert f(8, 8, DUMMY, 8, 4, 1, 1, 1e-3, 8, NULL, DUMMY, NULL, None, NULL) == -13
+    assert f(8, 8, DUMMY, 8, 4, 1, 1, 1e-3, 8, NULL, NULL, NULL, C.byref(k), NULL) == -11
+    assert f(8, 8, DUMMY, 7, 4, 1, 1, 1e-3, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == -4
+
+
 def _arr(t, vals):
     return (t * len(vals))(*vals)
 
