@@ -125,6 +125,30 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
                    const rrf_opts* opts);
 
 /*
+ * The randomized SVD (RSVD) -- Sec. 3.3 (its relation to powerURV).
+ *
+ * Y = (A A^T)^q A G with G the n x l Gaussian of stream 0 (the first l columns
+ * of powerURV's G for the same seed), Q from a Householder QR of Y, the thin
+ * SVD Q^T A = W diag(S) V^T, U = Q W: A ~ U diag(S) V^T with the error of the
+ * rank-l projection Q Q^T A. Any m, n (no transposition needed). FP64.
+ *
+ *  m, n   : rows and columns of A                           (args 1, 2)
+ *  A, lda : input, lda >= m                                 (args 3, 4)
+ *  l      : rank, 1 <= l <= min(m, n), l <= 256             (arg 5)
+ *  q      : power steps, q >= 0                             (arg 6)
+ *  seed   : generator key                                   (arg 7)
+ *  U      : m x l output (ld m) or NULL                     (arg 8)
+ *  S      : l singular values, descending, non-negative     (arg 9)
+ *  V      : n x l output (ld n) or NULL                     (arg 10)
+ *  opts   : stream, workspace (rrf_rsvd_workspace_size bytes), async,
+ *           check_finite; precision must be RRF_PREC_FP64
+ * All pointers are device memory; l > 256 returns RRF_E_NOTSUP.
+ */
+int rrf_rsvd(int64_t m, int64_t n, const double* A, int64_t lda, int64_t l, int32_t q,
+             uint64_t seed, double* U, double* S, double* V, const rrf_opts* opts);
+size_t rrf_rsvd_workspace_size(int64_t m, int64_t n, int64_t l, int32_t q);
+
+/*
  * randUTV halted early -- Sec. 4.1 (error of the rank-k approximation).
  *
  * Runs the steps of rrf_randutv_ex and, before each step (c0 = i b columns

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import RRFError
 
 __all__ = [
-    "RRFError", "randutv", "randutv_boosted", "randutv_partial", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
+    "RRFError", "randutv", "randutv_boosted", "randutv_partial", "rsvd", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
     "batched_workspace_size", "batched_block",
@@ -140,6 +140,33 @@ def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool =
     T, U and V (RRF_PREC_BF16_X3; results accurate to about 1e-5)."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
                    inplace, precision)
+
+
+def rsvd(A, l: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
+         check_finite: bool = False):
+    """Randomized SVD (Sec. 3.3): returns (U, S, V), U m x l, S (l,), V n x l
+    (U/V None if not wanted), A ~ U diag(S) V^T."""
+    torch = _torch()
+    _require(A, "A")
+    m, n = int(A.shape[0]), int(A.shape[1])
+    dev = A.device
+    U = empty_colmajor(m, l, dev) if want_u else None
+    V = empty_colmajor(n, l, dev) if want_v else None
+    S = torch.empty(l, dtype=torch.float64, device=dev)
+    nbytes = int(lib.rrf_rsvd_workspace_size(m, n, l, q))
+    if nbytes == 0:
+        raise RRFError(_lib.RRF_E_NOTSUP, "rrf_rsvd", "no workspace size for these arguments")
+    ws = _workspace(dev, nbytes)
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.stream = _stream_ptr(dev)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = ws.numel()
+    opts.check_finite = 1 if check_finite else 0
+    _check(lib.rrf_rsvd(m, n, A.data_ptr(), _ld(A), l, q, seed,
+                        U.data_ptr() if U is not None else None, S.data_ptr(),
+                        V.data_ptr() if V is not None else None, C.byref(opts)), "rrf_rsvd")
+    return U, S, V
 
 
 def randutv_partial(A, b: int, q: int, seed: int, tol: float, kmax: int | None = None, *,

@@ -257,6 +257,46 @@ int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int6
                  -1, 2);
 }
 
+size_t rrf_rsvd_workspace_size(int64_t m, int64_t n, int64_t l, int32_t q) {
+  if (m < 1 || n < 1 || q < 0 || !rsvd_supported(m, n, l)) return 0;
+  return rsvd_workspace(m, n, l);
+}
+
+int rrf_rsvd(int64_t m, int64_t n, const double* A, int64_t lda, int64_t l, int32_t q,
+             uint64_t seed, double* U, double* S, double* V, const rrf_opts* opts) {
+  if (m < 1) return set_error(-1, "m must be >= 1"), -1;
+  if (n < 1) return set_error(-2, "n must be >= 1"), -2;
+  if (A == nullptr) return set_error(-3, "A is NULL"), -3;
+  if (lda < m) return set_error(-4, "lda must be >= m"), -4;
+  if (l < 1 || l > std::min(m, n)) return set_error(-5, "l must be in [1, min(m, n)]"), -5;
+  if (q < 0) return set_error(-6, "q must be >= 0"), -6;
+  if (S == nullptr) return set_error(-9, "S is NULL"), -9;
+  if (!rsvd_supported(m, n, l)) return set_error(RRF_E_NOTSUP, "rsvd: needs l <= 256");
+  rrf_opts o;
+  rrf_opts_init(&o);
+  if (opts) o = *opts;
+  if (o.precision != RRF_PREC_FP64) return set_error(RRF_E_NOTSUP, "rsvd: only RRF_PREC_FP64");
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  RRF_TRY(check_device_ptr(A, 3));
+  RRF_TRY(check_device_ptr(U, 8));
+  RRF_TRY(check_device_ptr(S, 9));
+  RRF_TRY(check_device_ptr(V, 10));
+  const size_t need = rsvd_workspace(m, n, l);
+  void* ws = o.workspace;
+  size_t ws_bytes = o.workspace_bytes;
+  if (ws == nullptr) {
+    RRF_TRY(cached_workspace(dev, need, &ws));
+    ws_bytes = need;
+  } else if (ws_bytes < need) {
+    return set_error(RRF_E_NOMEM, "workspace smaller than rrf_rsvd_workspace_size()");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
+  RRF_TRY(rsvd_run(st, m, n, A, lda, l, q, seed, U, m, S, V, n, ws, ws_bytes, o.check_finite != 0));
+  if (o.async) return RRF_OK;
+  return finish(st, reinterpret_cast<const int*>(ws));
+}
+
 int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                 uint64_t seed, double* U, double* T, double* V) {
   return rrf_randutv_ex(m, n, A, lda, b, q, seed, U, T, V, nullptr);

@@ -32,6 +32,15 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
                  int q, uint64_t seed, double* U, double* T, double* V, void* ws, size_t ws_bytes,
                  bool check_input, int precision);
 
+// The randomized SVD (Sec. 3.3): U (m x l, ld ldu) and V (n x l, ld ldv) may
+// be null; S receives the l singular values (descending). Status layout as
+// for Alg. 3.
+bool rsvd_supported(int64_t m, int64_t n, int64_t l);
+size_t rsvd_workspace(int64_t m, int64_t n, int64_t l);
+int rsvd_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t l, int q,
+             uint64_t seed, double* U, int64_t ldu, double* S, double* V, int64_t ldv, void* ws,
+             size_t ws_bytes, bool check_input);
+
 // Batched Alg. 3 (one block size b for the whole call; matrix j keyed by
 // seeds[j]); outputs packed column-major (ld m, m, n). The status words of
 // `ws` (word 0: device-side failure bits) are not cleared here.

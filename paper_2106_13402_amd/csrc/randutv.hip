@@ -230,15 +230,6 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B, in
   return true;
 }
 
-// Q(:, 0:k) of the Householder QR (W unit lower trapezoidal M x k, Tf k x k):
-// (I - W Tf W^T)(:, 0:k) = [I; 0] - W (Tf W(0:k, :)^T).
-int thin_q(hipStream_t st, int64_t M, int64_t k, const double* W, int64_t ldw, const double* Tf,
-           int64_t ldt, double* Q, int64_t ldq, double* C) {
-  RRF_TRY(dgemm(st, false, true, k, k, k, 1.0, Tf, ldt, W, ldw, 0.0, C, k, nullptr, 0));
-  RRF_TRY(set_identity(st, M, k, Q, ldq));
-  return dgemm(st, false, false, M, k, k, -1.0, W, ldw, C, k, 1.0, Q, ldq, nullptr, 0);
-}
-
 // The sample and V_i of step i (0-based) of Alg. 2, for the trailing block
 // T22 (Mi x Ni) with b + pi samples: Y (Sec. 4.3: at the first step b + pi
 // fresh samples through q power steps; later b fresh ones through q - 1

@@ -89,6 +89,13 @@ int set_identity(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t 
   return RRF_OK;
 }
 
+int thin_q(hipStream_t st, int64_t M, int64_t k, const double* W, int64_t ldw, const double* Tf,
+           int64_t ldt, double* Q, int64_t ldq, double* C) {
+  RRF_TRY(dgemm(st, false, true, k, k, k, 1.0, Tf, ldt, W, ldw, 0.0, C, k, nullptr, 0));
+  RRF_TRY(set_identity(st, M, k, Q, ldq));
+  return dgemm(st, false, false, M, k, k, -1.0, W, ldw, C, k, 1.0, Q, ldq, nullptr, 0);
+}
+
 int copy_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int64_t lds,
                 double* D, int64_t ldd) {
   if (rows <= 0 || cols <= 0) return RRF_OK;

@@ -167,6 +167,20 @@ def test_partial_argument_errors(lib):
     assert f(8, 8, DUMMY, 7, 4, 1, 1, 1e-3, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == -4
 
 
+def test_rsvd_argument_errors(lib):
+    f = lib.rrf_rsvd
+    assert f(0, 8, DUMMY, 8, 4, 1, 1, NULL, DUMMY, NULL, NULL) == -1
+    assert f(8, 8, DUMMY, 7, 4, 1, 1, NULL, DUMMY, NULL, NULL) == -4
+    assert f(8, 6, DUMMY, 8, 7, 1, 1, NULL, DUMMY, NULL, NULL) == -5
+    assert f(8, 6, DUMMY, 8, 0, 1, 1, NULL, DUMMY, NULL, NULL) == -5
+    assert f(8, 6, DUMMY, 8, 4, -1, 1, NULL, DUMMY, NULL, NULL) == -6
+    assert f(8, 6, DUMMY, 8, 4, 1, 1, NULL, NULL, NULL, NULL) == -9
+    assert f(600, 600, DUMMY, 600, 300, 1, 1, NULL, DUMMY, NULL, NULL) == _lib.RRF_E_NOTSUP
+    ws = lib.rrf_rsvd_workspace_size
+    assert ws(1000, 500, 64, 1) > 0 and ws(500, 1000, 64, 1) > 0
+    assert ws(100, 50, 60, 1) == 0 and ws(1000, 1000, 300, 1) == 0
+
+
 def _arr(t, vals):
     return (t * len(vals))(*vals)
 
