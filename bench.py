@@ -15,7 +15,9 @@ sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), the same with the
 split-bfloat16 three-pass updates (RRF_PREC_BF16_X3, "mixed_x3"; results
 accurate to about 1e-5, so the gate covers sigma_{k+1} >= 100 x that), the
 powerURV leg, the FP64 CPU oracle
-timed on a bounded sample of the same workload, ("gap") the 32768 x 8192
+timed on a bounded sample of the same workload, ("boosted", "partial",
+"rsvd") Alg. 2 with p = b, the early-stopped randUTV and the RSVD on the
+same matrix, ("gap") the 32768 x 8192
 sharp-gap workload in the three precision modes with e_k around k = 1000,
 and ("batched") the batched
 call on 4096 small matrices (n ~ U{64..512}, m ~ U{n..2n}, graded spectrum,
@@ -346,6 +348,61 @@ def gap_leg(args, dev):
     return leg
 
 
+def extra_legs(A, s, kgrid, b, q, args, dev, ek_basic):
+    """The rows built beyond the headline path, on the headline matrix:
+    randUTV_boosted (Alg. 2, p = b), randUTV halted at ||T22||_F <= 1e-2
+    ||A||_F (Sec. 4.1) and the RSVD at l = b (Sec. 3.3). One warm call and
+    one timed call each (the boosted run takes seconds)."""
+    import numpy as np
+    import torch
+
+    import paper_2106_13402_amd as rrf
+
+    n = A.shape[1]
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    sec, (U, T, V) = timed(lambda: rrf.randutv_boosted(A, b, q, b, args.seed))
+    acc = accuracy(A, U, T, V, s, kgrid) if not args.no_accuracy else None
+    leg = {"workload": f"randUTV_boosted n={n} b={b} p={b} q={q}", "value": sec, "unit": "s"}
+    if acc:
+        leg["accuracy"] = acc
+        if ek_basic:
+            leg["ek_over_basic"] = [e / r for e, r in zip(acc["e_k"], ek_basic)]
+    out["boosted"] = leg
+    log(f"boosted: {sec:.3f} s")
+    del U, T, V
+    torch.cuda.empty_cache()
+
+    tol = 1e-2
+    sec, (U, T, V, k) = timed(lambda: rrf.randutv_partial(A, b, q, args.seed, tol))
+    e = float(torch.linalg.matrix_norm(T[k:, k:])) / float(torch.linalg.matrix_norm(A))
+    out["partial"] = {"workload": f"randUTV n={n} b={b} q={q} halted at ||T22||_F <= {tol} ||A||_F",
+                      "value": sec, "unit": "s", "k": k, "rel_frobenius_remainder": e,
+                      "expected_k": int(np.ceil(400 * np.log(1 / tol ** 2) / b) * b)}
+    log(f"partial: {sec:.3f} s, k = {k}, ||T22||_F / ||A||_F = {e:.2e}")
+    del U, T, V
+    torch.cuda.empty_cache()
+
+    l = b
+    sec, (U, S, V) = timed(lambda: rrf.rsvd(A, l, q, args.seed))
+    err = _power_norm(lambda x: A @ x - U @ (S[:, None] * (V.t() @ x)),
+                      lambda y: A.t() @ y - V @ (S[:, None] * (U.t() @ y)), n, dev)
+    sv = np.asarray(s[:l])
+    out["rsvd"] = {"workload": f"RSVD n={n} l={l} q={q}", "value": sec, "unit": "s",
+                   "err_over_sigma_l1": err / float(s[l]),
+                   "sigma_rel_err_max": float(np.max(np.abs(S.cpu().numpy() - sv) / sv))}
+    log(f"rsvd: {sec * 1e3:.1f} ms, ||A - U S V^T|| / sigma_(l+1) = {err / float(s[l]):.3f}")
+    return out
+
+
 def auto_block(n: int, m: int = 0) -> int:
     """Block size the batched call picks for b = 0."""
     import paper_2106_13402_amd as rrf
@@ -479,6 +536,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-powerurv", action="store_true")
     ap.add_argument("--no-gap", action="store_true", help="skip the 32768 x 8192 gap workload")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the boosted, early-stop and RSVD legs")
     ap.add_argument("--batch", type=int, default=4096, help="matrices in the batched leg")
     ap.add_argument("--batch-q", type=int, default=1)
     args = ap.parse_args()
@@ -630,6 +689,9 @@ def main() -> int:
     if not args.no_mixed:
         out["mixed"] = mixed_leg("bf16_sketch")
         out["mixed_x3"] = mixed_leg("bf16_x3")
+    if not args.no_extra:
+        out.update(extra_legs(A, s, kgrid, b, q, args, dev,
+                              None if args.no_accuracy else out["accuracy"]["e_k"]))
     if not args.no_powerurv:
         out["powerurv"] = powerurv_leg(A, U, T, V, s, kgrid, b, q, args, dev,
                                        None if args.no_accuracy else out["accuracy"])
