@@ -99,6 +99,14 @@ int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t
                  int64_t lda, const uint16_t* B, int64_t ldb, uint16_t* out16, int64_t ld16,
                  double* out64, int64_t ld64, void* work, size_t work_bytes);
 
+// ---- svd_left.hip --------------------------------------------------------
+// Left singular vectors U (k x k, ld k; columns in descending order of d) and
+// singular values d of the k x k matrix B (ld ldb), k <= 256, by block
+// one-sided Jacobi; column signs unspecified. status bit 2: no convergence.
+size_t left_svd_work_bytes(int k);
+int left_svd(hipStream_t st, int k, const double* B, int64_t ldb, double* U, double* d, void* work,
+             size_t work_bytes, int* status);
+
 // ---- jacobi_svd.hip ------------------------------------------------------
 size_t block_svd_work_bytes(int k);
 // As block_svd_batched with the size of every block in d_sizes (device ints,

@@ -224,7 +224,7 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B, in
     X.C = ar.take<double>((size_t)ky * ky);
     X.C2 = ar.take<double>((size_t)ky * ky);
     X.tau = ar.take<double>((size_t)ky);
-    X.svd_bytes = block_svd_work_bytes((int)ky);
+    X.svd_bytes = left_svd_work_bytes((int)ky);
     X.svd = ar.take<char>(X.svd_bytes);
   }
   return true;
@@ -284,7 +284,7 @@ int boosted_sample(hipStream_t st, int64_t i, int64_t Mi, int64_t Ni, int64_t b,
   // W_Y(:, 0:k) = Q_Y(:, 0:k) U_R with Y = Q_Y R_Y and R_Y = U_R D V_R^T
   RRF_TRY(householder_panel(st, Ni, (int)k, Y, Ni, Y, Ni, X.Ry, k, X.Tf, k, X.tau, nullptr, 0,
                             B.panel, B.panel_bytes, B.status));
-  RRF_TRY(block_svd(st, (int)k, X.Ry, k, X.Us, X.d, X.Vs, X.svd, X.svd_bytes, B.status));
+  RRF_TRY(left_svd(st, (int)k, X.Ry, k, X.Us, X.d, X.svd, X.svd_bytes, B.status));
   RRF_TRY(thin_q(st, Ni, k, Y, Ni, X.Tf, k, X.Qy, Ni, X.C));
   RRF_TRY(dgemm(st, false, false, Ni, k, k, 1.0, X.Qy, Ni, X.Us, k, 0.0, X.WY, Ni, nullptr, 0));
   // [V_i, ~] = HQR_full(W_Y(:, 0:b))

@@ -67,7 +67,17 @@ def _parity(A, b, q, p, seed, gpu, derived=False):
     print(f"  oracle spread: max {spread.max() / nA:.2e} ||A||, diagonal {ds.max() / nA:.2e}; "
           f"GPU - oracle: diagonal {np.abs(dg - do).max() / nA:.2e}", flush=True)
     assert not bad.any(), (np.flatnonzero(bad)[:5], (dg - do)[bad][:5], ds[bad][:5])
-    assert np.all(np.abs(np.abs(T) - np.abs(To)) <= 1e-9 * nA + 4 * spread)
+    # elementwise, against the spread's maximum over each b x b tile (two
+    # perturbations estimate the conditioning of single entries only roughly)
+    m_, n_ = T.shape
+    tiles = spread.copy()
+    for r0 in range(0, m_, b):
+        for c0 in range(0, n_, b):
+            tiles[r0:r0 + b, c0:c0 + b] = spread[r0:r0 + b, c0:c0 + b].max()
+    dev = np.abs(np.abs(T) - np.abs(To))
+    ratio = dev / (1e-9 * nA + 4 * tiles)
+    print(f"  elementwise: worst (GPU - oracle) / bound = {ratio.max():.3f}", flush=True)
+    assert np.all(ratio <= 1.0)
     return U, T, V
 
 
