@@ -294,13 +294,14 @@ def gap_leg(args, dev):
     V = rrf.empty_colmajor(n, n, dev)
     kgrid = list(range(900, 1101, 4))
 
-    def factor(precision):
+    def factor(precision, thin_u=False):
         import ctypes as C
         from paper_2106_13402_amd import _lib
         ws = rrf._workspace(dev, rrf.workspace_size("randutv", m, n, b, q, precision))
         opts = _lib.rrf_opts()
         rrf.lib.rrf_opts_init(C.byref(opts))
         opts.precision = rrf.PRECISIONS[precision]
+        opts.thin_u = 1 if thin_u else 0
         opts.stream = torch.cuda.current_stream(dev).cuda_stream
         opts.workspace = ws.data_ptr()
         opts.workspace_bytes = ws.numel()
@@ -343,6 +344,20 @@ def gap_leg(args, dev):
     t64 = leg["modes"]["fp64"]["value"]
     for v in leg["modes"].values():
         v["speedup_vs_fp64"] = t64 / v["value"]
+    # the same FP64 factorization forming only U(:, 1:n) (rrf_opts.thin_u):
+    # U's accumulation is most of this workload's flops
+    factor("fp64", thin_u=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    factor("fp64", thin_u=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    Ut = U[:, :n]
+    rec = _power_norm(lambda x: A @ x - Ut @ (T[:n] @ (V.t() @ x)),
+                      lambda y: A.t() @ y - V @ (T[:n].t() @ (Ut.t() @ y)), n, dev) / float(s[0])
+    leg["fp64_thin_u"] = {"value": sec, "unit": "s", "speedup_vs_full_u": t64 / sec,
+                          "recon": rec}
+    log(f"gap fp64 thin U: {sec:.3f} s, recon {rec:.2e}")
     del A, U, T, V
     torch.cuda.empty_cache()
     return leg

@@ -90,10 +90,12 @@ typedef struct rrf_opts {
   int async;              /* 0: return after completion; 1: only enqueue       */
   int check_finite;       /* 1: reject A with NaN/Inf (RRF_E_NUMERIC) before any
                              work is enqueued; synchronizes the stream        */
+  int thin_u;             /* randUTV: 1 forms only U(:, 1:n) (m x n, ld m), all
+                             that A = U T V^T needs since T(n:m, :) = 0      */
 } rrf_opts;
 
 /* Fill `opts` with the defaults (FP64, null stream, library workspace,
- * synchronous, no finiteness check). */
+ * synchronous, no finiteness check, full m x m U). */
 void rrf_opts_init(rrf_opts* opts);
 
 /*
@@ -112,7 +114,7 @@ void rrf_opts_init(rrf_opts* opts);
  *  b      : block size, b >= 1                             (arg 5)
  *  q      : number of power iterations, q >= 0             (arg 6)
  *  seed   : generator key                                  (arg 7)
- *  U      : m x m output or NULL                           (arg 8)
+ *  U      : m x m output (m x n with opts->thin_u) or NULL  (arg 8)
  *  T      : m x n output, upper trapezoidal; every b x b diagonal block is
  *           diagonal with non-negative entries in descending order (arg 9)
  *  V      : n x n output or NULL                           (arg 10)

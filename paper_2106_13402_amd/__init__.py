@@ -94,11 +94,12 @@ def workspace_size(alg: str, m: int, n: int, b: int, q: int, precision: str = "f
 
 
 def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, want_v: bool,
-            check_finite: bool, inplace: bool, precision: str = "fp64", p=None):
+            check_finite: bool, inplace: bool, precision: str = "fp64", p=None,
+            thin_u: bool = False):
     _require(A, "A")
     m, n = int(A.shape[0]), int(A.shape[1])
     dev = A.device
-    U = empty_colmajor(m, m, dev) if want_u else None
+    U = empty_colmajor(m, n if thin_u else m, dev) if want_u else None
     V = empty_colmajor(n, n, dev) if want_v else None
     if inplace:
         if _ld(A) != m:
@@ -121,6 +122,7 @@ def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, wa
     opts.workspace_bytes = ws.numel()
     opts.async_ = 0
     opts.check_finite = 1 if check_finite else 0
+    opts.thin_u = 1 if thin_u else 0
     fn = getattr(lib, fname)
     extra = () if p is None else (p,)
     st = fn(m, n, A.data_ptr(), _ld(A), b, q, *extra, seed,
@@ -131,15 +133,17 @@ def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, wa
 
 
 def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
-            check_finite: bool = False, inplace: bool = False, precision: str = "fp64"):
+            check_finite: bool = False, inplace: bool = False, precision: str = "fp64",
+            thin_u: bool = False):
     """randUTV (Alg. 3): returns (U, T, V) with A = U T V^T (U/V None if not wanted).
 
     precision "bf16_sketch" forms each step's sketch from bfloat16 copies with
     FP32 accumulation (RRF_PREC_BF16_SKETCH); everything else stays FP64.
     "bf16_x3" adds the split-bfloat16 three-pass product to every update of
-    T, U and V (RRF_PREC_BF16_X3; results accurate to about 1e-5)."""
+    T, U and V (RRF_PREC_BF16_X3; results accurate to about 1e-5).
+    thin_u forms only U(:, :n) (m x n), all that A = U T V^T needs."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
-                   inplace, precision)
+                   inplace, precision, thin_u=thin_u)
 
 
 def rsvd(A, l: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,

@@ -32,6 +32,7 @@ class rrf_opts(C.Structure):
         ("workspace_bytes", C.c_size_t),
         ("async_", C.c_int),
         ("check_finite", C.c_int),
+        ("thin_u", C.c_int),
     ]
 
 

@@ -206,7 +206,8 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;
                    return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
-                                      opts ? opts->precision : RRF_PREC_FP64, &dummy);
+                                      opts ? opts->precision : RRF_PREC_FP64, &dummy, -1,
+                                      nullptr, opts && opts->thin_u);
                  });
 }
 
@@ -226,7 +227,7 @@ int rrf_randutv_boosted_ex(int64_t m, int64_t n, const double* A, int64_t lda, i
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;
                    return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
-                                      RRF_PREC_FP64, &dummy, p);
+                                      RRF_PREC_FP64, &dummy, p, nullptr, opts && opts->thin_u);
                  },
                  p);
 }
@@ -252,7 +253,7 @@ int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int6
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;
                    return randutv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,
-                                      o.precision, &dummy, -1, &stop);
+                                      o.precision, &dummy, -1, &stop, o.thin_u != 0);
                  },
                  -1, 2);
 }

@@ -23,7 +23,7 @@ size_t randutv_workspace(int64_t m, int64_t n, int64_t b, int precision, int64_t
 int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                 int q, uint64_t seed, double* U, double* T, double* V, void* ws, size_t ws_bytes,
                 bool check_input, int precision, int* status_out, int64_t p = -1,
-                const EarlyStop* stop = nullptr);
+                const EarlyStop* stop = nullptr, bool thin_u = false);
 
 // Alg. 1, same status layout.
 bool powerurv_supported(int64_t m, int64_t n, int64_t b);

@@ -310,8 +310,9 @@ int right_mult(hipStream_t st, int64_t rows, int64_t k, double* X, int64_t ldx, 
   return copy_matrix(st, rows, k, tmp, rows, X, ldx);
 }
 
-// Q (N x N, ld ldq) <- H_0 H_1 ... H_{s-1}, formed backward from the
-// identity. Step i's reflectors are the kbs[i] columns of Wall (N x *, ld
+// Q(:, 0:ncols) (N x ncols, ld ldq) <- (H_0 H_1 ... H_{s-1})(:, 0:ncols), formed
+// backward from the identity's first ncols columns (ncols = N: all of Q; the
+// thin U of a tall A needs only its first n columns). Step i's reflectors are the kbs[i] columns of Wall (N x *, ld
 // ldw) starting at row and column i*b (zero above), with triangular factor
 // Tall + i*bb*bb (ld bb); kbs[i] = 0 means none. Groups of up to kGroup
 // consecutive steps are merged into one compact-WY factor
@@ -320,8 +321,8 @@ int right_mult(hipStream_t st, int64_t rows, int64_t k, double* X, int64_t ldx, 
 int accumulate_backward(hipStream_t st, int64_t N, double* Q, int64_t ldq, const double* Wall,
                         int64_t ldw, const double* Tall, int64_t bb, int64_t b,
                         const std::vector<int64_t>& kbs, const Back& k, size_t split_elems,
-                        GemmFn upd) {
-  RRF_TRY(set_identity(st, N, N, Q, ldq));
+                        GemmFn upd, int64_t ncols) {
+  RRF_TRY(set_identity(st, N, ncols, Q, ldq));
   int64_t i1 = (int64_t)kbs.size();
   while (i1 > 0) {
     while (i1 > 0 && kbs[i1 - 1] == 0) --i1;
@@ -352,13 +353,14 @@ int accumulate_backward(hipStream_t st, int64_t N, double* Q, int64_t ldq, const
       RRF_TRY(copy_matrix(st, kbi, kbi, Ti, bb, k.TG + p + p * width, width));
       p += kbi;
     }
-    // Q(ca:, ca:) <- (I - W_G T_G W_G^T) Q(ca:, ca:)
+    // Q(ca:, ca:nc) <- (I - W_G T_G W_G^T) Q(ca:, ca:nc)
     double* Qb = Q + ca + ca * ldq;
-    RRF_TRY(upd(st, true, false, width, Nq, Nq, 1.0, WG, ldw, Qb, ldq, 0.0, k.Z, width, k.split,
+    const int64_t Nc = ncols - ca;
+    RRF_TRY(upd(st, true, false, width, Nc, Nq, 1.0, WG, ldw, Qb, ldq, 0.0, k.Z, width, k.split,
                 split_elems));
-    RRF_TRY(dgemm(st, false, false, width, Nq, width, 1.0, k.TG, width, k.Z, width, 0.0, k.Z2,
+    RRF_TRY(dgemm(st, false, false, width, Nc, width, 1.0, k.TG, width, k.Z, width, 0.0, k.Z2,
                   width, nullptr, 0));
-    RRF_TRY(upd(st, false, false, Nq, Nq, width, -1.0, WG, ldw, k.Z2, width, 1.0, Qb, ldq,
+    RRF_TRY(upd(st, false, false, Nq, Nc, width, -1.0, WG, ldw, k.Z2, width, 1.0, Qb, ldq,
                 nullptr, 0));
     i1 = i0;
   }
@@ -410,7 +412,7 @@ size_t randutv_workspace(int64_t m, int64_t n, int64_t b, int precision, int64_t
 int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                 int q, uint64_t seed, double* U, double* T, double* V, void* ws,
                 size_t ws_bytes, bool check_input, int precision, int* status_out, int64_t p,
-                const EarlyStop* stop) {
+                const EarlyStop* stop, bool thin_u) {
   if (stop && ceil_div(m, 256) > kNormParts)
     return set_error(RRF_E_NOTSUP, "randutv: early stop needs m <= 262144");
   Arena ar;
@@ -552,11 +554,12 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   trace_mark_stream(sv);
   if (U) {
     RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvLoop], 0));
-    RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE, upd));
+    RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE, upd,
+                                thin_u ? n : m));
   }
   if (V) {
     RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvLoop], 0));
-    RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE, upd));
+    RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE, upd, n));
   }
   if (s_done > 0)
     RRF_TRY(block_svd_batched(st, (int)s_done, (int)bb, (int)k_last, B.R, bb, bb * bb, B.Us, B.d,
