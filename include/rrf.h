@@ -118,7 +118,11 @@ void rrf_opts_init(rrf_opts* opts);
  *  T      : m x n output, upper trapezoidal; every b x b diagonal block is
  *           diagonal with non-negative entries in descending order (arg 9)
  *  V      : n x n output or NULL                           (arg 10)
- * m < n returns RRF_E_NOTSUP.
+ * m < n (Sec. 3.2): A^T is factored instead, A^T = U' T' V'^T, and the
+ * result is returned as U = V' (m x m), T = T'^T (m x n, lower trapezoidal,
+ * diagonal b x b blocks) and V = U' (n x n); opts->thin_u does not apply.
+ * rrf_workspace_size then covers the transpose's factorization plus A^T and
+ * T^T (2 m n doubles).
  */
 int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                 int32_t q, uint64_t seed, double* U, double* T, double* V);

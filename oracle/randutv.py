@@ -16,7 +16,9 @@ small blocks. Readings of points the paper leaves open:
   of Sec. 4.2, remark on Chan's method); for ``m == n`` with ``b | n`` it is a
   plain b x b SVD;
 * small SVDs are ordered descending with the sign rule of ``small_svd``;
-* the loop bound is ``s = ceil(n / b)`` for ``m >= n``.
+* the loop bound is ``s = ceil(n / b)`` for ``m >= n``;
+* a wide A (m < n) is factored through its transpose (Sec. 3.2), which
+  makes T lower trapezoidal.
 """
 from __future__ import annotations
 
@@ -52,7 +54,12 @@ def randutv(
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if m < n:
-        raise ValueError("randutv oracle requires m >= n")
+        # Sec. 3.2: a wide matrix is factored through its transpose,
+        # A^T = U' T' V'^T, so A = V' T'^T U'^T with T'^T lower trapezoidal
+        if stop_before is not None or max_steps is not None or on_step is not None:
+            raise ValueError("the step hooks need m >= n")
+        Ut, Tt, Vt = randutv(A.T, b, q, seed, want_u=want_v, want_v=want_u)
+        return Vt, np.asfortranarray(Tt.T), Ut
     if b < 1 or q < 0:
         raise ValueError("need b >= 1 and q >= 0")
     T = np.array(A, order="F", copy=True)

@@ -99,7 +99,7 @@ def _factor(fname: str, alg: str, A, b: int, q: int, seed: int, want_u: bool, wa
     _require(A, "A")
     m, n = int(A.shape[0]), int(A.shape[1])
     dev = A.device
-    U = empty_colmajor(m, n if thin_u else m, dev) if want_u else None
+    U = empty_colmajor(m, n if thin_u and m >= n else m, dev) if want_u else None
     V = empty_colmajor(n, n, dev) if want_v else None
     if inplace:
         if _ld(A) != m:

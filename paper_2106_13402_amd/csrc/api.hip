@@ -102,7 +102,7 @@ int finish(hipStream_t st, const int* status_dev) {
 
 // Shared argument checks of rrf_randutv / rrf_powerurv (LAPACK numbering).
 int check_args(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
-               const double* T, int shift = 0) {
+               const double* T, int shift = 0, bool allow_wide = false) {
   if (m < 1) return set_error(-1, "m must be >= 1"), -1;
   if (n < 1) return set_error(-2, "n must be >= 1"), -2;
   if (A == nullptr) return set_error(-3, "A is NULL"), -3;
@@ -111,8 +111,15 @@ int check_args(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, in
   if (q < 0) return set_error(-6, "q must be >= 0"), -6;
   if (T == nullptr) return set_error(-9 - shift, "T is NULL"), -9 - shift;
   if (T == A && lda != m) return set_error(-4, "T may alias A only when lda == m"), -4;
-  if (m < n) return set_error(RRF_E_NOTSUP, "m < n is not supported (factor A^T instead)");
+  if (m < n && !allow_wide)
+    return set_error(RRF_E_NOTSUP, "m < n is not supported here (factor A^T instead)");
   return RRF_OK;
+}
+
+// Bytes of the randUTV arena for the n x m transpose of a wide A, rounded.
+size_t wide_arena(int64_t m, int64_t n, int64_t b, int precision) {
+  const size_t w = randutv_workspace(n, m, b, precision);
+  return w == 0 ? 0 : (size_t)round_up((int64_t)w, 256);
 }
 
 typedef bool (*SupportedFn)(int64_t, int64_t, int64_t);
@@ -187,21 +194,80 @@ void rrf_opts_init(rrf_opts* opts) {
 }
 
 size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q, int precision) {
-  if (m < 1 || n < 1 || b < 1 || q < 0 || m < n) return 0;
+  if (m < 1 || n < 1 || b < 1 || q < 0) return 0;
   if (alg == RRF_ALG_RANDUTV) {
     if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH &&
         precision != RRF_PREC_BF16_X3)
       return 0;
+    if (m < n) {  // the factorization of A^T plus A^T and T^T
+      if (!randutv_supported(n, m, b)) return 0;
+      const size_t w = wide_arena(m, n, b, precision);
+      return w == 0 ? 0 : w + (size_t)2 * round_up((int64_t)m * n * 8, 256);
+    }
     return randutv_supported(m, n, b) ? randutv_workspace(m, n, b, precision) : 0;
   }
+  if (m < n) return 0;
   if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
   if (alg == RRF_ALG_POWERURV)
     return powerurv_supported(m, n, b) ? powerurv_workspace(m, n, b, q, precision) : 0;
   return 0;
 }
 
+// m < n (Sec. 3.2: the paper factors the transpose): A^T = U' T' V'^T, so
+// A = V' T'^T U'^T; U' is written to V, V' to U, and T = T'^T is lower
+// trapezoidal.
+static int randutv_wide(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
+                        uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
+  RRF_TRY(check_args(m, n, A, lda, b, q, T, 0, true));
+  rrf_opts o;
+  rrf_opts_init(&o);
+  if (opts) o = *opts;
+  if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH &&
+      o.precision != RRF_PREC_BF16_X3)
+    return set_error(RRF_E_NOTSUP, "precision mode not implemented for this algorithm");
+  if (!randutv_supported(n, m, b))
+    return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  RRF_TRY(check_device_ptr(A, 3));
+  RRF_TRY(check_device_ptr(U, 8));
+  RRF_TRY(check_device_ptr(T, 9));
+  RRF_TRY(check_device_ptr(V, 10));
+  const size_t need = rrf_workspace_size(RRF_ALG_RANDUTV, m, n, b, q, o.precision);
+  if (need == 0) return set_error(RRF_E_NOTSUP, "shape outside the kernel limits");
+  void* ws = o.workspace;
+  size_t ws_bytes = o.workspace_bytes;
+  if (ws == nullptr) {
+    RRF_TRY(cached_workspace(dev, need, &ws));
+    ws_bytes = need;
+  } else if (ws_bytes < need) {
+    return set_error(RRF_E_NOMEM, "workspace smaller than rrf_workspace_size()");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
+  const size_t arena = wide_arena(m, n, b, o.precision);
+  double* At = reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + arena);
+  double* Tt = At + round_up((int64_t)m * n * 8, 256) / 8;
+  if (o.check_finite) {
+    int* flag = reinterpret_cast<int*>(ws) + 1;
+    RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(flag), 1, 0u));
+    RRF_TRY(check_finite(st, m, n, A, lda, flag));
+    int h = 0;
+    RRF_CHECK_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, st));
+    RRF_CHECK_HIP(hipStreamSynchronize(st));
+    if (h) return set_error(RRF_E_NUMERIC, "input holds NaN or infinity");
+  }
+  RRF_TRY(transpose_matrix(st, m, n, A, lda, At, n));
+  int dummy = 0;
+  RRF_TRY(randutv_run(st, n, m, At, n, b, q, seed, V, Tt, U, ws, arena, false, o.precision,
+                      &dummy));
+  RRF_TRY(transpose_matrix(st, n, m, Tt, n, T, m));
+  if (o.async) return RRF_OK;
+  return finish(st, reinterpret_cast<const int*>(ws));
+}
+
 int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                    uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
+  if (m >= 1 && n >= 1 && m < n) return randutv_wide(m, n, A, lda, b, q, seed, U, T, V, opts);
   return run_alg(RRF_ALG_RANDUTV, m, n, A, lda, b, q, U, T, V, opts,
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;

@@ -33,6 +33,9 @@ int gaussian(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, in
 
 // ---- util.hip ------------------------------------------------------------
 int set_identity(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld);
+// D (cols x rows, ld ldd) = S^T (S rows x cols, ld lds).
+int transpose_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int64_t lds,
+                     double* D, int64_t ldd);
 // Q(:, 0:k) of a Householder QR (W unit lower trapezoidal M x k, Tf k x k):
 // (I - W Tf W^T)(:, 0:k) = [I; 0] - W (Tf W(0:k, :)^T); C: k x k scratch.
 int thin_q(hipStream_t st, int64_t M, int64_t k, const double* W, int64_t ldw, const double* Tf,

@@ -89,6 +89,38 @@ int set_identity(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t 
   return RRF_OK;
 }
 
+namespace {
+// D(c, r) = S(r, c) through 32 x 32 tiles in LDS (both sides coalesced).
+__global__ __launch_bounds__(256) void transpose_kernel(int64_t rows, int64_t cols,
+                                                        const double* __restrict__ S, int64_t lds,
+                                                        double* __restrict__ D, int64_t ldd) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t r = r0 + tx, c = c0 + j;
+    if (r < rows && c < cols) tile[j][tx] = S[r + c * lds];
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t c = c0 + tx, r = r0 + j;  // D(c, r)
+    if (r < rows && c < cols) D[c + r * ldd] = tile[tx][j];
+  }
+}
+}  // namespace
+
+int transpose_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int64_t lds,
+                     double* D, int64_t ldd) {
+  if (rows <= 0 || cols <= 0) return RRF_OK;
+  if (ceil_div(cols, 32) > 65535) return set_error(RRF_E_NOTSUP, "transpose: too many columns");
+  int tok = trace_begin(st, kTrElementwise, 0.0, 16.0 * rows * cols);
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)ceil_div(rows, 32), (unsigned)ceil_div(cols, 32)),
+                     dim3(256), 0, st, rows, cols, S, lds, D, ldd);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
+
 int thin_q(hipStream_t st, int64_t M, int64_t k, const double* W, int64_t ldw, const double* Tf,
            int64_t ldt, double* Q, int64_t ldq, double* C) {
   RRF_TRY(dgemm(st, false, true, k, k, k, 1.0, Tf, ldt, W, ldw, 0.0, C, k, nullptr, 0));

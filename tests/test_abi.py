@@ -60,7 +60,11 @@ def test_argument_errors(lib, fn, args, code):
 @pytest.mark.parametrize("fn", ["rrf_randutv", "rrf_powerurv"])
 def test_null_T_and_wide_input(lib, fn):
     assert getattr(lib, fn)(4, 4, DUMMY, 4, 2, 0, 1, NULL, NULL, NULL) == -9
-    assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, 0, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP
+    if fn == "rrf_powerurv":
+        assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, 0, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP
+    else:  # randUTV takes a wide A through its transpose; arguments still checked
+        assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, 0, 1, NULL, NULL, NULL) == -9
+        assert getattr(lib, fn)(3, 5, DUMMY, 2, 2, 0, 1, NULL, DUMMY, NULL) == -4
 
 
 def test_alias_requires_tight_lda(lib):
@@ -78,7 +82,10 @@ def test_workspace_size(lib):
     assert pw + 4 * 2 * 512 * 512 <= pm <= pw + 4 * 2 * 512 * 512 + 16 * 4 * 512 * 512 + 2 ** 20
     assert f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 0, 1) == f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 0, 0)
     assert f(_lib.RRF_ALG_POWERURV, 512, 512, 32, 1, 2) == 0
-    assert f(_lib.RRF_ALG_RANDUTV, 512, 600, 32, 1, 0) == 0     # m < n
+    # m < n: the factorization of the transpose plus A^T and T^T
+    assert f(_lib.RRF_ALG_RANDUTV, 512, 600, 32, 1, 0) == (
+        f(_lib.RRF_ALG_RANDUTV, 600, 512, 32, 1, 0) + 2 * 512 * 600 * 8)
+    assert f(_lib.RRF_ALG_POWERURV, 512, 600, 32, 1, 0) == 0    # powerURV: m >= n only
     assert f(_lib.RRF_ALG_RANDUTV, 512, 512, 300, 1, 0) == 0    # b > 256
     assert f(7, 512, 512, 32, 1, 0) == 0
     # the reflectors of every step are kept (m x n for U, n x n for V) so that

@@ -447,3 +447,21 @@ def test_randutv_bf16_sketch_steep_block_limit(gpu):
     U, T, V = _run_mixed(A, b, q, 3, gpu)
     worst = _mixed_gate(T, A, b, q, 3, s, M.recon_error(A, U, T, V), factor=2.0)
     print(f"steep spectrum: worst e_k(mixed) / e_k(FP64 envelope) = {worst:.2f}", flush=True)
+
+
+@pytest.mark.parametrize("m,n,b,q,precision", [(300, 500, 64, 1, "fp64"), (129, 1000, 32, 2, "fp64"),
+                                               (400, 640, 64, 1, "bf16_sketch")])
+def test_randutv_wide_through_transpose(gpu, m, n, b, q, precision):
+    """m < n (Sec. 3.2): the factorization of A^T, transposed back: T lower
+    trapezoidal and |T| equal to the oracle's (which takes the same route)."""
+    from paper_2106_13402_amd import randutv
+    print(f"case: randutv wide m={m} n={n} b={b} q={q} {precision}", flush=True)
+    A = gaussian_matrix(n, m, seed=m + n).T.copy(order="F")
+    U, T, V = (_host(x) for x in randutv(_to_dev(A, gpu), b, q, 5, precision=precision))
+    assert U.shape == (m, m) and T.shape == (m, n) and V.shape == (n, n)
+    assert np.all(np.triu(T, 1) == 0.0)
+    assert M.orth_error(U) <= 1e-13 and M.orth_error(V) <= 1e-13
+    assert M.recon_error(A, U, T, V) <= 1e-13
+    if precision == "fp64":
+        _, To, _ = oracle.randutv(A, b, q, 5, want_u=False, want_v=False)
+        np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * M.spec(A))

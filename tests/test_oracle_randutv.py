@@ -231,3 +231,21 @@ def test_pins_catch_planted_mistake(name):
     A = np.random.default_rng(77).standard_normal((24, 24))
     fn = _mutant(name)
     assert pin_failures(fn, A, 6, 1) != [], name
+
+
+def test_wide_matrix_through_the_transpose():
+    """m < n (Sec. 3.2): A = U T V^T with T = T'^T lower trapezoidal, where
+    A^T = U' T' V'^T is the factorization of the tall transpose; the
+    singular values survive and the diagonal blocks are diagonal."""
+    A = np.random.default_rng(12).standard_normal((40, 70))
+    U, T, V = oracle.randutv(A, 8, 1, 3)
+    Ut, Tt, Vt = oracle.randutv(A.T, 8, 1, 3)
+    np.testing.assert_array_equal(T, Tt.T)
+    np.testing.assert_array_equal(U, Vt)
+    np.testing.assert_array_equal(V, Ut)
+    assert U.shape == (40, 40) and V.shape == (70, 70)
+    assert np.all(np.triu(T, 1) == 0.0)
+    assert M.orth_error(U) < 1e-13 and M.orth_error(V) < 1e-13
+    assert np.linalg.norm(A - U @ T @ V.T, 2) < 1e-13 * np.linalg.norm(A, 2)
+    np.testing.assert_allclose(np.linalg.svd(T, compute_uv=False),
+                               np.linalg.svd(A, compute_uv=False), atol=1e-13 * np.linalg.norm(A, 2))
