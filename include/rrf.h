@@ -181,6 +181,27 @@ int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int6
                         double* V, int64_t* k_out, const rrf_opts* opts);
 
 /*
+ * Resume an early-stopped randUTV: continue the steps of
+ * rrf_randutv_partial from its state (T with T(k_in:, k_in:) unreduced, and
+ * the U, V it returned) with a new tol / kmax. The steps use the same
+ * generator streams, so the result is that of one rrf_randutv_partial call
+ * with the new criteria (to rounding: U and V are continued by applying the
+ * new steps' Householder transforms to them). ||A||_F is taken as ||T||_F.
+ *
+ *  m, n   : as for rrf_randutv (m >= n)                    (args 1, 2)
+ *  b, q, seed : the values of the interrupted call         (args 3-5)
+ *  tol, kmax  : the new stopping criteria                  (args 6, 7)
+ *  k_in   : columns already reduced (the k it returned)    (arg 8)
+ *  U, T, V: in/out, U m x m (or NULL), T m x n, V n x n (or NULL), the
+ *           arrays the interrupted call filled             (args 9-11)
+ *  k_out  : host int64 receiving the new k                 (arg 12)
+ *  opts   : as for rrf_randutv_partial; thin_u is rejected (RRF_E_NOTSUP)
+ */
+int rrf_randutv_resume(int64_t m, int64_t n, int64_t b, int32_t q, uint64_t seed, double tol,
+                       int64_t kmax, int64_t k_in, double* U, double* T, double* V,
+                       int64_t* k_out, const rrf_opts* opts);
+
+/*
  * randUTV_boosted -- Alg. 2 (Sec. 4.2-4.3): randUTV with oversampling.
  *
  * Each step samples the trailing block with b + p_i columns,

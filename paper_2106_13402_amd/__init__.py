@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import RRFError
 
 __all__ = [
-    "RRFError", "randutv", "randutv_boosted", "randutv_partial", "rsvd", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
+    "RRFError", "randutv", "randutv_boosted", "randutv_partial", "randutv_resume", "rsvd", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
     "batched_workspace_size", "batched_block",
@@ -201,6 +201,31 @@ def randutv_partial(A, b: int, q: int, seed: int, tol: float, kmax: int | None =
                                  C.byref(opts))
     _check(st, "rrf_randutv_partial")
     return U, T, V, int(k.value)
+
+
+def randutv_resume(U, T, V, k: int, b: int, q: int, seed: int, tol: float,
+                   kmax: int | None = None, precision: str = "fp64"):
+    """Continue a randutv_partial result (U, T, V, k) in place with new
+    stopping criteria; returns the new k."""
+    _require(T, "T")
+    m, n = int(T.shape[0]), int(T.shape[1])
+    dev = T.device
+    nbytes = workspace_size("randutv", m, n, b, q, precision)
+    if nbytes == 0:
+        raise RRFError(_lib.RRF_E_NOTSUP, "rrf_randutv_resume", "no workspace size")
+    ws = _workspace(dev, nbytes)
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.precision = PRECISIONS[precision]
+    opts.stream = _stream_ptr(dev)
+    opts.workspace = ws.data_ptr()
+    opts.workspace_bytes = ws.numel()
+    kout = C.c_int64(0)
+    _check(lib.rrf_randutv_resume(m, n, b, q, seed, float(tol), n if kmax is None else int(kmax),
+                                  int(k), U.data_ptr() if U is not None else None, T.data_ptr(),
+                                  V.data_ptr() if V is not None else None, C.byref(kout),
+                                  C.byref(opts)), "rrf_randutv_resume")
+    return int(kout.value)
 
 
 def randutv_boosted(A, b: int, q: int, p: int, seed: int, *, want_u: bool = True,

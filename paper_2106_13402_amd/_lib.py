@@ -63,6 +63,8 @@ PROTOTYPES = {
                                       C.POINTER(rrf_opts)]),
     "rrf_randutv_batched_workspace_size": (_sz, [_i64, _vp, _vp, _i64, C.c_int]),
     "rrf_randutv_batched_block": (_i64, [_i64, _i64]),
+    "rrf_randutv_resume": (C.c_int, [_i64, _i64, _i64, _i32, _u64, _d, _i64, _i64, _dp, _dp, _dp,
+                                     C.POINTER(C.c_int64), C.POINTER(rrf_opts)]),
     "rrf_rsvd": (C.c_int, [_i64, _i64, _dp, _i64, _i64, _i32, _u64, _dp, _dp, _dp,
                            C.POINTER(rrf_opts)]),
     "rrf_rsvd_workspace_size": (_sz, [_i64, _i64, _i64, _i32]),

@@ -310,7 +310,7 @@ int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int6
   if (kmax < 0) return set_error(-9, "kmax must be >= 0"), -9;
   if (k_out == nullptr) return set_error(-13, "k_out is NULL"), -13;
   *k_out = 0;
-  EarlyStop stop{tol, kmax, k_out};
+  EarlyStop stop{tol, kmax, k_out, 0};
   rrf_opts o;
   rrf_opts_init(&o);
   if (opts) o = *opts;
@@ -322,6 +322,37 @@ int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int6
                                       o.precision, &dummy, -1, &stop, o.thin_u != 0);
                  },
                  -1, 2);
+}
+
+int rrf_randutv_resume(int64_t m, int64_t n, int64_t b, int32_t q, uint64_t seed, double tol,
+                       int64_t kmax, int64_t k_in, double* U, double* T, double* V, int64_t* k_out,
+                       const rrf_opts* opts) {
+  if (m < 1) return set_error(-1, "m must be >= 1"), -1;
+  if (n < 1) return set_error(-2, "n must be >= 1"), -2;
+  if (b < 1) return set_error(-3, "b must be >= 1"), -3;
+  if (q < 0) return set_error(-4, "q must be >= 0"), -4;
+  if (!(tol >= 0.0)) return set_error(-6, "tol must be >= 0"), -6;
+  if (kmax < 0) return set_error(-7, "kmax must be >= 0"), -7;
+  if (k_in < 0 || k_in > n || (k_in % b != 0 && k_in != n))
+    return set_error(-8, "k_in must be a multiple of b in [0, n] (or n)"), -8;
+  if (T == nullptr) return set_error(-10, "T is NULL"), -10;
+  if (k_out == nullptr) return set_error(-12, "k_out is NULL"), -12;
+  *k_out = k_in;
+  rrf_opts o;
+  rrf_opts_init(&o);
+  if (opts) o = *opts;
+  if (o.thin_u) return set_error(RRF_E_NOTSUP, "resume needs the full m x m U");
+  o.async = 0;
+  if (k_in >= n) return RRF_OK;  // nothing left to reduce
+  EarlyStop stop{tol, kmax, k_out, k_in / b};
+  // T holds the state and is factored in place (A = T, lda = m)
+  return run_alg(RRF_ALG_RANDUTV, m, n, T, m, b, q, U, T, V, &o,
+                 [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
+                   int dummy = 0;
+                   return randutv_run(st, m, n, T, m, b, q, seed, U, T, V, ws, bytes, chk,
+                                      o.precision, &dummy, -1, &stop, false);
+                 },
+                 -1, 1);
 }
 
 size_t rrf_rsvd_workspace_size(int64_t m, int64_t n, int64_t l, int32_t q) {

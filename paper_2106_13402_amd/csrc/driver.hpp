@@ -14,6 +14,7 @@ struct EarlyStop {
   double tol;
   int64_t kmax;
   int64_t* k_out;
+  int64_t i0;  // first step: > 0 resumes a partial run whose state is in T, U, V
 };
 
 // p < 0 runs Alg. 3; p >= 0 runs Alg. 2 (randUTV_boosted) with oversampling p

@@ -367,6 +367,28 @@ int accumulate_backward(hipStream_t st, int64_t N, double* Q, int64_t ldq, const
   return RRF_OK;
 }
 
+// Q(:, c0:) <- Q(:, c0:) (I - W_i Tf_i W_i^T) for the steps i >= i0 in order:
+// continues U or V of an earlier (partial) run whose steps before i0 are
+// already in Q. Scratch: k.Z and k.Z2 (N x kb each).
+int accumulate_forward(hipStream_t st, int64_t N, double* Q, int64_t ldq, const double* Wall,
+                       int64_t ldw, const double* Tall, int64_t bb, int64_t b,
+                       const std::vector<int64_t>& kbs, int64_t i0, const Back& k,
+                       size_t split_elems, GemmFn upd) {
+  for (int64_t i = i0; i < (int64_t)kbs.size(); ++i) {
+    const int64_t kb = kbs[i];
+    if (kb == 0) continue;
+    const int64_t c0 = i * b;
+    const double* W = Wall + c0 + c0 * ldw;  // (N - c0) x kb
+    double* Qc = Q + c0 * ldq;
+    RRF_TRY(upd(st, false, false, N, kb, N - c0, 1.0, Qc, ldq, W, ldw, 0.0, k.Z, N, k.split,
+                split_elems));
+    RRF_TRY(dgemm(st, false, false, N, kb, kb, 1.0, k.Z, N, Tall + i * bb * bb, bb, 0.0, k.Z2, N,
+                  nullptr, 0));
+    RRF_TRY(upd(st, false, true, N, N - c0, kb, -1.0, k.Z2, N, W, ldw, 1.0, Qc, ldq, nullptr, 0));
+  }
+  return RRF_OK;
+}
+
 // The sketch of the mixed mode into Y (Ni x kb, FP64): bfloat16 copies of
 // the scaled T22 and of G, products with FP32 accumulation, each
 // intermediate column renormalised by a power of two; the last product is
@@ -452,10 +474,17 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   const int64_t s = ceil_div(n, b);
   const int64_t bb = std::min(b, n);  // block slot size of R, Us, Vs, d, TU, TV
   std::vector<int64_t> ku(s, 0), kv(s, 0);  // reflector columns per step
-  int64_t s_done = 0;                        // steps carried out
+  const int64_t i0 = stop ? stop->i0 : 0;    // first step (> 0: resuming)
+  int64_t s_done = i0;                       // steps carried out
   double e0 = 0.0;
   if (stop) RRF_TRY(maxabs(st, m, n, T, ldt, B.nword));
-  for (int64_t i = 0; i < s; ++i) {
+  if (i0 > 0) {
+    // ||A||_F = ||T||_F (orthogonal invariance): the reference of the tolerance
+    RRF_TRY(frob_norm(st, m, n, T, ldt, B.nword, B.nparts, kNormParts, B.nout));
+    RRF_CHECK_HIP(hipMemcpyAsync(&e0, B.nout, sizeof e0, hipMemcpyDeviceToHost, st));
+    RRF_CHECK_HIP(hipStreamSynchronize(st));
+  }
+  for (int64_t i = i0; i < s; ++i) {
     const int64_t c0 = i * b;
     const int64_t c2 = std::min(c0 + b, n);
     const int64_t r2 = std::min(c0 + b, m);
@@ -554,20 +583,27 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   trace_mark_stream(sv);
   if (U) {
     RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvLoop], 0));
-    RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE, upd,
-                                thin_u ? n : m));
+    if (i0 > 0)
+      RRF_TRY(accumulate_forward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, i0, B.back[0], SE, upd));
+    else
+      RRF_TRY(accumulate_backward(su, m, U, ldu, B.WU, m, B.TU, bb, b, ku, B.back[0], SE, upd,
+                                  thin_u ? n : m));
   }
   if (V) {
     RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvLoop], 0));
-    RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE, upd, n));
+    if (i0 > 0)
+      RRF_TRY(accumulate_forward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, i0, B.back[1], SE, upd));
+    else
+      RRF_TRY(accumulate_backward(sv, n, V, ldv, B.WV, n, B.TV, bb, b, kv, B.back[1], SE, upd, n));
   }
-  if (s_done > 0)
-    RRF_TRY(block_svd_batched(st, (int)s_done, (int)bb, (int)k_last, B.R, bb, bb * bb, B.Us, B.d,
-                              bb, B.Vs, B.svd, B.svd_bytes, B.status));
+  if (s_done > i0)
+    RRF_TRY(block_svd_batched(st, (int)(s_done - i0), (int)bb, (int)k_last, B.R + i0 * bb * bb, bb,
+                              bb * bb, B.Us + i0 * bb * bb, B.d + i0 * bb, bb,
+                              B.Vs + i0 * bb * bb, B.svd, B.svd_bytes, B.status));
   RRF_CHECK_HIP(hipEventRecord(ev[kEvSvd], st));
   if (U) RRF_CHECK_HIP(hipStreamWaitEvent(su, ev[kEvSvd], 0));
   if (V) RRF_CHECK_HIP(hipStreamWaitEvent(sv, ev[kEvSvd], 0));
-  for (int64_t i = 0; i < s_done; ++i) {
+  for (int64_t i = i0; i < s_done; ++i) {
     const int64_t c0 = i * b;
     const int64_t kb = std::min(b, n - c0);
     const int64_t c2 = c0 + kb;

@@ -188,6 +188,19 @@ def test_rsvd_argument_errors(lib):
     assert ws(100, 50, 60, 1) == 0 and ws(1000, 1000, 300, 1) == 0
 
 
+def test_resume_argument_errors(lib):
+    f = lib.rrf_randutv_resume
+    k = C.c_int64(7)
+    assert f(8, 8, 0, 1, 1, 1e-3, 8, 0, NULL, DUMMY, NULL, C.byref(k), NULL) == -3
+    assert f(8, 8, 4, 1, 1, -1.0, 8, 0, NULL, DUMMY, NULL, C.byref(k), NULL) == -6
+    assert f(8, 8, 4, 1, 1, 1e-3, 8, 3, NULL, DUMMY, NULL, C.byref(k), NULL) == -8
+    assert f(8, 8, 4, 1, 1, 1e-3, 8, 12, NULL, DUMMY, NULL, C.byref(k), NULL) == -8
+    assert f(8, 8, 4, 1, 1, 1e-3, 8, 4, NULL, NULL, NULL, C.byref(k), NULL) == -10
+    assert f(8, 8, 4, 1, 1, 1e-3, 8, 4, NULL, DUMMY, NULL, None, NULL) == -12
+    # everything already reduced: nothing to do, k unchanged
+    assert f(8, 8, 4, 1, 1, 1e-3, 8, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == 0 and k.value == 8
+
+
 def _arr(t, vals):
     return (t * len(vals))(*vals)
 

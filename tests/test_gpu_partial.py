@@ -66,3 +66,24 @@ def test_partial_zero_and_mixed(gpu):
         assert np.linalg.norm(T[k - 64:, k - 64:]) > 1e-3 * nA
         rec = M.recon_error(A, U, T, V)
         assert rec <= (1e-13 if precision == "bf16_sketch" else 1e-4), rec
+
+
+@pytest.mark.parametrize("tol1,tol2,kmax2", [(1e-2, 1e-6, None), (1e-3, 0.0, 96), (1e-5, 1e-5, None),
+                                             (1e-2, 0.0, None)])
+def test_resume_matches_one_partial_run(gpu, tol1, tol2, kmax2):
+    """partial(tol1) then resume(tol2, kmax2) equals one partial run with
+    (tol2, kmax2): same k, |T| within 1e-9 ||A|| of the oracle's single run,
+    U and V orthogonal and A = U T V^T to 1e-13."""
+    from paper_2106_13402_amd import randutv_partial, randutv_resume
+    print(f"case: resume tol1={tol1} tol2={tol2} kmax2={kmax2}", flush=True)
+    m, n, b = 250, 200, 16
+    A = spectral_matrix(m, n, spectrum("geometric", n, decades=8.0), seed=1)
+    U, T, V, k1 = randutv_partial(_to_dev(A, gpu), b, 1, 3, tol1)
+    k2 = randutv_resume(U, T, V, k1, b, 1, 3, tol2, kmax2)
+    Uo, To, Vo, ko = oracle.randutv_partial(A, b, 1, 3, tol2, n if kmax2 is None else kmax2)
+    assert k2 == max(k1, ko)
+    U, T, V = _host(U), _host(T), _host(V)
+    assert M.orth_error(U) <= 1e-13 and M.orth_error(V) <= 1e-13
+    assert M.recon_error(A, U, T, V) <= 1e-13
+    if k2 == ko:
+        np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * M.spec(A))
