@@ -7,7 +7,8 @@
  * Given A (m x n, m >= n), every factorization here returns
  *     A = U * T * V^T,
  * U (m x m) and V (n x n) orthogonal, T (m x n) upper trapezoidal
- * (Sec. 1, the UTV problem statement).
+ * (Sec. 1, the UTV problem statement). rrf_randutv, rrf_randutv_boosted and
+ * rrf_powerurv also take m < n, through the transpose (T lower trapezoidal).
  *
  * Conventions shared by every entry point:
  *  - All matrices are column-major IEEE binary64 in DEVICE memory of the
@@ -223,7 +224,9 @@ int rrf_randutv_resume(int64_t m, int64_t n, int64_t b, int32_t q, uint64_t seed
  *  seed, U, T, V      : as for rrf_randutv                 (args 8-11)
  * opts: precision must be RRF_PREC_FP64; the workspace must hold
  * rrf_randutv_boosted_workspace_size(m, n, b, q, p) bytes. b + p > 256
- * returns RRF_E_NOTSUP.
+ * returns RRF_E_NOTSUP. m < n goes through the transpose as for rrf_randutv
+ * (p is then clipped against m - b, and the workspace size covers A^T and
+ * T^T).
  */
 int rrf_randutv_boosted(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                         int32_t q, int64_t p, uint64_t seed, double* U, double* T, double* V);
@@ -243,7 +246,11 @@ size_t rrf_randutv_boosted_workspace_size(int64_t m, int64_t n, int64_t b, int32
  * Gaussian. T(k,k) carries the sign of the Householder R diagonal.
  *
  * Arguments as for rrf_randutv, except that b is the panel width of the
- * blocked Householder QR (it changes rounding only).
+ * blocked Householder QR (it changes rounding only; b > min(m, n) acts as
+ * min(m, n)).
+ * m < n goes through the transpose as for rrf_randutv: A^T = U' T' V'^T is
+ * factored and U = V' (m x m), T = T'^T (lower trapezoidal), V = U'
+ * (n x n); rrf_workspace_size covers A^T and T^T as well.
  */
 int rrf_powerurv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                  int32_t q, uint64_t seed, double* U, double* T, double* V);

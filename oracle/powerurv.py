@@ -45,7 +45,12 @@ def powerurv(A: np.ndarray, q: int, seed: int, *, rounds: int | None = None,
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if m < n:
-        raise ValueError("powerurv oracle requires m >= n")
+        # Sec. 3.2's reading for a wide matrix, as in randUTV: factor the
+        # transpose, A^T = U' T' V'^T, so A = V' T'^T U'^T (T lower trapezoidal)
+        if rounds is not None:
+            raise ValueError("rounds needs m >= n")
+        Ut, Tt, Vt = powerurv(A.T, q, seed, precision=precision)
+        return Vt, np.asfortranarray(Tt.T), Ut
     if q < 0:
         raise ValueError("q must be non-negative")
     G = gaussian(seed, 0, n, n)

@@ -60,7 +60,9 @@ def randutv_boosted(A: np.ndarray, b: int, q: int, p: int, seed: int, *, want_u:
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     if m < n:
-        raise ValueError("randutv_boosted oracle requires m >= n")
+        # a wide matrix through its transpose (Sec. 3.2), as for Alg. 3
+        Ut, Tt, Vt = randutv_boosted(A.T, b, q, p, seed, want_u=want_v, want_v=want_u)
+        return Vt, np.asfortranarray(Tt.T), Ut
     if b < 1 or q < 0 or p < 0:
         raise ValueError("need b >= 1, q >= 0 and p >= 0")
     T = np.array(A, order="F", copy=True)

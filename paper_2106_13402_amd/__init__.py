@@ -309,8 +309,8 @@ def powerurv(A, q: int, seed: int, *, b: int = 128, want_u: bool = True, want_v:
 
     precision "bf16_sketch" forms the 2q power products from bfloat16 values
     with FP32 accumulation (RRF_PREC_BF16_SKETCH); everything else stays FP64."""
-    n = int(A.shape[1])
-    return _factor("rrf_powerurv_ex", "powerurv", A, min(b, max(n, 1)), q, seed, want_u, want_v,
+    k = min(int(A.shape[0]), int(A.shape[1]))
+    return _factor("rrf_powerurv_ex", "powerurv", A, min(b, max(k, 1)), q, seed, want_u, want_v,
                    check_finite, inplace, precision)
 
 

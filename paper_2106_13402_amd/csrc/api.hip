@@ -116,10 +116,35 @@ int check_args(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, in
   return RRF_OK;
 }
 
-// Bytes of the randUTV arena for the n x m transpose of a wide A, rounded.
-size_t wide_arena(int64_t m, int64_t n, int64_t b, int precision) {
-  const size_t w = randutv_workspace(n, m, b, precision);
+// Bytes of the arena that factors the n x m transpose of a wide A (alg and
+// boost_p as in run_alg), rounded; 0 outside the kernel limits.
+size_t wide_arena(int alg, int64_t m, int64_t n, int64_t b, int32_t q, int precision,
+                  int64_t boost_p = -1) {
+  size_t w = 0;
+  if (alg == RRF_ALG_RANDUTV)
+    w = randutv_supported(n, m, b) ? randutv_workspace(n, m, b, precision, boost_p) : 0;
+  else if (alg == RRF_ALG_POWERURV)
+    w = powerurv_supported(n, m, b) ? powerurv_workspace(n, m, b, q, precision) : 0;
   return w == 0 ? 0 : (size_t)round_up((int64_t)w, 256);
+}
+
+// The wide path's whole workspace: the arena, then A^T and T^T (n x m each).
+size_t wide_workspace(int alg, int64_t m, int64_t n, int64_t b, int32_t q, int precision,
+                      int64_t boost_p = -1) {
+  const size_t w = wide_arena(alg, m, n, b, q, precision, boost_p);
+  return w == 0 ? 0 : w + (size_t)2 * round_up((int64_t)m * n * 8, 256);
+}
+
+// b + p <= 256 for Alg. 2 on an n-column input (p is clipped to n - b).
+bool boosted_fits(int64_t n, int64_t b, int64_t p) {
+  return std::min(b, n) + std::min(p, std::max<int64_t>(n - b, 0)) <= 256;
+}
+
+// Precision modes each algorithm implements (boost_p >= 0: Alg. 2, FP64 only).
+bool precision_ok(int alg, int precision, int64_t boost_p = -1) {
+  if (boost_p >= 0) return precision == RRF_PREC_FP64;
+  if (precision == RRF_PREC_FP64 || precision == RRF_PREC_BF16_SKETCH) return true;
+  return alg == RRF_ALG_RANDUTV && precision == RRF_PREC_BF16_X3;
 }
 
 typedef bool (*SupportedFn)(int64_t, int64_t, int64_t);
@@ -138,10 +163,9 @@ int run_alg(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t
   if (boost_p >= 0) {
     if (o.precision != RRF_PREC_FP64)
       return set_error(RRF_E_NOTSUP, "randutv_boosted: only RRF_PREC_FP64");
-    if (std::min(b, n) + std::min(boost_p, std::max<int64_t>(n - b, 0)) > 256)
+    if (!boosted_fits(n, b, boost_p))
       return set_error(RRF_E_NOTSUP, "randutv_boosted: needs b + p <= 256");
-  } else if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH &&
-             !(alg == RRF_ALG_RANDUTV && o.precision == RRF_PREC_BF16_X3)) {
+  } else if (!precision_ok(alg, o.precision)) {
     return set_error(RRF_E_NOTSUP, "precision mode not implemented for this algorithm");
   }
   const bool ok = alg == RRF_ALG_RANDUTV ? randutv_supported(m, n, b) : powerurv_supported(m, n, b);
@@ -195,46 +219,44 @@ void rrf_opts_init(rrf_opts* opts) {
 
 size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q, int precision) {
   if (m < 1 || n < 1 || b < 1 || q < 0) return 0;
-  if (alg == RRF_ALG_RANDUTV) {
-    if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH &&
-        precision != RRF_PREC_BF16_X3)
-      return 0;
-    if (m < n) {  // the factorization of A^T plus A^T and T^T
-      if (!randutv_supported(n, m, b)) return 0;
-      const size_t w = wide_arena(m, n, b, precision);
-      return w == 0 ? 0 : w + (size_t)2 * round_up((int64_t)m * n * 8, 256);
-    }
+  if (alg != RRF_ALG_RANDUTV && alg != RRF_ALG_POWERURV) return 0;
+  if (!precision_ok(alg, precision)) return 0;
+  if (m < n) return wide_workspace(alg, m, n, b, q, precision);  // A^T's factorization
+  if (alg == RRF_ALG_RANDUTV)
     return randutv_supported(m, n, b) ? randutv_workspace(m, n, b, precision) : 0;
-  }
-  if (m < n) return 0;
-  if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
-  if (alg == RRF_ALG_POWERURV)
-    return powerurv_supported(m, n, b) ? powerurv_workspace(m, n, b, q, precision) : 0;
-  return 0;
+  return powerurv_supported(m, n, b) ? powerurv_workspace(m, n, b, q, precision) : 0;
 }
 
 // m < n (Sec. 3.2: the paper factors the transpose): A^T = U' T' V'^T, so
 // A = V' T'^T U'^T; U' is written to V, V' to U, and T = T'^T is lower
-// trapezoidal.
-static int randutv_wide(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
-                        uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
-  RRF_TRY(check_args(m, n, A, lda, b, q, T, 0, true));
+// trapezoidal. alg and boost_p as in run_alg; thin_u does not apply (U is
+// m x m = m x min(m, n) already).
+static int wide_run(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                    int32_t q, uint64_t seed, double* U, double* T, double* V,
+                    const rrf_opts* opts, int64_t boost_p = -1) {
+  const int shift = boost_p >= 0 ? 1 : 0;
+  RRF_TRY(check_args(m, n, A, lda, b, q, T, shift, true));
   rrf_opts o;
   rrf_opts_init(&o);
   if (opts) o = *opts;
-  if (o.precision != RRF_PREC_FP64 && o.precision != RRF_PREC_BF16_SKETCH &&
-      o.precision != RRF_PREC_BF16_X3)
+  if (boost_p >= 0) {
+    if (o.precision != RRF_PREC_FP64)
+      return set_error(RRF_E_NOTSUP, "randutv_boosted: only RRF_PREC_FP64");
+    if (!boosted_fits(m, b, boost_p))
+      return set_error(RRF_E_NOTSUP, "randutv_boosted: needs b + p <= 256");
+  } else if (!precision_ok(alg, o.precision)) {
     return set_error(RRF_E_NOTSUP, "precision mode not implemented for this algorithm");
-  if (!randutv_supported(n, m, b))
+  }
+  const size_t arena = wide_arena(alg, m, n, b, q, o.precision, boost_p);
+  if (arena == 0)
     return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
   int dev = 0;
   RRF_TRY(device_ready(&dev));
   RRF_TRY(check_device_ptr(A, 3));
-  RRF_TRY(check_device_ptr(U, 8));
-  RRF_TRY(check_device_ptr(T, 9));
-  RRF_TRY(check_device_ptr(V, 10));
-  const size_t need = rrf_workspace_size(RRF_ALG_RANDUTV, m, n, b, q, o.precision);
-  if (need == 0) return set_error(RRF_E_NOTSUP, "shape outside the kernel limits");
+  RRF_TRY(check_device_ptr(U, 8 + shift));
+  RRF_TRY(check_device_ptr(T, 9 + shift));
+  RRF_TRY(check_device_ptr(V, 10 + shift));
+  const size_t need = wide_workspace(alg, m, n, b, q, o.precision, boost_p);
   void* ws = o.workspace;
   size_t ws_bytes = o.workspace_bytes;
   if (ws == nullptr) {
@@ -244,7 +266,6 @@ static int randutv_wide(int64_t m, int64_t n, const double* A, int64_t lda, int6
     return set_error(RRF_E_NOMEM, "workspace smaller than rrf_workspace_size()");
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
-  const size_t arena = wide_arena(m, n, b, o.precision);
   double* At = reinterpret_cast<double*>(reinterpret_cast<char*>(ws) + arena);
   double* Tt = At + round_up((int64_t)m * n * 8, 256) / 8;
   if (o.check_finite) {
@@ -257,9 +278,13 @@ static int randutv_wide(int64_t m, int64_t n, const double* A, int64_t lda, int6
     if (h) return set_error(RRF_E_NUMERIC, "input holds NaN or infinity");
   }
   RRF_TRY(transpose_matrix(st, m, n, A, lda, At, n));
-  int dummy = 0;
-  RRF_TRY(randutv_run(st, n, m, At, n, b, q, seed, V, Tt, U, ws, arena, false, o.precision,
-                      &dummy));
+  if (alg == RRF_ALG_RANDUTV) {
+    int dummy = 0;
+    RRF_TRY(randutv_run(st, n, m, At, n, b, q, seed, V, Tt, U, ws, arena, false, o.precision,
+                        &dummy, boost_p));
+  } else {
+    RRF_TRY(powerurv_run(st, n, m, At, n, b, q, seed, V, Tt, U, ws, arena, false, o.precision));
+  }
   RRF_TRY(transpose_matrix(st, n, m, Tt, n, T, m));
   if (o.async) return RRF_OK;
   return finish(st, reinterpret_cast<const int*>(ws));
@@ -267,7 +292,8 @@ static int randutv_wide(int64_t m, int64_t n, const double* A, int64_t lda, int6
 
 int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                    uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
-  if (m >= 1 && n >= 1 && m < n) return randutv_wide(m, n, A, lda, b, q, seed, U, T, V, opts);
+  if (m >= 1 && n >= 1 && m < n)
+    return wide_run(RRF_ALG_RANDUTV, m, n, A, lda, b, q, seed, U, T, V, opts);
   return run_alg(RRF_ALG_RANDUTV, m, n, A, lda, b, q, U, T, V, opts,
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;
@@ -280,8 +306,9 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
 size_t rrf_randutv_boosted_workspace_size(int64_t m, int64_t n, int64_t b, int32_t q,
                                           int64_t p) {
   (void)q;
-  if (m < 1 || n < 1 || b < 1 || q < 0 || p < 0 || m < n) return 0;
-  if (std::min(b, n) + std::min(p, std::max<int64_t>(n - b, 0)) > 256) return 0;
+  if (m < 1 || n < 1 || b < 1 || q < 0 || p < 0) return 0;
+  if (!boosted_fits(std::min(m, n), b, p)) return 0;
+  if (m < n) return wide_workspace(RRF_ALG_RANDUTV, m, n, b, q, RRF_PREC_FP64, p);
   return randutv_supported(m, n, b) ? randutv_workspace(m, n, b, RRF_PREC_FP64, p) : 0;
 }
 
@@ -289,6 +316,8 @@ int rrf_randutv_boosted_ex(int64_t m, int64_t n, const double* A, int64_t lda, i
                            int32_t q, int64_t p, uint64_t seed, double* U, double* T, double* V,
                            const rrf_opts* opts) {
   if (p < 0) return set_error(-7, "p must be >= 0"), -7;
+  if (m >= 1 && n >= 1 && m < n)
+    return wide_run(RRF_ALG_RANDUTV, m, n, A, lda, b, q, seed, U, T, V, opts, p);
   return run_alg(RRF_ALG_RANDUTV, m, n, A, lda, b, q, U, T, V, opts,
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;
@@ -522,6 +551,8 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
 
 int rrf_powerurv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                     uint64_t seed, double* U, double* T, double* V, const rrf_opts* opts) {
+  if (m >= 1 && n >= 1 && m < n)
+    return wide_run(RRF_ALG_POWERURV, m, n, A, lda, b, q, seed, U, T, V, opts);
   return run_alg(RRF_ALG_POWERURV, m, n, A, lda, b, q, U, T, V, opts,
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    return powerurv_run(st, m, n, A, lda, b, q, seed, U, T, V, ws, bytes, chk,

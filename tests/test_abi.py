@@ -60,11 +60,10 @@ def test_argument_errors(lib, fn, args, code):
 @pytest.mark.parametrize("fn", ["rrf_randutv", "rrf_powerurv"])
 def test_null_T_and_wide_input(lib, fn):
     assert getattr(lib, fn)(4, 4, DUMMY, 4, 2, 0, 1, NULL, NULL, NULL) == -9
-    if fn == "rrf_powerurv":
-        assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, 0, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP
-    else:  # randUTV takes a wide A through its transpose; arguments still checked
-        assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, 0, 1, NULL, NULL, NULL) == -9
-        assert getattr(lib, fn)(3, 5, DUMMY, 2, 2, 0, 1, NULL, DUMMY, NULL) == -4
+    # a wide A goes through its transpose; arguments are still checked
+    assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, 0, 1, NULL, NULL, NULL) == -9
+    assert getattr(lib, fn)(3, 5, DUMMY, 2, 2, 0, 1, NULL, DUMMY, NULL) == -4
+    assert getattr(lib, fn)(3, 5, DUMMY, 3, 2, -1, 1, NULL, DUMMY, NULL) == -6
 
 
 def test_alias_requires_tight_lda(lib):
@@ -85,7 +84,11 @@ def test_workspace_size(lib):
     # m < n: the factorization of the transpose plus A^T and T^T
     assert f(_lib.RRF_ALG_RANDUTV, 512, 600, 32, 1, 0) == (
         f(_lib.RRF_ALG_RANDUTV, 600, 512, 32, 1, 0) + 2 * 512 * 600 * 8)
-    assert f(_lib.RRF_ALG_POWERURV, 512, 600, 32, 1, 0) == 0    # powerURV: m >= n only
+    for prec in (0, 1):
+        wide, tall = (f(_lib.RRF_ALG_POWERURV, 512, 600, 32, 1, prec),
+                      f(_lib.RRF_ALG_POWERURV, 600, 512, 32, 1, prec))
+        assert tall + 2 * 512 * 600 * 8 <= wide < tall + 2 * 512 * 600 * 8 + 256
+    assert f(_lib.RRF_ALG_POWERURV, 512, 600, 32, 1, _lib.RRF_PREC_BF16_X3) == 0
     assert f(_lib.RRF_ALG_RANDUTV, 512, 512, 300, 1, 0) == 0    # b > 256
     assert f(7, 512, 512, 32, 1, 0) == 0
     # the reflectors of every step are kept (m x n for U, n x n for V) so that
@@ -150,7 +153,10 @@ def test_boosted_argument_errors(lib):
     assert f(8, 8, DUMMY, 8, 4, 1, -1, 1, NULL, DUMMY, NULL) == -7
     assert f(8, 8, DUMMY, 8, 4, -1, 2, 1, NULL, DUMMY, NULL) == -6
     assert f(8, 8, DUMMY, 8, 4, 1, 2, 1, NULL, NULL, NULL) == -10
-    assert f(8, 9, DUMMY, 8, 4, 1, 2, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP  # m < n
+    # m < n goes through the transpose: arguments checked, b + p against m
+    assert f(8, 9, DUMMY, 7, 4, 1, 2, 1, NULL, DUMMY, NULL) == -4
+    assert f(8, 9, DUMMY, 8, 4, 1, 2, 1, NULL, NULL, NULL) == -10
+    assert f(300, 400, DUMMY, 300, 200, 1, 100, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP
     assert f(400, 300, DUMMY, 400, 200, 1, 100, 1, NULL, DUMMY, NULL) == _lib.RRF_E_NOTSUP
     o = _lib.rrf_opts()
     lib.rrf_opts_init(C.byref(o))
@@ -160,7 +166,9 @@ def test_boosted_argument_errors(lib):
     ws = lib.rrf_randutv_boosted_workspace_size
     assert ws(16384, 16384, 128, 2, 128) > lib.rrf_workspace_size(0, 16384, 16384, 128, 2, 0)
     assert ws(100, 50, 16, 1, 300) > 0  # p is clipped to n - b
-    assert ws(1000, 500, 200, 1, 100) == 0 and ws(10, 20, 4, 1, 2) == 0 and ws(10, 8, 4, 1, -1) == 0
+    assert ws(1000, 500, 200, 1, 100) == 0 and ws(500, 1000, 200, 1, 100) == 0
+    assert ws(10, 8, 4, 1, -1) == 0
+    assert ws(10, 20, 4, 1, 2) >= ws(20, 10, 4, 1, 2) + 2 * 10 * 20 * 8  # + A^T and T^T
 
 
 def test_partial_argument_errors(lib):

@@ -145,3 +145,19 @@ def test_boosted_beats_basic_at_block_edges(gpu):
     r3 = np.max(M.trailing_norms(T3, ks) / s[ks])
     print(f"  max e_k/sigma: boosted {rb:.3f}, basic {r3:.3f}", flush=True)
     assert rb < 0.9 * r3
+
+
+@pytest.mark.parametrize("m,n,b,q,p", [(300, 500, 32, 1, 32), (120, 257, 16, 2, 8)])
+def test_boosted_wide_through_transpose(gpu, m, n, b, q, p):
+    """m < n through the transpose (Sec. 3.2, as for Alg. 3): T = T'^T lower
+    trapezoidal with diagonal blocks, |T| equal to the oracle's."""
+    print(f"case: boosted wide m={m} n={n} b={b} q={q} p={p}", flush=True)
+    A = gaussian_matrix(n, m, seed=m + n + p).T.copy(order="F")
+    U, T, V = _run(A, b, q, p, 11, gpu)
+    assert U.shape == (m, m) and T.shape == (m, n) and V.shape == (n, n)
+    _check_factorization(A.T, V, T.T, U)
+    _check_blocks(T.T, b)
+    _, To, _ = boosted_ref(A, b, q, p, 11, want_u=False, want_v=False)
+    nA = M.spec(A)
+    _diag_parity(T, To, nA, n)
+    np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * nA)

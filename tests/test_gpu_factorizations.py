@@ -288,6 +288,23 @@ def test_powerurv_parity(gpu, m, n, b, q):
     np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * 2.0)
 
 
+@pytest.mark.parametrize("m,n,b,q", [(200, 330, 64, 1), (129, 300, 32, 2)])
+def test_powerurv_wide_through_transpose(gpu, m, n, b, q):
+    """m < n through the transpose (the Sec. 3.2 reading, as for randUTV):
+    T = T'^T lower trapezoidal, U m x m, V n x n, and |T| equal to the
+    oracle's, which takes the same route."""
+    from paper_2106_13402_amd import powerurv
+    print(f"case: powerurv wide m={m} n={n} b={b} q={q}", flush=True)
+    s = np.linspace(2.0, 1.0, m)
+    A = spectral_matrix(n, m, s, seed=m + n).T.copy(order="F")
+    U, T, V = (_host(x) for x in powerurv(_to_dev(A, gpu), q, 1, b=b))
+    assert U.shape == (m, m) and T.shape == (m, n) and V.shape == (n, n)
+    _check_factorization(A.T, V, T.T, U)
+    _, To, _ = oracle.powerurv(A, q, 1)
+    _diag_parity(T, To, 2.0, n)
+    np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * 2.0)
+
+
 # ------------------------------------------------ powerURV, bfloat16 power products
 POWER_MIXED = [(300, 256, 32, 1, 64.0), (400, 256, 64, 2, 40.0), (256, 256, 16, 2, 1e9),
                (520, 300, 128, 1, 75.0)]

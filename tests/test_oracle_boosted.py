@@ -132,3 +132,20 @@ def test_boosted_removes_the_block_edge_spikes(kind, kw):
         r3 = np.max(M.trailing_norms(T3, ks) / s[ks])
         rb = np.max(M.trailing_norms(Tb, ks) / s[ks])
         assert rb < 0.9 * r3, (q, r3, rb)
+
+
+def test_boosted_wide_matrix_through_the_transpose():
+    """m < n (Sec. 3.2, as for Alg. 3): the transpose's factorization,
+    transposed back; T lower trapezoidal with diagonal, non-negative,
+    descending b x b blocks, and the singular values of A."""
+    A = gaussian_matrix(70, 45, seed=14).T.copy()
+    U, T, V = randutv_boosted(A, 8, 1, 8, 5)
+    Ut, Tt, Vt = randutv_boosted(A.T, 8, 1, 8, 5)
+    np.testing.assert_array_equal(T, Tt.T)
+    np.testing.assert_array_equal(U, Vt)
+    np.testing.assert_array_equal(V, Ut)
+    assert U.shape == (45, 45) and V.shape == (70, 70)
+    _check_utv(A.T, V, T.T, U, 8)
+    _, Tn, Vn = randutv_boosted(A, 8, 1, 8, 5, want_u=False)
+    np.testing.assert_array_equal(Tn, T)
+    np.testing.assert_array_equal(Vn, V)

@@ -211,3 +211,25 @@ def test_mixed_resolution_limit():
     assert all(ek[i] <= max(1.5 * s[ks[i]], 1.1 * env[i]) for i in hi)
     r = ek[lo] / env[lo]
     assert 1.2 < r.max() < 6.0, r
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_wide_matrix_through_the_transpose(precision):
+    """m < n (the reading of Sec. 3.2 used for randUTV): A = U T V^T with
+    T = T'^T lower trapezoidal, A^T = U' T' V'^T being the tall transpose's
+    factorization; U, V orthogonal, the singular values kept."""
+    A = np.random.default_rng(13).standard_normal((30, 52))
+    U, T, V = oracle.powerurv(A, 1, 4, precision=precision)
+    Ut, Tt, Vt = oracle.powerurv(A.T, 1, 4, precision=precision)
+    np.testing.assert_array_equal(T, Tt.T)
+    np.testing.assert_array_equal(U, Vt)
+    np.testing.assert_array_equal(V, Ut)
+    assert U.shape == (30, 30) and T.shape == (30, 52) and V.shape == (52, 52)
+    assert np.all(np.triu(T, 1) == 0.0)
+    nA = np.linalg.norm(A, 2)
+    assert M.orth_error(U) < 1e-13 and M.orth_error(V) < 1e-13
+    assert np.linalg.norm(A - U @ T @ V.T, 2) < 1e-13 * nA
+    np.testing.assert_allclose(np.linalg.svd(T, compute_uv=False),
+                               np.linalg.svd(A, compute_uv=False), atol=1e-13 * nA)
+    with pytest.raises(ValueError):
+        oracle.powerurv(A, 1, 4, rounds=1)
