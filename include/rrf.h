@@ -168,6 +168,9 @@ size_t rrf_rsvd_workspace_size(int64_t m, int64_t n, int64_t l, int32_t q);
  * upper triangular with diagonal, non-negative, descending b x b blocks,
  * and T22 = T(k:m, k:n) the unreduced remainder (U, V the product of the
  * steps taken). tol = 0 and kmax >= n give rrf_randutv_ex's result.
+ * m < n goes through the transpose as for rrf_randutv: k counts the
+ * transpose's reduced columns (k <= m), T = [T11 0; T21 T22] with T11
+ * lower triangular, and the workspace is rrf_workspace_size's for m < n.
  *
  *  m, n, A, lda, b, q, seed : as for rrf_randutv            (args 1-7)
  *  tol    : relative Frobenius tolerance, tol >= 0         (arg 8)
@@ -189,14 +192,18 @@ int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int6
  * with the new criteria (to rounding: U and V are continued by applying the
  * new steps' Householder transforms to them). ||A||_F is taken as ||T||_F.
  *
- *  m, n   : as for rrf_randutv (m >= n)                    (args 1, 2)
+ *  m, n   : as for rrf_randutv                             (args 1, 2)
  *  b, q, seed : the values of the interrupted call         (args 3-5)
  *  tol, kmax  : the new stopping criteria                  (args 6, 7)
- *  k_in   : columns already reduced (the k it returned)    (arg 8)
+ *  k_in   : columns already reduced (the k it returned), a multiple of b
+ *           in [0, min(m, n)] or min(m, n) itself           (arg 8)
  *  U, T, V: in/out, U m x m (or NULL), T m x n, V n x n (or NULL), the
  *           arrays the interrupted call filled             (args 9-11)
  *  k_out  : host int64 receiving the new k                 (arg 12)
  *  opts   : as for rrf_randutv_partial; thin_u is rejected (RRF_E_NOTSUP)
+ * m < n: the state is that of a wide rrf_randutv_partial (T lower
+ * trapezoidal); T is transposed into the workspace, the transpose's steps
+ * continue (V carrying its U, U its V) and the result is transposed back.
  */
 int rrf_randutv_resume(int64_t m, int64_t n, int64_t b, int32_t q, uint64_t seed, double tol,
                        int64_t kmax, int64_t k_in, double* U, double* T, double* V,

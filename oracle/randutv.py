@@ -137,6 +137,12 @@ def randutv_partial(A: np.ndarray, b: int, q: int, seed: int, tol: float, kmax: 
     e_i = ||T(c0:, c0:)||_F <= tol ||A||_F. Returns ``(U, T, V, k)`` with
     k = the columns already reduced (T(k:, k:) is the unreduced remainder
     and A = U T V^T holds exactly as for the full factorization)."""
+    A = np.asarray(A, dtype=np.float64)
+    if A.shape[0] < A.shape[1]:
+        # a wide matrix through its transpose (Sec. 3.2), k counting the
+        # transpose's reduced columns
+        Ut, Tt, Vt, k = randutv_partial(A.T, b, q, seed, tol, kmax, want_u=want_v, want_v=want_u)
+        return Vt, np.asfortranarray(Tt.T), Ut, k
     e0 = float(np.linalg.norm(A))
     done = [0]
 

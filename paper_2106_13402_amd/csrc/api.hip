@@ -229,12 +229,15 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q, i
 
 // m < n (Sec. 3.2: the paper factors the transpose): A^T = U' T' V'^T, so
 // A = V' T'^T U'^T; U' is written to V, V' to U, and T = T'^T is lower
-// trapezoidal. alg and boost_p as in run_alg; thin_u does not apply (U is
-// m x m = m x min(m, n) already).
+// trapezoidal. alg, boost_p and ptr_shift as in run_alg; stop as for
+// randutv_run (a resumed state is the transpose's: T is transposed in, the
+// caller's V continues U' and U continues V'); a_arg numbers A's pointer in
+// error codes. thin_u does not apply (U is m x m = m x min(m, n) already).
 static int wide_run(int alg, int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
                     int32_t q, uint64_t seed, double* U, double* T, double* V,
-                    const rrf_opts* opts, int64_t boost_p = -1) {
-  const int shift = boost_p >= 0 ? 1 : 0;
+                    const rrf_opts* opts, int64_t boost_p = -1, const EarlyStop* stop = nullptr,
+                    int ptr_shift = -1, int a_arg = 3) {
+  const int shift = ptr_shift >= 0 ? ptr_shift : (boost_p >= 0 ? 1 : 0);
   RRF_TRY(check_args(m, n, A, lda, b, q, T, shift, true));
   rrf_opts o;
   rrf_opts_init(&o);
@@ -252,7 +255,7 @@ static int wide_run(int alg, int64_t m, int64_t n, const double* A, int64_t lda,
     return set_error(RRF_E_NOTSUP, "block size or shape outside the panel kernel limits");
   int dev = 0;
   RRF_TRY(device_ready(&dev));
-  RRF_TRY(check_device_ptr(A, 3));
+  RRF_TRY(check_device_ptr(A, a_arg));
   RRF_TRY(check_device_ptr(U, 8 + shift));
   RRF_TRY(check_device_ptr(T, 9 + shift));
   RRF_TRY(check_device_ptr(V, 10 + shift));
@@ -281,7 +284,7 @@ static int wide_run(int alg, int64_t m, int64_t n, const double* A, int64_t lda,
   if (alg == RRF_ALG_RANDUTV) {
     int dummy = 0;
     RRF_TRY(randutv_run(st, n, m, At, n, b, q, seed, V, Tt, U, ws, arena, false, o.precision,
-                        &dummy, boost_p));
+                        &dummy, boost_p, stop));
   } else {
     RRF_TRY(powerurv_run(st, n, m, At, n, b, q, seed, V, Tt, U, ws, arena, false, o.precision));
   }
@@ -344,6 +347,8 @@ int rrf_randutv_partial(int64_t m, int64_t n, const double* A, int64_t lda, int6
   rrf_opts_init(&o);
   if (opts) o = *opts;
   o.async = 0;  // the stopping test reads each step's norm on the host
+  if (m >= 1 && n >= 1 && m < n)
+    return wide_run(RRF_ALG_RANDUTV, m, n, A, lda, b, q, seed, U, T, V, &o, -1, &stop, 2);
   return run_alg(RRF_ALG_RANDUTV, m, n, A, lda, b, q, U, T, V, &o,
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {
                    int dummy = 0;
@@ -362,8 +367,9 @@ int rrf_randutv_resume(int64_t m, int64_t n, int64_t b, int32_t q, uint64_t seed
   if (q < 0) return set_error(-4, "q must be >= 0"), -4;
   if (!(tol >= 0.0)) return set_error(-6, "tol must be >= 0"), -6;
   if (kmax < 0) return set_error(-7, "kmax must be >= 0"), -7;
-  if (k_in < 0 || k_in > n || (k_in % b != 0 && k_in != n))
-    return set_error(-8, "k_in must be a multiple of b in [0, n] (or n)"), -8;
+  const int64_t kdim = std::min(m, n);  // m < n: the transpose's column count
+  if (k_in < 0 || k_in > kdim || (k_in % b != 0 && k_in != kdim))
+    return set_error(-8, "k_in must be a multiple of b in [0, min(m, n)] (or min(m, n))"), -8;
   if (T == nullptr) return set_error(-10, "T is NULL"), -10;
   if (k_out == nullptr) return set_error(-12, "k_out is NULL"), -12;
   *k_out = k_in;
@@ -372,8 +378,10 @@ int rrf_randutv_resume(int64_t m, int64_t n, int64_t b, int32_t q, uint64_t seed
   if (opts) o = *opts;
   if (o.thin_u) return set_error(RRF_E_NOTSUP, "resume needs the full m x m U");
   o.async = 0;
-  if (k_in >= n) return RRF_OK;  // nothing left to reduce
+  if (k_in >= kdim) return RRF_OK;  // nothing left to reduce
   EarlyStop stop{tol, kmax, k_out, k_in / b};
+  if (m < n)  // the state is the transpose's, T = T'^T (factored from a copy)
+    return wide_run(RRF_ALG_RANDUTV, m, n, T, m, b, q, seed, U, T, V, &o, -1, &stop, 1, 10);
   // T holds the state and is factored in place (A = T, lda = m)
   return run_alg(RRF_ALG_RANDUTV, m, n, T, m, b, q, U, T, V, &o,
                  [&](hipStream_t st, void* ws, size_t bytes, bool chk) {

@@ -180,6 +180,9 @@ def test_partial_argument_errors(lib):
     assert f(8, 8, DUMMY, 8, 4, 1, 1, 1e-3, 8, NULL, DUMMY, NULL, None, NULL) == -13
     assert f(8, 8, DUMMY, 8, 4, 1, 1, 1e-3, 8, NULL, NULL, NULL, C.byref(k), NULL) == -11
     assert f(8, 8, DUMMY, 7, 4, 1, 1, 1e-3, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == -4
+    # m < n goes through the transpose; its arguments are checked the same way
+    assert f(6, 9, DUMMY, 5, 4, 1, 1, 1e-3, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == -4
+    assert f(6, 9, DUMMY, 6, 4, 1, 1, 1e-3, 8, NULL, NULL, NULL, C.byref(k), NULL) == -11
 
 
 def test_rsvd_argument_errors(lib):
@@ -207,6 +210,9 @@ def test_resume_argument_errors(lib):
     assert f(8, 8, 4, 1, 1, 1e-3, 8, 4, NULL, DUMMY, NULL, None, NULL) == -12
     # everything already reduced: nothing to do, k unchanged
     assert f(8, 8, 4, 1, 1, 1e-3, 8, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == 0 and k.value == 8
+    # m < n: k_in counts the transpose's columns, at most min(m, n)
+    assert f(6, 9, 4, 1, 1, 1e-3, 8, 8, NULL, DUMMY, NULL, C.byref(k), NULL) == -8
+    assert f(6, 9, 4, 1, 1, 1e-3, 8, 6, NULL, DUMMY, NULL, C.byref(k), NULL) == 0 and k.value == 6
 
 
 def _arr(t, vals):

@@ -87,3 +87,39 @@ def test_resume_matches_one_partial_run(gpu, tol1, tol2, kmax2):
     assert M.recon_error(A, U, T, V) <= 1e-13
     if k2 == ko:
         np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * M.spec(A))
+
+
+@pytest.mark.parametrize("tol,kmax", [(1e-5, None), (0.0, 32)])
+def test_partial_wide_parity(gpu, tol, kmax):
+    """m < n through the transpose: same k as the oracle (which takes the
+    same route), T(:k, k:) = 0, |T| within 1e-9 ||A||, A = U T V^T."""
+    print(f"case: partial wide tol={tol} kmax={kmax}", flush=True)
+    m, n, b = 120, 200, 16
+    A = spectral_matrix(n, m, spectrum("geometric", m, decades=8.0), seed=2).T.copy(order="F")
+    U, T, V, k = _run(A, b, 1, 3, tol, kmax, gpu)
+    _, To, _, ko = oracle.randutv_partial(A, b, 1, 3, tol, n if kmax is None else kmax,
+                                          want_u=False, want_v=False)
+    assert k == ko and 0 < k < m
+    assert U.shape == (m, m) and V.shape == (n, n)
+    assert M.orth_error(U) <= 1e-13 and M.orth_error(V) <= 1e-13
+    assert M.recon_error(A, U, T, V) <= 1e-13
+    assert np.all(T[:k, k:] == 0.0)
+    _check_blocks(T[:k, :k].T, b)
+    np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * M.spec(A))
+
+
+def test_resume_wide(gpu):
+    """m < n: partial(1e-2) then resume(1e-6) equals the oracle's single
+    partial run at 1e-6."""
+    from paper_2106_13402_amd import randutv_partial, randutv_resume
+    print("case: resume wide", flush=True)
+    m, n, b = 120, 200, 16
+    A = spectral_matrix(n, m, spectrum("geometric", m, decades=8.0), seed=2).T.copy(order="F")
+    U, T, V, k1 = randutv_partial(_to_dev(A, gpu), b, 1, 3, 1e-2)
+    k2 = randutv_resume(U, T, V, k1, b, 1, 3, 1e-6)
+    _, To, _, ko = oracle.randutv_partial(A, b, 1, 3, 1e-6, n, want_u=False, want_v=False)
+    assert 0 < k1 < k2 == ko
+    U, T, V = _host(U), _host(T), _host(V)
+    assert M.orth_error(U) <= 1e-13 and M.orth_error(V) <= 1e-13
+    assert M.recon_error(A, U, T, V) <= 1e-13
+    np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * M.spec(A))

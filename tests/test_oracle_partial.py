@@ -77,3 +77,31 @@ def test_frobenius_update_formula_of_the_paper():
 
     oracle.randutv(A, b, 1, 7, on_step=on_step)
     np.testing.assert_allclose(rec[:-1], direct[:-1], rtol=0, atol=100 * n * U64 * e0sq)
+
+
+@pytest.mark.parametrize("tol,kmax", [(1e-5, 10 ** 6), (0.0, 32)])
+def test_partial_wide_through_the_transpose(tol, kmax):
+    """m < n (Sec. 3.2, as for the full run): the transpose's early stop,
+    transposed back. k is where the full wide run's trailing norm first meets
+    the criteria, T(:k, :k) is the full run's (lower triangular), T(:k, k:) = 0
+    and A = U T V^T."""
+    m, n, b = 120, 200, 16
+    A = spectral_matrix(n, m, spectrum("geometric", m, decades=8.0), seed=2).T.copy()
+    e0 = np.linalg.norm(A)
+    _, Tf, _ = _full(A, b, 1, 3)
+    U, T, V, k = oracle.randutv_partial(A, b, 1, 3, tol, kmax)
+    Ut, Tt, Vt, kt = oracle.randutv_partial(A.T, b, 1, 3, tol, kmax)
+    assert k == kt
+    np.testing.assert_array_equal(T, Tt.T)
+    np.testing.assert_array_equal(U, Vt)
+    np.testing.assert_array_equal(V, Ut)
+    want = m
+    for c0 in range(0, m, b):
+        if c0 >= kmax or np.linalg.norm(Tf[c0:, c0:]) <= tol * e0:
+            want = c0
+            break
+    assert k == want and 0 < k < m
+    np.testing.assert_array_equal(T[:k, :k], Tf[:k, :k])
+    assert np.all(np.triu(T[:k, :k], 1) == 0.0) and np.all(T[:k, k:] == 0.0)
+    assert M.orth_error(U) < 1e-13 and M.orth_error(V) < 1e-13
+    assert M.recon_error(A, U, T, V) < 1e-13
