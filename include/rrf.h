@@ -278,7 +278,7 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
  * agree to rounding, as the products are summed in another order).
  *
  *  count  : number of matrices, >= 0 (0: nothing to do)              (arg 1)
- *  m, n   : host arrays of count sizes, 1 <= n[j] <= m[j] <= 4096   (args 2, 3)
+ *  m, n   : host arrays of count sizes, 1 <= m[j], n[j] <= 4096      (args 2, 3)
  *  A      : host array of count device pointers, read only unless T[j] == A[j]
  *                                                                     (arg 4)
  *  lda    : host array, lda[j] >= m[j]                                (arg 5)
@@ -294,8 +294,10 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
  *  opts   : as for rrf_randutv_ex (RRF_PREC_FP64, or RRF_PREC_BF16_SKETCH for
  *           the bfloat16 sketch of every step); the workspace must hold
  *           rrf_randutv_batched_workspace_size(count, m, n, b, precision) bytes
- * The output of every matrix has the form rrf_randutv documents. The host
- * arrays are read during the call only. The call keeps a small pinned host
+ * The output of every matrix has the form rrf_randutv documents, a wide one
+ * (m[j] < n[j]) included: it is factored through its transpose, in a
+ * lockstep group of its own, from a copy of A[j]^T held in the workspace
+ * (T lower trapezoidal). The host arrays are read during the call only. The call keeps a small pinned host
  * staging ring per device (freed by rrf_release_workspace) and may wait for
  * earlier work on `stream` while it enqueues.
  */
@@ -304,10 +306,11 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
                         int32_t q, uint64_t seed, double* const* U, double* const* T,
                         double* const* V, const rrf_opts* opts);
 /* The block size rrf_randutv_batched uses for an m x n matrix when called
- * with b = 0 (16 for n <= 256, else 32); 0 for invalid sizes. */
+ * with b = 0 (16 for min(m, n) <= 256, else 32); 0 for invalid sizes. */
 int64_t rrf_randutv_batched_block(int64_t m, int64_t n);
-/* Bytes of device workspace for rrf_randutv_batched; 0 for invalid sizes or
- * precision. */
+/* Bytes of device workspace for rrf_randutv_batched (the largest group's,
+ * plus 8 m[j] n[j] bytes for each wide matrix's transposed copy); 0 for
+ * invalid sizes or precision. */
 size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m,
                                           const int64_t* n, int64_t b, int precision);
 

@@ -438,32 +438,78 @@ int rrf_randutv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, i
 }
 
 int64_t rrf_randutv_batched_block(int64_t m, int64_t n) {
-  if (n < 1 || m < n) return 0;
-  return randutv_batched_block(m, n);
+  if (m < 1 || n < 1) return 0;
+  return randutv_batched_block(std::max(m, n), std::min(m, n));  // m < n: the transpose's
 }
+
+}  // extern "C"
+
+namespace rrf {
+namespace {
+
+// The batched call runs its matrices in groups, one lockstep run each: per
+// block size (b, or the automatic rule) and per orientation. A wide matrix
+// (m < n) enters its group as its transpose (Sec. 3.2, as for rrf_randutv):
+// A^T is copied into a buffer of its own after the runs' arena, factored
+// there in place with U and V exchanged, and T = T'^T is copied back.
+struct BatchedGroup {
+  std::vector<int64_t> m, n;  // the factored shape (m >= n)
+  std::vector<int64_t> idx;   // caller's matrix index
+};
+
+std::vector<std::pair<int64_t, BatchedGroup>> batched_groups(int64_t count, const int64_t* m,
+                                                             const int64_t* n, int64_t b) {
+  std::vector<std::pair<int64_t, BatchedGroup>> out;
+  const std::vector<int64_t> blocks = b > 0 ? std::vector<int64_t>{b} : std::vector<int64_t>{16, 32};
+  for (int64_t bg : blocks)
+    for (int wide = 0; wide < 2; ++wide) {
+      BatchedGroup g;
+      for (int64_t j = 0; j < count; ++j) {
+        if ((m[j] < n[j]) != (wide == 1)) continue;
+        const int64_t M = std::max(m[j], n[j]), N = std::min(m[j], n[j]);
+        if (b == 0 && randutv_batched_block(M, N) != bg) continue;
+        g.m.push_back(M);
+        g.n.push_back(N);
+        g.idx.push_back(j);
+      }
+      if (!g.idx.empty()) out.emplace_back(bg, std::move(g));
+    }
+  return out;
+}
+
+size_t wide_copy_bytes(int64_t m, int64_t n) {
+  return m < n ? (size_t)round_up(m * n * 8, 256) : 0;
+}
+
+// Arena of the largest group (0 if a group is outside the kernel limits).
+size_t batched_arena(int64_t count, const int64_t* m, const int64_t* n, int64_t b, int precision) {
+  size_t arena = 0;
+  for (const auto& [bg, g] : batched_groups(count, m, n, b)) {
+    const size_t w = randutv_batched_workspace((int64_t)g.idx.size(), g.m.data(), g.n.data(), bg,
+                                               precision);
+    if (w == 0) return 0;
+    arena = std::max(arena, w);
+  }
+  return arena;
+}
+
+}  // namespace
+}  // namespace rrf
+
+extern "C" {
 
 size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m, const int64_t* n,
                                           int64_t b, int precision) {
-  if (count < 0 || (count > 0 && (m == nullptr || n == nullptr)) || b < 0 || b > kBatchedMaxB)
-    return 0;
+  if (count <= 0 || m == nullptr || n == nullptr || b < 0 || b > kBatchedMaxB) return 0;
   if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH) return 0;
-  for (int64_t j = 0; j < count; ++j)
-    if (n[j] < 1 || m[j] < n[j] || m[j] > kBatchedMaxDim) return 0;
-  if (b > 0) return count > 0 ? randutv_batched_workspace(count, m, n, b, precision) : 0;
-  // automatic block size: the groups run one after another in one workspace
-  size_t need = 0;
-  for (int64_t bg : {16, 32}) {
-    std::vector<int64_t> gm, gn;
-    for (int64_t j = 0; j < count; ++j)
-      if (randutv_batched_block(m[j], n[j]) == bg) {
-        gm.push_back(m[j]);
-        gn.push_back(n[j]);
-      }
-    if (!gm.empty())
-      need = std::max(need, randutv_batched_workspace((int64_t)gm.size(), gm.data(), gn.data(), bg,
-                                                      precision));
+  size_t wide = 0;
+  for (int64_t j = 0; j < count; ++j) {
+    if (m[j] < 1 || n[j] < 1 || std::max(m[j], n[j]) > kBatchedMaxDim) return 0;
+    wide += wide_copy_bytes(m[j], n[j]);
   }
-  return need;
+  const size_t arena = batched_arena(count, m, n, b, precision);
+  if (arena == 0) return 0;
+  return wide == 0 ? arena : (size_t)round_up((int64_t)arena, 256) + wide;
 }
 
 int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
@@ -479,6 +525,7 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
   if (b < 0 || b > kBatchedMaxB) return set_error(-6, "b must be 0 or in [1, 64]"), -6;
   if (q < 0) return set_error(-7, "q must be >= 0"), -7;
   if (T == nullptr) return set_error(-10, "T is NULL"), -10;
+  size_t wide_bytes = 0;
   for (int64_t j = 0; j < count; ++j) {
     if (m[j] < 1) return set_error(-2, "m[j] must be >= 1"), -2;
     if (n[j] < 1) return set_error(-3, "n[j] must be >= 1"), -3;
@@ -489,9 +536,9 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
     if (V && V[j] == nullptr) return set_error(-11, "V[j] is NULL"), -11;
     if (T[j] == A[j] && lda[j] != m[j])
       return set_error(-5, "T[j] may alias A[j] only when lda[j] == m[j]"), -5;
-    if (m[j] < n[j]) return set_error(RRF_E_NOTSUP, "m < n is not supported (factor A^T instead)");
-    if (m[j] > kBatchedMaxDim)
-      return set_error(RRF_E_NOTSUP, "batched randutv: m above 4096 (use rrf_randutv)");
+    if (std::max(m[j], n[j]) > kBatchedMaxDim)
+      return set_error(RRF_E_NOTSUP, "batched randutv: m or n above 4096 (use rrf_randutv)");
+    wide_bytes += wide_copy_bytes(m[j], n[j]);
   }
   rrf_opts o;
   rrf_opts_init(&o);
@@ -507,6 +554,7 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
     if (V) RRF_TRY(check_device_ptr(V[j], 11));
   }
   const size_t need = rrf_randutv_batched_workspace_size(count, m, n, b, o.precision);
+  if (need == 0) return set_error(RRF_E_NOTSUP, "batched randutv: sizes outside the kernel limits");
   void* ws = o.workspace;
   size_t ws_bytes = o.workspace_bytes;
   if (ws == nullptr) {
@@ -514,6 +562,17 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
     ws_bytes = need;
   } else if (ws_bytes < need) {
     return set_error(RRF_E_NOMEM, "workspace smaller than rrf_randutv_batched_workspace_size()");
+  }
+  // the runs' arena first, then the transposed copies of the wide matrices
+  const size_t arena_bytes = need - wide_bytes;
+  std::vector<double*> Wt(count, nullptr);
+  {
+    char* base = reinterpret_cast<char*>(ws) + arena_bytes;
+    for (int64_t j = 0; j < count; ++j) {
+      if (m[j] >= n[j]) continue;
+      Wt[j] = reinterpret_cast<double*>(base);
+      base += wide_copy_bytes(m[j], n[j]);
+    }
   }
   hipStream_t st = reinterpret_cast<hipStream_t>(o.stream);
   int* status = reinterpret_cast<int*>(ws);
@@ -525,34 +584,33 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
     RRF_CHECK_HIP(hipStreamSynchronize(st));
     if (h) return set_error(RRF_E_NUMERIC, "input holds NaN or infinity");
   }
-  std::vector<uint64_t> seeds(count);
-  for (int64_t j = 0; j < count; ++j) seeds[j] = seed + (uint64_t)j;
-  if (b > 0) {
-    RRF_TRY(randutv_batched_run(st, count, m, n, A, lda, b, q, seeds.data(), U, T, V, ws, ws_bytes,
-                                o.precision));
-  } else {
-    for (int64_t bg : {16, 32}) {
-      std::vector<int64_t> gm, gn, gl;
-      std::vector<const double*> gA;
-      std::vector<double*> gU, gT, gV;
-      std::vector<uint64_t> gs;
-      for (int64_t j = 0; j < count; ++j) {
-        if (randutv_batched_block(m[j], n[j]) != bg) continue;
-        gm.push_back(m[j]);
-        gn.push_back(n[j]);
-        gl.push_back(lda[j]);
-        gA.push_back(A[j]);
-        gT.push_back(T[j]);
-        if (U) gU.push_back(U[j]);
-        if (V) gV.push_back(V[j]);
-        gs.push_back(seeds[j]);
-      }
-      if (gm.empty()) continue;
-      RRF_TRY(randutv_batched_run(st, (int64_t)gm.size(), gm.data(), gn.data(), gA.data(),
-                                  gl.data(), bg, q, gs.data(), U ? gU.data() : nullptr, gT.data(),
-                                  V ? gV.data() : nullptr, ws, ws_bytes, o.precision));
+  for (int64_t j = 0; j < count; ++j)
+    if (Wt[j]) RRF_TRY(transpose_matrix(st, m[j], n[j], A[j], lda[j], Wt[j], n[j]));
+  for (const auto& [bg, g] : batched_groups(count, m, n, b)) {
+    const int64_t cnt = (int64_t)g.idx.size();
+    const bool wide = m[g.idx[0]] < n[g.idx[0]];
+    // the factored matrix's U is the caller's V for a wide matrix, and vice versa
+    double* const* Uf = wide ? V : U;
+    double* const* Vf = wide ? U : V;
+    std::vector<int64_t> gl(cnt);
+    std::vector<const double*> gA(cnt);
+    std::vector<double*> gU, gT(cnt), gV;
+    std::vector<uint64_t> gs(cnt);
+    for (int64_t t = 0; t < cnt; ++t) {
+      const int64_t j = g.idx[t];
+      gl[t] = wide ? n[j] : lda[j];
+      gA[t] = wide ? Wt[j] : A[j];
+      gT[t] = wide ? Wt[j] : T[j];
+      if (Uf) gU.push_back(Uf[j]);
+      if (Vf) gV.push_back(Vf[j]);
+      gs[t] = seed + (uint64_t)j;  // matrix j is keyed by seed + j
     }
+    RRF_TRY(randutv_batched_run(st, cnt, g.m.data(), g.n.data(), gA.data(), gl.data(), bg, q,
+                                gs.data(), Uf ? gU.data() : nullptr, gT.data(),
+                                Vf ? gV.data() : nullptr, ws, arena_bytes, o.precision));
   }
+  for (int64_t j = 0; j < count; ++j)
+    if (Wt[j]) RRF_TRY(transpose_matrix(st, n[j], m[j], Wt[j], n[j], T[j], m[j]));
   if (o.async) return RRF_OK;
   return finish(st, status);
 }

@@ -237,8 +237,10 @@ def test_batched_argument_errors(lib):
     assert f(2, m, n, A, _arr(C.c_int64, [9, 6]), 4, 1, 1, NULL, alias, NULL, NULL) == -5
     one_null = _arr(C.c_void_p, [0x5000, 0])
     assert f(2, m, n, A, lda, 4, 1, 1, one_null, T, NULL, NULL) == -9
+    # a wide matrix goes through its transpose; its arguments are still checked
     wide = _arr(C.c_int64, [8, 7])
-    assert f(2, m, wide, A, lda, 4, 1, 1, NULL, T, NULL, NULL) == _lib.RRF_E_NOTSUP
+    assert f(2, m, wide, A, bad_lda, 4, 1, 1, NULL, T, NULL, NULL) == -5
+    assert f(2, m, wide, A, lda, 4, 1, 1, one_null, T, NULL, NULL) == -9
     huge = _arr(C.c_int64, [8, 5000])
     assert f(2, huge, n, A, _arr(C.c_int64, [8, 5000]), 4, 1, 1, NULL, T, NULL,
              NULL) == _lib.RRF_E_NOTSUP
@@ -256,7 +258,11 @@ def test_batched_workspace_size(lib):
     assert refl < w16 and refl < w64
     assert wauto <= max(w16, w64)
     assert f(3, m, n, 65, 0) == 0
-    assert f(3, m, _arr(C.c_int64, [64, 301, 512]), 16, 0) == 0   # n > m
+    # n > m: the transpose's arena plus the transposed copy (8 m n bytes, rounded)
+    wn = f(3, m, _arr(C.c_int64, [64, 301, 512]), 16, 0)
+    wt = f(3, _arr(C.c_int64, [100, 301, 512]), _arr(C.c_int64, [64, 300, 512]), 16, 0)
+    assert wn >= 8 * 300 * 301 and wn > 0 and wt > 0
+    assert f(1, _arr(C.c_int64, [4]), _arr(C.c_int64, [4097]), 16, 0) == 0
     assert f(1, _arr(C.c_int64, [4097]), _arr(C.c_int64, [4]), 16, 0) == 0
     assert f(2, m, n, 16, 0) < w16
     # the mixed sketch adds bfloat16 copies of T22 (both layouts), G, Y, Z and FP32 products
@@ -268,4 +274,5 @@ def test_batched_workspace_size(lib):
 def test_batched_block_rule(lib):
     f = lib.rrf_randutv_batched_block
     assert f(100, 64) == 16 and f(512, 256) == 16 and f(300, 257) == 32 and f(1024, 512) == 32
-    assert f(10, 11) == 0 and f(5, 0) == 0
+    assert f(10, 11) == f(11, 10) == 16 and f(300, 600) == 32  # m < n: the transpose's rule
+    assert f(5, 0) == 0 and f(0, 5) == 0

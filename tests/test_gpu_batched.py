@@ -194,3 +194,37 @@ def test_batched_slices(gpu):
         _check_blocks(Ts[j], 8)
         _, To, _ = oracle.randutv(A, 8, 1, 60 + j, want_u=False, want_v=False)
         np.testing.assert_allclose(np.abs(Ts[j]), np.abs(To), atol=1e-9 * M.spec(A))
+
+
+@pytest.mark.parametrize("b,want_u,want_v", [(0, True, True), (16, True, False), (8, False, True)])
+def test_batched_wide_through_transpose(gpu, b, want_u, want_v):
+    """Wide matrices (m < n) in one batch with tall ones: each is factored
+    through its transpose in a group of its own (U and V exchanged, T = T'^T
+    lower trapezoidal), keyed by seed + j like the rest; |T| equals the
+    oracle's (which takes the same route) and A = U T V^T."""
+    print(f"case: batched wide b={b} want_u={want_u} want_v={want_v}", flush=True)
+    shapes = [(80, 120), (120, 80), (50, 200), (1, 7), (64, 64), (257, 300), (30, 31)]
+    As = [gaussian_matrix(n, m, seed=500 + j).T.copy(order="F") if m < n
+          else gaussian_matrix(m, n, seed=500 + j) for j, (m, n) in enumerate(shapes)]
+    Us, Ts, Vs = _run(As, b, 1, 60, gpu, want_u=want_u, want_v=want_v)
+    assert (Us is None) != want_u and (Vs is None) != want_v
+    for j, A in enumerate(As):
+        m, n = A.shape
+        bj = b if b > 0 else _auto_b(min(m, n))
+        T = Ts[j]
+        assert T.shape == (m, n)
+        if m < n:
+            assert np.all(np.triu(T, 1) == 0.0)
+            _check_blocks(T.T, bj)
+        else:
+            assert np.all(np.tril(T, -1) == 0.0)
+            _check_blocks(T, bj)
+        if want_u and want_v:
+            assert M.orth_error(Us[j]) <= 1e-13 and M.orth_error(Vs[j]) <= 1e-13
+            assert M.recon_error(A, Us[j], T, Vs[j]) <= 1e-13
+        elif want_u:
+            assert Us[j].shape == (m, m) and M.orth_error(Us[j]) <= 1e-13
+        else:
+            assert Vs[j].shape == (n, n) and M.orth_error(Vs[j]) <= 1e-13
+        _, To, _ = oracle.randutv(A, bj, 1, 60 + j, want_u=False, want_v=False)
+        np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * M.spec(A))
