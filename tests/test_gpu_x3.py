@@ -164,3 +164,17 @@ def test_randutv_x3_differs_from_bf16_sketch(gpu):
     _, T3b, _ = _factor_x3(A, b, 1, 7, gpu)
     np.testing.assert_array_equal(T3, T3b)
     assert np.abs(T3 - T1).max() > 1e-9 * np.abs(A).max()
+
+
+def test_randutv_x3_wide(gpu):
+    """m < n in the x3 mode: the transpose's factorization (U and V
+    exchanged, T lower trapezoidal) to the same x3 accuracy and e_k gate as a
+    tall input."""
+    m, n, b, q = 300, 520, 64, 1
+    s = spectrum("exp", m, scale=m / 2.0)
+    A = spectral_matrix(n, m, s, seed=2).T.copy(order="F")
+    print(f"case: randutv x3 wide m={m} n={n} b={b} q={q}", flush=True)
+    U, T, V = _factor_x3(A, b, q, 3, gpu)
+    assert U.shape == (m, m) and T.shape == (m, n) and V.shape == (n, n)
+    rec = _check_x3(A.T, V, T.T, U, b, 1e-4)
+    _mixed_gate(T.T, A.T, b, q, 3, s, rec)
