@@ -413,6 +413,11 @@ typedef struct rrf_trace_entry {
   double bytes;      /* summed algorithmic HBM bytes (read + written)      */
 } rrf_trace_entry;
 int rrf_trace_enable(int on);
+/* Like rrf_trace_enable(1), but records events around the launches of one
+ * kernel class only (a name rrf_trace_read reports, ":UV" suffix included),
+ * so that timing one class leaves the other launches uninstrumented.
+ * Returns -1 for NULL or an unknown name. rrf_trace_enable ends the filter. */
+int rrf_trace_enable_class(const char* name);
 int rrf_trace_read(rrf_trace_entry* out, int max_entries);
 
 #ifdef __cplusplus

@@ -17,7 +17,7 @@ from ._lib import RRFError
 
 __all__ = [
     "RRFError", "randutv", "randutv_boosted", "randutv_partial", "randutv_resume", "rsvd", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
-    "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable",
+    "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable", "trace_enable_class",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
     "batched_workspace_size", "batched_block",
 ]
@@ -380,6 +380,11 @@ def householder_panel(P, *, inplace: bool = False):
 def trace_enable(on: bool = True) -> None:
     """Switch the library's per-kernel event timing on/off (clears totals)."""
     _check(lib.rrf_trace_enable(1 if on else 0), "rrf_trace_enable")
+
+
+def trace_enable_class(name: str) -> None:
+    """Time only the launches of one kernel class (clears totals)."""
+    _check(lib.rrf_trace_enable_class(name.encode()), "rrf_trace_enable_class")
 
 
 def trace_read() -> list[dict]:

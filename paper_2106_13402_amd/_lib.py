@@ -92,6 +92,7 @@ PROTOTYPES = {
     "rrf_gemm_bf16_tn": (C.c_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _dp, _i64,
                                    _vp, _sz, _vp]),
     "rrf_trace_enable": (C.c_int, [C.c_int]),
+    "rrf_trace_enable_class": (C.c_int, [C.c_char_p]),
     "rrf_trace_read": (C.c_int, [C.POINTER(rrf_trace_entry), C.c_int]),
     "rrf_status_string": (C.c_char_p, [C.c_int]),
     "rrf_last_error": (C.c_char_p, []),

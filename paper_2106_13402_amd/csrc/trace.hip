@@ -6,6 +6,7 @@
 // as separate classes, named with a ":UV" suffix.
 #include <cstring>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -30,6 +31,7 @@ struct Totals {
 
 std::mutex g_mu;
 bool g_on = false;
+int g_only = -1;  // trace only this class index (-1: all)
 std::unordered_map<int, Record> g_pending;  // by token
 int g_next = 0;
 std::vector<hipEvent_t> g_free;
@@ -97,6 +99,7 @@ int trace_begin(hipStream_t st, int cls, double flops, double bytes) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (hipStream_t m : g_marked)
     if (m == st) cls += kTraceClasses;
+  if (g_only >= 0 && cls != g_only) return -1;
   Record r{cls, flops, bytes, get_event(), get_event(), false};
   if (r.e0) (void)hipEventRecord(r.e0, st);
   const int token = g_next;
@@ -130,6 +133,24 @@ int rrf_trace_enable(int on) {
   drain_locked();
   for (auto& t : g_tot) t = Totals{};
   g_on = on != 0;
+  g_only = -1;
+  return RRF_OK;
+}
+
+int rrf_trace_enable_class(const char* name) {
+  if (name == nullptr) return set_error(-1, "name is NULL"), -1;
+  const size_t len = strlen(name);
+  const bool uv = len > 3 && strcmp(name + len - 3, ":UV") == 0;
+  const std::string base(name, uv ? len - 3 : len);
+  int cls = -1;
+  for (int c = 0; c < kTraceClasses; ++c)
+    if (base == kNames[c]) cls = c + (uv ? kTraceClasses : 0);
+  if (cls < 0) return set_error(-1, "unknown kernel class"), -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  drain_locked();
+  for (auto& t : g_tot) t = Totals{};
+  g_on = true;
+  g_only = cls;
   return RRF_OK;
 }
 

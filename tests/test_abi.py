@@ -276,3 +276,11 @@ def test_batched_block_rule(lib):
     assert f(100, 64) == 16 and f(512, 256) == 16 and f(300, 257) == 32 and f(1024, 512) == 32
     assert f(10, 11) == f(11, 10) == 16 and f(300, 600) == 32  # m < n: the transpose's rule
     assert f(5, 0) == 0 and f(0, 5) == 0
+
+
+def test_trace_class_filter_arguments(lib):
+    assert lib.rrf_trace_enable_class(None) == -1
+    assert lib.rrf_trace_enable_class(b"no_such_kernel") == -1
+    assert lib.rrf_trace_enable_class(b"dgemm_mfma_128x128_TN") == 0
+    assert lib.rrf_trace_enable_class(b"dgemm_mfma_128x128_NN:UV") == 0
+    assert lib.rrf_trace_enable(0) == 0

@@ -279,3 +279,26 @@ def test_gemm_bf16_tn_exact_products(gpu, M, N, K):
         ref = exact[:, j] * s
         assert 0.5 <= np.max(np.abs(col)) <= 1.0
         np.testing.assert_array_less(np.abs(col - ref), 2.0 ** -7 * np.abs(ref) + bound[:, j] * s + 1e-300)
+
+
+def test_trace_records_only_the_selected_class(gpu):
+    """rrf_trace_enable_class times one kernel class and leaves the other
+    launches uninstrumented; rrf_trace_enable(1) times them all."""
+    from paper_2106_13402_amd import dgemm, trace_enable, trace_enable_class, trace_read
+    print("case: trace class filter", flush=True)
+    rng = np.random.default_rng(3)
+    A = _to_dev(rng.standard_normal((256, 256)), gpu)
+    B = _to_dev(rng.standard_normal((256, 256)), gpu)
+    try:
+        trace_enable_class("dgemm_mfma_128x128_TN")
+        dgemm(A, B, transa=True)
+        dgemm(A, B)
+        names = {e["name"]: e for e in trace_read()}
+        assert set(names) == {"dgemm_mfma_128x128_TN"} and names["dgemm_mfma_128x128_TN"]["launches"] == 1
+        assert names["dgemm_mfma_128x128_TN"]["ms"] > 0
+        trace_enable(True)
+        dgemm(A, B, transa=True)
+        dgemm(A, B)
+        assert {"dgemm_mfma_128x128_TN", "dgemm_mfma_128x128_NN"} <= {e["name"] for e in trace_read()}
+    finally:
+        trace_enable(False)
