@@ -6,22 +6,20 @@ Haar (synthetic, seeded, generated on the GPU), b = 128, q = 2, sketch seed 1,
 U and V accumulated. One "step" is one complete factorization A = U T V^T with
 A, U, T, V and the workspace resident in HBM before the timed region starts.
 
-Printed: ONE JSON line with the time per FP64 factorization (`value`,
-seconds, lower is better), the roofline entry of the dominant kernel measured
-live with HIP events on the library's stream, the accuracy of the result
-against the known spectrum, the same factorization with the bfloat16 sketch
-(RRF_PREC_BF16_SKETCH) timed the same way and held to e_k <= max(1.5
-sigma_{k+1}, 1.1 e_k(FP64)) on the k-grid ("mixed"), the same with the
-split-bfloat16 three-pass updates (RRF_PREC_BF16_X3, "mixed_x3"; results
-accurate to about 1e-5, so the gate covers sigma_{k+1} >= 100 x that), the
-powerURV leg, the FP64 CPU oracle
-timed on a bounded sample of the same workload, ("boosted", "partial",
-"rsvd") Alg. 2 with p = b, the early-stopped randUTV and the RSVD on the
-same matrix, ("gap") the 32768 x 8192
-sharp-gap workload in the three precision modes with e_k around k = 1000,
-and ("batched") the batched
-call on 4096 small matrices (n ~ U{64..512}, m ~ U{n..2n}, graded spectrum,
-q = 1, automatic b) in matrices per second with every matrix's residual.
+Printed on stdout: ONE short JSON line (the last line) with the time per FP64
+factorization (`value`, seconds, lower is better), the roofline entry of the
+dominant kernel measured live with HIP events on the library's stream, the
+FP64 CPU oracle timed on a bounded sample of the same workload
+(`cpu_baseline`), the accuracy of the result against the known spectrum, and
+one scalar summary per further leg: the same factorization with the bfloat16
+sketch (RRF_PREC_BF16_SKETCH) held to e_k <= max(1.5 sigma_{k+1}, 1.1
+e_k(FP64)) on the k-grid ("mixed"), with the split-bfloat16 updates
+(RRF_PREC_BF16_X3, "mixed_x3"), powerURV, Alg. 2 with p = b, the early-stopped
+randUTV, the RSVD, the 32768 x 8192 sharp-gap workload in the three precision
+modes ("gap") and the batched call on 4096 small matrices (n ~ U{64..512},
+m ~ U{n..2n}, graded spectrum, q = 1, automatic b) in matrices per second.
+The full object (kernel tables, e_k arrays, per-mode details) is written to
+`--full-json` (default gpurun_out/bench_full.json).
 
     python bench.py [--steps K] [--warmup W] [--n N] [--b B] [--q Q]
 """
@@ -538,6 +536,86 @@ def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seco
     return leg
 
 
+# ------------------------------------------------------------ headline line
+def _r(x, digits=4):
+    """Round a float to `digits` significant digits (None passes through)."""
+    if x is None or isinstance(x, bool) or not isinstance(x, float):
+        return x
+    if x == 0.0 or not math.isfinite(x):
+        return x
+    return float(f"{x:.{digits}g}")
+
+
+def _acc_summary(acc):
+    if not acc:
+        return None
+    return {"recon": _r(acc["recon"], 3), "orth_U": _r(acc["orth_U"], 3),
+            "orth_V": _r(acc["orth_V"], 3), "ek_over_sigma_max": _r(acc["ek_over_sigma_max"], 4),
+            "ek_over_sigma_argmax_k": acc["ek_over_sigma_argmax_k"]}
+
+
+def headline(out: dict) -> dict:
+    """The one-line result: the contract's keys, the roofline and CPU baseline
+    of the headline workload, and one scalar summary per extra leg. Arrays and
+    kernel tables stay in the full object (written to a file)."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+            "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")
+    h = {k: _r(out[k]) if isinstance(out[k], float) else out[k] for k in keys}
+    h["roofline"] = {k: _r(v) for k, v in out["roofline"].items()}
+    if "cpu_baseline" in out:
+        h["cpu_baseline"] = {k: _r(v) for k, v in out["cpu_baseline"].items()}
+    h["model_tflops"] = _r(out["model_tflops"])
+    h["gemm_all_frac"] = _r(out["gemm_all"]["frac"])
+    if "accuracy" in out:
+        h["accuracy"] = _acc_summary(out["accuracy"])
+    legs = {}
+    for name in ("mixed", "mixed_x3"):
+        if name in out:
+            leg = out[name]
+            legs[name] = {"precision": leg["precision"], "value": _r(leg["value"]),
+                          "speedup_vs_fp64": _r(leg["speedup_vs_fp64"]),
+                          "recon": _r(leg["accuracy"]["recon"], 3) if "accuracy" in leg else None,
+                          "ek_over_fp64_max": _r(leg.get("ek_over_fp64_max")),
+                          "ek_gate_pass": leg.get("ek_gate_pass"),
+                          "recon_le_1e-6": leg.get("recon_le_1e-6")}
+    if "powerurv" in out:
+        p = out["powerurv"]
+        legs["powerurv"] = {"fp64_s": _r(p["fp64"]["value"]),
+                            "fp64_model_tflops": _r(p["fp64"]["model_tflops"]),
+                            "bf16_s": _r(p["bf16_sketch"]["value"]),
+                            "speedup_mixed": _r(p["speedup_mixed"]),
+                            "bf16_ek_gate_pass": p["bf16_sketch"].get("ek_gate_pass"),
+                            "fp64_recon": _r(p["fp64"]["accuracy"]["recon"], 3)
+                            if "accuracy" in p["fp64"] else None}
+    if "gap" in out:
+        g = out["gap"]["modes"]
+        legs["gap"] = {mode: {"value": _r(v["value"]), "speedup_vs_fp64": _r(v["speedup_vs_fp64"]),
+                              "recon": _r(v["recon"], 3), "e_1000": _r(v["e_1000"], 4)}
+                       for mode, v in g.items()}
+        if "fp64_thin_u" in out["gap"]:
+            legs["gap"]["fp64_thin_u_s"] = _r(out["gap"]["fp64_thin_u"]["value"])
+    if "boosted" in out:
+        legs["boosted_s"] = _r(out["boosted"]["value"])
+    if "partial" in out:
+        legs["partial"] = {"value": _r(out["partial"]["value"]), "k": out["partial"]["k"]}
+    if "rsvd" in out:
+        legs["rsvd"] = {"value": _r(out["rsvd"]["value"]),
+                        "err_over_sigma_l1": _r(out["rsvd"]["err_over_sigma_l1"])}
+    if "batched" in out:
+        bt = out["batched"]
+        legs["batched"] = {k: _r(bt[k]) for k in ("value", "unit", "ms_per_call", "model_tflops")
+                           if k in bt}
+        for k in ("roofline_frac", "mode"):
+            if k in bt:
+                legs["batched"][k] = _r(bt[k])
+        legs["batched"]["residual_max"] = _r(bt["residual_fro_rel"]["max"], 3)
+        if "cpu_baseline" in bt:
+            legs["batched"]["cpu_matrices_per_s"] = _r(bt["cpu_baseline"]["value"])
+    h["legs"] = legs
+    h["full_results"] = out.get("full_results")
+    return h
+
+
 # ---------------------------------------------------------------------- main
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
@@ -558,6 +636,9 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the boosted, early-stop and RSVD legs")
     ap.add_argument("--batch", type=int, default=4096, help="matrices in the batched leg")
+    ap.add_argument("--full-json", default=os.path.join("gpurun_out", "bench_full.json"),
+                    help="file for the full results (kernel tables, e_k arrays); "
+                         "empty to skip")
     ap.add_argument("--batch-q", type=int, default=1)
     args = ap.parse_args()
 
@@ -744,7 +825,15 @@ def main() -> int:
     if not args.no_batched:
         out["batched"] = batched_leg(args.batch, args.batch_q, args.steps, args.warmup, args.seed,
                                      args.cpu_seconds / 2, not args.no_cpu_baseline)
-    print(json.dumps(out), flush=True)
+    full_path = args.full_json
+    out["full_results"] = full_path or None
+    if full_path:
+        os.makedirs(os.path.dirname(os.path.abspath(full_path)), exist_ok=True)
+        with open(full_path, "w") as f:
+            json.dump(out, f, indent=1)
+        log(f"full results written to {full_path}")
+    line = json.dumps(headline(out), separators=(",", ":"))
+    print(line, flush=True)
     return 0
 
 
