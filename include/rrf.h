@@ -78,6 +78,14 @@ extern "C" {
  * orthogonality of U and V are then about 1e-5, not binary64 level; e_k is
  * resolved down to about 1e-5 of each step's trailing norm. */
 #define RRF_PREC_BF16_X3 2
+/* randUTV only: as RRF_PREC_BF16_X3 with the updates formed by the six-term
+ * product of rrf_gemm_x6 (each operand split into three bfloat16 parts of
+ * its binary32 rounding; per K slice of 32 the terms are summed in binary32,
+ * the slices in binary64). The error per term is about 2^-22 |a| |b|, so
+ * ||A - U T V^T|| / ||A|| and the orthogonality of U and V come to about
+ * 1e-7, and e_k is resolved down to about that fraction of each step's
+ * trailing norm. */
+#define RRF_PREC_BF16_X6 3
 
 /* ---- algorithms (for rrf_workspace_size) -------------------------------- */
 #define RRF_ALG_RANDUTV  0
@@ -93,10 +101,14 @@ typedef struct rrf_opts {
                              work is enqueued; synchronizes the stream        */
   int thin_u;             /* randUTV: 1 forms only U(:, 1:n) (m x n, ld m), all
                              that A = U T V^T needs since T(n:m, :) = 0      */
+  int no_replay;          /* rrf_randutv_batched: 1 issues the lockstep rounds
+                             directly; 0 (default) records the call's launches
+                             as HIP graphs and replays them on later calls
+                             with the same shapes                            */
 } rrf_opts;
 
 /* Fill `opts` with the defaults (FP64, null stream, library workspace,
- * synchronous, no finiteness check, full m x m U). */
+ * synchronous, no finiteness check, full m x m U, batched calls replayed). */
 void rrf_opts_init(rrf_opts* opts);
 
 /*
@@ -282,8 +294,9 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
  *  A      : host array of count device pointers, read only unless T[j] == A[j]
  *                                                                     (arg 4)
  *  lda    : host array, lda[j] >= m[j]                                (arg 5)
- *  b      : block size for every matrix, 1 <= b <= 64; 0 = chosen per matrix
- *           by rrf_randutv_batched_block(m[j], n[j])                 (arg 6)
+ *  b      : block size for every matrix, 1 <= b <= 64; 0 = the configuration
+ *           rrf_batched_config(m[j], n[j], precision) gives (tuned table
+ *           or built-in rule)                                         (arg 6)
  *  q      : power iterations, >= 0                                    (arg 7)
  *  seed   : generator key of matrix 0                                 (arg 8)
  *  U      : host array of count device pointers to m[j] x m[j] outputs
@@ -297,16 +310,31 @@ size_t rrf_workspace_size(int alg, int64_t m, int64_t n, int64_t b, int32_t q,
  * The output of every matrix has the form rrf_randutv documents, a wide one
  * (m[j] < n[j]) included: it is factored through its transpose, in a
  * lockstep group of its own, from a copy of A[j]^T held in the workspace
- * (T lower trapezoidal). The host arrays are read during the call only. The call keeps a small pinned host
- * staging ring per device (freed by rrf_release_workspace) and may wait for
- * earlier work on `stream` while it enqueues.
+ * (T lower trapezoidal). The host arrays are read during the call only.
+ *
+ * Execution. The first call with a given set of shapes (count, m[], n[], b,
+ * q, precision) builds the descriptors of every stage of every step for every
+ * matrix into one device buffer, records the launches as HIP graphs (one per
+ * slice of about equal work, up to four, replayed on the library's own
+ * streams ordered after and before `stream`) and replays them. A later call
+ * with the same shapes only replays the graphs; if pointers, leading
+ * dimensions, the seed or the workspace differ, the descriptors are rebuilt
+ * on the host and uploaded into the same buffer first. Up to eight recordings
+ * are kept per device (least recently used evicted; freed by
+ * rrf_release_workspace). With opts->no_replay, or while tracing, the stages
+ * are issued directly from host-built descriptors streamed through a pinned
+ * ring per slice. Either way the call may wait on the host for earlier work
+ * of its own enqueueing while it runs, and consecutive calls on different
+ * streams are ordered by the library where they share its buffers.
  */
 int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
                         const double* const* A, const int64_t* lda, int64_t b,
                         int32_t q, uint64_t seed, double* const* U, double* const* T,
                         double* const* V, const rrf_opts* opts);
-/* The block size rrf_randutv_batched uses for an m x n matrix when called
- * with b = 0 (16 for min(m, n) <= 256, else 32); 0 for invalid sizes. */
+/* The block size of the built-in rule for an m x n matrix (16 for
+ * min(m, n) <= 256, else 32), which b = 0 follows where no tuning table
+ * applies (rrf_batched_config gives the configuration actually used); 0 for
+ * invalid sizes. */
 int64_t rrf_randutv_batched_block(int64_t m, int64_t n);
 /* Bytes of device workspace for rrf_randutv_batched (the largest group's,
  * plus 8 m[j] n[j] bytes for each wide matrix's transposed copy); 0 for
@@ -314,8 +342,58 @@ int64_t rrf_randutv_batched_block(int64_t m, int64_t n);
 size_t rrf_randutv_batched_workspace_size(int64_t count, const int64_t* m,
                                           const int64_t* n, int64_t b, int precision);
 
+/*
+ * Autotuner of the batched call (tuned per bucket of sizes; the paper has no
+ * batched form -- the buckets follow the many-small-matrices workload).
+ *
+ * A configuration is the block size b, the tile shapes the grouped GEMM may
+ * use (bit mask of RRF_TILE_*; 64 x 64 is always allowed) and the panel leaf
+ * width (a panel wider than `leaf` columns is factored by the column split of
+ * the compact-WY merge; 0: as wide as one workgroup holds).
+ */
+#define RRF_TILE_64x64   (1 << 0)
+#define RRF_TILE_128x64  (1 << 1)
+#define RRF_TILE_128x32  (1 << 2)
+#define RRF_TILE_128x16  (1 << 3)
+#define RRF_TILE_128x128 (1 << 4)
+typedef struct rrf_batched_cfg {
+  int64_t b;
+  int tile_mask;
+  int leaf;
+  int tuned;  /* 1: taken from a tuning table; 0: the built-in rule */
+} rrf_batched_cfg;
+
+/* Time candidate configurations (b in {16, 32, 64}; every tile shape, no
+ * 128 x 128, or only the narrow 128 x 32 / 128 x 16 / 64 x 64 shapes; leaf 0
+ * or 16) on synthetic batches of each bucket of n (1-64, 65-128, ..., 449-512
+ * in steps of 64, 513-768, 769-1024) up to nmax: `count` Gaussian matrices per
+ * bucket up to n = 256 (fewer above, about the same work), n uniform in the
+ * bucket and m in [n, 2n] (a generator seeded by `seed`), q power
+ * iterations, U and V formed, replayed calls timed by HIP events (median of
+ * three after a recording call). The fastest per bucket forms the table of
+ * (the current device's architecture, precision), which replaces any loaded
+ * one and is written with all loaded tables to `path` (NULL: not written).
+ * Allocates its own device buffers; runs on opts->stream.
+ *  precision : RRF_PREC_FP64 or RRF_PREC_BF16_SKETCH   (arg 1)
+ *  q >= 0 (arg 2), count >= 1 (arg 3), 1 <= nmax <= 1024 (arg 4)
+ * Returns -6 when `path` cannot be written. */
+int rrf_batched_autotune(int precision, int32_t q, int64_t count, int64_t nmax, uint64_t seed,
+                         const char* path, const rrf_opts* opts);
+/* Replace the loaded tuning tables by those of the cache file `path` (NULL:
+ * unload them, so b = 0 follows the built-in rule). -1 when the file cannot
+ * be read or is not a valid cache. Without any call the library loads
+ * $RRF_TUNE_CACHE (empty: none), else tuning/batched.json beside librrf.so,
+ * on its first lookup. */
+int rrf_batched_tune_load(const char* path);
+/* The configuration rrf_randutv_batched uses with b = 0 for an m x n matrix
+ * (the transpose's when m < n) in `precision`: from the loaded table of the
+ * current device's architecture when one has a bucket holding min(m, n),
+ * else the built-in rule (b = rrf_randutv_batched_block(m, n), every tile,
+ * leaf 0). Lookups are deterministic: the same table gives the same choice. */
+int rrf_batched_config(int64_t m, int64_t n, int precision, rrf_batched_cfg* out);
+
 /* Release the library-managed workspace cache of the current device and the
- * batched call's staging rings of every device. */
+ * batched call's staging rings and recordings on every device. */
 int rrf_release_workspace(void);
 
 /* ---- building blocks, exported for component tests ------------------------
@@ -330,6 +408,16 @@ int rrf_release_workspace(void);
  * the product of the RRF_PREC_BF16_X3 updates (a mixed-precision extension;
  * the paper computes in binary64). Errors and arguments as rrf_dgemm. */
 int rrf_gemm_x3(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                double* C, int64_t ldc, void* work, size_t work_bytes, void* stream);
+
+/* As rrf_gemm_x3 with the six-term product of the RRF_PREC_BF16_X6 updates:
+ * x32 = x rounded to binary32, hi = x32 rounded to bfloat16, mid = (x32 - hi)
+ * and lo = (x32 - hi - mid) rounded to bfloat16 (nearest even; the
+ * subtractions are exact), op(A) op(B) formed as hi hi + hi mid + mid hi +
+ * hi lo + lo hi + mid mid on the bfloat16 matrix cores, binary32 sums per K
+ * slice of 32 added in binary64. Errors and arguments as rrf_dgemm. */
+int rrf_gemm_x6(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                 double* C, int64_t ldc, void* work, size_t work_bytes, void* stream);
 

@@ -24,6 +24,15 @@ FP64. The definitions the GPU path follows:
   GPU sums them in FP32: ``fp32_x3_bound``). The split keeps about 17
   bits (|x - hi - lo| <= (2^-17 + 2^-24) |x|); per term the dropped part,
   mostly lo_a lo_b, is at most about 2^-15 |a| |b|.
+* ``split_x6(x)`` and ``gemm_x6(A, B)``: the product of the x6 updates.
+  x32 as above, hi = x32 rounded to bfloat16, mid = (x32 - hi) rounded to
+  bfloat16, lo = (x32 - hi - mid) rounded to bfloat16 (nearest even, each
+  subtraction exact in binary32), so hi + mid + lo = x32. The product keeps
+  the six leading terms of (hi_a + mid_a + lo_a)(hi_b + mid_b + lo_b),
+  hi hi + hi mid + mid hi + hi lo + lo hi + mid mid, each exact, summed here
+  in FP64 (the GPU sums the terms of each K slice of 32 in binary32 and the
+  slices in binary64: ``fp32_x6_bound``). The dropped mid lo + lo mid + lo lo
+  is below about 2^-23 |a| |b| per term.
 * ``sketch_bf16(T22, G, q)``: T22 is scaled by its pow2_scale and rounded
   to bfloat16, G (standard normal, in range) is rounded as it is;
   Y = T^T G; then q times: round Y column by column
@@ -128,3 +137,37 @@ def fp32_x3_bound(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     g = K3 * U32 / (1.0 - K3 * U32)
     absprod = np.abs(Ah) @ np.abs(Bh) + np.abs(Ah) @ np.abs(Bl) + np.abs(Al) @ np.abs(Bh)
     return (g + U32) * absprod
+
+
+def split_x6(x: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """(hi, mid, lo) of the x6 split (module docstring), as binary64 arrays."""
+    x32 = np.asarray(x, np.float64).astype(np.float32).astype(np.float64)
+    hi = bf16_round(x32)
+    mid = bf16_round(x32 - hi)
+    lo = bf16_round(x32 - hi - mid)
+    return hi, mid, lo
+
+
+def _x6_terms(A: np.ndarray, B: np.ndarray):
+    Ah, Am, Al = split_x6(A)
+    Bh, Bm, Bl = split_x6(B)
+    return [(Ah, Bh), (Ah, Bm), (Am, Bh), (Ah, Bl), (Al, Bh), (Am, Bm)]
+
+
+def gemm_x6(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """A B (A: M x K, B: K x N) by the six-term split product, in FP64."""
+    return sum(a @ b for a, b in _x6_terms(A, B))
+
+
+def fp32_x6_bound(A: np.ndarray, B: np.ndarray, slice_k: int = 32) -> np.ndarray:
+    """Elementwise bound on |GPU - gemm_x6(A, B)|: per K slice of slice_k,
+    its 6 slice_k exact terms summed in binary32 in any order
+    (gamma_{6 slice_k}) and rounded to binary32, the slice sums added in
+    binary64 (gamma of the slice count at u = 2^-53)."""
+    K = A.shape[1]
+    n6 = 6 * slice_k
+    g32 = n6 * U32 / (1.0 - n6 * U32) + U32
+    nslices = max(1, -(-K // slice_k))
+    g64 = nslices * 2.0 ** -53 / (1.0 - nslices * 2.0 ** -53)
+    absprod = sum(np.abs(a) @ np.abs(b) for a, b in _x6_terms(A, B))
+    return (g32 + g64) * absprod

@@ -244,9 +244,43 @@ def _ptr_array(vals):
     return (C.c_void_p * max(len(vals), 1))(*vals)
 
 
-def batched_block(m: int, n: int) -> int:
+def batched_block(m: int, n: int, precision: str = "fp64") -> int:
     """Block size the batched call uses for an m x n matrix when b = 0."""
-    return int(lib.rrf_randutv_batched_block(m, n))
+    return batched_config(m, n, precision)["b"]
+
+
+def batched_config(m: int, n: int, precision: str = "fp64") -> dict:
+    """The configuration (b, tile_mask, leaf, tuned) the batched call uses for
+    an m x n matrix when b = 0 (rrf_batched_config)."""
+    cfg = _lib.rrf_batched_cfg()
+    _check(lib.rrf_batched_config(m, n, PRECISIONS[precision], C.byref(cfg)), "rrf_batched_config")
+    return {"b": int(cfg.b), "tile_mask": int(cfg.tile_mask), "leaf": int(cfg.leaf),
+            "tuned": bool(cfg.tuned)}
+
+
+def batched_autotune(precision: str = "fp64", q: int = 1, count: int = 256, nmax: int = 512,
+                     seed: int = 0, path: str | None = None) -> None:
+    """Run the batched call's autotuner on the current device
+    (rrf_batched_autotune); the table is loaded and, with ``path``, written."""
+    torch = _torch()
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.stream = torch.cuda.current_stream().cuda_stream
+    _check(lib.rrf_batched_autotune(PRECISIONS[precision], q, count, nmax, seed,
+                                    path.encode() if path else None, C.byref(opts)),
+           "rrf_batched_autotune")
+
+
+def batched_tune_load(path: str | None) -> None:
+    """Replace the loaded tuning tables by the cache file ``path`` (None:
+    unload them; b = 0 then follows the built-in rule)."""
+    _check(lib.rrf_batched_tune_load(path.encode() if path else None), "rrf_batched_tune_load")
+
+
+def default_tune_path() -> str:
+    """The cache the library loads by default (tuning/batched.json beside it)."""
+    import os
+    return os.path.join(os.path.dirname(_lib.LIB_PATH), "tuning", "batched.json")
 
 
 def batched_workspace_size(ms, ns, b: int, precision: str = "fp64") -> int:
@@ -256,10 +290,14 @@ def batched_workspace_size(ms, ns, b: int, precision: str = "fp64") -> int:
 
 
 def randutv_batched(As, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
-                    check_finite: bool = False, out=None, precision: str = "fp64"):
+                    check_finite: bool = False, out=None, precision: str = "fp64",
+                    replay: bool = True):
     """Batched randUTV (Alg. 3) of the matrices in the list ``As``; matrix j is
     keyed by ``seed + j``; ``b = 0`` picks the block size per matrix;
     precision "bf16_sketch" forms every step's sketch from bfloat16 copies.
+    ``replay`` (default) records the call as HIP graphs on first use and
+    replays them for later calls with the same shapes; False issues the
+    lockstep rounds directly (rrf_opts.no_replay).
 
     Returns three lists (Us, Ts, Vs) (Us / Vs None when not wanted). ``out``
     may pass such lists (tight column-major tensors of the right shapes) to be
@@ -293,6 +331,7 @@ def randutv_batched(As, b: int, q: int, seed: int, *, want_u: bool = True, want_
     opts.workspace = ws.data_ptr()
     opts.workspace_bytes = ws.numel()
     opts.check_finite = 1 if check_finite else 0
+    opts.no_replay = 0 if replay else 1
     st = lib.rrf_randutv_batched(
         count, _i64_array(ms), _i64_array(ns), _ptr_array([A.data_ptr() for A in As]),
         _i64_array([_ld(A) for A in As]), b, q, seed,
@@ -332,6 +371,12 @@ def gemm_x3(A, B, *, transa: bool = False, transb: bool = False, alpha: float = 
             beta: float = 0.0, C_out=None, split_work: bool = True):
     """C = alpha op(A) op(B) + beta C by the split-bfloat16 three-pass product."""
     return _gemm("rrf_gemm_x3", A, B, transa, transb, alpha, beta, C_out, split_work)
+
+
+def gemm_x6(A, B, *, transa: bool = False, transb: bool = False, alpha: float = 1.0,
+            beta: float = 0.0, C_out=None, split_work: bool = True):
+    """C = alpha op(A) op(B) + beta C by the split-bfloat16 six-term product."""
+    return _gemm("rrf_gemm_x6", A, B, transa, transb, alpha, beta, C_out, split_work)
 
 
 def _gemm(name, A, B, transa, transb, alpha, beta, C_out, split_work):

@@ -20,6 +20,7 @@ RRF_E_INTERNAL = 5
 RRF_PREC_FP64 = 0
 RRF_PREC_BF16_SKETCH = 1
 RRF_PREC_BF16_X3 = 2
+RRF_PREC_BF16_X6 = 3
 RRF_ALG_RANDUTV = 0
 RRF_ALG_POWERURV = 1
 
@@ -33,6 +34,16 @@ class rrf_opts(C.Structure):
         ("async_", C.c_int),
         ("check_finite", C.c_int),
         ("thin_u", C.c_int),
+        ("no_replay", C.c_int),
+    ]
+
+
+class rrf_batched_cfg(C.Structure):
+    _fields_ = [
+        ("b", C.c_int64),
+        ("tile_mask", C.c_int),
+        ("leaf", C.c_int),
+        ("tuned", C.c_int),
     ]
 
 
@@ -63,6 +74,10 @@ PROTOTYPES = {
                                       C.POINTER(rrf_opts)]),
     "rrf_randutv_batched_workspace_size": (_sz, [_i64, _vp, _vp, _i64, C.c_int]),
     "rrf_randutv_batched_block": (_i64, [_i64, _i64]),
+    "rrf_batched_autotune": (C.c_int, [C.c_int, _i32, _i64, _i64, _u64, C.c_char_p,
+                                       C.POINTER(rrf_opts)]),
+    "rrf_batched_tune_load": (C.c_int, [C.c_char_p]),
+    "rrf_batched_config": (C.c_int, [_i64, _i64, C.c_int, C.POINTER(rrf_batched_cfg)]),
     "rrf_randutv_resume": (C.c_int, [_i64, _i64, _i64, _i32, _u64, _d, _i64, _i64, _dp, _dp, _dp,
                                      C.POINTER(C.c_int64), C.POINTER(rrf_opts)]),
     "rrf_rsvd": (C.c_int, [_i64, _i64, _dp, _i64, _i64, _i32, _u64, _dp, _dp, _dp,
@@ -80,6 +95,8 @@ PROTOTYPES = {
     "rrf_dgemm": (C.c_int, [C.c_int, C.c_int, _i64, _i64, _i64, _d, _dp, _i64, _dp, _i64, _d,
                             _dp, _i64, _vp, _sz, _vp]),
     "rrf_gemm_x3": (C.c_int, [C.c_int, C.c_int, _i64, _i64, _i64, _d, _dp, _i64, _dp, _i64, _d,
+                              _dp, _i64, _vp, _sz, _vp]),
+    "rrf_gemm_x6": (C.c_int, [C.c_int, C.c_int, _i64, _i64, _i64, _d, _dp, _i64, _dp, _i64, _d,
                               _dp, _i64, _vp, _sz, _vp]),
     "rrf_panel_workspace_size": (_sz, [_i64, _i64]),
     "rrf_householder_panel": (C.c_int, [_i64, _i64, _dp, _i64, _dp, _i64, _dp, _i64, _dp, _i64,

@@ -1,5 +1,6 @@
 // The C-ABI of librrf: argument checks (before any HIP call), workspace
 // management, status read-back, and the exported building blocks.
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -144,7 +145,8 @@ bool boosted_fits(int64_t n, int64_t b, int64_t p) {
 bool precision_ok(int alg, int precision, int64_t boost_p = -1) {
   if (boost_p >= 0) return precision == RRF_PREC_FP64;
   if (precision == RRF_PREC_FP64 || precision == RRF_PREC_BF16_SKETCH) return true;
-  return alg == RRF_ALG_RANDUTV && precision == RRF_PREC_BF16_X3;
+  return alg == RRF_ALG_RANDUTV &&
+         (precision == RRF_PREC_BF16_X3 || precision == RRF_PREC_BF16_X6);
 }
 
 typedef bool (*SupportedFn)(int64_t, int64_t, int64_t);
@@ -448,31 +450,48 @@ namespace rrf {
 namespace {
 
 // The batched call runs its matrices in groups, one lockstep run each: per
-// block size (b, or the automatic rule) and per orientation. A wide matrix
-// (m < n) enters its group as its transpose (Sec. 3.2, as for rrf_randutv):
-// A^T is copied into a buffer of its own after the runs' arena, factored
-// there in place with U and V exchanged, and T = T'^T is copied back.
+// configuration (block size, tile shapes and panel leaf: b, or the tuned or
+// built-in choice for b = 0) and per orientation. A wide matrix (m < n)
+// enters its group as its transpose (Sec. 3.2, as for rrf_randutv): A^T is
+// copied into a buffer of its own after the runs' arena, factored there in
+// place with U and V exchanged, and T = T'^T is copied back.
 struct BatchedGroup {
   std::vector<int64_t> m, n;  // the factored shape (m >= n)
   std::vector<int64_t> idx;   // caller's matrix index
 };
 
-std::vector<std::pair<int64_t, BatchedGroup>> batched_groups(int64_t count, const int64_t* m,
-                                                             const int64_t* n, int64_t b) {
-  std::vector<std::pair<int64_t, BatchedGroup>> out;
-  const std::vector<int64_t> blocks = b > 0 ? std::vector<int64_t>{b} : std::vector<int64_t>{16, 32};
-  for (int64_t bg : blocks)
+bool cfg_less(const BatchedCfg& x, const BatchedCfg& y) {
+  if (x.b != y.b) return x.b < y.b;
+  if (x.tile_mask != y.tile_mask) return x.tile_mask < y.tile_mask;
+  return x.leaf < y.leaf;
+}
+
+std::vector<std::pair<BatchedCfg, BatchedGroup>> batched_groups(int64_t count, const int64_t* m,
+                                                                const int64_t* n, int64_t b,
+                                                                int precision) {
+  std::vector<BatchedCfg> cfg(count);
+  std::vector<BatchedCfg> distinct;
+  for (int64_t j = 0; j < count; ++j) {
+    const int64_t M = std::max(m[j], n[j]), N = std::min(m[j], n[j]);
+    cfg[j] = b > 0 ? BatchedCfg{b, kTileMaskAll, 0} : batched_config(M, N, precision);
+    bool seen = false;
+    for (const auto& d : distinct)
+      seen = seen || (!cfg_less(d, cfg[j]) && !cfg_less(cfg[j], d));
+    if (!seen) distinct.push_back(cfg[j]);
+  }
+  std::sort(distinct.begin(), distinct.end(), cfg_less);
+  std::vector<std::pair<BatchedCfg, BatchedGroup>> out;
+  for (const auto& c : distinct)
     for (int wide = 0; wide < 2; ++wide) {
       BatchedGroup g;
       for (int64_t j = 0; j < count; ++j) {
         if ((m[j] < n[j]) != (wide == 1)) continue;
-        const int64_t M = std::max(m[j], n[j]), N = std::min(m[j], n[j]);
-        if (b == 0 && randutv_batched_block(M, N) != bg) continue;
-        g.m.push_back(M);
-        g.n.push_back(N);
+        if (cfg_less(cfg[j], c) || cfg_less(c, cfg[j])) continue;
+        g.m.push_back(std::max(m[j], n[j]));
+        g.n.push_back(std::min(m[j], n[j]));
         g.idx.push_back(j);
       }
-      if (!g.idx.empty()) out.emplace_back(bg, std::move(g));
+      if (!g.idx.empty()) out.emplace_back(c, std::move(g));
     }
   return out;
 }
@@ -484,8 +503,8 @@ size_t wide_copy_bytes(int64_t m, int64_t n) {
 // Arena of the largest group (0 if a group is outside the kernel limits).
 size_t batched_arena(int64_t count, const int64_t* m, const int64_t* n, int64_t b, int precision) {
   size_t arena = 0;
-  for (const auto& [bg, g] : batched_groups(count, m, n, b)) {
-    const size_t w = randutv_batched_workspace((int64_t)g.idx.size(), g.m.data(), g.n.data(), bg,
+  for (const auto& [cg, g] : batched_groups(count, m, n, b, precision)) {
+    const size_t w = randutv_batched_workspace((int64_t)g.idx.size(), g.m.data(), g.n.data(), cg.b,
                                                precision);
     if (w == 0) return 0;
     arena = std::max(arena, w);
@@ -586,7 +605,7 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
   }
   for (int64_t j = 0; j < count; ++j)
     if (Wt[j]) RRF_TRY(transpose_matrix(st, m[j], n[j], A[j], lda[j], Wt[j], n[j]));
-  for (const auto& [bg, g] : batched_groups(count, m, n, b)) {
+  for (const auto& [cg, g] : batched_groups(count, m, n, b, o.precision)) {
     const int64_t cnt = (int64_t)g.idx.size();
     const bool wide = m[g.idx[0]] < n[g.idx[0]];
     // the factored matrix's U is the caller's V for a wide matrix, and vice versa
@@ -605,9 +624,10 @@ int rrf_randutv_batched(int64_t count, const int64_t* m, const int64_t* n,
       if (Vf) gV.push_back(Vf[j]);
       gs[t] = seed + (uint64_t)j;  // matrix j is keyed by seed + j
     }
-    RRF_TRY(randutv_batched_run(st, cnt, g.m.data(), g.n.data(), gA.data(), gl.data(), bg, q,
+    RRF_TRY(randutv_batched_run(st, cnt, g.m.data(), g.n.data(), gA.data(), gl.data(), cg, q,
                                 gs.data(), Uf ? gU.data() : nullptr, gT.data(),
-                                Vf ? gV.data() : nullptr, ws, arena_bytes, o.precision));
+                                Vf ? gV.data() : nullptr, ws, arena_bytes, o.precision,
+                                !o.no_replay));
   }
   for (int64_t j = 0; j < count; ++j)
     if (Wt[j]) RRF_TRY(transpose_matrix(st, n[j], m[j], Wt[j], n[j], T[j], m[j]));
@@ -689,6 +709,13 @@ int rrf_gemm_x3(int transa, int transb, int64_t M, int64_t N, int64_t K, double 
                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                 double* C, int64_t ldc, void* work, size_t work_bytes, void* stream) {
   return gemm_entry(gemm_x3, transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
+                    work_bytes, stream);
+}
+
+int rrf_gemm_x6(int transa, int transb, int64_t M, int64_t N, int64_t K, double alpha,
+                const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                double* C, int64_t ldc, void* work, size_t work_bytes, void* stream) {
+  return gemm_entry(gemm_x6, transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
                     work_bytes, stream);
 }
 

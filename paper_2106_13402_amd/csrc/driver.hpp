@@ -42,17 +42,38 @@ int rsvd_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t lda,
              uint64_t seed, double* U, int64_t ldu, double* S, double* V, int64_t ldv, void* ws,
              size_t ws_bytes, bool check_input);
 
-// Batched Alg. 3 (one block size b for the whole call; matrix j keyed by
+// Configuration of one lockstep group of the batched call: the block size,
+// the grouped GEMM's allowed tile shapes (bit mask over GemmTile of
+// batched.hpp; 64 x 64 is always allowed) and the widest panel one launch
+// factors before the column split takes over (0: as wide as one workgroup
+// holds).
+constexpr int kTileMaskAll = 0x1f;
+struct BatchedCfg {
+  int64_t b;
+  int tile_mask;
+  int leaf;
+};
+// The configuration b = 0 selects for an m x n matrix (m >= n) in `precision`:
+// the loaded tuning table of the current device's architecture when it has
+// a bucket holding n (autotune.hip), else the built-in rule
+// (randutv_batched_block, every tile shape, no forced split).
+BatchedCfg batched_config(int64_t m, int64_t n, int precision);
+
+// Batched Alg. 3 (one configuration for the whole call; matrix j keyed by
 // seeds[j]); outputs packed column-major (ld m, m, n). The status words of
-// `ws` (word 0: device-side failure bits) are not cleared here.
+// `ws` (word 0: device-side failure bits) are not cleared here. use_graph:
+// record the call's launches as HIP graphs on first use and replay them when
+// called again with the same shapes (ignored while tracing); else stream the
+// lockstep rounds through the descriptor rings.
 int64_t randutv_batched_block(int64_t m, int64_t n);
 size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t* n, int64_t b,
                                  int precision);
 int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const int64_t* n,
-                        const double* const* A, const int64_t* lda, int64_t b, int q,
+                        const double* const* A, const int64_t* lda, const BatchedCfg& cfg, int q,
                         const uint64_t* seeds, double* const* U, double* const* T,
-                        double* const* V, void* ws, size_t ws_bytes, int precision);
-// Free the descriptor rings of every device.
+                        double* const* V, void* ws, size_t ws_bytes, int precision,
+                        bool use_graph);
+// Free the descriptor rings and recorded calls of every device.
 int randutv_batched_release();
 
 }  // namespace rrf

@@ -27,6 +27,15 @@ int gemm_x3(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, d
             const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
             int64_t ldc, double* work, size_t work_elems);
 
+// ---- gemm_x6.hip -----------------------------------------------------------
+// As dgemm, with every operand split into bfloat16 hi + mid + lo (from its
+// binary32 rounding) and the six leading products hi hi + hi mid + mid hi +
+// hi lo + lo hi + mid mid accumulated in binary32 per K slice of 32, the
+// slices summed in binary64.
+int gemm_x6(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+            const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+            int64_t ldc, double* work, size_t work_elems);
+
 // ---- philox.hip ----------------------------------------------------------
 int gaussian(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
              double* out, int64_t ld);
@@ -85,9 +94,10 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
 int frob_norm(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
               const unsigned long long* word, double* parts, int max_parts, double* out);
 // X *= s (inverse: X /= s), s the power of two putting max|X| from *word in
-// [0.5, 1) (1 when the max is 0); exact.
+// [0.5, 1) (1 when the max is 0); exact. guard_exp > 0: s = 1 (nothing done)
+// unless s lies outside [2^-guard_exp, 2^guard_exp].
 int scale_pow2(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld,
-               const unsigned long long* word, bool inverse);
+               const unsigned long long* word, bool inverse, int guard_exp = 0);
 int to_bf16(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
             const unsigned long long* word, uint16_t* out, int64_t ldo, uint16_t* outT,
             int64_t ldot);

@@ -58,6 +58,9 @@
 
 namespace rrf {
 
+// Binary exponent range of max|A| that the binary64 modes factor unscaled.
+constexpr int kGuardExp = 400;
+
 namespace {
 
 constexpr int kGroup = 4;  // steps merged into one compact-WY factor for U and V
@@ -195,7 +198,8 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t b, int precision, Bufs* B, in
   B->panel = ar.take<char>(B->panel_bytes);
   B->svd_bytes = (size_t)s * block_svd_work_bytes((int)kb);
   B->svd = ar.take<char>(B->svd_bytes);
-  if (precision == RRF_PREC_BF16_SKETCH || precision == RRF_PREC_BF16_X3) {
+  if (precision == RRF_PREC_BF16_SKETCH || precision == RRF_PREC_BF16_X3 ||
+      precision == RRF_PREC_BF16_X6) {
     B->Tb = ar.take<uint16_t>((size_t)bf16_ld(m) * n);
     B->Tbt = ar.take<uint16_t>((size_t)bf16_ld(n) * m);
     B->Gb = ar.take<uint16_t>((size_t)bf16_ld(m) * kb);
@@ -450,23 +454,25 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipEvent_t* ev = ctx->ev;
   const size_t SE = B.split_elems;
-  const bool mixed_sketch = precision == RRF_PREC_BF16_SKETCH || precision == RRF_PREC_BF16_X3;
-  const bool x3 = precision == RRF_PREC_BF16_X3;
+  const bool x6 = precision == RRF_PREC_BF16_X6;
+  const bool x3 = precision == RRF_PREC_BF16_X3 || x6;  // split-bfloat16 updates
+  const bool mixed_sketch = precision == RRF_PREC_BF16_SKETCH || x3;
   // the products that update T, U and V
-  const GemmFn upd = x3 ? gemm_x3 : dgemm;
-  unsigned long long* scale_word = B.word + 8;  // max|A| of the x3 mode
+  const GemmFn upd = x6 ? gemm_x6 : (x3 ? gemm_x3 : dgemm);
+  unsigned long long* scale_word = B.nword + 2;  // max|A|, for the scaling of T
 
   RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(B.status), 64, 0u));
   if (check_input) RRF_TRY(check_finite(st, m, n, A, lda, B.status + 1));
   const int64_t ldt = m, ldu = m, ldv = n;
   if (T != A) RRF_TRY(copy_matrix(st, m, n, A, lda, T, ldt));
-  if (x3) {
-    // T = 2^-e A with max|T| in [0.5, 1): every entry of T, and of the
-    // products formed from it, stays inside the binary32 range of the split
-    // (the scaling is exact and undone at the end)
-    RRF_TRY(maxabs(st, m, n, T, ldt, scale_word));
-    RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, false));
-  }
+  // T = 2^-e A with max|T| in [0.5, 1) (exact, undone at the end). The split
+  // modes always scale: every entry of T, and of the products formed from
+  // it, stays inside the binary32 range of the split. The binary64 modes
+  // scale only a max|A| beyond 2^+-kGuardExp, where the squares summed by the
+  // Householder norms and the Jacobi rotations would overflow or underflow.
+  const int guard = x3 ? 0 : kGuardExp;
+  RRF_TRY(maxabs(st, m, n, T, ldt, scale_word));
+  RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, false, guard));
   // reflector stores: zero outside each step's block
   if (U) RRF_TRY(fill_matrix(st, m, n, 0.0, B.WU, m));
   if (V) RRF_TRY(fill_matrix(st, n, n, 0.0, B.WV, n));
@@ -635,7 +641,7 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
     RRF_CHECK_HIP(hipEventRecord(ev[kEvV], sv));
     RRF_CHECK_HIP(hipStreamWaitEvent(st, ev[kEvV], 0));
   }
-  if (x3) RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, true));
+  RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, true, guard));
   if (stop && stop->k_out) *stop->k_out = std::min(s_done * b, n);
   *status_out = 0;
   return RRF_OK;

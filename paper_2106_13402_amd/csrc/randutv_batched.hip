@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -33,12 +34,21 @@
 #include "common.hpp"
 #include "driver.hpp"
 #include "kernels.hpp"
+#include "trace.hpp"
 
 namespace rrf {
 
 namespace {
 
 constexpr int kBGroup = 4;            // steps merged per backward application
+
+// Tunable choices of the plan (set per building thread from the call's
+// configuration, see BatchedCfg): the grouped GEMM's allowed tile shapes (a
+// bit mask over GemmTile) and the widest panel one launch factors before the
+// column split takes over (0: as wide as one workgroup holds).
+static_assert(kTileMaskAll == (1 << kGemmTiles) - 1, "every tile shape");
+thread_local int t_tile_mask = kTileMaskAll;
+thread_local int t_panel_leaf = 0;
 constexpr int kSlots = 4;             // descriptor ring
 constexpr size_t kDescPerMat = 2048;  // descriptor bytes per matrix and round (bound)
 
@@ -61,7 +71,7 @@ struct Mat {
 
 // One round: descriptors packed in `bytes`, launches in `ops` order.
 struct Plan {
-  enum { kGemm, kElem, kGauss, kPanel, kMax, kBf16, kGemm16, kRound };
+  enum { kGemm, kElem, kGauss, kPanel, kMax, kBf16, kGemm16, kRound, kCopyIn, kCall };
   struct Op {
     int kind;
     bool ta, tb;
@@ -72,6 +82,8 @@ struct Plan {
     double flops;
     size_t off2;  // GEMM: running tile counts
     bool vec;     // GEMM: 16-byte loads
+    void* dst = nullptr;                    // kCopyIn: aux bytes at off go to dst
+    std::function<int(hipStream_t)> fn{};  // kCall: a launch that takes no descriptors
   };
   std::vector<unsigned char> bytes;
   std::vector<Op> ops;
@@ -86,18 +98,23 @@ struct Plan {
   // The tile shape with the least padded work, weighted by how well each
   // shape keeps the matrix cores fed (wider tiles reuse each loaded slice
   // more often).
+  // Among the tile shapes the plan allows (64 x 64 always), the one with the
+  // least padded work, weighted by how well each shape keeps the matrix cores
+  // fed (wider tiles reuse each loaded slice more often).
   static int pick_tile(const std::vector<GemmDesc>& v) {
     static const int order[5] = {kTile128x128, kTile128x64, kTile64x64, kTile128x32, kTile128x16};
     static const double weight[5] = {1.0, 1.1, 1.3, 1.25, 1.5};
+    const int mask = t_tile_mask | (1 << kTile64x64);
     int best = kTile64x64;
-    double best_cost = 0.0;
+    double best_cost = -1.0;
     for (int c = 0; c < 5; ++c) {
       const int t = order[c];
+      if (!(mask & (1 << t))) continue;
       double area = 0.0;
       for (const auto& g : v)
         area += (double)tile_count(t, g.M, g.N) * tile_rows(t) * tile_cols(t) * (double)g.K;
       const double cost = area * weight[c];
-      if (c == 0 || cost < best_cost) {
+      if (best_cost < 0.0 || cost < best_cost) {
         best = t;
         best_cost = cost;
       }
@@ -167,6 +184,20 @@ struct Plan {
     for (const auto& e : v) cols = std::max(cols, e.N);
     ops.push_back({kRound, false, false, put(v), (int)v.size(), cols, 0, 0.0, 0, false});
   }
+  // device copy of `bytes` host bytes to dst, staged in this round's descriptors
+  void copy_in(const void* src, size_t bytes, void* dst) {
+    const size_t off = (this->bytes.size() + 15) & ~(size_t)15;
+    this->bytes.resize(off + bytes);
+    memcpy(this->bytes.data() + off, src, bytes);
+    Op o{kCopyIn, false, false, off, 0, (int64_t)bytes, 0, 0.0, 0, false};
+    o.dst = dst;
+    ops.push_back(std::move(o));
+  }
+  void call(std::function<int(hipStream_t)> f) {
+    Op o{kCall, false, false, 0, 0, 0, 0, 0.0, 0, false};
+    o.fn = std::move(f);
+    ops.push_back(std::move(o));
+  }
   void panel(const std::vector<PanelDesc>& v, int k) {
     if (v.empty()) return;
     int64_t rows = 0;
@@ -208,21 +239,8 @@ int ring_reserve(Ring& r, size_t cap) {
   return RRF_OK;
 }
 
-int run_plan(hipStream_t st, Ring& r, const Plan& p) {
-  if (p.ops.empty()) return RRF_OK;
-  if (p.bytes.size() > r.cap)
-    return set_error(RRF_E_INTERNAL, "batched randutv: descriptor round exceeds its slot");
-  const int s = r.slot;
-  r.slot = (r.slot + 1) % kSlots;
-  // once the slot's previous copy has completed, its host side is free; its
-  // device side is read only by kernels enqueued before the next copy
-  if (r.pending[s]) RRF_CHECK_HIP(hipEventSynchronize(r.copied[s]));
-  unsigned char* h = r.host + (size_t)s * r.cap;
-  unsigned char* d = r.dev + (size_t)s * r.cap;
-  memcpy(h, p.bytes.data(), p.bytes.size());
-  RRF_CHECK_HIP(hipMemcpyAsync(d, h, p.bytes.size(), hipMemcpyHostToDevice, st));
-  RRF_CHECK_HIP(hipEventRecord(r.copied[s], st));
-  r.pending[s] = true;
+// Enqueue the launches of round `p` whose descriptors sit at device address d.
+int enqueue_plan(hipStream_t st, const Plan& p, const unsigned char* d) {
   for (const auto& op : p.ops) {
     const void* dd = d + op.off;
     switch (op.kind) {
@@ -251,6 +269,12 @@ int run_plan(hipStream_t st, Ring& r, const Plan& p) {
       case Plan::kRound:
         RRF_TRY(round_columns_batched(st, static_cast<const RoundDesc*>(dd), op.count, op.aux));
         break;
+      case Plan::kCopyIn:
+        RRF_CHECK_HIP(hipMemcpyAsync(op.dst, dd, (size_t)op.aux, hipMemcpyDeviceToDevice, st));
+        break;
+      case Plan::kCall:
+        RRF_TRY(op.fn(st));
+        break;
       default:
         RRF_TRY(panel_wg_batched(st, static_cast<const PanelDesc*>(dd), op.count, op.k, op.aux));
     }
@@ -258,19 +282,30 @@ int run_plan(hipStream_t st, Ring& r, const Plan& p) {
   return RRF_OK;
 }
 
-// Copy `bytes` of host data to device memory `dst` through a ring slot.
-int upload(hipStream_t st, Ring& r, const void* src, size_t bytes, void* dst) {
-  if (bytes > r.cap) return set_error(RRF_E_INTERNAL, "batched randutv: upload exceeds its slot");
+// Stream round `p` through the next ring slot: its descriptors are copied to
+// the slot's device side, then its launches are enqueued on `st`.
+int run_plan(hipStream_t st, Ring& r, const Plan& p) {
+  if (p.ops.empty()) return RRF_OK;
+  if (p.bytes.size() > r.cap)
+    return set_error(RRF_E_INTERNAL, "batched randutv: descriptor round exceeds its slot");
   const int s = r.slot;
   r.slot = (r.slot + 1) % kSlots;
+  // once the slot's previous copy has completed, its host side is free; its
+  // device side is read only by kernels enqueued before the next copy
   if (r.pending[s]) RRF_CHECK_HIP(hipEventSynchronize(r.copied[s]));
   unsigned char* h = r.host + (size_t)s * r.cap;
-  memcpy(h, src, bytes);
-  RRF_CHECK_HIP(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st));
+  unsigned char* d = r.dev + (size_t)s * r.cap;
+  if (!p.bytes.empty()) {
+    memcpy(h, p.bytes.data(), p.bytes.size());
+    RRF_CHECK_HIP(hipMemcpyAsync(d, h, p.bytes.size(), hipMemcpyHostToDevice, st));
+  }
   RRF_CHECK_HIP(hipEventRecord(r.copied[s], st));
   r.pending[s] = true;
-  return RRF_OK;
+  return enqueue_plan(st, p, d);
 }
+
+// Where a finished round goes: streamed through a ring, or kept for a recording.
+using Emit = std::function<int(Plan&)>;
 
 GemmDesc gd(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda,
             const double* B, int64_t ldb, double beta, double* C, int64_t ldc) {
@@ -297,7 +332,7 @@ bool plan_panel(std::vector<Plan>& rounds, const std::vector<PanelDesc>& P,
   // too tall for one workgroup, all are split
   int64_t maxM = 0;
   for (const auto& p : P) maxM = std::max(maxM, p.M);
-  if (maxM <= panel_wg_max_rows(k)) {
+  if (maxM <= panel_wg_max_rows(k) && (t_panel_leaf <= 0 || k <= t_panel_leaf)) {
     rounds.emplace_back();
     rounds.back().panel(P, k);
     return true;
@@ -517,8 +552,8 @@ void plan_sketch_bf16(std::vector<Plan>& rounds, std::vector<Mat>& mats,
 }
 
 // The loop of Alg. 3 for every matrix, step i of all together.
-int run_loop(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh, int64_t b,
-             int q, int precision, std::vector<std::vector<int64_t>>& ku,
+int run_loop(const Emit& emit, std::vector<Mat>& mats, const Shared& sh, int64_t b, int q,
+             int precision, std::vector<std::vector<int64_t>>& ku,
              std::vector<std::vector<int64_t>>& kv) {
   const int64_t bb = b;
   const int64_t count = (int64_t)mats.size();
@@ -674,7 +709,7 @@ int run_loop(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& s
       p.gemm(false, false, zc);
       p.gemm(false, true, up);
     }
-    for (auto& p : rounds) RRF_TRY(run_plan(st, ring, p));
+    for (auto& p : rounds) RRF_TRY(emit(p));
     rounds.clear();
   }
   return RRF_OK;
@@ -682,10 +717,16 @@ int run_loop(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& s
 
 // Block SVDs, T's diagonal blocks, and the block updates T(I1, J2) Vs and
 // Us^T T(J2, J3).
-int run_blocks(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh, int64_t b) {
+int run_blocks(const Emit& emit, std::vector<Mat>& mats, const Shared& sh, int64_t b) {
   const int64_t bb = b;
-  RRF_TRY(block_svd_sized(st, (int)sh.nblocks, (int)b, sh.sizes, sh.R, bb, bb * bb, sh.Us, sh.d,
-                          bb, sh.Vs, sh.svd, sh.svd_bytes, sh.status));
+  {
+    Plan sv;
+    sv.call([sh, b, bb](hipStream_t st) {
+      return block_svd_sized(st, (int)sh.nblocks, (int)b, sh.sizes, sh.R, bb, bb * bb, sh.Us,
+                             sh.d, bb, sh.Vs, sh.svd, sh.svd_bytes, sh.status);
+    });
+    RRF_TRY(emit(sv));
+  }
   int64_t smax = 0;
   for (auto& x : mats) smax = std::max(smax, x.s);
   for (int64_t i = 0; i < smax; ++i) {
@@ -716,7 +757,7 @@ int run_blocks(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared&
     p.gemm(false, false, t1);
     p.gemm(true, false, t2);
     p.elem(cb);
-    RRF_TRY(run_plan(st, ring, p));
+    RRF_TRY(emit(p));
   }
   return RRF_OK;
 }
@@ -724,7 +765,7 @@ int run_blocks(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared&
 // U = H_0 ... H_{s-1} and V likewise, applied to I from the last group of
 // kBGroup steps backward (only Q(ca:, ca:) changes), then the rotations of
 // their block columns by Us and Vs.
-int run_backward(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh, int64_t b,
+int run_backward(const Emit& emit, std::vector<Mat>& mats, const Shared& sh, int64_t b,
                  const std::vector<std::vector<int64_t>>& ku,
                  const std::vector<std::vector<int64_t>>& kv) {
   const int64_t bb = b;
@@ -779,7 +820,7 @@ int run_backward(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Share
     for (auto& jb : jobs)
       id.push_back(ElemDesc{kElemIdentity, jb.N, jb.N, nullptr, 0, jb.Q, jb.N, 0.0});
     p.elem(id);
-    RRF_TRY(run_plan(st, ring, p));
+    RRF_TRY(emit(p));
   }
   size_t rmax = 0;
   for (auto& jb : jobs) rmax = std::max(rmax, jb.groups.size());
@@ -816,7 +857,7 @@ int run_backward(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Share
       pl.gemm(false, false, s2);
       pl.gemm(false, false, s3);
       pl.elem(cp);
-      RRF_TRY(run_plan(st, ring, pl));
+      RRF_TRY(emit(pl));
     }
     // Q(ca:, ca:) -= W_G (T_G (W_G^T Q(ca:, ca:)))
     Plan pl;
@@ -835,7 +876,7 @@ int run_backward(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Share
     pl.gemm(true, false, a1);
     pl.gemm(false, false, a2);
     pl.gemm(false, false, a3);
-    RRF_TRY(run_plan(st, ring, pl));
+    RRF_TRY(emit(pl));
   }
   int64_t smax = 0;
   for (auto& x : mats) smax = std::max(smax, x.s);
@@ -860,7 +901,7 @@ int run_backward(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Share
     }
     p.gemm(false, false, g);
     p.elem(cb);
-    RRF_TRY(run_plan(st, ring, p));
+    RRF_TRY(emit(p));
   }
   return RRF_OK;
 }
@@ -882,13 +923,14 @@ size_t randutv_batched_workspace(int64_t count, const int64_t* m, const int64_t*
 
 namespace {
 
-// One slice of the batch on its own stream: set-up, the loop, the block
-// SVDs and updates, and U and V. mats[j].blk0 and sh index the slice's own
-// blocks.
-int run_slice(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh, int64_t b,
-              int q, int precision) {
-  RRF_TRY(ring_reserve(ring, std::max(mats.size() * kDescPerMat, (size_t)sh.nblocks * 4) +
-                                 (1 << 16)));
+// Every round of one slice of the batch, in order: set-up, the loop, the
+// block SVDs and updates, and U and V. mats[j].blk0 and sh index the slice's
+// own blocks.
+int plan_slice(const Emit& emit, std::vector<Mat>& mats, const Shared& sh, const BatchedCfg& cfg,
+               int q, int precision) {
+  const int64_t b = cfg.b;
+  t_tile_mask = cfg.tile_mask;
+  t_panel_leaf = cfg.leaf;
   {
     Plan p;
     std::vector<ElemDesc> e;
@@ -898,39 +940,77 @@ int run_slice(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& 
       if (x.V) e.push_back(fill(x.n, x.n, 0.0, x.WV, x.n));
     }
     p.elem(e);
-    RRF_TRY(run_plan(st, ring, p));
+    RRF_TRY(emit(p));
   }
   {
     std::vector<int> hs((size_t)sh.nblocks);
     for (auto& x : mats)
       for (int64_t i = 0; i < x.s; ++i) hs[x.blk0 + i] = (int)std::min(b, x.n - i * b);
-    RRF_TRY(upload(st, ring, hs.data(), hs.size() * sizeof(int), sh.sizes));
+    Plan p;
+    p.copy_in(hs.data(), hs.size() * sizeof(int), sh.sizes);
+    RRF_TRY(emit(p));
   }
   std::vector<std::vector<int64_t>> ku(mats.size()), kv(mats.size());
   for (size_t j = 0; j < mats.size(); ++j) {
     ku[j].assign(mats[j].s, 0);
     kv[j].assign(mats[j].s, 0);
   }
-  RRF_TRY(run_loop(st, ring, mats, sh, b, q, precision, ku, kv));
-  RRF_TRY(run_blocks(st, ring, mats, sh, b));
-  RRF_TRY(run_backward(st, ring, mats, sh, b, ku, kv));
+  RRF_TRY(run_loop(emit, mats, sh, b, q, precision, ku, kv));
+  RRF_TRY(run_blocks(emit, mats, sh, b));
+  RRF_TRY(run_backward(emit, mats, sh, b, ku, kv));
   return RRF_OK;
 }
 
-// Per-device resources kept between calls: the slices' streams (default
-// priority), their descriptor rings, and the events that order them after
-// and before the caller's stream.
+// One slice streamed through its descriptor ring on `st`.
+int run_slice(hipStream_t st, Ring& ring, std::vector<Mat>& mats, const Shared& sh,
+              const BatchedCfg& cfg, int q, int precision) {
+  RRF_TRY(ring_reserve(ring, std::max(mats.size() * kDescPerMat, (size_t)sh.nblocks * 4) +
+                                 (1 << 16)));
+  return plan_slice([&](Plan& p) { return run_plan(st, ring, p); }, mats, sh, cfg, q, precision);
+}
+
+// A recorded batched call: the descriptors of every round of every slice in
+// one resident device buffer, and the launches of each slice captured into a
+// HIP graph. A later call with the same shapes replays the graphs; when only
+// pointers or seeds differ, the descriptors are rebuilt on the host and
+// uploaded into the same buffer first (the rounds and launches depend on the
+// shapes alone).
 constexpr int kMaxSlices = 4;
+constexpr int kMaxRecordings = 8;  // per device, least recently used evicted
+struct Recording {
+  BatchedCfg cfg{};
+  int q = 0, precision = 0, S = 0;
+  std::vector<int64_t> m, n, cut;
+  uint64_t args = 0;              // hash of the workspace, pointers, ld and seeds
+  std::vector<size_t> sizes;      // byte size of every round (layout check)
+  std::vector<size_t> offsets;    // device offset of every round
+  unsigned char* dev = nullptr;   // resident descriptors
+  unsigned char* host = nullptr;  // pinned staging of the last upload
+  size_t bytes = 0;
+  hipGraphExec_t exec[kMaxSlices] = {};
+  hipEvent_t uploaded = nullptr;  // the staging copy has been read
+  hipEvent_t done = nullptr;      // the last replay has completed
+  uint64_t used = 0;
+};
+
+// Per-device resources kept between calls: the slices' streams (default
+// priority), their descriptor rings, the events that order them after and
+// before the caller's stream, and the recorded calls.
 struct DeviceRes {
   Ring rings[kMaxSlices];
   hipStream_t streams[kMaxSlices] = {};
   hipEvent_t done[kMaxSlices] = {};
   hipEvent_t start = nullptr;
+  hipEvent_t ring_done = nullptr;  // the last lockstep call's rounds are enqueued up to here
+  bool ring_used = false;
+  std::vector<Recording*> recs;
+  uint64_t clock = 0;
 };
 std::unordered_map<int, DeviceRes> g_res;
 
 int slice_resources(DeviceRes& r, int S) {
   if (!r.start) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.start, hipEventDisableTiming));
+  if (!r.ring_done) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.ring_done, hipEventDisableTiming));
   for (int i = 0; i < S; ++i) {
     if (!r.streams[i]) RRF_CHECK_HIP(hipStreamCreateWithFlags(&r.streams[i], hipStreamNonBlocking));
     if (!r.done[i]) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.done[i], hipEventDisableTiming));
@@ -938,13 +1018,223 @@ int slice_resources(DeviceRes& r, int S) {
   return RRF_OK;
 }
 
+int free_recording(Recording* r) {
+  if (r->done) RRF_CHECK_HIP(hipEventSynchronize(r->done));
+  if (r->uploaded) RRF_CHECK_HIP(hipEventSynchronize(r->uploaded));
+  for (int i = 0; i < kMaxSlices; ++i)
+    if (r->exec[i]) RRF_CHECK_HIP(hipGraphExecDestroy(r->exec[i]));
+  if (r->dev) RRF_CHECK_HIP(hipFree(r->dev));
+  if (r->host) RRF_CHECK_HIP(hipHostFree(r->host));
+  if (r->done) RRF_CHECK_HIP(hipEventDestroy(r->done));
+  if (r->uploaded) RRF_CHECK_HIP(hipEventDestroy(r->uploaded));
+  delete r;
+  return RRF_OK;
+}
+
+uint64_t fnv(uint64_t h, uint64_t v) {
+  for (int i = 0; i < 8; ++i) {
+    h ^= (v >> (8 * i)) & 0xff;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+uint64_t args_hash(const std::vector<Mat>& mats, const void* ws) {
+  uint64_t h = fnv(1469598103934665603ull, (uintptr_t)ws);
+  for (const auto& x : mats) {
+    h = fnv(h, (uintptr_t)x.A);
+    h = fnv(h, (uint64_t)x.lda);
+    h = fnv(h, (uintptr_t)x.U);
+    h = fnv(h, (uintptr_t)x.T);
+    h = fnv(h, (uintptr_t)x.V);
+    h = fnv(h, x.seed);
+  }
+  return h;
+}
+
+struct Slice {
+  std::vector<Mat> mats;
+  Shared sh;
+  int rc = RRF_OK;
+  std::string msg;
+  std::vector<Plan> plans;  // replay mode: every round, in order
+};
+
+// Build every slice's rounds on host threads (one per slice).
+int build_plans(int dev, std::vector<Slice>& work, const BatchedCfg& cfg, int q, int precision) {
+  std::vector<std::thread> threads;
+  for (size_t i = 0; i < work.size(); ++i) {
+    threads.emplace_back([&, i]() {
+      Slice& w = work[i];
+      w.plans.clear();
+      hipError_t e = hipSetDevice(dev);
+      if (e != hipSuccess) {
+        w.rc = set_hip_error(e, "hipSetDevice", __FILE__, __LINE__);
+      } else if (!w.mats.empty()) {
+        w.rc = plan_slice([&](Plan& p) {
+          if (!p.ops.empty()) w.plans.push_back(std::move(p));
+          return RRF_OK;
+        }, w.mats, w.sh, cfg, q, precision);
+      }
+      if (w.rc != RRF_OK) w.msg = rrf_last_error();
+    });
+  }
+  for (auto& t : threads) t.join();
+  for (auto& w : work)
+    if (w.rc != RRF_OK) return set_error(w.rc, w.msg.c_str());
+  return RRF_OK;
+}
+
+// Concatenated descriptors of every round (256-byte aligned) into `host`.
+void pack_plans(const std::vector<Slice>& work, const std::vector<size_t>& offsets,
+                unsigned char* host) {
+  size_t r = 0;
+  for (const auto& w : work)
+    for (const auto& p : w.plans) {
+      if (!p.bytes.empty()) memcpy(host + offsets[r], p.bytes.data(), p.bytes.size());
+      ++r;
+    }
+}
+
+int record(hipStream_t st, DeviceRes& res, std::vector<Slice>& work, Recording* rec) {
+  size_t total = 0;
+  for (const auto& w : work)
+    for (const auto& p : w.plans) {
+      rec->sizes.push_back(p.bytes.size());
+      rec->offsets.push_back(total);
+      total += (p.bytes.size() + 255) & ~(size_t)255;
+    }
+  rec->bytes = std::max<size_t>(total, 256);
+  RRF_CHECK_HIP(hipMalloc((void**)&rec->dev, rec->bytes));
+  RRF_CHECK_HIP(hipHostMalloc((void**)&rec->host, rec->bytes, hipHostMallocDefault));
+  RRF_CHECK_HIP(hipEventCreateWithFlags(&rec->uploaded, hipEventDisableTiming));
+  RRF_CHECK_HIP(hipEventCreateWithFlags(&rec->done, hipEventDisableTiming));
+  pack_plans(work, rec->offsets, rec->host);
+  RRF_CHECK_HIP(hipMemcpyAsync(rec->dev, rec->host, rec->bytes, hipMemcpyHostToDevice, st));
+  RRF_CHECK_HIP(hipEventRecord(rec->uploaded, st));
+  // capture each slice's launches on its own stream (nothing runs while
+  // capturing; the descriptors are read when the graph is launched)
+  size_t r = 0;
+  for (int i = 0; i < rec->S; ++i) {
+    hipStream_t cs = res.streams[i];
+    RRF_CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = RRF_OK;
+    for (const auto& p : work[i].plans) {
+      rc = enqueue_plan(cs, p, rec->dev + rec->offsets[r++]);
+      if (rc != RRF_OK) break;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != RRF_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    RRF_CHECK_HIP(e);
+    e = hipGraphInstantiate(&rec->exec[i], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    RRF_CHECK_HIP(e);
+  }
+  return RRF_OK;
+}
+
+// Launch the recorded graphs, each slice on its own stream, ordered after
+// and before the caller's stream.
+int replay(hipStream_t st, DeviceRes& res, Recording* rec) {
+  RRF_CHECK_HIP(hipEventRecord(res.start, st));
+  for (int i = 0; i < rec->S; ++i) {
+    RRF_CHECK_HIP(hipStreamWaitEvent(res.streams[i], res.start, 0));
+    RRF_CHECK_HIP(hipGraphLaunch(rec->exec[i], res.streams[i]));
+    RRF_CHECK_HIP(hipEventRecord(res.done[i], res.streams[i]));
+    RRF_CHECK_HIP(hipStreamWaitEvent(st, res.done[i], 0));
+  }
+  RRF_CHECK_HIP(hipEventRecord(rec->done, st));
+  return RRF_OK;
+}
+
+bool same_shapes(const Recording* r, const std::vector<Mat>& mats, const std::vector<int64_t>& cut,
+                 const BatchedCfg& cfg, int q, int precision) {
+  if (r->cfg.b != cfg.b || r->cfg.tile_mask != cfg.tile_mask || r->cfg.leaf != cfg.leaf ||
+      r->q != q || r->precision != precision || r->cut != cut || r->m.size() != mats.size())
+    return false;
+  for (size_t j = 0; j < mats.size(); ++j)
+    if (r->m[j] != mats[j].m || r->n[j] != mats[j].n) return false;
+  return true;
+}
+
+int run_recorded(hipStream_t st, int dev, DeviceRes& res, std::vector<Slice>& work,
+                 const std::vector<Mat>& mats, const std::vector<int64_t>& cut, const void* ws,
+                 const BatchedCfg& cfg, int q, int precision) {
+  const uint64_t h = args_hash(mats, ws);
+  Recording* rec = nullptr;
+  for (auto* r : res.recs)
+    if (same_shapes(r, mats, cut, cfg, q, precision)) rec = r;
+  if (rec && rec->args != h) {
+    RRF_TRY(build_plans(dev, work, cfg, q, precision));
+    size_t nr = 0;
+    bool same = true;
+    for (const auto& w : work)
+      for (const auto& p : w.plans) {
+        same = same && nr < rec->sizes.size() && rec->sizes[nr] == p.bytes.size();
+        ++nr;
+      }
+    if (same && nr == rec->sizes.size()) {
+      // the staging buffer is reused once its last copy has been read, and
+      // the device buffer once the last replay (on any stream) has read it
+      RRF_CHECK_HIP(hipEventSynchronize(rec->uploaded));
+      pack_plans(work, rec->offsets, rec->host);
+      RRF_CHECK_HIP(hipStreamWaitEvent(st, rec->done, 0));
+      RRF_CHECK_HIP(hipMemcpyAsync(rec->dev, rec->host, rec->bytes, hipMemcpyHostToDevice, st));
+      RRF_CHECK_HIP(hipEventRecord(rec->uploaded, st));
+      rec->args = h;
+    } else {  // not expected (the rounds follow the shapes): record afresh
+      res.recs.erase(std::find(res.recs.begin(), res.recs.end(), rec));
+      RRF_TRY(free_recording(rec));
+      rec = nullptr;
+    }
+  }
+  if (!rec) {
+    if (work[0].plans.empty()) RRF_TRY(build_plans(dev, work, cfg, q, precision));
+    if ((int)res.recs.size() >= kMaxRecordings) {
+      auto lru = std::min_element(res.recs.begin(), res.recs.end(),
+                                  [](const Recording* x, const Recording* y) {
+                                    return x->used < y->used;
+                                  });
+      Recording* old = *lru;
+      res.recs.erase(lru);
+      RRF_TRY(free_recording(old));
+    }
+    rec = new Recording();
+    rec->cfg = cfg;
+    rec->q = q;
+    rec->precision = precision;
+    rec->S = (int)work.size();
+    rec->cut = cut;
+    for (const auto& x : mats) {
+      rec->m.push_back(x.m);
+      rec->n.push_back(x.n);
+    }
+    rec->args = h;
+    const int rc = record(st, res, work, rec);
+    if (rc != RRF_OK) {
+      const std::string msg = rrf_last_error();
+      (void)free_recording(rec);
+      return set_error(rc, msg.c_str());
+    }
+    res.recs.push_back(rec);
+  }
+  rec->used = ++res.clock;
+  return replay(st, res, rec);
+}
+
 }  // namespace
 
 int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const int64_t* n,
-                        const double* const* A, const int64_t* lda, int64_t b, int q,
+                        const double* const* A, const int64_t* lda, const BatchedCfg& cfg, int q,
                         const uint64_t* seeds, double* const* U, double* const* T,
-                        double* const* V, void* ws, size_t ws_bytes, int precision) {
+                        double* const* V, void* ws, size_t ws_bytes, int precision,
+                        bool use_graph) {
   if (count < 1) return RRF_OK;
+  const int64_t b = cfg.b;
   std::vector<Mat> mats;
   Shared sh;
   const size_t need =
@@ -967,8 +1257,7 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
   // rounds of one slice leave the chip partly idle in their latency-bound
   // launches (panels, small SVDs), which the other slices' GEMMs fill.
   const int S = (int)std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, count / 256));
-  if (S == 1) return run_slice(st, res.rings[0], mats, sh, b, q, precision);
-  RRF_TRY(slice_resources(res, S));
+  RRF_TRY(slice_resources(res, std::max(S, 1)));
   double total = 0.0;
   for (auto& x : mats) total += (double)x.m * x.n * x.n;
   std::vector<int64_t> cut(S + 1, count);
@@ -981,16 +1270,10 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
       if (acc >= total * c / S) cut[c++] = j + 1;
     }
   }
-  struct Work {
-    std::vector<Mat> mats;
-    Shared sh;
-    int rc = RRF_OK;
-    std::string msg;
-  };
-  std::vector<Work> work(S);
+  std::vector<Slice> work(S);
   const size_t svd_per_block = sh.nblocks ? sh.svd_bytes / (size_t)sh.nblocks : 0;
   for (int i = 0; i < S; ++i) {
-    Work& w = work[i];
+    Slice& w = work[i];
     w.mats.assign(mats.begin() + cut[i], mats.begin() + cut[i + 1]);
     const int64_t off = w.mats.empty() ? 0 : w.mats.front().blk0;
     int64_t nb = 0;
@@ -1008,17 +1291,30 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
     w.sh.svd = static_cast<char*>(sh.svd) + off * svd_per_block;
     w.sh.svd_bytes = nb * svd_per_block;
   }
+  if (use_graph && !trace_on())
+    return run_recorded(st, dev, res, work, mats, cut, ws, cfg, q, precision);
+
+  // lockstep rounds streamed through the descriptor rings; the rings' slots
+  // are reused only after every round a previous call enqueued (possibly on
+  // another stream) has been read
+  if (res.ring_used) RRF_CHECK_HIP(hipStreamWaitEvent(st, res.ring_done, 0));
+  if (S == 1) {
+    const int rc = run_slice(st, res.rings[0], work[0].mats, work[0].sh, cfg, q, precision);
+    RRF_CHECK_HIP(hipEventRecord(res.ring_done, st));
+    res.ring_used = true;
+    return rc;
+  }
   RRF_CHECK_HIP(hipEventRecord(res.start, st));
   for (int i = 0; i < S; ++i) RRF_CHECK_HIP(hipStreamWaitEvent(res.streams[i], res.start, 0));
   std::vector<std::thread> threads;
   for (int i = 0; i < S; ++i) {
     threads.emplace_back([&, i]() {
-      Work& w = work[i];
+      Slice& w = work[i];
       hipError_t e = hipSetDevice(dev);  // the current device is per thread
       if (e != hipSuccess) {
         w.rc = set_hip_error(e, "hipSetDevice", __FILE__, __LINE__);
       } else if (!w.mats.empty()) {
-        w.rc = run_slice(res.streams[i], res.rings[i], w.mats, w.sh, b, q, precision);
+        w.rc = run_slice(res.streams[i], res.rings[i], w.mats, w.sh, cfg, q, precision);
       }
       if (w.rc != RRF_OK) w.msg = rrf_last_error();
     });
@@ -1029,6 +1325,8 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
     RRF_CHECK_HIP(hipEventRecord(res.done[i], res.streams[i]));
     RRF_CHECK_HIP(hipStreamWaitEvent(st, res.done[i], 0));
   }
+  RRF_CHECK_HIP(hipEventRecord(res.ring_done, st));
+  res.ring_used = true;
   for (auto& w : work)
     if (w.rc != RRF_OK) return set_error(w.rc, w.msg.c_str());
   return RRF_OK;
@@ -1048,11 +1346,14 @@ int randutv_batched_release() {
       if (ring.host) RRF_CHECK_HIP(hipHostFree(ring.host));
       if (ring.dev) RRF_CHECK_HIP(hipFree(ring.dev));
     }
+    for (auto* rec : r.recs) RRF_TRY(free_recording(rec));
+    r.recs.clear();
     for (int i = 0; i < kMaxSlices; ++i) {
       if (r.streams[i]) RRF_CHECK_HIP(hipStreamDestroy(r.streams[i]));
       if (r.done[i]) RRF_CHECK_HIP(hipEventDestroy(r.done[i]));
     }
     if (r.start) RRF_CHECK_HIP(hipEventDestroy(r.start));
+    if (r.ring_done) RRF_CHECK_HIP(hipEventDestroy(r.ring_done));
   }
   g_res.clear();
   RRF_CHECK_HIP(hipSetDevice(cur));

@@ -105,8 +105,10 @@ __global__ __launch_bounds__(256) void maxabs_kernel(int64_t rows, int64_t cols,
 __global__ __launch_bounds__(256) void scale_pow2_kernel(int64_t rows, int64_t cols, double* X,
                                                          int64_t ld,
                                                          const unsigned long long* word,
-                                                         bool inverse) {
+                                                         bool inverse, int guard_exp) {
   const double s0 = pow2_scale(__longlong_as_double((long long)*word));
+  // guarded: only a max|X| with binary exponent beyond +-guard_exp is scaled
+  if (guard_exp > 0 && s0 >= ldexp(1.0, -guard_exp) && s0 <= ldexp(1.0, guard_exp)) return;
   const double s = inverse ? 1.0 / s0 : s0;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= rows) return;
@@ -539,11 +541,12 @@ int frob_norm(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64
 }
 
 int scale_pow2(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld,
-               const unsigned long long* word, bool inverse) {
+               const unsigned long long* word, bool inverse, int guard_exp) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
   const dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 65535));
   int tok = trace_begin(st, kTrElementwise, 0.0, 16.0 * rows * cols);
-  hipLaunchKernelGGL(scale_pow2_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word, inverse);
+  hipLaunchKernelGGL(scale_pow2_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word, inverse,
+                     guard_exp);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;

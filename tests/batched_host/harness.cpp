@@ -1,24 +1,41 @@
 // Runs the batched driver against the test double of mock_kernels.cpp:
 // reads matrices from argv[1], writes T (and U, V) to argv[2], prints the
 // status and the number of access violations.
+//
+// Mode 0 streams the lockstep rounds through the descriptor rings. Mode 1
+// records the call as graphs and replays it three times: the recording call,
+// a replay into the same buffers after they were overwritten with NaN (A
+// restored for an in-place call), and a replay into newly allocated outputs
+// (the descriptors rebuilt and uploaded); the last results are written.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 #include <cstdint>
 #include <hip/hip_runtime.h>
 #include "driver.hpp"
 extern "C" long mock_errors();
+extern "C" long mock_graph_launches();
 extern "C" void* mock_malloc(size_t);
+
+static void poison(double* p, size_t count) {
+  for (size_t i = 0; i < count; ++i) p[i] = NAN;
+}
+
 int main(int argc, char** argv) {
   FILE* f = fopen(argv[1], "rb");
-  int64_t hdr[8];
-  if (fread(hdr, 8, 8, f) != 8) return 2;
+  int64_t hdr[10];
+  if (fread(hdr, 8, 10, f) != 10) return 2;
   const int64_t count = hdr[0], b = hdr[1], q = hdr[2];
   const uint64_t seed = hdr[3];
   const bool wu = hdr[4], wv = hdr[5], inplace = hdr[6];
   const int precision = (int)hdr[7];
+  const bool graph = hdr[8] != 0;
+  const int leaf = (int)hdr[9];
   std::vector<int64_t> m(count), n(count), lda(count);
   std::vector<const double*> A(count);
+  std::vector<std::vector<double>> Ahost(count);
   std::vector<double*> U(count), T(count), V(count);
   std::vector<uint64_t> seeds(count);
   for (int64_t j = 0; j < count; ++j) {
@@ -27,6 +44,7 @@ int main(int argc, char** argv) {
     m[j] = s[0]; n[j] = s[1]; lda[j] = s[2];
     double* a = (double*)mock_malloc(8 * lda[j] * n[j]);
     if (fread(a, 8, lda[j] * n[j], f) != (size_t)(lda[j] * n[j])) return 2;
+    Ahost[j].assign(a, a + lda[j] * n[j]);
     A[j] = a;
     T[j] = inplace ? a : (double*)mock_malloc(8 * m[j] * n[j]);
     U[j] = wu ? (double*)mock_malloc(8 * m[j] * m[j]) : nullptr;
@@ -37,10 +55,39 @@ int main(int argc, char** argv) {
   size_t ws = rrf::randutv_batched_workspace(count, m.data(), n.data(), b, precision);
   void* w = mock_malloc(ws);
   ((int*)w)[0] = 0; ((int*)w)[1] = 0;
-  int rc = rrf::randutv_batched_run(nullptr, count, m.data(), n.data(), A.data(), lda.data(), b, (int)q,
-                                    seeds.data(), wu ? U.data() : nullptr, T.data(),
-                                    wv ? V.data() : nullptr, w, ws, precision);
-  printf("rc=%d mock_errors=%ld ws=%zu\n", rc, mock_errors(), ws);
+  auto call = [&]() {
+    const rrf::BatchedCfg cfg{b, rrf::kTileMaskAll, leaf};
+    return rrf::randutv_batched_run(nullptr, count, m.data(), n.data(), A.data(), lda.data(), cfg,
+                                    (int)q, seeds.data(), wu ? U.data() : nullptr, T.data(),
+                                    wv ? V.data() : nullptr, w, ws, precision, graph);
+  };
+  int rc = call();
+  if (graph && rc == 0) {
+    for (int64_t j = 0; j < count; ++j) {
+      if (inplace) memcpy((void*)A[j], Ahost[j].data(), 8 * lda[j] * n[j]);
+      else poison(T[j], m[j] * n[j]);
+      if (wu) poison(U[j], m[j] * m[j]);
+      if (wv) poison(V[j], n[j] * n[j]);
+    }
+    rc = call();
+  }
+  if (graph && rc == 0) {
+    for (int64_t j = 0; j < count; ++j) {
+      if (inplace) {
+        double* a = (double*)mock_malloc(8 * lda[j] * n[j]);
+        memcpy(a, Ahost[j].data(), 8 * lda[j] * n[j]);
+        A[j] = a;
+        T[j] = a;
+      } else {
+        T[j] = (double*)mock_malloc(8 * m[j] * n[j]);
+      }
+      if (wu) U[j] = (double*)mock_malloc(8 * m[j] * m[j]);
+      if (wv) V[j] = (double*)mock_malloc(8 * n[j] * n[j]);
+    }
+    rc = call();
+  }
+  printf("rc=%d mock_errors=%ld ws=%zu graph_launches=%ld\n", rc, mock_errors(), ws,
+         mock_graph_launches());
   FILE* o = fopen(argv[2], "wb");
   for (int64_t j = 0; j < count; ++j) {
     fwrite(T[j], 8, m[j] * n[j], o);

@@ -21,6 +21,7 @@
 #include <unordered_map>
 #include <vector>
 #include <algorithm>
+#include <functional>
 
 #include "batched.hpp"
 #include "common.hpp"
@@ -97,7 +98,61 @@ hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned) { *e = (hipEvent_t)m
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 hipError_t hipEventDestroy(hipEvent_t e) { free(e); return hipSuccess; }
-hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) {
+// Stream capture: operations enqueued on the capturing stream are kept as
+// closures in the graph (descriptors and data are read when the graph is
+// launched, as on the device) instead of running at once.
+struct MockGraph {
+  std::vector<std::function<void()>> ops;
+};
+static hipStream_t g_capture = nullptr;
+static MockGraph* g_captured = nullptr;
+static long g_graph_launches = 0;
+static bool mock_capturing(hipStream_t st) { return st != nullptr && st == g_capture; }
+static void mock_defer(std::function<void()> f) { g_captured->ops.push_back(std::move(f)); }
+#define MOCK_DEFER(st, call)                   \
+  if (mock_capturing(st)) {                    \
+    mock_defer([=]() { (void)(call); });       \
+    return RRF_OK;                             \
+  }
+
+hipError_t hipStreamBeginCapture(hipStream_t st, hipStreamCaptureMode) {
+  if (g_capture) return hipErrorIllegalState;
+  g_capture = st;
+  g_captured = new MockGraph();
+  return hipSuccess;
+}
+hipError_t hipStreamEndCapture(hipStream_t st, hipGraph_t* g) {
+  if (st != g_capture) return hipErrorIllegalState;
+  *g = reinterpret_cast<hipGraph_t>(g_captured);
+  g_capture = nullptr;
+  g_captured = nullptr;
+  return hipSuccess;
+}
+hipError_t hipGraphInstantiate(hipGraphExec_t* e, hipGraph_t g, hipGraphNode_t*, char*, size_t) {
+  *e = reinterpret_cast<hipGraphExec_t>(new MockGraph(*reinterpret_cast<MockGraph*>(g)));
+  return hipSuccess;
+}
+hipError_t hipGraphDestroy(hipGraph_t g) {
+  delete reinterpret_cast<MockGraph*>(g);
+  return hipSuccess;
+}
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) {
+  delete reinterpret_cast<MockGraph*>(e);
+  return hipSuccess;
+}
+hipError_t hipGraphLaunch(hipGraphExec_t e, hipStream_t) {
+  ++g_graph_launches;
+  for (auto& f : reinterpret_cast<MockGraph*>(e)->ops) f();
+  return hipSuccess;
+}
+extern "C" long mock_graph_launches() { return g_graph_launches; }
+
+hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st) {
+  if (mock_capturing(st)) {
+    mock_defer([=]() { (void)hipMemcpyAsync(d, s, n, k, nullptr); });
+    return hipSuccess;
+  }
+  if (!inb(d, n) && g_alloc.size() && k != hipMemcpyDeviceToHost) fail("copy to unallocated memory", d);
   memcpy(d, s, n);
   return hipSuccess;
 }
@@ -121,13 +176,15 @@ int set_error(int status, const char* msg) {
 }
 
 extern "C" const char* rrf_last_error(void) { return "mock"; }
+bool trace_on() { return false; }
 int fill_u32(hipStream_t, unsigned* p, int64_t count, unsigned v) {
   for (int64_t i = 0; i < count; ++i) p[i] = v;
   return RRF_OK;
 }
 
-int gemm_grouped(hipStream_t, bool ta, bool tb, int tile, bool vec, const GemmDesc* d,
+int gemm_grouped(hipStream_t st_, bool ta, bool tb, int tile, bool vec, const GemmDesc* d,
                  const int* prefix, int count, int64_t total_tiles, double) {
+  MOCK_DEFER(st_, gemm_grouped(nullptr, ta, tb, tile, vec, d, prefix, count, total_tiles, 0.0));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   if (vec)
     for (int p = 0; p < count; ++p)
@@ -160,7 +217,8 @@ int gemm_grouped(hipStream_t, bool ta, bool tb, int tile, bool vec, const GemmDe
   return RRF_OK;
 }
 
-int elem_batched(hipStream_t, const ElemDesc* d, int count, int64_t max_cols) {
+int elem_batched(hipStream_t st_, const ElemDesc* d, int count, int64_t max_cols) {
+  MOCK_DEFER(st_, elem_batched(nullptr, d, count, max_cols));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("elem");
   for (int p = 0; p < count; ++p) {
@@ -207,7 +265,8 @@ static void gauss4(uint64_t seed, uint64_t sid, uint64_t gr, uint64_t c, double 
   v[2] = rb * cos(tw * vb); v[3] = rb * sin(tw * vb);
 }
 
-int gauss_batched(hipStream_t, const GaussDesc* d, int count, int64_t max_elems) {
+int gauss_batched(hipStream_t st_, const GaussDesc* d, int count, int64_t max_elems) {
+  MOCK_DEFER(st_, gauss_batched(nullptr, d, count, max_elems));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("gauss");
   for (int p = 0; p < count; ++p) {
@@ -258,7 +317,8 @@ static double pow2s(double m) {
   return ldexp(1.0, -e);
 }
 
-int maxabs_batched(hipStream_t, const MaxDesc* d, int count, int64_t max_rows) {
+int maxabs_batched(hipStream_t st_, const MaxDesc* d, int count, int64_t max_rows) {
+  MOCK_DEFER(st_, maxabs_batched(nullptr, d, count, max_rows));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("maxabs_batched");
   for (int p = 0; p < count; ++p) {
@@ -274,7 +334,8 @@ int maxabs_batched(hipStream_t, const MaxDesc* d, int count, int64_t max_rows) {
   return RRF_OK;
 }
 
-int to_bf16_batched(hipStream_t, const Bf16Desc* d, int count, int64_t max_tiles) {
+int to_bf16_batched(hipStream_t st_, const Bf16Desc* d, int count, int64_t max_tiles) {
+  MOCK_DEFER(st_, to_bf16_batched(nullptr, d, count, max_tiles));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("to_bf16_batched");
   for (int p = 0; p < count; ++p) {
@@ -301,8 +362,9 @@ int to_bf16_batched(hipStream_t, const Bf16Desc* d, int count, int64_t max_tiles
   return RRF_OK;
 }
 
-int gemm_bf16_grouped(hipStream_t, const Bf16GemmDesc* d, const int* prefix, int count,
+int gemm_bf16_grouped(hipStream_t st_, const Bf16GemmDesc* d, const int* prefix, int count,
                       int64_t total_tiles, double) {
+  MOCK_DEFER(st_, gemm_bf16_grouped(nullptr, d, prefix, count, total_tiles, 0.0));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("gemm_bf16_grouped");
   if (prefix[0] != 0 || prefix[count] != total_tiles) fail("prefix ends", nullptr);
@@ -327,7 +389,8 @@ int gemm_bf16_grouped(hipStream_t, const Bf16GemmDesc* d, const int* prefix, int
   return RRF_OK;
 }
 
-int round_columns_batched(hipStream_t, const RoundDesc* d, int count, int64_t max_cols) {
+int round_columns_batched(hipStream_t st_, const RoundDesc* d, int count, int64_t max_cols) {
+  MOCK_DEFER(st_, round_columns_batched(nullptr, d, count, max_cols));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("round_columns_batched");
   for (int p = 0; p < count; ++p) {
@@ -353,7 +416,8 @@ int64_t panel_wg_max_rows(int k) {
   return 512 * std::max(1, std::min(32 / K, 8));
 }
 
-int panel_wg_batched(hipStream_t, const PanelDesc* d, int count, int k, int64_t max_rows) {
+int panel_wg_batched(hipStream_t st_, const PanelDesc* d, int count, int k, int64_t max_rows) {
+  MOCK_DEFER(st_, panel_wg_batched(nullptr, d, count, k, max_rows));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("panel");
   if (k < 1 || k > 64 || max_rows > panel_wg_max_rows(k)) return set_error(5, "panel shape");
@@ -419,9 +483,11 @@ int panel_wg_batched(hipStream_t, const PanelDesc* d, int count, int k, int64_t 
 
 size_t block_svd_work_bytes(int k) { return (size_t)2 * k * k * 8 + 256; }
 
-int block_svd_sized(hipStream_t, int count, int kmax, const int* sizes, const double* B,
+int block_svd_sized(hipStream_t st_, int count, int kmax, const int* sizes, const double* B,
                     int64_t ldb, int64_t stride, double* Us, double* d, int64_t dstride,
                     double* Vs, void* work, size_t work_bytes, int* status) {
+  MOCK_DEFER(st_, block_svd_sized(nullptr, count, kmax, sizes, B, ldb, stride, Us, d, dstride, Vs,
+                                  work, work_bytes, status));
   std::lock_guard<std::recursive_mutex> lk_(g_kmu);
   begin_launch("svd");
   (void)work; (void)work_bytes; (void)status;

@@ -1,0 +1,83 @@
+"""The batched call's tuning cache on the host: valid caches load, malformed
+ones are rejected whole (-1) and leave the loaded tables as they were, and
+without a device every lookup falls back to the built-in rule."""
+import json
+
+import pytest
+
+import paper_2106_13402_amd as rrf
+
+GOOD = {"format": "rrf-batched-tune-1", "tables": [
+    {"arch": "gfx950", "precision": 0, "q": 1, "count": 64, "buckets": [
+        {"nmin": 1, "nmax": 64, "b": 16, "tile_mask": 31, "leaf": 0, "ms": 1.0, "candidates": 6},
+        {"nmin": 65, "nmax": 512, "b": 32, "tile_mask": 7, "leaf": 16, "ms": 2.0,
+         "candidates": 18}]}]}
+
+
+@pytest.fixture(autouse=True)
+def restore_default():
+    yield
+    import os
+    p = rrf.default_tune_path()
+    rrf.batched_tune_load(p if os.path.exists(p) else None)
+
+
+def _write(tmp_path, obj, name="t.json"):
+    p = tmp_path / name
+    p.write_text(obj if isinstance(obj, str) else json.dumps(obj))
+    return str(p)
+
+
+def test_valid_cache_loads(tmp_path):
+    rrf.batched_tune_load(_write(tmp_path, GOOD))
+    rrf.batched_tune_load(None)
+
+
+@pytest.mark.parametrize("bad", [
+    "{",                                                       # truncated
+    '{"format": "other", "tables": []}',                       # wrong format tag
+    {"format": "rrf-batched-tune-1"},                          # no tables
+    {"format": "rrf-batched-tune-1", "tables": [{"arch": "gfx950", "precision": 0,
+                                                 "buckets": [{"nmin": 1, "nmax": 64, "b": 0}]}]},
+    {"format": "rrf-batched-tune-1", "tables": [{"arch": "gfx950", "precision": 0,
+                                                 "buckets": [{"nmin": 9, "nmax": 4, "b": 16}]}]},
+    {"format": "rrf-batched-tune-1", "tables": [{"arch": "gfx950", "precision": 0,
+                                                 "buckets": [{"nmin": 1, "nmax": 4, "b": 16,
+                                                              "tile_mask": 64}]}]},
+    '{"format": "rrf-batched-tune-1", "tables": []} trailing',
+])
+def test_malformed_cache_rejected(tmp_path, bad):
+    with pytest.raises(rrf.RRFError) as e:
+        rrf.batched_tune_load(_write(tmp_path, bad))
+    assert e.value.status == -1
+
+
+def test_missing_file_rejected(tmp_path):
+    with pytest.raises(rrf.RRFError) as e:
+        rrf.batched_tune_load(str(tmp_path / "absent.json"))
+    assert e.value.status == -1
+
+
+def test_lookup_without_device_is_builtin(tmp_path):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("host-only check")
+    rrf.batched_tune_load(_write(tmp_path, GOOD))
+    for m, n, b in ((100, 60, 16), (600, 300, 32), (40, 700, 16), (300, 700, 32)):
+        c = rrf.batched_config(m, n)
+        assert c == {"b": b, "tile_mask": 31, "leaf": 0, "tuned": False}
+
+
+def test_config_argument_errors():
+    with pytest.raises(rrf.RRFError) as e:
+        rrf.batched_config(0, 4)
+    assert e.value.status == -1
+    import ctypes as C
+    from paper_2106_13402_amd import _lib
+    cfg = _lib.rrf_batched_cfg()
+    assert rrf.lib.rrf_batched_config(4, 4, 2, C.byref(cfg)) == -3  # x3: not batched
+    assert rrf.lib.rrf_batched_config(4, 4, 0, None) == -4
+    assert rrf.lib.rrf_batched_autotune(5, 1, 8, 64, 0, None, None) == -1
+    assert rrf.lib.rrf_batched_autotune(0, -1, 8, 64, 0, None, None) == -2
+    assert rrf.lib.rrf_batched_autotune(0, 1, 0, 64, 0, None, None) == -3
+    assert rrf.lib.rrf_batched_autotune(0, 1, 8, 2048, 0, None, None) == -4

@@ -47,14 +47,15 @@ def harness(tmp_path_factory):
     return exe, out
 
 
-def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0, precision=0):
+def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0, precision=0,
+         graph=False, leaf=0):
     exe, out = harness
     rng = np.random.default_rng(len(shapes) * 7 + b + q)
     As = []
     fin, fout = str(out / "in.bin"), str(out / "out.bin")
     with open(fin, "wb") as f:
-        f.write(struct.pack("<8q", len(shapes), b, q, seed, int(wu), int(wv), int(inplace),
-                            precision))
+        f.write(struct.pack("<10q", len(shapes), b, q, seed, int(wu), int(wv), int(inplace),
+                            precision, int(graph), leaf))
         for m, n in shapes:
             A = rng.standard_normal((m, n))
             As.append(A)
@@ -66,6 +67,8 @@ def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0, pr
     r = subprocess.run([exe, fin, fout], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "mock_errors=0" in r.stdout, r.stdout + r.stderr[:2000]
+    launches = int(r.stdout.split("graph_launches=")[1].split()[0])
+    assert (launches > 0) == graph, r.stdout
     raw = np.fromfile(fout)
     off = 0
     for j, (m, n) in enumerate(shapes):
@@ -97,38 +100,51 @@ def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0, pr
             assert np.all(eg <= 1.5 * eo + 1e-12 * nA), (eg, eo)
 
 
-def test_planner_ragged_batch(harness):
+MODES = pytest.mark.parametrize("graph", [False, True], ids=["lockstep", "replay"])
+
+
+@MODES
+def test_planner_ragged_batch(harness, graph):
     _run(harness, [(40, 30), (64, 64), (33, 17), (100, 64), (9, 4), (70, 70), (1, 1), (5, 1)],
-         8, 1, 5)
+         8, 1, 5, graph=graph)
 
 
-def test_planner_no_u_and_narrow(harness):
-    _run(harness, [(40, 30), (64, 64), (33, 17), (20, 5), (7, 7)], 16, 0, 5, wu=False)
-    _run(harness, [(50, 20), (20, 20)], 4, 2, 9, wv=False, pad=3)
+@MODES
+def test_planner_no_u_and_narrow(harness, graph):
+    _run(harness, [(40, 30), (64, 64), (33, 17), (20, 5), (7, 7)], 16, 0, 5, wu=False,
+         graph=graph)
+    _run(harness, [(50, 20), (20, 20)], 4, 2, 9, wv=False, pad=3, graph=graph)
 
 
-def test_planner_in_place(harness):
-    _run(harness, [(30, 30), (45, 31)], 64, 1, 3, inplace=True)
+@MODES
+def test_planner_in_place(harness, graph):
+    _run(harness, [(30, 30), (45, 31)], 64, 1, 3, inplace=True, graph=graph)
 
 
-def test_planner_split_panels(harness):
+@MODES
+def test_planner_split_panels(harness, graph):
     # b = 64: 300-row panels exceed one workgroup at k = 64 and are split
     # once; b = 32 with 1100 rows is split twice (32 -> 16 -> 8)
-    _run(harness, [(300, 200), (130, 64), (64, 10)], 64, 1, 11)
-    _run(harness, [(1100, 24), (31, 31)], 32, 0, 2, wv=False)
+    _run(harness, [(300, 200), (130, 64), (64, 10)], 64, 1, 11, graph=graph)
+    _run(harness, [(1100, 24), (31, 31)], 32, 0, 2, wv=False, graph=graph)
+    # a forced leaf width (the tuner's panel knob): 32-column panels factored
+    # as 8-column leaves merged twice, though one workgroup would hold them
+    _run(harness, [(120, 70), (64, 33)], 32, 1, 4, graph=graph, leaf=8)
 
 
-def test_planner_slices(harness):
-    # 520 matrices: cut into two slices, each driven by its own host thread
+@MODES
+def test_planner_slices(harness, graph):
+    # 520 matrices: cut into two slices, each on its own stream
     rng = np.random.default_rng(7)
     ns = rng.integers(1, 7, size=520)
     shapes = [(int(rng.integers(n, 2 * n + 1)), int(n)) for n in ns]
-    _run(harness, shapes, 4, 1, 13)
+    _run(harness, shapes, 4, 1, 13, graph=graph)
 
 
-def test_planner_mixed_sketch(harness):
+@MODES
+def test_planner_mixed_sketch(harness, graph):
     # the bfloat16 sketch: its conversions, grouped products and column
     # roundings go through the same bounds, race and padding checks
     _run(harness, [(40, 30), (64, 64), (33, 17), (100, 64), (9, 4), (70, 70)], 8, 1, 5,
-         precision=1)
-    _run(harness, [(300, 200), (64, 10)], 32, 2, 11, precision=1)
+         precision=1, graph=graph)
+    _run(harness, [(300, 200), (64, 10)], 32, 2, 11, precision=1, graph=graph)

@@ -37,13 +37,14 @@ def _run(As_host, b, q, seed, gpu, **kw):
             [_host(V) for V in Vs] if Vs is not None else None)
 
 
-def _check_against_oracle(As, Us, Ts, Vs, b, q, seed):
+def _check_against_oracle(As, Us, Ts, Vs, b, q, seed, seeds=None):
     for j, A in enumerate(As):
         bj = b if b > 0 else _auto_b(A.shape[1])
+        sj = seeds[j] if seeds is not None else seed + j
         print(f"  matrix {j}: {A.shape[0]}x{A.shape[1]} b={bj}", flush=True)
         _check_factorization(A, Us[j], Ts[j], Vs[j])
         _check_blocks(Ts[j], bj)
-        To, rel = _diag_parity_derived(Ts[j], A, bj, q, seed + j)
+        To, rel = _diag_parity_derived(Ts[j], A, bj, q, sj)
         if rel < 1e-12:
             np.testing.assert_allclose(np.abs(Ts[j]), np.abs(To), atol=1e-9 * M.spec(A))
 
@@ -228,3 +229,46 @@ def test_batched_wide_through_transpose(gpu, b, want_u, want_v):
             assert Vs[j].shape == (n, n) and M.orth_error(Vs[j]) <= 1e-13
         _, To, _ = oracle.randutv(A, bj, 1, 60 + j, want_u=False, want_v=False)
         np.testing.assert_allclose(np.abs(T), np.abs(To), rtol=0, atol=1e-9 * M.spec(A))
+
+
+def test_batched_replay_matches_lockstep(gpu):
+    """The recorded HIP graphs replay exactly the lockstep rounds: U, T and V
+    bitwise equal to the lockstep call on every replay, with the program's
+    own eager work and host synchronizations between the replays and the
+    outputs overwritten before each; then into new output buffers (the
+    descriptors rebuilt and uploaded) and with another seed. 600 matrices
+    make two slices, each replayed on its own stream."""
+    import torch
+    from paper_2106_13402_amd import empty_colmajor, randutv_batched
+    shapes = batch_shapes(600, seed=3, nmin=8, nmax=140)
+    As = [_to_dev(A, gpu) for A in batch_gaussians(shapes, seed=4)]
+    print("case: batched replay 600 matrices q=1 b=0", flush=True)
+    ref = randutv_batched(As, 0, 1, 5, replay=False)
+    torch.cuda.synchronize()
+    outs = ([empty_colmajor(m, m, gpu) for m, n in shapes],
+            [empty_colmajor(m, n, gpu) for m, n in shapes],
+            [empty_colmajor(n, n, gpu) for m, n in shapes])
+
+    def equal(got, want):
+        return all(torch.equal(x, y) for gl, wl in zip(got, want) for x, y in zip(gl, wl))
+
+    X = torch.randn(512, 512, dtype=torch.float64, device=gpu)
+    for rep in range(4):
+        for lst in outs:
+            for t in lst:
+                t.fill_(float("nan"))
+        got = randutv_batched(As, 0, 1, 5, out=outs)
+        Y = X @ X  # eager work between the replays
+        torch.cuda.synchronize()
+        assert float(Y.abs().sum()) > 0
+        assert equal(got, ref), f"replay {rep}"
+    fresh = randutv_batched(As, 0, 1, 5)
+    torch.cuda.synchronize()
+    assert equal(fresh, ref)
+    ref9 = randutv_batched(As, 0, 1, 9, replay=False)
+    got9 = randutv_batched(As, 0, 1, 9, out=outs)
+    torch.cuda.synchronize()
+    assert equal(got9, ref9)
+    # the seed reached the replay (a matrix with n > b has a random sketch)
+    big = max(range(len(shapes)), key=lambda j: shapes[j][1])
+    assert not torch.equal(ref9[1][big], ref[1][big])

@@ -264,6 +264,25 @@ def test_randutv_options_and_layouts(gpu):
     assert torch.equal(T1, T2)
 
 
+@pytest.mark.parametrize("p", [600, -600, 300])
+def test_randutv_extreme_scale(gpu, p):
+    """Entries near 2^600 (or 2^-600): squared column norms would overflow
+    (underflow) binary64, so T is factored from 2^-e A, max|2^-e A| in
+    [0.5, 1), and scaled back; 2^300 stays inside the unscaled range. |T_kk|
+    2^-p matches the oracle on the unscaled A, and U, V and A = U T V^T hold
+    to binary64 accuracy."""
+    print(f"case: randutv extreme scale 2^{p}", flush=True)
+    A = gaussian_matrix(200, 150, seed=11)
+    As = A * 2.0 ** p
+    U, T, V = run_randutv(As, 32, 1, 3, gpu)
+    assert np.all(np.isfinite(T)) and np.all(np.isfinite(U)) and np.all(np.isfinite(V))
+    assert M.orth_error(U) <= 1e-13 and M.orth_error(V) <= 1e-13
+    R = A - U @ (T * 2.0 ** -p) @ V.T
+    assert M.spec(R) <= 1e-13 * M.spec(A)
+    _, To, _ = oracle.randutv(A, 32, 1, 3, want_u=False, want_v=False)
+    _diag_parity(T * 2.0 ** -p, To, M.spec(A), 150)
+
+
 def test_randutv_rejects_nonfinite(gpu):
     from paper_2106_13402_amd import RRFError, randutv
     A = gaussian_matrix(40, 30, seed=1)

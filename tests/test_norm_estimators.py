@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from oracle import metrics as M
-from tests import device_norms as D
+import device_norms as D
 
 CASES = ["gauss_square", "gauss_tall", "power_decay", "rank_one", "tiny", "zero", "upper_tri"]
 

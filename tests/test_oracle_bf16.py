@@ -6,8 +6,9 @@ import numpy as np
 import pytest
 import torch
 
-from oracle.bf16 import (bf16_round, fp32_gemm_bound, fp32_x3_bound, gemm_tn_reference, gemm_x3,
-                         pow2_scale, sketch_bf16, split_x3)
+from oracle.bf16 import (bf16_round, fp32_gemm_bound, fp32_x3_bound, fp32_x6_bound,
+                         gemm_tn_reference, gemm_x3, gemm_x6, pow2_scale, sketch_bf16, split_x3,
+                         split_x6)
 
 
 def _torch_bf16(x32):
@@ -223,3 +224,88 @@ def test_fp32_x3_bound_covers_binary32_sums():
                     s = np.float32(s + t)
                 assert abs(float(s) - ref[i, j]) <= bound[i, j]
         assert np.max(bound / (np.abs(A) @ np.abs(B))) < 1e-3
+
+
+# --------------------------------------------------------- x6 split product
+def test_split_x6_matches_torch_roundings():
+    # hi, mid and lo are torch's bfloat16 roundings of the binary32 value and
+    # of the successive (exact) binary32 remainders
+    rng = np.random.default_rng(20)
+    x = np.concatenate([rng.standard_normal(20000),
+                        rng.standard_normal(5000) * 2.0 ** rng.integers(-100, 100, 5000)])
+    hi, mid, lo = split_x6(x)
+    x32 = torch.from_numpy(x).to(torch.float32)
+    hi_t = x32.to(torch.bfloat16).to(torch.float32)
+    mid_t = (x32 - hi_t).to(torch.bfloat16).to(torch.float32)
+    lo_t = (x32 - hi_t - mid_t).to(torch.bfloat16).to(torch.float32)
+    np.testing.assert_array_equal(hi, hi_t.to(torch.float64).numpy())
+    np.testing.assert_array_equal(mid, mid_t.to(torch.float64).numpy())
+    np.testing.assert_array_equal(lo, lo_t.to(torch.float64).numpy())
+
+
+def test_split_x6_is_exact_on_binary32():
+    # three 8-bit parts hold the 24 bits of x32 (normal range): the split of
+    # the binary32 value loses nothing, only the rounding to binary32 does
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal(200000) * 2.0 ** rng.integers(-60, 60, 200000)
+    hi, mid, lo = split_x6(x)
+    x32 = x.astype(np.float32).astype(np.float64)
+    np.testing.assert_array_equal(hi + mid + lo, x32)
+    rel = np.abs(x - hi - mid - lo) / np.abs(x)
+    assert rel.max() <= 2.0 ** -24 and rel.max() >= 2.0 ** -25
+    # mid within half an ulp of hi, lo within half an ulp of mid
+    assert np.all(np.abs(mid) <= 2.0 ** -8 * np.abs(hi))
+    assert np.all(np.abs(lo) <= 2.0 ** -8 * np.abs(mid) + 1e-300)
+
+
+def test_split_x6_hand_case_and_dropped_terms():
+    # a = 1 + 2^-9 + 2^-18 splits as hi = 1, mid = 2^-9, lo = 2^-18; a a keeps
+    # hh + hm + mh + hl + lh + mm = 1 + 2^-8 + 2^-17 + 2^-18 and drops
+    # ml + lm + ll = 2^-26 + 2^-36
+    a = np.array([[1.0 + 2.0 ** -9 + 2.0 ** -18]])
+    hi, mid, lo = split_x6(a)
+    assert hi[0, 0] == 1.0 and mid[0, 0] == 2.0 ** -9 and lo[0, 0] == 2.0 ** -18
+    assert gemm_x6(a, a)[0, 0] == 1.0 + 2.0 ** -8 + 2.0 ** -17 + 2.0 ** -18
+    assert (a @ a)[0, 0] - gemm_x6(a, a)[0, 0] == 2.0 ** -26 + 2.0 ** -36
+
+
+def test_gemm_x6_error_bound():
+    # per term ab - x6(a, b) = a r_b + r_a b - r_a r_b + (ml + lm + ll) with
+    # r = x - x32 (<= 2^-24 |x|) and |mid| <= 2^-8 |x|, |lo| <= 2^-16 |x|:
+    # at most about 2^-22 |a| |b|; far below the x3 product's 2^-15
+    rng = np.random.default_rng(22)
+    A = rng.standard_normal((40, 300)) * 2.0 ** rng.integers(-8, 8, (40, 300))
+    B = rng.standard_normal((300, 30))
+    err = np.abs(gemm_x6(A, B) - A @ B)
+    scale = np.abs(A) @ np.abs(B)
+    assert np.all(err <= 2.0 ** -22 * scale)
+    err3 = np.abs(gemm_x3(A, B) - A @ B)
+    assert np.max(err3 / scale) > 2.0 ** 6 * np.max(err / scale)
+
+
+def test_fp32_x6_bound_covers_sliced_binary32_sums():
+    # per K slice of 32 the 192 exact terms summed in binary32 in a random
+    # order, the slice sums added in binary64
+    rng = np.random.default_rng(23)
+    for K in (8, 100, 3000):
+        A = rng.standard_normal((4, K))
+        B = rng.standard_normal((K, 3))
+        Ah, Am, Al = split_x6(A)
+        Bh, Bm, Bl = split_x6(B)
+        ref = gemm_x6(A, B)
+        bound = fp32_x6_bound(A, B)
+        for i in range(4):
+            for j in range(3):
+                total = 0.0
+                for k0 in range(0, K, 32):
+                    sl = slice(k0, min(k0 + 32, K))
+                    terms = np.concatenate([Ah[i, sl] * Bh[sl, j], Ah[i, sl] * Bm[sl, j],
+                                            Am[i, sl] * Bh[sl, j], Ah[i, sl] * Bl[sl, j],
+                                            Al[i, sl] * Bh[sl, j], Am[i, sl] * Bm[sl, j]])
+                    s = np.float32(0.0)
+                    for t in rng.permutation(terms).astype(np.float32):
+                        s = np.float32(s + t)
+                    total += float(s)
+                assert abs(total - ref[i, j]) <= bound[i, j]
+        # the slice bound does not grow with K
+        assert np.max(bound / (np.abs(A) @ np.abs(B))) < 2e-5
