@@ -363,22 +363,31 @@ typedef struct rrf_batched_cfg {
   int tuned;  /* 1: taken from a tuning table; 0: the built-in rule */
 } rrf_batched_cfg;
 
-/* Time candidate configurations (b in {16, 32, 64}; every tile shape, no
- * 128 x 128, or only the narrow 128 x 32 / 128 x 16 / 64 x 64 shapes; leaf 0
- * or 16) on synthetic batches of each bucket of n (1-64, 65-128, ..., 449-512
- * in steps of 64, 513-768, 769-1024) up to nmax: `count` Gaussian matrices per
- * bucket up to n = 256 (fewer above, about the same work), n uniform in the
- * bucket and m in [n, 2n] (a generator seeded by `seed`), q power
- * iterations, U and V formed, replayed calls timed by HIP events (median of
- * three after a recording call). The fastest per bucket forms the table of
- * (the current device's architecture, precision), which replaces any loaded
- * one and is written with all loaded tables to `path` (NULL: not written).
- * Allocates its own device buffers; runs on opts->stream.
- *  precision : RRF_PREC_FP64 or RRF_PREC_BF16_SKETCH   (arg 1)
- *  q >= 0 (arg 2), count >= 1 (arg 3), 1 <= nmax <= 1024 (arg 4)
- * Returns -6 when `path` cannot be written. */
-int rrf_batched_autotune(int precision, int32_t q, int64_t count, int64_t nmax, uint64_t seed,
-                         const char* path, const rrf_opts* opts);
+/* Choose a configuration per bucket of n (1-64, 65-128, ..., 449-512 in
+ * steps of 64, 513-768, 769-1024; buckets above nmax are not tuned) among the
+ * candidates b in {16, 32, 64} x {every tile shape, no 128 x 128, only the
+ * narrow 128 x 32 / 128 x 16 / 64 x 64} x leaf {0, 16}, by timing replayed
+ * calls with HIP events (q power iterations, U and V formed, Gaussian
+ * matrices from `seed`):
+ *  - m and n given (host arrays of `count` sizes, each in [1, 4096]): on that
+ *    workload. Every bucket holding some min(m[j], n[j]) starts at the
+ *    built-in rule; bucket by bucket each candidate is installed and the whole
+ *    batched call timed (median of three replays after the recording call);
+ *    the fastest is kept. Meanwhile the trial tables are the process's
+ *    tables (batched calls of other threads follow them).
+ *  - m and n NULL: on a synthetic batch per bucket, `count` matrices with n
+ *    uniform in the bucket and m in [n, 2n].
+ * The result forms the table of (the current device's architecture,
+ * precision), which replaces any loaded one and is written with all loaded
+ * tables to `path` (NULL: not written). Allocates its own device buffers;
+ * runs on opts->stream.
+ *  precision : RRF_PREC_FP64 or RRF_PREC_BF16_SKETCH             (arg 1)
+ *  q >= 0 (arg 2), count >= 1 (arg 3), m, n (args 4, 5),
+ *  1 <= nmax <= 1024 (arg 6), seed (arg 7)
+ * Returns -8 when `path` cannot be written. */
+int rrf_batched_autotune(int precision, int32_t q, int64_t count, const int64_t* m,
+                         const int64_t* n, int64_t nmax, uint64_t seed, const char* path,
+                         const rrf_opts* opts);
 /* Replace the loaded tuning tables by those of the cache file `path` (NULL:
  * unload them, so b = 0 follows the built-in rule). -1 when the file cannot
  * be read or is not a valid cache. Without any call the library loads

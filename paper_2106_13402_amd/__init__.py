@@ -259,14 +259,21 @@ def batched_config(m: int, n: int, precision: str = "fp64") -> dict:
 
 
 def batched_autotune(precision: str = "fp64", q: int = 1, count: int = 256, nmax: int = 512,
-                     seed: int = 0, path: str | None = None) -> None:
+                     seed: int = 0, path: str | None = None, shapes=None) -> None:
     """Run the batched call's autotuner on the current device
-    (rrf_batched_autotune); the table is loaded and, with ``path``, written."""
+    (rrf_batched_autotune): on ``shapes`` (a list of (m, n)) when given, else
+    on ``count`` synthetic matrices per size bucket. The table is loaded and,
+    with ``path``, written."""
     torch = _torch()
     opts = _lib.rrf_opts()
     lib.rrf_opts_init(C.byref(opts))
     opts.stream = torch.cuda.current_stream().cuda_stream
-    _check(lib.rrf_batched_autotune(PRECISIONS[precision], q, count, nmax, seed,
+    if shapes is not None:
+        count = len(shapes)
+        ms, ns = _i64_array([m for m, n in shapes]), _i64_array([n for m, n in shapes])
+    else:
+        ms = ns = None
+    _check(lib.rrf_batched_autotune(PRECISIONS[precision], q, count, ms, ns, nmax, seed,
                                     path.encode() if path else None, C.byref(opts)),
            "rrf_batched_autotune")
 

@@ -74,7 +74,7 @@ PROTOTYPES = {
                                       C.POINTER(rrf_opts)]),
     "rrf_randutv_batched_workspace_size": (_sz, [_i64, _vp, _vp, _i64, C.c_int]),
     "rrf_randutv_batched_block": (_i64, [_i64, _i64]),
-    "rrf_batched_autotune": (C.c_int, [C.c_int, _i32, _i64, _i64, _u64, C.c_char_p,
+    "rrf_batched_autotune": (C.c_int, [C.c_int, _i32, _i64, _vp, _vp, _i64, _u64, C.c_char_p,
                                        C.POINTER(rrf_opts)]),
     "rrf_batched_tune_load": (C.c_int, [C.c_char_p]),
     "rrf_batched_config": (C.c_int, [_i64, _i64, C.c_int, C.POINTER(rrf_batched_cfg)]),

@@ -373,16 +373,9 @@ int read_status(hipStream_t st, const int* status) {
   return RRF_OK;
 }
 
-// Time every candidate on one bucket; fills *best.
-int tune_bucket(hipStream_t st, int64_t nmin, int64_t nmax, int precision, int q, int64_t count,
-                uint64_t seed, Bucket* best) {
-  Rng rng{seed * 0x100000001b3ull + (uint64_t)nmax};
-  std::vector<int64_t> m(count), n(count), lda(count);
-  for (int64_t j = 0; j < count; ++j) {
-    n[j] = rng.uniform(nmin, nmax);
-    m[j] = rng.uniform(n[j], 2 * n[j]);
-    lda[j] = m[j];
-  }
+// The configurations tried for a bucket whose largest n is nmax: b in
+// {16, 32, 64} (b > nmax only for 16), three tile families, leaf 0 or 16.
+std::vector<BatchedCfg> candidates(int64_t nmax) {
   std::vector<BatchedCfg> cands;
   const int masks[3] = {kTileMaskAll, kTileMaskAll & ~(1 << kTile128x128),
                         (1 << kTile128x32) | (1 << kTile128x16) | (1 << kTile64x64)};
@@ -394,6 +387,20 @@ int tune_bucket(hipStream_t st, int64_t nmin, int64_t nmax, int precision, int q
         cands.push_back(BatchedCfg{b, mask, leaf});
       }
   }
+  return cands;
+}
+
+// Time every candidate on one bucket; fills *best.
+int tune_bucket(hipStream_t st, int64_t nmin, int64_t nmax, int precision, int q, int64_t count,
+                uint64_t seed, Bucket* best) {
+  Rng rng{seed * 0x100000001b3ull + (uint64_t)nmax};
+  std::vector<int64_t> m(count), n(count), lda(count);
+  for (int64_t j = 0; j < count; ++j) {
+    n[j] = rng.uniform(nmin, nmax);
+    m[j] = rng.uniform(n[j], 2 * n[j]);
+    lda[j] = m[j];
+  }
+  const std::vector<BatchedCfg> cands = candidates(nmax);
   size_t ws_bytes = 0, a_el = 0, u_el = 0, v_el = 0;
   for (const auto& c : cands)
     ws_bytes = std::max(ws_bytes, randutv_batched_workspace(count, m.data(), n.data(), c.b, precision));
@@ -466,6 +473,125 @@ int tune_bucket(hipStream_t st, int64_t nmin, int64_t nmax, int precision, int q
   return rc;
 }
 
+int bucket_of(int64_t n) {
+  for (int i = 0; i < (int)(sizeof kBuckets / sizeof kBuckets[0]); ++i)
+    if (n >= kBuckets[i][0] && n <= kBuckets[i][1]) return i;
+  return -1;
+}
+
+// Install `t` as the table of its (arch, precision).
+void install(const Table& t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_default_tried = true;
+  merge_tables(std::vector<Table>{t});
+}
+
+// Tuning on the caller's workload: every bucket that holds a matrix of the
+// batch starts at the built-in configuration; bucket by bucket, each
+// candidate is installed and the whole batched call timed (one recording
+// call, the median of three replays), and the fastest kept.
+int tune_workload(hipStream_t st, int precision, int q, int64_t count, const int64_t* m,
+                  const int64_t* n, int64_t nmax, uint64_t seed, Table* tab) {
+  std::vector<int> present(sizeof kBuckets / sizeof kBuckets[0], 0);
+  size_t a_el = 0, u_el = 0, v_el = 0;
+  for (int64_t j = 0; j < count; ++j) {
+    const int bk = bucket_of(std::min(m[j], n[j]));
+    if (bk >= 0 && kBuckets[bk][0] <= nmax) present[bk] = 1;
+    a_el += (size_t)m[j] * n[j];
+    u_el += (size_t)m[j] * m[j];
+    v_el += (size_t)n[j] * n[j];
+  }
+  for (size_t i = 0; i < present.size(); ++i)
+    if (present[i]) {
+      const int64_t hi = std::min(kBuckets[i][1], nmax);
+      tab->buckets.push_back(
+          Bucket{kBuckets[i][0], hi, builtin_config(2 * hi, hi), 0.0, 0});
+    }
+  if (tab->buckets.empty()) return set_error(-4, "autotune: no matrix of the batch in a bucket");
+  DevBuf a, t, u, v, ws;
+  size_t ws_bytes = 0;
+  RRF_TRY(a.alloc(a_el * 8));
+  RRF_TRY(t.alloc(a_el * 8));
+  RRF_TRY(u.alloc(u_el * 8));
+  RRF_TRY(v.alloc(v_el * 8));
+  std::vector<const double*> A(count);
+  std::vector<double*> T(count), U(count), V(count);
+  std::vector<int64_t> lda(count);
+  size_t oa = 0, ou = 0, ov = 0;
+  for (int64_t j = 0; j < count; ++j) {
+    double* aj = static_cast<double*>(a.p) + oa;
+    A[j] = aj;
+    T[j] = static_cast<double*>(t.p) + oa;
+    U[j] = static_cast<double*>(u.p) + ou;
+    V[j] = static_cast<double*>(v.p) + ov;
+    lda[j] = m[j];
+    oa += (size_t)m[j] * n[j];
+    ou += (size_t)m[j] * m[j];
+    ov += (size_t)n[j] * n[j];
+    RRF_TRY(gaussian(st, seed, (uint64_t)(1u << 20) + (uint64_t)j, m[j], n[j], aj, m[j]));
+  }
+  hipEvent_t e0, e1;
+  RRF_CHECK_HIP(hipEventCreate(&e0));
+  RRF_CHECK_HIP(hipEventCreate(&e1));
+  auto timed = [&](const Table& cand, double* ms) -> int {
+    install(cand);
+    const size_t need = rrf_randutv_batched_workspace_size(count, m, n, 0, precision);
+    if (need == 0) return set_error(RRF_E_NOTSUP, "autotune: workspace size");
+    if (need > ws_bytes) {
+      if (ws.p) RRF_CHECK_HIP(hipFree(ws.p));
+      ws.p = nullptr;
+      RRF_TRY(ws.alloc(need));
+      ws_bytes = need;
+    }
+    rrf_opts o;
+    rrf_opts_init(&o);
+    o.precision = precision;
+    o.stream = st;
+    o.workspace = ws.p;
+    o.workspace_bytes = ws_bytes;
+    double t_ms[3] = {0, 0, 0};
+    for (int r = -1; r < 3; ++r) {
+      if (r >= 0) RRF_CHECK_HIP(hipEventRecord(e0, st));
+      RRF_TRY(rrf_randutv_batched(count, m, n, A.data(), lda.data(), 0, q, seed, U.data(),
+                                  T.data(), V.data(), &o));
+      if (r >= 0) {
+        float f = 0.f;
+        RRF_CHECK_HIP(hipEventRecord(e1, st));
+        RRF_CHECK_HIP(hipEventSynchronize(e1));
+        RRF_CHECK_HIP(hipEventElapsedTime(&f, e0, e1));
+        t_ms[r] = f;
+      }
+    }
+    std::sort(t_ms, t_ms + 3);
+    *ms = t_ms[1];
+    return RRF_OK;
+  };
+  int rc = RRF_OK;
+  double best_ms = 0.0;
+  rc = timed(*tab, &best_ms);
+  for (size_t bi = 0; bi < tab->buckets.size() && rc == RRF_OK; ++bi) {
+    Bucket& bk = tab->buckets[bi];
+    const std::vector<BatchedCfg> cands = candidates(bk.nmax);
+    bk.candidates = (int)cands.size();
+    for (const auto& c : cands) {
+      if (c.b == bk.cfg.b && c.tile_mask == bk.cfg.tile_mask && c.leaf == bk.cfg.leaf) continue;
+      Table trial = *tab;
+      trial.buckets[bi].cfg = c;
+      double ms = 0.0;
+      rc = timed(trial, &ms);
+      if (rc != RRF_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        bk.cfg = c;
+      }
+    }
+  }
+  for (auto& bk : tab->buckets) bk.ms = best_ms;  // the whole call's time
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 }  // namespace
 
 BatchedCfg batched_config(int64_t m, int64_t n, int precision) {
@@ -520,13 +646,21 @@ int rrf_batched_config(int64_t m, int64_t n, int precision, rrf_batched_cfg* out
   return RRF_OK;
 }
 
-int rrf_batched_autotune(int precision, int32_t q, int64_t count, int64_t nmax, uint64_t seed,
-                         const char* path, const rrf_opts* opts) {
+int rrf_batched_autotune(int precision, int32_t q, int64_t count, const int64_t* m,
+                         const int64_t* n, int64_t nmax, uint64_t seed, const char* path,
+                         const rrf_opts* opts) {
   if (precision != RRF_PREC_FP64 && precision != RRF_PREC_BF16_SKETCH)
     return set_error(-1, "precision must be RRF_PREC_FP64 or RRF_PREC_BF16_SKETCH"), -1;
   if (q < 0) return set_error(-2, "q must be >= 0"), -2;
   if (count < 1) return set_error(-3, "count must be >= 1"), -3;
-  if (nmax < 1 || nmax > 1024) return set_error(-4, "nmax must be in [1, 1024]"), -4;
+  if ((m == nullptr) != (n == nullptr))
+    return set_error(-4, "m and n must both be given or both be NULL"), -4;
+  if (m)
+    for (int64_t j = 0; j < count; ++j) {
+      if (m[j] < 1 || m[j] > 4096) return set_error(-4, "m[j] must be in [1, 4096]"), -4;
+      if (n[j] < 1 || n[j] > 4096) return set_error(-5, "n[j] must be in [1, 4096]"), -5;
+    }
+  if (nmax < 1 || nmax > 1024) return set_error(-6, "nmax must be in [1, 1024]"), -6;
   const std::string arch = current_arch();
   if (arch.empty()) return set_error(RRF_E_HIP, "autotune: no HIP device");
   hipStream_t st = opts ? reinterpret_cast<hipStream_t>(opts->stream) : nullptr;
@@ -535,25 +669,38 @@ int rrf_batched_autotune(int precision, int32_t q, int64_t count, int64_t nmax, 
   tab.precision = precision;
   tab.q = q;
   tab.count = count;
-  for (const auto& bk : kBuckets) {
-    if (bk[0] > nmax) break;
-    // fewer matrices in the larger buckets: about the same work per bucket
-    const double scale = 256.0 / (double)std::max<int64_t>(bk[1], 256);
-    const int64_t cnt = std::max<int64_t>(8, (int64_t)std::llround(count * scale * scale));
-    Bucket best{};
-    RRF_TRY(tune_bucket(st, bk[0], std::min(bk[1], nmax), precision, q, cnt, seed, &best));
-    tab.buckets.push_back(best);
+  if (m) {
+    // a failed trial leaves the tables as they were before the call
+    std::vector<Table> saved;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      load_default_locked();
+      saved = g_tables;
+    }
+    const int rc = tune_workload(st, precision, q, count, m, n, nmax, seed, &tab);
+    if (rc != RRF_OK) {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_tables = saved;
+      return rc;
+    }
+  } else {
+    for (const auto& bk : kBuckets) {
+      if (bk[0] > nmax) break;
+      Bucket best{};
+      RRF_TRY(tune_bucket(st, bk[0], std::min(bk[1], nmax), precision, q, count, seed, &best));
+      tab.buckets.push_back(best);
+    }
   }
   std::lock_guard<std::mutex> lk(g_mu);
   g_default_tried = true;
   merge_tables(std::vector<Table>{tab});
   if (path) {
     FILE* f = fopen(path, "wb");
-    if (!f) return set_error(-6, "rrf_batched_autotune: cannot write the cache file");
+    if (!f) return set_error(-8, "rrf_batched_autotune: cannot write the cache file");
     const std::string text = format_tables(g_tables);
     const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
     fclose(f);
-    if (!ok) return set_error(-6, "rrf_batched_autotune: cannot write the cache file");
+    if (!ok) return set_error(-8, "rrf_batched_autotune: cannot write the cache file");
   }
   return RRF_OK;
 }

@@ -77,7 +77,12 @@ def test_config_argument_errors():
     cfg = _lib.rrf_batched_cfg()
     assert rrf.lib.rrf_batched_config(4, 4, 2, C.byref(cfg)) == -3  # x3: not batched
     assert rrf.lib.rrf_batched_config(4, 4, 0, None) == -4
-    assert rrf.lib.rrf_batched_autotune(5, 1, 8, 64, 0, None, None) == -1
-    assert rrf.lib.rrf_batched_autotune(0, -1, 8, 64, 0, None, None) == -2
-    assert rrf.lib.rrf_batched_autotune(0, 1, 0, 64, 0, None, None) == -3
-    assert rrf.lib.rrf_batched_autotune(0, 1, 8, 2048, 0, None, None) == -4
+    f = rrf.lib.rrf_batched_autotune
+    assert f(5, 1, 8, None, None, 64, 0, None, None) == -1
+    assert f(0, -1, 8, None, None, 64, 0, None, None) == -2
+    assert f(0, 1, 0, None, None, 64, 0, None, None) == -3
+    two = (C.c_int64 * 2)(10, 20)
+    assert f(0, 1, 2, two, None, 64, 0, None, None) == -4
+    bad = (C.c_int64 * 2)(10, 5000)
+    assert f(0, 1, 2, two, bad, 64, 0, None, None) == -5
+    assert f(0, 1, 8, None, None, 2048, 0, None, None) == -6

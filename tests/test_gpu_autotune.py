@@ -71,7 +71,7 @@ def test_autotune_short_run(gpu, tmp_path):
     import paper_2106_13402_amd as rrf
     path = str(tmp_path / "tuned.json")
     print("case: autotune count=12 nmax=128", flush=True)
-    rrf.batched_autotune("fp64", q=1, count=12, nmax=128, seed=5, path=path)
+    rrf.batched_autotune("fp64", q=1, count=12, nmax=128, seed=5, path=path)  # synthetic
     tab = json.load(open(path))
     assert tab["format"] == "rrf-batched-tune-1"
     t = [x for x in tab["tables"] if x["arch"] == _arch() and x["precision"] == 0][0]
@@ -84,5 +84,24 @@ def test_autotune_short_run(gpu, tmp_path):
     rrf.batched_tune_load(path)
     shapes = batch_shapes(10, seed=2, nmin=20, nmax=128)
     As = [gaussian_matrix(m, n, seed=40 + i) for i, (m, n) in enumerate(shapes)]
+    Us, Ts, Vs = _run_b0(As, 1, 11, gpu)
+    _check_against_oracle(As, Us, Ts, Vs, 0, 1, 11)
+
+
+def test_autotune_on_a_workload(gpu, tmp_path):
+    """Tuning on the caller's shapes: only the buckets the batch occupies get
+    entries, each one of the candidates, and the batched call follows them."""
+    import paper_2106_13402_amd as rrf
+    shapes = [(90, 70), (120, 100), (80, 80), (200, 150), (300, 180), (160, 130)] * 4
+    path = str(tmp_path / "wl.json")
+    print("case: autotune on a 24-matrix workload", flush=True)
+    rrf.batched_autotune("fp64", q=1, shapes=shapes, nmax=1024, seed=3, path=path)
+    t = [x for x in json.load(open(path))["tables"] if x["arch"] == _arch() and x["precision"] == 0][0]
+    assert [(bk["nmin"], bk["nmax"]) for bk in t["buckets"]] == [(65, 128), (129, 192)]
+    for bk in t["buckets"]:
+        assert bk["b"] in (16, 32, 64) and bk["tile_mask"] in (31, 15, 13) and bk["leaf"] in (0, 16)
+    assert rrf.batched_config(150, 130)["tuned"] is True
+    assert rrf.batched_config(600, 300)["tuned"] is False   # no entry beyond the workload
+    As = [gaussian_matrix(m, n, seed=70 + i) for i, (m, n) in enumerate(shapes[:6])]
     Us, Ts, Vs = _run_b0(As, 1, 11, gpu)
     _check_against_oracle(As, Us, Ts, Vs, 0, 1, 11)
