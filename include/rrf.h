@@ -81,10 +81,11 @@ extern "C" {
 /* randUTV only: as RRF_PREC_BF16_X3 with the updates formed by the six-term
  * product of rrf_gemm_x6 (each operand split into three bfloat16 parts of
  * its binary32 rounding; per K slice of 32 the terms are summed in binary32,
- * the slices in binary64). The error per term is about 2^-22 |a| |b|, so
- * ||A - U T V^T|| / ||A|| and the orthogonality of U and V come to about
- * 1e-7, and e_k is resolved down to about that fraction of each step's
- * trailing norm. */
+ * the slices in binary64), about 1e-8 relative per product. The
+ * accumulation of U and V from Householder transforms amplifies that: at
+ * n = 16384 ||A - U T V^T|| / ||A|| comes to about 1.4e-6 and the
+ * orthogonality of U and V to about 3e-5 (20x and 1.5x closer than the x3
+ * mode); e_k is resolved down to about 1e-6 of each step's trailing norm. */
 #define RRF_PREC_BF16_X6 3
 
 /* ---- algorithms (for rrf_workspace_size) -------------------------------- */

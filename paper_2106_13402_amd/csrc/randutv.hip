@@ -58,8 +58,9 @@
 
 namespace rrf {
 
-// Binary exponent range of max|A| that the binary64 modes factor unscaled.
-constexpr int kGuardExp = 400;
+// Binary exponent range of max|A| that the binary64 modes factor unscaled at
+// q = 0 (divided by 2q + 1 for q power iterations).
+constexpr int kGuardExp = 450;
 
 namespace {
 
@@ -468,9 +469,10 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
   // T = 2^-e A with max|T| in [0.5, 1) (exact, undone at the end). The split
   // modes always scale: every entry of T, and of the products formed from
   // it, stays inside the binary32 range of the split. The binary64 modes
-  // scale only a max|A| beyond 2^+-kGuardExp, where the squares summed by the
-  // Householder norms and the Jacobi rotations would overflow or underflow.
-  const int guard = x3 ? 0 : kGuardExp;
+  // scale only a max|A| beyond 2^+-g: the sketch grows like |A|^(2q+1) and
+  // the Householder norms of the sketch and of T sum its squares, so
+  // g = kGuardExp / (2q+1) keeps those squares inside the binary64 range.
+  const int guard = x3 ? 0 : std::max(1, kGuardExp / (2 * q + 1));
   RRF_TRY(maxabs(st, m, n, T, ldt, scale_word));
   RRF_TRY(scale_pow2(st, m, n, T, ldt, scale_word, false, guard));
   // reflector stores: zero outside each step's block

@@ -264,13 +264,14 @@ def test_randutv_options_and_layouts(gpu):
     assert torch.equal(T1, T2)
 
 
-@pytest.mark.parametrize("p", [600, -600, 300])
+@pytest.mark.parametrize("p", [600, -600, 300, -300, 100])
 def test_randutv_extreme_scale(gpu, p):
     """Entries near 2^600 (or 2^-600): squared column norms would overflow
-    (underflow) binary64, so T is factored from 2^-e A, max|2^-e A| in
-    [0.5, 1), and scaled back; 2^300 stays inside the unscaled range. |T_kk|
-    2^-p matches the oracle on the unscaled A, and U, V and A = U T V^T hold
-    to binary64 accuracy."""
+    (underflow) binary64; near 2^300 the q = 1 sketch, which grows like
+    |A|^3, would. T is then factored from 2^-e A, max|2^-e A| in [0.5, 1),
+    and scaled back; 2^100 stays inside the unscaled range (2^150 at q = 1).
+    |T_kk| 2^-p matches the oracle on the unscaled A, and U, V and
+    A = U T V^T hold to binary64 accuracy."""
     print(f"case: randutv extreme scale 2^{p}", flush=True)
     A = gaussian_matrix(200, 150, seed=11)
     As = A * 2.0 ** p
