@@ -145,6 +145,31 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
                    const rrf_opts* opts);
 
 /*
+ * rrf_randutv_noalloc -- rrf_randutv_ex for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc. Same arguments, results and error codes
+ * as rrf_randutv_ex (bitwise the same results), except:
+ *  - opts->workspace must be NULL and opts->workspace_bytes 0 (else -11):
+ *    the workspace is a static device array of RRF_NOALLOC_SCRATCH_BYTES
+ *    (64 MiB) inside the library, one per device, held until the process
+ *    ends. A request whose rrf_workspace_size() exceeds it returns
+ *    RRF_E_NOMEM before any device work (square FP64 inputs at q = 1 fit up
+ *    to n = 1824 at b = 16, 1628 at b = 32, 1292 at b = 64, 824 at b = 128).
+ *  - The call itself performs no hipMalloc/hipFree and calls no allocating
+ *    library routine. The first call on a device looks up the array's
+ *    device address and creates the library's side streams there.
+ *  - Every call on one device shares that device's array, which keeps the
+ *    previous call's contents (the kernels clear what must start at zero):
+ *    calls that overlap on one device (other host threads, or opts->async
+ *    with work still in flight on another stream) race and must be ordered
+ *    by the caller.
+ */
+#define RRF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int rrf_randutv_noalloc(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                        int32_t q, uint64_t seed, double* U, double* T, double* V,
+                        const rrf_opts* opts);
+
+/*
  * The randomized SVD (RSVD) -- Sec. 3.3 (its relation to powerURV).
  *
  * Y = (A A^T)^q A G with G the n x l Gaussian of stream 0 (the first l columns

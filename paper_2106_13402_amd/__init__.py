@@ -16,15 +16,16 @@ from . import _lib
 from ._lib import RRFError
 
 __all__ = [
-    "RRFError", "randutv", "randutv_boosted", "randutv_partial", "randutv_resume", "rsvd", "powerurv", "gaussian", "dgemm", "gemm_x3", "householder_panel",
+    "RRFError", "randutv", "randutv_noalloc", "randutv_boosted", "randutv_partial", "randutv_resume", "rsvd", "powerurv", "gaussian", "dgemm", "gemm_x3", "gemm_x6", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable", "trace_enable_class",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
-    "batched_workspace_size", "batched_block",
+    "batched_workspace_size", "batched_block", "batched_config", "batched_autotune",
+    "batched_tune_load", "default_tune_path",
 ]
 
 # precision names of rrf_opts.precision
 PRECISIONS = {"fp64": _lib.RRF_PREC_FP64, "bf16_sketch": _lib.RRF_PREC_BF16_SKETCH,
-              "bf16_x3": _lib.RRF_PREC_BF16_X3}
+              "bf16_x3": _lib.RRF_PREC_BF16_X3, "bf16_x6": _lib.RRF_PREC_BF16_X6}
 
 lib = _lib.load()
 
@@ -144,6 +145,32 @@ def randutv(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool =
     thin_u forms only U(:, :n) (m x n), all that A = U T V^T needs."""
     return _factor("rrf_randutv_ex", "randutv", A, b, q, seed, want_u, want_v, check_finite,
                    inplace, precision, thin_u=thin_u)
+
+
+def randutv_noalloc(A, b: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,
+                    precision: str = "fp64", out=None):
+    """randUTV through rrf_randutv_noalloc: the library works in its static
+    device scratch and allocates nothing during the call. ``out`` = (U, T, V)
+    preallocated column-major outputs (U/V may be None); allocated here when
+    omitted. Returns (U, T, V)."""
+    _require(A, "A")
+    m, n = int(A.shape[0]), int(A.shape[1])
+    dev = A.device
+    if out is None:
+        U = empty_colmajor(m, m, dev) if want_u else None
+        T = empty_colmajor(m, n, dev)
+        V = empty_colmajor(n, n, dev) if want_v else None
+    else:
+        U, T, V = out
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.precision = PRECISIONS[precision]
+    opts.stream = _stream_ptr(dev)
+    st = lib.rrf_randutv_noalloc(m, n, A.data_ptr(), _ld(A), b, q, seed,
+                                 U.data_ptr() if U is not None else None, T.data_ptr(),
+                                 V.data_ptr() if V is not None else None, C.byref(opts))
+    _check(st, "rrf_randutv_noalloc")
+    return U, T, V
 
 
 def rsvd(A, l: int, q: int, seed: int, *, want_u: bool = True, want_v: bool = True,

@@ -66,6 +66,8 @@ PROTOTYPES = {
     "rrf_randutv": (C.c_int, [_i64, _i64, _dp, _i64, _i64, _i32, _u64, _dp, _dp, _dp]),
     "rrf_randutv_ex": (C.c_int, [_i64, _i64, _dp, _i64, _i64, _i32, _u64, _dp, _dp, _dp,
                                  C.POINTER(rrf_opts)]),
+    "rrf_randutv_noalloc": (C.c_int, [_i64, _i64, _dp, _i64, _i64, _i32, _u64, _dp, _dp, _dp,
+                                      C.POINTER(rrf_opts)]),
     "rrf_powerurv": (C.c_int, [_i64, _i64, _dp, _i64, _i64, _i32, _u64, _dp, _dp, _dp]),
     "rrf_powerurv_ex": (C.c_int, [_i64, _i64, _dp, _i64, _i64, _i32, _u64, _dp, _dp, _dp,
                                   C.POINTER(rrf_opts)]),

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "context.hpp"
 #include "driver.hpp"
 #include "kernels.hpp"
 
@@ -649,6 +650,72 @@ int rrf_powerurv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t 
 int rrf_powerurv(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b, int32_t q,
                  uint64_t seed, double* U, double* T, double* V) {
   return rrf_powerurv_ex(m, n, A, lda, b, q, seed, U, T, V, nullptr);
+}
+
+}  // extern "C"
+
+// ---- allocation-free randUTV ------------------------------------------------
+// A file-scope device array stands in for the workspace of rrf_randutv_noalloc.
+// Its name is a host-side handle: host code only ever passes the device
+// address that hipGetSymbolAddress returns for the current device, looked up
+// once per device and kept in g_scratch.
+namespace rrf {
+namespace {
+constexpr size_t kScratchBytes = (size_t)RRF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::unordered_map<int, void*> g_scratch;
+
+// Device address of `scratch` on device `dev` (current); the first call on a
+// device also creates the side streams and events the drivers use there.
+int scratch_pointer(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(dev);
+  if (it != g_scratch.end()) {
+    *out = it->second;
+    return RRF_OK;
+  }
+  void* p = nullptr;
+  RRF_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (p == nullptr) return set_error(RRF_E_HIP, "no device address for the static scratch");
+  DeviceContext* ctx = nullptr;
+  RRF_TRY(device_context(&ctx));
+  g_scratch[dev] = p;
+  *out = p;
+  return RRF_OK;
+}
+}  // namespace
+}  // namespace rrf
+
+extern "C" {
+
+int rrf_randutv_noalloc(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b,
+                        int32_t q, uint64_t seed, double* U, double* T, double* V,
+                        const rrf_opts* opts) {
+  rrf_opts o;
+  rrf_opts_init(&o);
+  if (opts) o = *opts;
+  if (o.workspace != nullptr || o.workspace_bytes != 0)
+    return set_error(-11, "rrf_randutv_noalloc takes no workspace (opts->workspace must be "
+                          "NULL); use rrf_randutv_ex to pass one"), -11;
+  RRF_TRY(check_args(m, n, A, lda, b, q, T, 0, true));
+  const size_t need = rrf_workspace_size(RRF_ALG_RANDUTV, m, n, b, q, o.precision);
+  if (need == 0)
+    return set_error(RRF_E_NOTSUP, "block size, shape or precision outside the kernel limits");
+  if (need > kScratchBytes) {
+    char buf[256];
+    snprintf(buf, sizeof buf,
+             "rrf_randutv_noalloc: this factorization needs %zu bytes of scratch, more than "
+             "the static %zu (use rrf_randutv_ex with a workspace)", need, kScratchBytes);
+    return set_error(RRF_E_NOMEM, buf);
+  }
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  void* p = nullptr;
+  RRF_TRY(scratch_pointer(dev, &p));
+  o.workspace = p;
+  o.workspace_bytes = kScratchBytes;
+  return rrf_randutv_ex(m, n, A, lda, b, q, seed, U, T, V, &o);
 }
 
 int rrf_release_workspace(void) {

@@ -284,3 +284,26 @@ def test_trace_class_filter_arguments(lib):
     assert lib.rrf_trace_enable_class(b"dgemm_mfma_128x128_TN") == 0
     assert lib.rrf_trace_enable_class(b"dgemm_mfma_128x128_NN:UV") == 0
     assert lib.rrf_trace_enable(0) == 0
+
+
+def test_noalloc_host_side_rejections(lib):
+    """rrf_randutv_noalloc checks its arguments, a caller workspace and the
+    static scratch limit before any device call."""
+    f = lib.rrf_randutv_noalloc
+    assert f(0, 4, DUMMY, 4, 2, 0, 1, NULL, DUMMY, NULL, None) == -1
+    assert f(4, 4, DUMMY, 4, 2, -1, 1, NULL, DUMMY, NULL, None) == -6
+    assert f(4, 4, DUMMY, 4, 2, 0, 1, NULL, NULL, NULL, None) == -9
+    opts = _lib.rrf_opts()
+    lib.rrf_opts_init(C.byref(opts))
+    opts.workspace = 0x2000
+    opts.workspace_bytes = 1 << 20
+    assert f(64, 64, DUMMY, 64, 16, 1, 1, NULL, DUMMY, NULL, C.byref(opts)) == -11
+    assert b"no workspace" in lib.rrf_last_error()
+    # beyond the 64 MiB scratch: RRF_E_NOMEM with the sizes in the message
+    limit = 64 << 20
+    assert lib.rrf_workspace_size(_lib.RRF_ALG_RANDUTV, 4096, 4096, 128, 1, 0) > limit
+    assert f(4096, 4096, DUMMY, 4096, 128, 1, 1, NULL, DUMMY, NULL, None) == _lib.RRF_E_NOMEM
+    msg = lib.rrf_last_error()
+    assert b"rrf_randutv_ex" in msg and str(limit).encode() in msg
+    # the wide path is sized the same way (A^T's factorization plus A^T, T^T)
+    assert f(1024, 4096, DUMMY, 1024, 128, 1, 1, NULL, DUMMY, NULL, None) == _lib.RRF_E_NOMEM
