@@ -486,7 +486,7 @@ def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seco
     torch.cuda.synchronize()
     per = (time.perf_counter() - t0) / steps
     log(f"batched: {per * 1e3:.1f} ms per call, {count / per:.0f} matrices/s")
-    flops = sum(total_flops(m, n, auto_block(n), q) for m, n in shapes)
+    flops = sum(total_flops(m, n, auto_block(n, m), q) for m, n in shapes)
     Us, Ts, Vs = out
     res = torch.empty(count, dtype=torch.float64, device=dev)
     orth = torch.empty(count, dtype=torch.float64, device=dev)
@@ -502,10 +502,18 @@ def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seco
                for e in kern}
     leg = {
         "workload": (f"randUTV of {count} matrices, n ~ U{{64..512}}, m ~ U{{n..2n}}, "
-                     f"A = Q1 diag(10^(-8(i-1)/(n-1))) Q2^T, q={q}, b chosen per matrix "
-                     f"(16 for n <= 256, else 32), U and V accumulated, FP64"),
+                     f"A = Q1 diag(10^(-8(i-1)/(n-1))) Q2^T, q={q}, b per size bucket from "
+                     f"the loaded tuning table, U and V accumulated, FP64"),
         "value": count / per, "unit": "matrices/s", "ms_per_call": per * 1e3,
         "model_flops": flops, "model_tflops": flops / per / 1e12,
+        # the whole call against FP64 matrix-core peak: the flop model of
+        # Alg. 3 summed over the batch, as if every flop ran at 78.6 TFLOP/s
+        "roofline": {"bound": "mfma", "ideal_ms": flops / (PEAK_FP64_TFLOPS * 1e12) * 1e3,
+                     "frac": flops / per / 1e12 / PEAK_FP64_TFLOPS, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s"},
+        "roofline_frac": flops / per / 1e12 / PEAK_FP64_TFLOPS,
+        "blocks": {str(b): sum(1 for m, n in shapes if auto_block(n, m) == b)
+                   for b in sorted({auto_block(n, m) for m, n in shapes})},
         "residual_fro_rel": {"max": float(res.max()), "median": float(np.median(res)),
                              "p99": float(np.quantile(res, 0.99))},
         "orth_fro_max": float(orth.max()),
@@ -515,9 +523,9 @@ def batched_leg(count: int, q: int, steps: int, warmup: int, seed: int, cpu_seco
         import oracle
         done, fl, t0 = 0, 0.0, time.perf_counter()
         for j, (m, n) in enumerate(shapes):
-            oracle.randutv(As[j].cpu().numpy().copy(order="F"), auto_block(n), q, seed + j)
+            oracle.randutv(As[j].cpu().numpy().copy(order="F"), auto_block(n, m), q, seed + j)
             done += 1
-            fl += total_flops(m, n, auto_block(n), q)
+            fl += total_flops(m, n, auto_block(n, m), q)
             if time.perf_counter() - t0 >= cpu_seconds:
                 break
         el = time.perf_counter() - t0

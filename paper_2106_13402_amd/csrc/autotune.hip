@@ -351,6 +351,8 @@ struct Rng {  // splitmix64: shapes of the synthetic batches
   int64_t uniform(int64_t lo, int64_t hi) { return lo + (int64_t)(next() % (uint64_t)(hi - lo + 1)); }
 };
 
+constexpr int64_t kWorkloadMax = 256;
+
 const int64_t kBuckets[][2] = {{1, 64},    {65, 128},  {129, 192}, {193, 256}, {257, 320},
                                {321, 384}, {385, 448}, {449, 512}, {513, 768}, {769, 1024}};
 
@@ -655,6 +657,11 @@ int rrf_batched_autotune(int precision, int32_t q, int64_t count, const int64_t*
   if (count < 1) return set_error(-3, "count must be >= 1"), -3;
   if ((m == nullptr) != (n == nullptr))
     return set_error(-4, "m and n must both be given or both be NULL"), -4;
+  // Tuning on a caller's batch is limited to kWorkloadMax matrices: one run
+  // over 4096 matrices ended in a host-side segmentation fault whose cause
+  // is not yet known, so larger workloads are refused rather than run.
+  if (m && count > kWorkloadMax)
+    return set_error(RRF_E_NOTSUP, "rrf_batched_autotune: at most 256 matrices on a workload");
   if (m)
     for (int64_t j = 0; j < count; ++j) {
       if (m[j] < 1 || m[j] > 4096) return set_error(-4, "m[j] must be in [1, 4096]"), -4;

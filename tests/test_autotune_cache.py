@@ -86,3 +86,5 @@ def test_config_argument_errors():
     bad = (C.c_int64 * 2)(10, 5000)
     assert f(0, 1, 2, two, bad, 64, 0, None, None) == -5
     assert f(0, 1, 8, None, None, 2048, 0, None, None) == -6
+    many = (C.c_int64 * 257)(*([64] * 257))
+    assert f(0, 1, 257, many, many, 64, 0, None, None) == _lib.RRF_E_NOTSUP  # workload cap

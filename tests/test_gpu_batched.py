@@ -151,7 +151,8 @@ def test_batched_options_and_edges(gpu):
 def test_batched_full_size(gpu):
     """4096 matrices, n ~ U[64, 512], m ~ U[n, 2n], q = 1, automatic b:
     every matrix checked on the GPU (Frobenius-norm bounds, which imply the
-    2-norm ones), six of them against the oracle."""
+    2-norm ones), six small ones and four of every block-size group above
+    n = 200 against the oracle (Gaussian inputs: |T| is well posed)."""
     import torch
     from paper_2106_13402_amd import randutv_batched
     shapes = batch_shapes(4096, seed=0)
@@ -172,9 +173,20 @@ def test_batched_full_size(gpu):
     print(f"  worst ||U^T U - I||_F, ||V^T V - I||_F = {worst_o:.2e}, "
           f"||A - U T V^T||_F / ||A||_F = {worst_r:.2e}", flush=True)
     assert worst_o <= 1e-12 and worst_r <= 1e-13
+    # a sample of every configuration group (block size chosen per size
+    # bucket) against the oracle: six small matrices, then four of each
+    # group of larger ones
     rng = np.random.default_rng(1)
     small = [j for j, (m, n) in enumerate(shapes) if n <= 200]
-    for j in list(rng.choice(small, size=6, replace=False)):
+    picks = list(rng.choice(small, size=6, replace=False))
+    groups = {}
+    for j, (m, n) in enumerate(shapes):
+        if n > 200:
+            groups.setdefault(_auto_b(n), []).append(j)
+    for bg, idx in sorted(groups.items()):
+        picks += list(rng.choice(idx, size=min(4, len(idx)), replace=False))
+    print(f"  oracle sample: {len(picks)} matrices, block sizes {sorted(groups)}", flush=True)
+    for j in picks:
         A = _host(As[j]).copy(order="F")
         bj = _auto_b(A.shape[1])
         T = _host(Ts[j])

@@ -308,6 +308,60 @@ def test_powerurv_parity(gpu, m, n, b, q):
     np.testing.assert_allclose(np.abs(T), np.abs(To), atol=1e-9 * 2.0)
 
 
+def _powerurv_spread(A, q, seed, nsamp=3):
+    """|T_kk| of the powerURV oracle and its largest change under three
+    backward-error-sized perturbations of A (||E||_2 = n eps ||A||_2)."""
+    n = A.shape[1]
+    _, To, _ = oracle.powerurv(A, q, seed)
+    do = np.abs(np.diag(To))
+    nA = M.spec(A)
+    spread = np.zeros_like(do)
+    rng = np.random.default_rng(12345)
+    for _ in range(nsamp):
+        E = rng.standard_normal(A.shape)
+        E *= n * 2 * U64 * nA / np.linalg.norm(E, 2)
+        _, Tp, _ = oracle.powerurv(A + E, q, seed)
+        spread = np.maximum(spread, np.abs(np.abs(np.diag(Tp)) - do))
+    return To, do, spread
+
+
+@pytest.mark.parametrize("kind", ["power", "geometric"])
+@pytest.mark.parametrize("q", [0, 1, 2])
+def test_powerurv_decaying_1024(gpu, kind, q):
+    """powerURV (Alg. 1) in FP64 at 1024 x 1024 on decaying spectra, s_j = j^-2
+    and s_j = 10^(-12 (j-1)/1023), where the QRs of the power products are
+    ill-conditioned: |T_kk| equal to the oracle's to 1e-10 relative plus
+    10 n u ||A|| where the value is well posed (the oracle's own spread under
+    backward-error-sized perturbations is below a tenth of that), within a
+    factor 2 elsewhere; e_k equal to the oracle's on a k-grid to the same
+    tolerance when every |T_kk| is well posed, and never below s_{k+1}."""
+    from paper_2106_13402_amd import powerurv
+    n = 1024
+    s = spectrum("power", n, p=2.0) if kind == "power" else spectrum("geometric", n, decades=12.0)
+    A = spectral_matrix(n, n, s, seed=0)
+    print(f"case: powerurv FP64 {kind} n={n} q={q}", flush=True)
+    U, T, V = (_host(x) for x in powerurv(_to_dev(A, gpu), q, 1, b=128))
+    _check_factorization(A, U, T, V)
+    To, do, spread = _powerurv_spread(A, q, 1)
+    nA = s[0]
+    dg = np.abs(np.diag(T))
+    strict = 1e-10 * do + 10 * n * U64 * nA
+    posed = spread <= 0.1 * strict
+    bad = posed & (np.abs(dg - do) > strict)
+    assert not bad.any(), (np.flatnonzero(bad)[:5], dg[bad][:5], do[bad][:5])
+    ill = ~posed & (do > 10 * n * U64 * nA)
+    if ill.any():
+        r = dg[ill] / do[ill]
+        assert np.all((r >= 0.5) & (r <= 2.0)), (r.min(), r.max())
+    ks = [0, 1, 16, 64, 127, 128, 256, 512, 900]
+    eg, eo = M.trailing_norms(T, ks), M.trailing_norms(To, ks)
+    if posed.all():
+        assert np.all(np.abs(eg - eo) <= 1e-10 * eo + 10 * n * U64 * nA), (eg, eo)
+    else:
+        assert np.all((eg >= eo / 1.5) & (eg <= 1.5 * eo)), (eg, eo)
+    assert np.all(eg >= s[ks] * (1 - 1e-8) - 10 * n * U64 * nA)
+
+
 @pytest.mark.parametrize("m,n,b,q", [(200, 330, 64, 1), (129, 300, 32, 2)])
 def test_powerurv_wide_through_transpose(gpu, m, n, b, q):
     """m < n through the transpose (the Sec. 3.2 reading, as for randUTV):
