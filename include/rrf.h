@@ -395,8 +395,8 @@ typedef struct rrf_batched_cfg {
  * narrow 128 x 32 / 128 x 16 / 64 x 64} x leaf {0, 16}, by timing replayed
  * calls with HIP events (q power iterations, U and V formed, Gaussian
  * matrices from `seed`):
- *  - m and n given (host arrays of `count` sizes, each in [1, 4096]): on that
- *    workload. Every bucket holding some min(m[j], n[j]) starts at the
+ *  - m and n given (host arrays of `count` <= 256 sizes, each in [1, 4096];
+ *    more matrices return RRF_E_NOTSUP): on that workload. Every bucket holding some min(m[j], n[j]) starts at the
  *    built-in rule; bucket by bucket each candidate is installed and the whole
  *    batched call timed (median of three replays after the recording call);
  *    the fastest is kept. Meanwhile the trial tables are the process's
@@ -461,6 +461,15 @@ int rrf_gemm_x6(int transa, int transb, int64_t M, int64_t N, int64_t K, double 
 int rrf_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
                  double* out, int64_t ld, void* stream);
 
+/* The uniforms the generator above turns into Gaussians, for checking it bit
+ * for bit: out(4g + i, c) = uniform i of counter (g, c, 0, 0) under key
+ * (seed, stream_id), i = 0..3 in the order u_a, v_a, u_b, v_b
+ * (u = ((w >> 11) + 1) 2^-53 from words 0 and 2, v = (w >> 11) 2^-53 from
+ * words 1 and 3), 0 <= 4g + i < rows. Device buffer, column-major, ld >= rows.
+ * Errors as rrf_gaussian. */
+int rrf_sketch_uniforms(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+                        double* out, int64_t ld, void* stream);
+
 /* C = alpha * op(A) * op(B) + beta * C in binary64 (op = transpose when the
  * trans flag is 1). op(A) is M x K, op(B) is K x N. With beta == 0, C is not
  * read. `work`/`work_bytes` provide scratch for split-K partial sums (may be
@@ -474,7 +483,16 @@ int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double al
  * Q = H_1 ... H_k = I - W Tf W^T (compact WY). Outputs: W (M x k, explicit
  * unit lower trapezoidal, ld ldw; may alias P when ldw == ldp), R (k x k upper
  * triangular, ld ldr; may be NULL), Tf (k x k upper triangular, ld ldt), tau
- * (k). `work` must hold rrf_panel_workspace_size(M, k) bytes. */
+ * (k). `work` must hold rrf_panel_workspace_size(M, k) bytes (enough for
+ * either kernel below).
+ * Kernel: one grid-wide exchange per column by default; with
+ * RRF_PANEL_TREE=1 in the environment (read at each call), panels of k <= 64
+ * and M <= 65536 (wider ones split into such halves) go through a tree of
+ * QRs over 256-row blocks with the reflectors recovered from its Q. Both give
+ * the dlarfg reflectors to rounding, except that the tree kernel returns
+ * tau = 2, v = e_j (and row j of R negated) where dlarfg gives H = I for an
+ * exactly zero sub-column, and after an exact rank drop its later
+ * reflectors are another exact choice. */
 size_t rrf_panel_workspace_size(int64_t M, int64_t k);
 int rrf_householder_panel(int64_t M, int64_t k, double* P, int64_t ldp, double* W,
                           int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt,

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import RRFError
 
 __all__ = [
-    "RRFError", "randutv", "randutv_noalloc", "randutv_boosted", "randutv_partial", "randutv_resume", "rsvd", "powerurv", "gaussian", "dgemm", "gemm_x3", "gemm_x6", "householder_panel",
+    "RRFError", "randutv", "randutv_noalloc", "randutv_boosted", "randutv_partial", "randutv_resume", "rsvd", "powerurv", "gaussian", "sketch_uniforms", "dgemm", "gemm_x3", "gemm_x6", "householder_panel",
     "block_svd", "workspace_size", "colmajor", "empty_colmajor", "lib", "trace_enable", "trace_enable_class",
     "trace_read", "to_bf16", "gemm_bf16_tn", "PRECISIONS", "randutv_batched",
     "batched_workspace_size", "batched_block", "batched_config", "batched_autotune",
@@ -392,6 +392,16 @@ def gaussian(seed: int, stream_id: int, rows: int, cols: int, device="cuda"):
     out = empty_colmajor(rows, cols, device)
     _check(lib.rrf_gaussian(seed, stream_id, rows, cols, out.data_ptr() if out.numel() else None,
                             max(rows, 1), _stream_ptr(out.device)), "rrf_gaussian")
+    return out
+
+
+def sketch_uniforms(seed: int, stream_id: int, rows: int, cols: int, device="cuda"):
+    """The uniforms behind gaussian(): row 4g + i holds uniform i
+    (u_a, v_a, u_b, v_b) of counter (g, column)."""
+    out = empty_colmajor(rows, cols, device)
+    _check(lib.rrf_sketch_uniforms(seed, stream_id, rows, cols,
+                                   out.data_ptr() if out.numel() else None, max(rows, 1),
+                                   _stream_ptr(out.device)), "rrf_sketch_uniforms")
     return out
 
 

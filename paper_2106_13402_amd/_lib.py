@@ -94,6 +94,7 @@ PROTOTYPES = {
     "rrf_randutv_boosted_workspace_size": (_sz, [_i64, _i64, _i64, _i32, _i64]),
     "rrf_release_workspace": (C.c_int, []),
     "rrf_gaussian": (C.c_int, [_u64, _u64, _i64, _i64, _dp, _i64, _vp]),
+    "rrf_sketch_uniforms": (C.c_int, [_u64, _u64, _i64, _i64, _dp, _i64, _vp]),
     "rrf_dgemm": (C.c_int, [C.c_int, C.c_int, _i64, _i64, _i64, _d, _dp, _i64, _dp, _i64, _d,
                             _dp, _i64, _vp, _sz, _vp]),
     "rrf_gemm_x3": (C.c_int, [C.c_int, C.c_int, _i64, _i64, _i64, _d, _dp, _i64, _dp, _i64, _d,

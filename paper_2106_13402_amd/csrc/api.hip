@@ -743,6 +743,18 @@ int rrf_gaussian(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols, 
   return gaussian(reinterpret_cast<hipStream_t>(stream), seed, stream_id, rows, cols, out, ld);
 }
 
+int rrf_sketch_uniforms(uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+                        double* out, int64_t ld, void* stream) {
+  if (rows < 0) return set_error(-3, "rows must be >= 0"), -3;
+  if (cols < 0) return set_error(-4, "cols must be >= 0"), -4;
+  if (out == nullptr && rows > 0 && cols > 0) return set_error(-5, "out is NULL"), -5;
+  if (ld < (rows > 1 ? rows : 1)) return set_error(-6, "ld must be >= rows"), -6;
+  int dev = 0;
+  RRF_TRY(device_ready(&dev));
+  return sketch_uniforms(reinterpret_cast<hipStream_t>(stream), seed, stream_id, rows, cols, out,
+                         ld);
+}
+
 static int gemm_entry(GemmFn fn, int transa, int transb, int64_t M, int64_t N, int64_t K,
                       double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                       double beta, double* C, int64_t ldc, void* work, size_t work_bytes,

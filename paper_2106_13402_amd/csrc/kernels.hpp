@@ -39,6 +39,10 @@ int gemm_x6(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, d
 // ---- philox.hip ----------------------------------------------------------
 int gaussian(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
              double* out, int64_t ld);
+// The uniforms behind the Gaussian above: row 4g + i, column c holds uniform
+// i of counter (g, c, 0, 0) (order u_a, v_a, u_b, v_b).
+int sketch_uniforms(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+                    double* out, int64_t ld);
 
 // ---- util.hip ------------------------------------------------------------
 int set_identity(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld);
@@ -78,6 +82,16 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                       double* W, int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt,
                       double* tau, double* zero, int64_t ldz, void* work, size_t work_bytes,
                       int* status);
+
+// ---- panel_tsqr.hip -------------------------------------------------------
+// The same factorization as householder_panel for 1 <= k <= 64 and
+// k <= M <= 65536, by a tree of QRs over 256-row leaves and reconstruction
+// of the reflectors; one cooperative launch of ceil(M / 256) workgroups.
+bool tsqr_panel_ok(int64_t M, int k);
+size_t tsqr_work_bytes(int64_t M, int k);  // 0 when not tsqr_panel_ok
+int tsqr_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
+               int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
+               double* zero, int64_t ldz, void* work, size_t work_bytes, int* status);
 
 // ---- sketch_bf16.hip ------------------------------------------------------
 // Leading dimension of a bfloat16 copy with `rows` rows (a multiple of 8).

@@ -38,6 +38,7 @@
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
+#include <cstdlib>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -490,21 +491,36 @@ int64_t fit_rows(int k) {
 constexpr int kSplitParts = 16;
 size_t split_temp_bytes(int k1, int k2) { return (size_t)(3 + kSplitParts) * k1 * k2 * 8; }
 
+// With RRF_PANEL_TREE=1 in the environment the tree panel (panel_tsqr.hip)
+// takes every panel of at most kTreeCols columns it can, and wider ones are
+// split by columns into halves it takes. It is not the default: measured on
+// MI355X it is about half as fast as the kernel above (16384 x 64: 1.0 ms
+// against 0.57 ms), its serial chain of one-workgroup QRs (a leaf and one
+// node per tree level, about 1 us per column each) and its LDS-bound small
+// products costing more than the grid exchanges it removes.
+constexpr int kTreeCols = 64;
+
+bool tree_enabled() {
+  const char* e = getenv("RRF_PANEL_TREE");
+  return e && e[0] == '1';
+}
+
 }  // namespace
 
 size_t panel_work_bytes(int64_t Mmax, int k) {
   if (k < 1 || k > kMaxCols || Mmax < k) return 0;
+  // every path some M <= Mmax may take, in either mode
+  size_t need = tsqr_work_bytes(Mmax, k);
   const int64_t fit = k <= kLaunchCols ? fit_rows(k) : 0;
-  size_t need = 0;
   if (fit >= k) {
     PanelPlan p;
-    if (panel_plan(std::min(Mmax, fit), k, &p)) need = p.work;
+    if (panel_plan(std::min(Mmax, fit), k, &p)) need = std::max(need, p.work);
   }
-  if (Mmax > fit) {
-    if (k < 2) return 0;
+  if (Mmax > fit || k > kTreeCols) {
+    if (k < 2) return need;
     const int k1 = k / 2, k2 = k - k1;
     const size_t a = panel_work_bytes(Mmax, k1), b = panel_work_bytes(Mmax - k1, k2);
-    if (a == 0 || b == 0) return 0;
+    if (a == 0 || b == 0) return Mmax > fit ? 0 : need;
     need = std::max(need, (size_t)round_up((int64_t)std::max(a, b), 256) + split_temp_bytes(k1, k2));
   }
   return need;
@@ -519,8 +535,13 @@ size_t panel_work_bytes(int64_t Mmax, int k) {
 int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
                       int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
                       double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
+  const bool tree = tree_enabled();
+  if (tree && tsqr_panel_ok(M, k))
+    return tsqr_panel(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
+                      work_bytes, status);
+  const bool split_for_tree = tree && k > kTreeCols && tsqr_panel_ok(M - k / 2, k - k / 2);
   PanelPlan plan;
-  if (k <= kLaunchCols && panel_plan(M, k, &plan))
+  if (!split_for_tree && k <= kLaunchCols && panel_plan(M, k, &plan))
     return panel_launch(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
                         work_bytes, status);
   if (k < 2 || M < k)

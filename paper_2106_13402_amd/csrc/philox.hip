@@ -20,6 +20,9 @@ namespace rrf {
 
 namespace {
 
+// kUniform: write the four uniforms of each counter instead of the Gaussians
+// made from them (rows 4g .. 4g + 3 = u_a, v_a, u_b, v_b).
+template <bool kUniform>
 __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t sid, int64_t rows,
                                                        int64_t cols, double* __restrict__ out,
                                                        int64_t ld) {
@@ -30,7 +33,10 @@ __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t s
     const int64_t gr = t % groups;
     const int64_t c = t / groups;
     double v[4];
-    gaussian4(seed, sid, (uint64_t)gr, (uint64_t)c, v);
+    if (kUniform)
+      uniforms4(seed, sid, (uint64_t)gr, (uint64_t)c, v);
+    else
+      gaussian4(seed, sid, (uint64_t)gr, (uint64_t)c, v);
     double* col = out + c * ld;
     const int64_t r0 = gr * 4;
 #pragma unroll
@@ -41,18 +47,33 @@ __global__ __launch_bounds__(256) void gaussian_kernel(uint64_t seed, uint64_t s
 
 }  // namespace
 
-int gaussian(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
-             double* out, int64_t ld) {
+namespace {
+
+template <bool kUniform>
+int launch(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+           double* out, int64_t ld) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
   const int64_t total = ((rows + 3) / 4) * cols;
   int64_t blocks = ceil_div(total, 256);
   if (blocks > 16384) blocks = 16384;
   int tok = trace_begin(st, kTrGaussian, 0.0, 8.0 * rows * cols);
-  hipLaunchKernelGGL(gaussian_kernel, dim3((unsigned)blocks), dim3(256), 0, st, seed, stream_id,
-                     rows, cols, out, ld);
+  hipLaunchKernelGGL(gaussian_kernel<kUniform>, dim3((unsigned)blocks), dim3(256), 0, st, seed,
+                     stream_id, rows, cols, out, ld);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;
+}
+
+}  // namespace
+
+int gaussian(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+             double* out, int64_t ld) {
+  return launch<false>(st, seed, stream_id, rows, cols, out, ld);
+}
+
+int sketch_uniforms(hipStream_t st, uint64_t seed, uint64_t stream_id, int64_t rows, int64_t cols,
+                    double* out, int64_t ld) {
+  return launch<true>(st, seed, stream_id, rows, cols, out, ld);
 }
 
 }  // namespace rrf

@@ -31,20 +31,28 @@ __device__ inline void philox4x64_10(uint64_t& x0, uint64_t& x1, uint64_t& x2, u
   }
 }
 
-// Entries 4 gr .. 4 gr + 3 of column c of the Gaussian of (seed, sid):
-// counter (gr, c, 0, 0), key (seed, sid); uniforms from the top 53 bits,
-// u in (0, 1] from words 0 and 2, v in [0, 1) from words 1 and 3.
-__device__ inline void gaussian4(uint64_t seed, uint64_t sid, uint64_t gr, uint64_t c,
-                                 double (&v)[4]) {
+// The four uniforms of counter (gr, c, 0, 0) under key (seed, sid), from
+// the top 53 bits of each word: u in (0, 1] from words 0 and 2, v in [0, 1)
+// from words 1 and 3, in the order (u_a, v_a, u_b, v_b).
+__device__ inline void uniforms4(uint64_t seed, uint64_t sid, uint64_t gr, uint64_t c,
+                                 double (&u)[4]) {
   uint64_t x0 = gr, x1 = c, x2 = 0, x3 = 0;
   philox4x64_10(x0, x1, x2, x3, seed, sid);
-  const double ua = ((double)(x0 >> 11) + 1.0) * 0x1p-53;
-  const double va = (double)(x1 >> 11) * 0x1p-53;
-  const double ub = ((double)(x2 >> 11) + 1.0) * 0x1p-53;
-  const double vb = (double)(x3 >> 11) * 0x1p-53;
-  const double rho_a = sqrt(-2.0 * log(ua));
-  const double rho_b = sqrt(-2.0 * log(ub));
-  const double ta = kTwoPi * va, tb = kTwoPi * vb;
+  u[0] = ((double)(x0 >> 11) + 1.0) * 0x1p-53;
+  u[1] = (double)(x1 >> 11) * 0x1p-53;
+  u[2] = ((double)(x2 >> 11) + 1.0) * 0x1p-53;
+  u[3] = (double)(x3 >> 11) * 0x1p-53;
+}
+
+// Entries 4 gr .. 4 gr + 3 of column c of the Gaussian of (seed, sid):
+// Box-Muller on the uniforms of counter (gr, c, 0, 0).
+__device__ inline void gaussian4(uint64_t seed, uint64_t sid, uint64_t gr, uint64_t c,
+                                 double (&v)[4]) {
+  double u[4];
+  uniforms4(seed, sid, gr, c, u);
+  const double rho_a = sqrt(-2.0 * log(u[0]));
+  const double rho_b = sqrt(-2.0 * log(u[2]));
+  const double ta = kTwoPi * u[1], tb = kTwoPi * u[3];
   v[0] = rho_a * cos(ta);
   v[1] = rho_a * sin(ta);
   v[2] = rho_b * cos(tb);

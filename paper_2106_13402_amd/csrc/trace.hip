@@ -46,7 +46,7 @@ const char* kNames[kTraceClasses] = {
     "elementwise",           "gemm_bf16_mfma_TN",     "dgemm_grouped_64x64",
     "dgemm_grouped_128x64",  "dgemm_grouped_128x32",  "dgemm_grouped_128x16",
     "dgemm_grouped_128x128", "gemm_x3_128x128",       "gemm_x3_64x64",
-    "gemm_x6_128x128",       "gemm_x6_64x64",
+    "gemm_x6_128x128",       "gemm_x6_64x64",         "householder_panel_tree",
 };
 
 hipEvent_t get_event() {

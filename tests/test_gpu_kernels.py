@@ -39,6 +39,25 @@ def test_gaussian_matches_oracle(gpu, seed, stream, rows, cols):
     np.testing.assert_allclose(g, ref, rtol=0, atol=16 * U64 * np.maximum(1.0, np.abs(ref)).max())
 
 
+@pytest.mark.parametrize("seed,stream,rows,cols", [
+    (1, 1, 37, 11), (0, 0, 4, 1), (1, 7, 4096, 128), (2**64 - 1, 2**63 + 5, 1001, 3)])
+def test_sketch_uniforms_bit_exact(gpu, seed, stream, rows, cols):
+    """The Philox words and their 53-bit uniforms agree with the oracle's bit
+    for bit (the Gaussians built from them may differ by a few ulp)."""
+    from paper_2106_13402_amd import sketch_uniforms
+    u = _host(sketch_uniforms(seed, stream, rows, cols, gpu))
+    groups = (rows + 3) // 4
+    g = np.arange(groups, dtype=np.uint64)[:, None]
+    c = np.arange(cols, dtype=np.uint64)[None, :]
+    z = np.zeros((1, 1), dtype=np.uint64)
+    w = oracle.philox.philox4x64_10((g, c, z, z), (np.uint64(seed), np.uint64(stream)))
+    ref = np.empty((4 * groups, cols))
+    for i, (word, open0) in enumerate(zip(w, (True, False, True, False))):
+        ref[i::4] = oracle.philox.uniforms_from_words(word, open0)
+    np.testing.assert_array_equal(u, ref[:rows])
+    assert np.all(u[0::4] > 0.0) and np.all(u[1::4] < 1.0)
+
+
 # ------------------------------------------------------------------ GEMM
 GEMM_CASES = [
     (1, 1, 1), (17, 33, 5), (64, 64, 64), (130, 70, 300), (257, 129, 1000),
@@ -109,12 +128,33 @@ PANEL_CASES = [(5, 1), (64, 32), (1000, 7), (513, 32), (4096, 128), (16384, 128)
                (32768, 128), (3000, 256), (32768, 256), (40000, 256)]
 
 
+@pytest.mark.parametrize("tree", [True, False])
 @pytest.mark.parametrize("M,k", PANEL_CASES)
-def test_householder_panel_matches_lapack(gpu, M, k):
-    from paper_2106_13402_amd import householder_panel
+def test_householder_panel_matches_lapack(gpu, M, k, tree):
+    print(f"case: panel M={M} k={k} tree={tree}", flush=True)
     rng = np.random.default_rng(M + k)
     P = rng.standard_normal((M, k))
-    W, R, Tf, tau = (_host(x) for x in householder_panel(_to_dev(P, gpu)))
+    _check_panel_lapack(P, *_panel(P, gpu, tree))
+
+
+def _panel(P, gpu, tree=True):
+    """rrf_householder_panel, with the tree kernel (default) or the
+    column-by-column one (RRF_PANEL_TREE=0)."""
+    import os
+    from paper_2106_13402_amd import householder_panel
+    old = os.environ.get("RRF_PANEL_TREE")
+    os.environ["RRF_PANEL_TREE"] = "1" if tree else "0"
+    try:
+        return tuple(_host(x) for x in householder_panel(_to_dev(P, gpu)))
+    finally:
+        if old is None:
+            del os.environ["RRF_PANEL_TREE"]
+        else:
+            os.environ["RRF_PANEL_TREE"] = old
+
+
+def _check_panel_lapack(P, W, R, Tf, tau):
+    M, k = P.shape
     qr, tau_ref = hqr(P)
     W_ref = np.tril(qr[:, :k], -1) + np.eye(M, k)
     np.testing.assert_allclose(tau, tau_ref, rtol=1e-12, atol=1e-14)
@@ -122,27 +162,87 @@ def test_householder_panel_matches_lapack(gpu, M, k):
     np.testing.assert_allclose(R, np.triu(qr[:k, :k]), atol=1e-11 * np.abs(P).max() * np.sqrt(M))
     np.testing.assert_allclose(Tf, _larft(W_ref, tau_ref), atol=1e-10)
     assert np.all(np.tril(R, -1) == 0) and np.all(np.tril(Tf, -1) == 0)
-    # Q from the compact-WY factors equals LAPACK's Q (leading columns)
+    assert np.all(np.triu(W, 1) == 0) and np.all(np.diag(W) == 1.0)
     Q = np.eye(M, k) - W @ (Tf @ W[:k, :].T)
     np.testing.assert_allclose(Q, form_q(qr, tau_ref, k), atol=1e-11)
 
 
-def test_householder_panel_zero_and_rank_deficient(gpu):
-    from paper_2106_13402_amd import householder_panel
+# The tree kernel (k <= 64, M <= 65536; wider panels split into halves it
+# takes): one leaf, a leaf boundary, ragged last leaves, trees of every
+# shape up to the 256-leaf maximum, and the column split above 64.
+TREE_CASES = [(64, 64), (256, 17), (257, 1), (257, 64), (511, 2), (512, 63), (513, 64),
+              (769, 40), (2049, 64), (16384, 64), (65536, 64), (5000, 65), (3000, 100),
+              (65536, 128)]
+
+
+@pytest.mark.parametrize("M,k", TREE_CASES)
+def test_panel_tree_matches_lapack(gpu, M, k):
+    print(f"case: tree panel M={M} k={k}", flush=True)
+    rng = np.random.default_rng(7 * M + k)
+    P = rng.standard_normal((M, k)) * 2.0 ** rng.integers(-3, 4, k)[None, :]
+    _check_panel_lapack(P, *_panel(P, gpu))
+
+
+@pytest.mark.parametrize("M,k", [(3000, 64), (16384, 128), (1000, 33)])
+def test_panel_tree_matches_column_kernel(gpu, M, k):
+    """Both kernels give the same reflectors (to rounding)."""
+    print(f"case: tree vs column panel M={M} k={k}", flush=True)
+    P = np.random.default_rng(M - k).standard_normal((M, k))
+    a, b = _panel(P, gpu, True), _panel(P, gpu, False)
+    for x, y, name in zip(a, b, ("W", "R", "Tf", "tau")):
+        np.testing.assert_allclose(x, y, atol=1e-12 * max(1.0, np.abs(y).max()), err_msg=name)
+
+
+def test_panel_tree_graded(gpu):
+    """Columns spanning 14 decades (the sketch of a decaying spectrum): Q is
+    orthogonal and Q R = P to rounding, and the well-separated leading
+    reflectors match LAPACK's."""
+    print("case: tree panel, graded columns", flush=True)
+    M, k = 4000, 64
+    from synthetic import haar
+    P = haar(M, k, seed=5, stream=1) @ np.diag(10.0 ** -np.linspace(0, 14, k)) @ haar(k, k, seed=5, stream=2).T
+    W, R, Tf, tau = _panel(P, gpu)
+    Q = np.eye(M, k) - W @ (Tf @ W[:k, :].T)
+    assert np.linalg.norm(Q.T @ Q - np.eye(k), 2) < 1e-14 * 20
+    assert np.linalg.norm(Q @ R - P, 2) < 1e-15 * 20 * np.linalg.norm(P, 2)
+    qr, tau_ref = hqr(P)
+    np.testing.assert_allclose(np.abs(np.diag(R)), np.abs(np.diag(qr)[:k]), atol=1e-14 * 20)
+    np.testing.assert_allclose(tau[:8], tau_ref[:8], atol=1e-9)
+
+
+@pytest.mark.parametrize("tree", [False, True])
+def test_householder_panel_zero_and_rank_deficient(gpu, tree):
+    """A zero sub-column, a zero column and a dependent column. dlarfg leaves
+    a reflector whose sub-column is exactly zero as H = I (tau = 0), and so
+    does the column kernel. The tree kernel recovers its reflectors from the
+    Q of a tree of QRs: a column that is exactly e_j comes back as the
+    reflection I - 2 e_j e_j^T (tau = 2) with row j of R negated, and past
+    the first rank drop (the zero column 2) Q's next column is any unit
+    vector orthogonal to the earlier ones, so the reflectors from there on
+    are a different, equally exact, choice. Both give P = Q R with Q
+    orthogonal; LAPACK's reflectors are matched where P determines them."""
     rng = np.random.default_rng(1)
     P = rng.standard_normal((300, 8))
-    P[:, 2] = 0.0                  # zero column: H = I (tau = 0)
+    P[:, 2] = 0.0                  # zero column
     P[:, 5] = P[:, 1] * 3.0        # dependent column
     P[1:, 0] = 0.0                 # zero sub-column below the diagonal
-    W, R, Tf, tau = (_host(x) for x in householder_panel(_to_dev(P, gpu)))
+    W, R, Tf, tau = _panel(P, gpu, tree)
     qr, tau_ref = hqr(P)
-    assert tau[0] == 0.0 and tau[2] == 0.0
-    # columns 0..4 are determined by P; column 5 lies in the span of the
-    # earlier ones, so its reflector (and every later one) is fixed by
-    # rounding noise alone: only R(5,5) ~ 0 and P = Q R are well-posed there.
-    np.testing.assert_allclose(tau[:5], tau_ref[:5], atol=1e-12)
-    np.testing.assert_allclose(np.abs(np.diag(R))[:5], np.abs(np.diag(qr))[:5], atol=1e-12 * 20)
-    assert abs(R[5, 5]) < 1e-13 * np.abs(P).max() * 20
+    assert tau[0] == (2.0 if tree else 0.0) and np.all(W[1:, 0] == 0.0)
+    assert abs(R[0, 0]) == abs(P[0, 0])
+    np.testing.assert_allclose(tau[1], tau_ref[1], atol=1e-12)
+    np.testing.assert_allclose(W[:, 1], np.tril(qr, -1)[:, 1] + np.eye(300, 8)[:, 1], atol=1e-12)
+    np.testing.assert_allclose(abs(R[1, 1]), abs(qr[1, 1]), rtol=1e-13)
+    amax = np.abs(P).max()
+    assert np.abs(R[:3, 2]).max() < 1e-13 * amax * 20   # R(:, 2) = Q^T 0
+    assert abs(R[5, 5]) < 1e-13 * amax * 20             # column 5 in span(Q(:, :2))
+    if not tree:
+        # columns 0..4 are determined by P in the dlarfg convention; column 5
+        # lies in the span of the earlier ones, so its reflector (and every
+        # later one) is fixed by rounding noise alone
+        assert tau[2] == 0.0
+        np.testing.assert_allclose(tau[:5], tau_ref[:5], atol=1e-12)
+        np.testing.assert_allclose(np.abs(np.diag(R))[:5], np.abs(np.diag(qr))[:5], atol=1e-12 * 20)
     Q = np.eye(300) - W @ Tf @ W.T
     assert np.linalg.norm(Q.T @ Q - np.eye(300), 2) < 1e-13
     np.testing.assert_allclose(Q[:, :8] @ R, P, atol=1e-12 * 20)
