@@ -75,16 +75,43 @@ __global__ __launch_bounds__(kThreads, 2) void dgemm_mfma_kernel(GemmF64Args g) 
   const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
   const int64_t kend = (kbeg + g.kchunk < g.K) ? kbeg + g.kchunk : g.K;
 
+  const int lr = lane & 15;  // row (mn) of the operand fragment
+  const int lk = lane >> 4;  // k of the operand fragment
+
+  // With beta != 0 (and no split) the accumulators start from
+  // (beta / alpha) C, read before the K loop so that its latency overlaps
+  // the operand loads instead of following the last MFMA; the epilogue then
+  // only scales by alpha and stores.
+  // (Only with 16-byte operand loads, whose address registers leave room.)
+  const bool c_first = VEC && g.P == nullptr && g.beta != 0.0;
+  const double cs = c_first ? g.beta / g.alpha : 0.0;
   f64x4 acc[MI][NI];
+  const int64_t ci = i0 + wm * WM + lr, cj = j0 + wn * WN + lk;
+  if (c_first && i0 + BM <= g.M && j0 + BN <= g.N) {
+    // whole tile inside C: one column pointer walked along the columns
+    const double* cp = g.C + ci + cj * g.ldc;
 #pragma unroll
-  for (int mi = 0; mi < MI; ++mi)
+    for (int ni = 0; ni < NI; ++ni)
 #pragma unroll
-    for (int ni = 0; ni < NI; ++ni) acc[mi][ni] = f64x4{0.0, 0.0, 0.0, 0.0};
+      for (int r = 0; r < 4; ++r) {
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi) acc[mi][ni][r] = cs * cp[mi * 16];
+        cp += 4 * g.ldc;
+      }
+  } else {
+#pragma unroll
+    for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < NI; ++ni)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gi = ci + mi * 16, gj = cj + ni * 16 + 4 * r;
+          acc[mi][ni][r] = (c_first && gi < g.M && gj < g.N) ? cs * g.C[gi + gj * g.ldc] : 0.0;
+        }
+  }
 
   double ra[OA::PER_T];
   double rb[OB::PER_T];
-  const int lr = lane & 15;  // row (mn) of the operand fragment
-  const int lk = lane >> 4;  // k of the operand fragment
 
   if (kbeg < kend) {
     OA::load(ra, g.A, g.lda, i0, g.M, kbeg, kend, tid);
@@ -141,7 +168,7 @@ __global__ __launch_bounds__(kThreads, 2) void dgemm_mfma_kernel(GemmF64Args g) 
           g.P[(int64_t)blockIdx.z * MN + gi + gj * g.M] = v;
         } else {
           double c = g.alpha * v;
-          if (g.beta != 0.0) c += g.beta * g.C[gi + gj * g.ldc];
+          if (!c_first && g.beta != 0.0) c += g.beta * g.C[gi + gj * g.ldc];
           g.C[gi + gj * g.ldc] = c;
         }
       }
