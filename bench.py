@@ -48,27 +48,49 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # They describe the GEMM sources whose concatenation has this SHA-256 prefix.
 TRAFFIC_SOURCES = ("paper_2106_13402_amd/csrc/gemm_f64.hip",
                    "paper_2106_13402_amd/csrc/gemm_tile.hpp")
-TRAFFIC_SHA256_16 = "8dab7403c870db34"
+TRAFFIC_SHA256_16 = "7b00cc8f3a0396a2"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "dgemm_mfma_128x128_NN": 608648606,
-    "dgemm_mfma_128x128_TN": 595841394,
-    "dgemm_mfma_128x128_NT": 931093346,
-    "dgemm_mfma_128x128_NN:UV": 427565173,
-    "dgemm_mfma_128x128_TN:UV": 856814214,
+    "dgemm_mfma_128x128_NN": 608540129,
+    "dgemm_mfma_128x128_TN": 595867251,
+    "dgemm_mfma_128x128_NT": 758557710,
+    "dgemm_mfma_128x128_NN:UV": 426821442,
+    "dgemm_mfma_128x128_TN:UV": 857670391,
 }
+
+# Matrix-core counters of the same classes on the same sources
+# (profiles/randutv_n16384_b128_q2_fp64_mfma_counters.md): FP64 MFMA flops
+# from SQ_INSTS_VALU_MFMA_MOPS_F64 over the dispatch time, as a fraction of
+# peak, and SQ_VALU_MFMA_BUSY_CYCLES over the active cycles of all SIMDs.
+MFMA_COUNTERS = {
+    "dgemm_mfma_128x128_TN": (0.631, 0.658),
+    "dgemm_mfma_128x128_NN": (0.668, 0.692),
+    "dgemm_mfma_128x128_NT": (0.587, 0.620),
+    "dgemm_mfma_128x128_NN:UV": (0.575, 0.581),
+    "dgemm_mfma_128x128_TN:UV": (0.565, 0.592),
+}
+
+
+def _sources_match() -> bool:
+    import hashlib
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16] == TRAFFIC_SHA256_16
+
+
+def measured_mfma(kernel: str, n: int, b: int, q: int):
+    """(counter flop fraction, MFMA busy fraction) of a GEMM class, or None
+    when the workload or the GEMM sources differ from the profiled ones."""
+    if (n, b, q) != (16384, 128, 2) or not _sources_match():
+        return None
+    return MFMA_COUNTERS.get(kernel)
 
 
 def measured_traffic(kernel: str, n: int, b: int, q: int):
     """Counter-measured HBM bytes per launch, or None when the workload or
     the GEMM source differ from those the counters were taken on."""
-    import hashlib
-    if (n, b, q) != (16384, 128, 2):
-        return None
-    h = hashlib.sha256()
-    for src in TRAFFIC_SOURCES:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest()[:16] != TRAFFIC_SHA256_16:
+    if (n, b, q) != (16384, 128, 2) or not _sources_match():
         return None
     return TRAFFIC_BYTES_PER_LAUNCH.get(kernel)
 
@@ -762,6 +784,8 @@ def main() -> int:
             "algorithmic_bytes_per_launch": dom["bytes"] / dom["launches"],
             "flops_per_launch": dom["flops"] / dom["launches"],
             "avg_launch_ms": dom["ms"] / dom["launches"],
+            "counter_frac": (measured_mfma(dom["name"], n, b, q) or (None, None))[0],
+            "mfma_busy": (measured_mfma(dom["name"], n, b, q) or (None, None))[1],
         },
         "gemm_all": {"tflops": gemm_flops / (gemm_ms * 1e-3) / 1e12,
                      "frac": gemm_flops / (gemm_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
