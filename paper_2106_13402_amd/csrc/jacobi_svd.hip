@@ -18,7 +18,10 @@
 //    a pair is rotated while |a_pq| > max(sqrt(k), 8) eps sqrt(a_pp a_qq)
 //    (the rounding level of the wave-tree dot product is ~log2(k) eps, so
 //    this converges, and the cosines left keep ||Us^T Us - I|| ~ k eps);
-//  * A_work and V live in LDS when 2 k^2 doubles fit, else in global scratch;
+//  * A_work and V live in LDS when 2 k^2 doubles fit; otherwise A_work alone
+//    when k^2 do (k <= 128: every inner product and rotation of A_work stays
+//    on chip, and V, touched once per rotation, stays in L2), else both in
+//    global scratch;
 //  * finally: singular values sorted descending (stable in column index),
 //    Us = A_work / d, columns with d = 0 completed to an orthonormal basis
 //    by projecting the coordinate vector least covered by the columns so
@@ -52,7 +55,7 @@ struct SvdArgs {
   double* d;
   double* Vs;
   double* gA;  // global scratch: per block 2 k^2 doubles when not in LDS
-  int use_lds;
+  int use_lds;  // 2: A_work and V in LDS, 1: A_work in LDS and V in gA, 0: both in gA
   int* status;
   const int* sizes;  // per-block sizes (device), or null
 };
@@ -202,9 +205,9 @@ __global__ __launch_bounds__(kThreads) void jacobi_svd_kernel(SvdArgs a) {
   const int blk = blockIdx.x;
   const int k = a.sizes ? a.sizes[blk] : ((blk == a.count - 1) ? a.k_last : a.k);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  double* gbase = a.use_lds ? nullptr : a.gA + (size_t)blk * 2 * a.k * a.k;
+  double* gbase = a.use_lds == 2 ? nullptr : a.gA + (size_t)blk * 2 * a.k * a.k;
   double* Aw = a.use_lds ? lds : gbase;
-  double* Vw = a.use_lds ? lds + (size_t)k * k : gbase + (size_t)a.k * a.k;
+  double* Vw = a.use_lds == 2 ? lds + (size_t)k * k : gbase + (size_t)a.k * a.k;
   const double* Bb = a.B + (int64_t)blk * a.stride;
   double* Usb = a.Us + (int64_t)blk * a.stride;
   double* Vsb = a.Vs + (int64_t)blk * a.stride;
@@ -401,6 +404,27 @@ int launch_small(hipStream_t st, const SvdArgs& a, int kmax) {
   return RRF_OK;
 }
 
+// The 1024-thread kernel for blocks up to kmax (> kSmallK): A_work and V in
+// LDS, A_work only, or neither, by what fits.
+int launch_large(hipStream_t st, SvdArgs& a, int kmax, void* work, size_t work_bytes) {
+  const size_t both = (size_t)2 * kmax * kmax * 8, one = both / 2;
+  a.use_lds = both <= kLdsBudget ? 2 : (one <= kLdsBudget ? 1 : 0);
+  if (a.use_lds < 2 && (work == nullptr || work_bytes < both * a.count))
+    return set_error(RRF_E_NOMEM, "block svd: workspace too small");
+  a.gA = a.use_lds == 2 ? nullptr : reinterpret_cast<double*>(work);
+  if (!g_attr_set) {
+    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)kLdsBudget));
+    g_attr_set = true;
+  }
+  const size_t lds = a.use_lds == 2 ? both : (a.use_lds == 1 ? one : 0);
+  int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * kmax * kmax * a.count);
+  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(a.count), dim3(kThreads), lds, st, a);
+  trace_end(st, tok);
+  RRF_CHECK_HIP(hipGetLastError());
+  return RRF_OK;
+}
 
 }  // namespace
 
@@ -427,16 +451,6 @@ int block_svd_batched(hipStream_t st, int count, int k, int k_last, const double
     a.status = status;
     return launch_small(st, a, k);
   }
-  const size_t need = (size_t)2 * k * k * 8;
-  const bool in_lds = need <= kLdsBudget;
-  if (!in_lds && (work == nullptr || work_bytes < need * count))
-    return set_error(RRF_E_NOMEM, "block svd: workspace too small");
-  if (!g_attr_set) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)kLdsBudget));
-    g_attr_set = true;
-  }
   SvdArgs a{};
   a.k = k;
   a.k_last = k_last;
@@ -448,14 +462,8 @@ int block_svd_batched(hipStream_t st, int count, int k, int k_last, const double
   a.Us = Us;
   a.d = d;
   a.Vs = Vs;
-  a.gA = in_lds ? nullptr : reinterpret_cast<double*>(work);
-  a.use_lds = in_lds ? 1 : 0;
   a.status = status;
-  int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * k * k * count);
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(count), dim3(kThreads), in_lds ? need : 0, st, a);
-  trace_end(st, tok);
-  RRF_CHECK_HIP(hipGetLastError());
-  return RRF_OK;
+  return launch_large(st, a, k, work, work_bytes);
 }
 
 int block_svd_sized(hipStream_t st, int count, int kmax, const int* d_sizes, const double* B,
@@ -479,16 +487,6 @@ int block_svd_sized(hipStream_t st, int count, int kmax, const int* d_sizes, con
     a.sizes = d_sizes;
     return launch_small(st, a, kmax);
   }
-  const size_t need = (size_t)2 * kmax * kmax * 8;
-  const bool in_lds = need <= kLdsBudget;
-  if (!in_lds && (work == nullptr || work_bytes < need * count))
-    return set_error(RRF_E_NOMEM, "block svd: workspace too small");
-  if (!g_attr_set) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)kLdsBudget));
-    g_attr_set = true;
-  }
   SvdArgs a{};
   a.k = kmax;
   a.k_last = kmax;
@@ -500,15 +498,9 @@ int block_svd_sized(hipStream_t st, int count, int kmax, const int* d_sizes, con
   a.Us = Us;
   a.d = d;
   a.Vs = Vs;
-  a.gA = in_lds ? nullptr : reinterpret_cast<double*>(work);
-  a.use_lds = in_lds ? 1 : 0;
   a.status = status;
   a.sizes = d_sizes;
-  int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * kmax * kmax * count);
-  hipLaunchKernelGGL(jacobi_svd_kernel, dim3(count), dim3(kThreads), in_lds ? need : 0, st, a);
-  trace_end(st, tok);
-  RRF_CHECK_HIP(hipGetLastError());
-  return RRF_OK;
+  return launch_large(st, a, kmax, work, work_bytes);
 }
 
 int block_svd(hipStream_t st, int k, const double* B, int64_t ldb, double* Us, double* d,
