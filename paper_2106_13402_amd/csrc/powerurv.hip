@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "context.hpp"
 #include "driver.hpp"
 #include "kernels.hpp"
 
@@ -82,25 +83,54 @@ bool plan(Arena& ar, int64_t m, int64_t n, int64_t nb, bool need_v, int precisio
 
 // Householder QR of X (M x N, ld ldx, destroyed): reflectors to W (M x N,
 // ld M), block factors to Tall, R (N x N, ld N).
+//
+// Look-ahead (with a side stream sp and two events): once block p's
+// reflectors are applied to the next nb columns, panel p+1 is factored on
+// sp while the rest of block p's trailing update runs on st, so the
+// latency-bound panels overlap the GEMMs instead of alternating with them.
+// Panel p+1 touches only its own columns (rows c0+nb..) and its slices of
+// W, Tall, R and tau; the update on st touches the columns after it.
 int hqr_blocked(hipStream_t st, int64_t M, int64_t N, int64_t nb, double* X, int64_t ldx,
-                PBufs& B, double* Rout) {
+                PBufs& B, double* Rout, hipStream_t sp, hipEvent_t ev_cols, hipEvent_t ev_panel) {
   RRF_TRY(fill_matrix(st, N, N, 0.0, Rout, N));
+  auto panel = [&](hipStream_t s, int64_t c0) -> int {
+    const int64_t k = std::min(nb, N - c0);
+    return householder_panel(s, M - c0, (int)k, X + c0 + c0 * ldx, ldx, B.Wall + c0 + c0 * M, M,
+                             Rout + c0 + c0 * N, N, B.Tall + c0 * nb, nb, B.tau + c0, nullptr, 0,
+                             B.panel, B.panel_bytes, B.status);
+  };
+  // Block p's reflectors applied to columns [j0, j0 + w) of X (rows c0..),
+  // and the finished rows c0..c0+k of those columns copied into R.
+  auto update = [&](int64_t c0, int64_t k, int64_t j0, int64_t w) -> int {
+    const int64_t Mp = M - c0;
+    const double* Wp = B.Wall + c0 + c0 * M;
+    double* Xr = X + c0 + j0 * ldx;
+    RRF_TRY(dgemm(st, true, false, k, w, Mp, 1.0, Wp, M, Xr, ldx, 0.0, B.Z, k, B.split,
+                  B.split_elems));
+    RRF_TRY(dgemm(st, false, false, Mp, w, k, -1.0, B.Wt, Mp, B.Z, k, 1.0, Xr, ldx, nullptr, 0));
+    return copy_matrix(st, k, w, Xr, ldx, Rout + c0 + j0 * N, N);
+  };
+  RRF_TRY(panel(st, 0));
   for (int64_t c0 = 0; c0 < N; c0 += nb) {
     const int64_t k = std::min(nb, N - c0);
     const int64_t Mp = M - c0;
-    double* Wp = B.Wall + c0 + c0 * M;
-    double* Tp = B.Tall + c0 * nb;
-    RRF_TRY(householder_panel(st, Mp, (int)k, X + c0 + c0 * ldx, ldx, Wp, M, Rout + c0 + c0 * N,
-                              N, Tp, nb, B.tau + c0, nullptr, 0, B.panel, B.panel_bytes,
-                              B.status));
     const int64_t Nr = N - c0 - k;
-    if (Nr > 0) {
-      double* Xr = X + c0 + (c0 + k) * ldx;
-      RRF_TRY(dgemm(st, false, true, Mp, k, k, 1.0, Wp, M, Tp, nb, 0.0, B.Wt, Mp, nullptr, 0));
-      RRF_TRY(dgemm(st, true, false, k, Nr, Mp, 1.0, Wp, M, Xr, ldx, 0.0, B.Z, k, B.split,
-                    B.split_elems));
-      RRF_TRY(dgemm(st, false, false, Mp, Nr, k, -1.0, B.Wt, Mp, B.Z, k, 1.0, Xr, ldx, nullptr, 0));
-      RRF_TRY(copy_matrix(st, k, Nr, Xr, ldx, Rout + c0 + (c0 + k) * N, N));
+    if (Nr <= 0) break;
+    // Wt = W Tf^T for block p: A <- (I - W Tf^T W^T) A = Q^T A
+    RRF_TRY(dgemm(st, false, true, Mp, k, k, 1.0, B.Wall + c0 + c0 * M, M, B.Tall + c0 * nb, nb,
+                  0.0, B.Wt, Mp, nullptr, 0));
+    const int64_t kn = std::min(nb, Nr);
+    RRF_TRY(update(c0, k, c0 + k, kn));
+    if (sp != nullptr && Nr > kn) {
+      RRF_CHECK_HIP(hipEventRecord(ev_cols, st));
+      RRF_CHECK_HIP(hipStreamWaitEvent(sp, ev_cols, 0));
+      RRF_TRY(panel(sp, c0 + k));
+      RRF_CHECK_HIP(hipEventRecord(ev_panel, sp));
+      RRF_TRY(update(c0, k, c0 + k + kn, Nr - kn));
+      RRF_CHECK_HIP(hipStreamWaitEvent(st, ev_panel, 0));
+    } else {
+      if (Nr > kn) RRF_TRY(update(c0, k, c0 + k + kn, Nr - kn));
+      RRF_TRY(panel(st, c0 + k));
     }
   }
   return RRF_OK;
@@ -159,10 +189,15 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
   RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(B.status), 64, 0u));
   if (check_input) RRF_TRY(check_finite(st, m, n, A, lda, B.status + 1));
   double* Vm = V ? V : B.Vw;
+  DeviceContext* ctx = nullptr;
+  RRF_TRY(device_context(&ctx));
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  hipStream_t sp = ctx->side[0];
+  hipEvent_t ev_cols = ctx->ev[0], ev_panel = ctx->ev[1];
 
   RRF_TRY(gaussian(st, seed, 0, n, n, Vm, n));
   if (q == 0) {
-    RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R));
+    RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R, sp, ev_cols, ev_panel));
     RRF_TRY(form_q(st, n, n, nb, n, B, Vm));
   }
   if (mixed) {
@@ -179,7 +214,7 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
       RRF_TRY(dgemm(st, false, false, m, n, n, 1.0, A, lda, Vm, n, 0.0, B.Yh, m, B.split,
                     B.split_elems));
     }
-    RRF_TRY(hqr_blocked(st, m, n, nb, B.Yh, m, B, B.R));
+    RRF_TRY(hqr_blocked(st, m, n, nb, B.Yh, m, B, B.R, sp, ev_cols, ev_panel));
     RRF_TRY(form_q(st, m, n, nb, n, B, B.Yh));  // V_hat in Yh
     if (mixed) {
       RRF_TRY(to_bf16(st, m, n, B.Yh, m, nullptr, B.Vhb, lm, nullptr, 0));
@@ -189,12 +224,12 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
       RRF_TRY(dgemm(st, true, false, n, n, m, 1.0, A, lda, B.Yh, m, 0.0, Vm, n, B.split,
                     B.split_elems));
     }
-    RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R));
+    RRF_TRY(hqr_blocked(st, n, n, nb, Vm, n, B, B.R, sp, ev_cols, ev_panel));
     RRF_TRY(form_q(st, n, n, nb, n, B, Vm));
   }
   RRF_TRY(dgemm(st, false, false, m, n, n, 1.0, A, lda, Vm, n, 0.0, B.Yh, m, B.split,
                 B.split_elems));
-  RRF_TRY(hqr_blocked(st, m, n, nb, B.Yh, m, B, B.R));
+  RRF_TRY(hqr_blocked(st, m, n, nb, B.Yh, m, B, B.R, sp, ev_cols, ev_panel));
   if (U) RRF_TRY(form_q(st, m, n, nb, m, B, U));
   RRF_TRY(fill_matrix(st, m, n, 0.0, T, m));
   RRF_TRY(copy_matrix(st, n, n, B.R, n, T, m));
