@@ -26,6 +26,7 @@
 #include "context.hpp"
 #include "driver.hpp"
 #include "kernels.hpp"
+#include "trace.hpp"
 
 namespace rrf {
 
@@ -193,6 +194,7 @@ int powerurv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t 
   RRF_TRY(device_context(&ctx));
   std::lock_guard<std::mutex> lk(ctx->mu);
   hipStream_t sp = ctx->side[0];
+  trace_unmark_stream(sp);
   hipEvent_t ev_cols = ctx->ev[0], ev_panel = ctx->ev[1];
 
   RRF_TRY(gaussian(st, seed, 0, n, n, Vm, n));

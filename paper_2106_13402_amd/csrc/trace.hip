@@ -95,6 +95,15 @@ void trace_mark_stream(hipStream_t st) {
   g_marked.push_back(st);
 }
 
+void trace_unmark_stream(hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (size_t i = 0; i < g_marked.size(); ++i)
+    if (g_marked[i] == st) {
+      g_marked.erase(g_marked.begin() + (long)i);
+      return;
+    }
+}
+
 int trace_begin(hipStream_t st, int cls, double flops, double bytes) {
   if (!g_on) return -1;
   std::lock_guard<std::mutex> lk(g_mu);

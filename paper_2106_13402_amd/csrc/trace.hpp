@@ -19,6 +19,8 @@ int trace_begin(hipStream_t st, int cls, double flops, double bytes);
 void trace_end(hipStream_t st, int token);
 // Launches on `st` are traced as separate ":UV" classes from now on.
 void trace_mark_stream(hipStream_t st);
+// ... and as their own classes again.
+void trace_unmark_stream(hipStream_t st);
 int gemm_trace_class(int tile, bool ta, bool tb);
 
 }  // namespace rrf
