@@ -78,25 +78,42 @@ __global__ __launch_bounds__(256) void maxabs_kernel(int64_t rows, int64_t cols,
                                                      const double* __restrict__ X, int64_t ld,
                                                      unsigned long long* word) {
   __shared__ double red[4];
-  double m0 = 0.0, m1 = 0.0;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // each thread takes two consecutive rows (one 16-byte load when X and ld
+  // allow) of four columns per iteration, so eight values are in flight
+  const bool pair = ((reinterpret_cast<uintptr_t>(X) & 15u) == 0) && (ld % 2 == 0);
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 2;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
   if (i < rows) {
-    int64_t j = blockIdx.y;
+    const bool two = i + 1 < rows;
     const int64_t step = gridDim.y;
-    for (; j + step < cols; j += 2 * step) {
-      m0 = fmax(m0, fabs(X[i + j * ld]));
-      m1 = fmax(m1, fabs(X[i + (j + step) * ld]));
-    }
-    if (j < cols) m0 = fmax(m0, fabs(X[i + j * ld]));
-  }
-  double m = fmax(m0, m1);
+    int64_t j = blockIdx.y;
+    for (; j + 3 * step < cols; j += 4 * step) {
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+      for (int u = 0; u < 4; ++u) {
+        const double* p = X + i + (j + u * step) * ld;
+        if (pair && two) {
+          const double2 v = *reinterpret_cast<const double2*>(p);
+          m[u] = fmax(m[u], fmax(fabs(v.x), fabs(v.y)));
+        } else {
+          m[u] = fmax(m[u], fabs(p[0]));
+          if (two) m[u] = fmax(m[u], fabs(p[1]));
+        }
+      }
+    }
+    for (; j < cols; j += step) {
+      const double* p = X + i + j * ld;
+      m[0] = fmax(m[0], fabs(p[0]));
+      if (two) m[0] = fmax(m[0], fabs(p[1]));
+    }
+  }
+  double mm = fmax(fmax(m[0], m[1]), fmax(m[2], m[3]));
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mm = fmax(mm, __shfl_xor(mm, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mm;
   __syncthreads();
   if (threadIdx.x == 0) {
-    m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    if (m > 0.0) atomicMax(word, (unsigned long long)__double_as_longlong(m));
+    mm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (mm > 0.0) atomicMax(word, (unsigned long long)__double_as_longlong(mm));
   }
 }
 
@@ -163,28 +180,64 @@ __global__ __launch_bounds__(256) void sumsq_finish_kernel(const double* __restr
 // transpose when non-null; s = pow2_scale(max) from `word` when non-null,
 // else 1. Rows [rows, ldo) of out and [cols, ldot) of outT are zero-filled so
 // that 16-byte loads along the inner dimension never need a ragged edge.
-// 64 x 64 tiles, transposed through LDS.
+// 64 x 64 tiles; thread (q, g) converts rows 4q..4q+3 of columns g, g+16,
+// g+32, g+48 (two 16-byte loads and one 8-byte store per column), and the
+// transpose goes through LDS to be stored the same way. ldo and ldot are
+// multiples of 8, so the 8-byte stores are aligned.
 __global__ __launch_bounds__(256) void to_bf16_kernel(int64_t rows, int64_t cols,
                                                       const double* __restrict__ X, int64_t ld,
                                                       const unsigned long long* word,
                                                       uint16_t* __restrict__ out, int64_t ldo,
                                                       uint16_t* __restrict__ outT, int64_t ldot) {
-  __shared__ uint16_t tile[64][65];
+  __shared__ uint16_t tile[64][68];  // [column][row]
   const double s = word ? pow2_scale(__longlong_as_double((long long)*word)) : 1.0;
   const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t r = r0 + tx, c = c0 + cc;
-    uint16_t v = 0;
-    if (r < rows && c < cols) v = bf16_from_f64(X[r + c * ld] * s);
-    if (r < ldo && c < cols) out[r + c * ldo] = v;
-    tile[cc][tx] = v;
+  const int q = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const bool vec = ((reinterpret_cast<uintptr_t>(X) & 15u) == 0) && (ld % 2 == 0);
+  const int64_t r = r0 + 4 * q;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int cc = g + 16 * u;
+    const int64_t c = c0 + cc;
+    double x[4] = {0.0, 0.0, 0.0, 0.0};
+    if (c < cols) {
+      const double* p = X + r + c * ld;
+      if (vec && r + 3 < rows) {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        x[0] = a.x; x[1] = a.y; x[2] = b.x; x[3] = b.y;
+      } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = (r + t < rows) ? p[t] : 0.0;
+      }
+    }
+    uint16_t h[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) h[t] = (c < cols && r + t < rows) ? bf16_from_f64(x[t] * s) : 0;
+    if (r < ldo && c < cols) {
+      const uint2 w = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                                 (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+      *reinterpret_cast<uint2*>(out + r + c * ldo) = w;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) tile[cc][4 * q + t] = h[t];
   }
   if (!outT) return;
   __syncthreads();
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t c = c0 + tx, r = r0 + rr;  // outT(c, r) = X(r, c)
-    if (c < ldot && r < rows) outT[c + r * ldot] = (c < cols) ? tile[tx][rr] : (uint16_t)0;
+  // outT(c, rr) = X(rr, c): thread (q, g) stores columns 4q..4q+3 of rows
+  // g, g+16, g+32, g+48 of outT's tile
+  const int64_t c = c0 + 4 * q;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int rr = g + 16 * u;
+    const int64_t rw = r0 + rr;
+    if (rw >= rows || c >= ldot) continue;
+    uint16_t h[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) h[t] = (c + t < cols) ? tile[4 * q + t][rr] : (uint16_t)0;
+    const uint2 w = make_uint2((uint32_t)h[0] | ((uint32_t)h[1] << 16),
+                               (uint32_t)h[2] | ((uint32_t)h[3] << 16));
+    *reinterpret_cast<uint2*>(outT + c + rw * ldot) = w;
   }
 }
 
@@ -516,7 +569,7 @@ int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t 
            unsigned long long* word) {
   RRF_TRY(fill_u32(st, reinterpret_cast<unsigned*>(word), 2, 0u));
   if (rows <= 0 || cols <= 0) return RRF_OK;
-  dim3 grid((unsigned)ceil_div(rows, 256), (unsigned)std::min<int64_t>(cols, 32));
+  dim3 grid((unsigned)ceil_div(rows, 512), (unsigned)std::min<int64_t>(cols, 64));
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
   hipLaunchKernelGGL(maxabs_kernel, grid, dim3(256), 0, st, rows, cols, X, ld, word);
   trace_end(st, tok);

@@ -2,6 +2,8 @@
 // copy of A into T, block copies, the diagonal write T(I2,J2) = D, and the
 // finiteness check of the input. All are HBM-bound grid-stride loops that
 // walk column-major storage with consecutive threads on consecutive rows.
+#include <algorithm>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
@@ -17,45 +19,58 @@ inline unsigned blocks_for(int64_t elems) {
   return (unsigned)b;
 }
 
+// 2-D launch over a rows x cols column-major block: a workgroup of 256
+// threads covers a tile of TR = min(256, rows rounded up to a power of two)
+// rows by 256 / TR columns (so short, wide blocks keep every thread busy),
+// tiles down the rows in x, across the columns in y with a stride loop. No
+// per-element division.
+struct Tile2 {
+  int tr_log2;  // log2 TR
+  dim3 grid;
+};
+
+inline Tile2 tile2(int64_t rows, int64_t cols) {
+  int lg = 0;
+  while ((1 << lg) < rows && lg < 8) ++lg;
+  const int64_t tc = 256 >> lg;
+  Tile2 t;
+  t.tr_log2 = lg;
+  t.grid = dim3((unsigned)ceil_div(rows, (int64_t)1 << lg),
+                (unsigned)std::min<int64_t>(ceil_div(cols, tc), 65535));
+  return t;
+}
+
+// Visit every (i, j) of the block with f(i, j).
+#define RRF_TILE2_LOOP(rows, cols, lg, body)                                        \
+  do {                                                                              \
+    const int tr_ = 1 << (lg), tc_ = 256 >> (lg);                                   \
+    const int64_t i = (int64_t)blockIdx.x * tr_ + (threadIdx.x & (tr_ - 1));        \
+    if (i < (rows))                                                                 \
+      for (int64_t j = (int64_t)blockIdx.y * tc_ + (threadIdx.x >> (lg)); j < (cols); \
+           j += (int64_t)gridDim.y * tc_) {                                         \
+        body;                                                                       \
+      }                                                                             \
+  } while (0)
+
 __global__ __launch_bounds__(256) void identity_kernel(int64_t rows, int64_t cols, double* X,
-                                                       int64_t ld) {
-  const int64_t total = rows * cols;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * 256) {
-    const int64_t i = t % rows, j = t / rows;
-    X[i + j * ld] = (i == j) ? 1.0 : 0.0;
-  }
+                                                       int64_t ld, int lg) {
+  RRF_TILE2_LOOP(rows, cols, lg, X[i + j * ld] = (i == j) ? 1.0 : 0.0);
 }
 
 __global__ __launch_bounds__(256) void copy_kernel(int64_t rows, int64_t cols,
                                                    const double* __restrict__ S, int64_t lds,
-                                                   double* __restrict__ D, int64_t ldd) {
-  const int64_t total = rows * cols;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * 256) {
-    const int64_t i = t % rows, j = t / rows;
-    D[i + j * ldd] = S[i + j * lds];
-  }
+                                                   double* __restrict__ D, int64_t ldd, int lg) {
+  RRF_TILE2_LOOP(rows, cols, lg, D[i + j * ldd] = S[i + j * lds]);
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(int64_t rows, int64_t cols, double v, double* X,
-                                                   int64_t ld) {
-  const int64_t total = rows * cols;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * 256) {
-    const int64_t i = t % rows, j = t / rows;
-    X[i + j * ld] = v;
-  }
+                                                   int64_t ld, int lg) {
+  RRF_TILE2_LOOP(rows, cols, lg, X[i + j * ld] = v);
 }
 
 __global__ __launch_bounds__(256) void diag_kernel(int64_t rows, int64_t cols, const double* d,
-                                                   double* X, int64_t ld) {
-  const int64_t total = rows * cols;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * 256) {
-    const int64_t i = t % rows, j = t / rows;
-    X[i + j * ld] = (i == j) ? d[i] : 0.0;
-  }
+                                                   double* X, int64_t ld, int lg) {
+  RRF_TILE2_LOOP(rows, cols, lg, X[i + j * ld] = (i == j) ? d[i] : 0.0);
 }
 
 __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int64_t count, unsigned v) {
@@ -65,15 +80,13 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int64_t coun
 }
 
 __global__ __launch_bounds__(256) void finite_kernel(int64_t rows, int64_t cols,
-                                                     const double* X, int64_t ld, int* status) {
-  const int64_t total = rows * cols;
+                                                     const double* X, int64_t ld, int* status,
+                                                     int lg) {
   bool bad = false;
-  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total;
-       t += (int64_t)gridDim.x * 256) {
-    const int64_t i = t % rows, j = t / rows;
+  RRF_TILE2_LOOP(rows, cols, lg, {
     const double v = X[i + j * ld];
     if (!(v - v == 0.0)) bad = true;  // NaN or +-Inf
-  }
+  });
   if (bad) atomicOr(status, 1);
 }
 
@@ -82,8 +95,8 @@ __global__ __launch_bounds__(256) void finite_kernel(int64_t rows, int64_t cols,
 int set_identity(hipStream_t st, int64_t rows, int64_t cols, double* X, int64_t ld) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
-  hipLaunchKernelGGL(identity_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols,
-                     X, ld);
+  const Tile2 g = tile2(rows, cols);
+  hipLaunchKernelGGL(identity_kernel, g.grid, dim3(256), 0, st, rows, cols, X, ld, g.tr_log2);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;
@@ -132,8 +145,8 @@ int copy_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int
                 double* D, int64_t ldd) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
   int tok = trace_begin(st, kTrElementwise, 0.0, 16.0 * rows * cols);
-  hipLaunchKernelGGL(copy_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols, S,
-                     lds, D, ldd);
+  const Tile2 g = tile2(rows, cols);
+  hipLaunchKernelGGL(copy_kernel, g.grid, dim3(256), 0, st, rows, cols, S, lds, D, ldd, g.tr_log2);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;
@@ -142,8 +155,8 @@ int copy_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int
 int fill_matrix(hipStream_t st, int64_t rows, int64_t cols, double v, double* X, int64_t ld) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
-  hipLaunchKernelGGL(fill_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols, v,
-                     X, ld);
+  const Tile2 g = tile2(rows, cols);
+  hipLaunchKernelGGL(fill_kernel, g.grid, dim3(256), 0, st, rows, cols, v, X, ld, g.tr_log2);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;
@@ -152,8 +165,8 @@ int fill_matrix(hipStream_t st, int64_t rows, int64_t cols, double v, double* X,
 int set_diag(hipStream_t st, int64_t rows, int64_t cols, const double* d, double* X, int64_t ld) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
-  hipLaunchKernelGGL(diag_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols, d,
-                     X, ld);
+  const Tile2 g = tile2(rows, cols);
+  hipLaunchKernelGGL(diag_kernel, g.grid, dim3(256), 0, st, rows, cols, d, X, ld, g.tr_log2);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;
@@ -170,8 +183,9 @@ int check_finite(hipStream_t st, int64_t rows, int64_t cols, const double* X, in
                  int* status) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
   int tok = trace_begin(st, kTrElementwise, 0.0, 8.0 * rows * cols);
-  hipLaunchKernelGGL(finite_kernel, dim3(blocks_for(rows * cols)), dim3(256), 0, st, rows, cols,
-                     X, ld, status);
+  const Tile2 g = tile2(rows, cols);
+  hipLaunchKernelGGL(finite_kernel, g.grid, dim3(256), 0, st, rows, cols, X, ld, status,
+                     g.tr_log2);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
   return RRF_OK;

@@ -35,7 +35,9 @@ from device_norms import gkl_norm, orth_error, recon_error
 pytestmark = pytest.mark.gpu
 U64 = np.finfo(np.float64).eps / 2
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-CASES = sorted(os.path.basename(p)[:-4] for p in glob.glob(os.path.join(GOLDEN, "c2_*.txt")))
+# grouped by input (c2_{alg}_{input}_q{q}), so each 8192^2 input is built once
+CASES = sorted((os.path.basename(p)[:-4] for p in glob.glob(os.path.join(GOLDEN, "c2_*.txt"))),
+               key=lambda c: (c.split("_")[2], c.split("_")[1], c))
 
 
 def load_golden(name):

@@ -452,14 +452,27 @@ def test_powerurv_bf16_resolution_limit(gpu):
 
 
 # ------------------------------------------------------- mixed-precision sketch
+_ENVELOPES = {}
+
+
 def _oracle_envelope(A, b, q, seeds, ks):
     """Largest e_k = ||T(k:, k:)||_2 over FP64 oracle runs with several sketch
-    seeds: the spread of the randomized algorithm itself."""
-    env = np.zeros(len(ks))
-    for sd in seeds:
-        _, To, _ = oracle.randutv(A, b, q, sd, want_u=False, want_v=False)
-        env = np.maximum(env, M.trailing_norms(To, ks))
-    return env
+    seeds: the spread of the randomized algorithm itself. Computed once per
+    (input, b, q, seeds) on the grid k = 0, n/64, ... and kept for the
+    session (the mixed-mode tests of every precision share it)."""
+    import hashlib
+    n = A.shape[1]
+    grid = list(range(0, n, max(1, n // 64)))
+    key = (hashlib.sha1(np.ascontiguousarray(A).tobytes()).hexdigest(), A.shape, b, q,
+           tuple(seeds))
+    if key not in _ENVELOPES:
+        env = np.zeros(len(grid))
+        for sd in seeds:
+            _, To, _ = oracle.randutv(A, b, q, sd, want_u=False, want_v=False)
+            env = np.maximum(env, M.trailing_norms(To, grid))
+        _ENVELOPES[key] = dict(zip(grid, env))
+    table = _ENVELOPES[key]
+    return np.array([table[k] for k in ks])
 
 
 def _mixed_gate(T, A, b, q, seed, s, rec_err, factor=1.1):

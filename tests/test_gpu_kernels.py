@@ -319,18 +319,22 @@ def _f64_to_bf16_bits(x):
     return (np.asarray(x, np.float64).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
 
 
+@pytest.mark.parametrize("aligned", [False, True])
 @pytest.mark.parametrize("scaled", [False, True])
-def test_to_bf16_bit_exact(gpu, scaled):
+def test_to_bf16_bit_exact(gpu, scaled, aligned):
+    """Strided (odd leading dimension: element loads) and 16-byte aligned
+    (pairs of loads, a ragged last group of four rows) inputs."""
     from oracle.bf16 import bf16_round, pow2_scale
     from paper_2106_13402_amd import to_bf16
     rng = np.random.default_rng(11)
-    M, N = 1000, 300
+    M, N = (1002, 300) if aligned else (1000, 300)
     X = rng.standard_normal((M, N)) * 2.0 ** rng.integers(-60, 40, (M, N))
     X[0, :5] = [0.0, -0.0, 3e-41, -2.2e-39, 1.0 + 2.0 ** -8 + 2.0 ** -30]  # zeros, underflow, direct rounding
     X[1:17, 7] = (np.arange(256, 272) + 0.5) * 2.0 ** -9                     # exact ties
-    big = np.zeros((M + 9, N + 3))
-    big[4:4 + M, 2:2 + N] = X
-    dX = _to_dev(big, gpu)[4:4 + M, 2:2 + N]                                # strided view
+    r0, ldx = (0, M + 6) if aligned else (4, M + 9)
+    big = np.zeros((ldx, N + 3))
+    big[r0:r0 + M, 2:2 + N] = X
+    dX = _to_dev(big, gpu)[r0:r0 + M, 2:2 + N]                              # strided view
     out, outT = to_bf16(dX, scaled=scaled, transpose=True)
     s = pow2_scale(X) if scaled else 1.0
     want = _f64_to_bf16_bits(bf16_round(X * s))
