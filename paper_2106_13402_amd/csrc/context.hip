@@ -1,5 +1,5 @@
-// Per-device execution context: the side streams and events the drivers use
-// to overlap independent work with the critical path. Created on first use
+// Per-device execution context: the streams and events the drivers use to
+// overlap independent work with the critical path. Created on first use
 // and kept for the life of the process; every stream has the default
 // priority and does not synchronize with the null stream.
 #include <mutex>
@@ -25,6 +25,8 @@ int device_context(DeviceContext** out) {
     return RRF_OK;
   }
   DeviceContext* c = new DeviceContext();
+  for (int i = 0; i < kSliceStreams; ++i)
+    RRF_CHECK_HIP(hipStreamCreateWithFlags(&c->slice[i], hipStreamNonBlocking));
   for (int i = 0; i < kSideStreams; ++i)
     RRF_CHECK_HIP(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
   for (int i = 0; i < kCtxEvents; ++i)

@@ -32,6 +32,7 @@
 
 #include "batched.hpp"
 #include "common.hpp"
+#include "context.hpp"
 #include "driver.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
@@ -993,12 +994,12 @@ struct Recording {
   uint64_t used = 0;
 };
 
-// Per-device resources kept between calls: the slices' streams (default
-// priority), their descriptor rings, the events that order them after and
-// before the caller's stream, and the recorded calls.
+// Per-device resources kept between calls: the slices' descriptor rings, the
+// events that order the slices after and before the caller's stream, and the
+// recorded calls. Slice 0 runs on the caller's stream, the others on the
+// device context's slice streams.
 struct DeviceRes {
   Ring rings[kMaxSlices];
-  hipStream_t streams[kMaxSlices] = {};
   hipEvent_t done[kMaxSlices] = {};
   hipEvent_t start = nullptr;
   hipEvent_t ring_done = nullptr;  // the last lockstep call's rounds are enqueued up to here
@@ -1008,11 +1009,18 @@ struct DeviceRes {
 };
 std::unordered_map<int, DeviceRes> g_res;
 
-int slice_resources(DeviceRes& r, int S) {
+static_assert(kMaxSlices == kSliceStreams + 1, "one slice per context stream plus the caller's");
+
+// The slices' streams of this call (`streams[0]` is the caller's) and the
+// events, created on first use.
+int slice_resources(DeviceRes& r, hipStream_t st, hipStream_t* streams) {
+  DeviceContext* ctx = nullptr;
+  RRF_TRY(device_context(&ctx));
   if (!r.start) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.start, hipEventDisableTiming));
   if (!r.ring_done) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.ring_done, hipEventDisableTiming));
-  for (int i = 0; i < S; ++i) {
-    if (!r.streams[i]) RRF_CHECK_HIP(hipStreamCreateWithFlags(&r.streams[i], hipStreamNonBlocking));
+  streams[0] = st;
+  for (int i = 0; i < kMaxSlices; ++i) {
+    if (i > 0) streams[i] = ctx->slice[i - 1];
     if (!r.done[i]) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.done[i], hipEventDisableTiming));
   }
   return RRF_OK;
@@ -1096,7 +1104,8 @@ void pack_plans(const std::vector<Slice>& work, const std::vector<size_t>& offse
     }
 }
 
-int record(hipStream_t st, DeviceRes& res, std::vector<Slice>& work, Recording* rec) {
+int record(hipStream_t st, const hipStream_t* streams, std::vector<Slice>& work,
+           Recording* rec) {
   size_t total = 0;
   for (const auto& w : work)
     for (const auto& p : w.plans) {
@@ -1112,11 +1121,13 @@ int record(hipStream_t st, DeviceRes& res, std::vector<Slice>& work, Recording* 
   pack_plans(work, rec->offsets, rec->host);
   RRF_CHECK_HIP(hipMemcpyAsync(rec->dev, rec->host, rec->bytes, hipMemcpyHostToDevice, st));
   RRF_CHECK_HIP(hipEventRecord(rec->uploaded, st));
-  // capture each slice's launches on its own stream (nothing runs while
-  // capturing; the descriptors are read when the graph is launched)
+  // capture each slice's launches (nothing runs while capturing; the
+  // descriptors are read when the graph is launched). The caller's stream may
+  // be the null stream, which cannot capture, so every slice is captured on a
+  // context stream; a graph runs on whichever stream launches it.
   size_t r = 0;
   for (int i = 0; i < rec->S; ++i) {
-    hipStream_t cs = res.streams[i];
+    hipStream_t cs = streams[1];
     RRF_CHECK_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = RRF_OK;
     for (const auto& p : work[i].plans) {
@@ -1137,16 +1148,17 @@ int record(hipStream_t st, DeviceRes& res, std::vector<Slice>& work, Recording* 
   return RRF_OK;
 }
 
-// Launch the recorded graphs, each slice on its own stream, ordered after
-// and before the caller's stream.
-int replay(hipStream_t st, DeviceRes& res, Recording* rec) {
-  RRF_CHECK_HIP(hipEventRecord(res.start, st));
-  for (int i = 0; i < rec->S; ++i) {
-    RRF_CHECK_HIP(hipStreamWaitEvent(res.streams[i], res.start, 0));
-    RRF_CHECK_HIP(hipGraphLaunch(rec->exec[i], res.streams[i]));
-    RRF_CHECK_HIP(hipEventRecord(res.done[i], res.streams[i]));
-    RRF_CHECK_HIP(hipStreamWaitEvent(st, res.done[i], 0));
+// Launch the recorded graphs, slice 0 on the caller's stream and the others on
+// their own, ordered after and before the caller's stream.
+int replay(hipStream_t st, const hipStream_t* streams, DeviceRes& res, Recording* rec) {
+  if (rec->S > 1) RRF_CHECK_HIP(hipEventRecord(res.start, st));
+  for (int i = 1; i < rec->S; ++i) {
+    RRF_CHECK_HIP(hipStreamWaitEvent(streams[i], res.start, 0));
+    RRF_CHECK_HIP(hipGraphLaunch(rec->exec[i], streams[i]));
+    RRF_CHECK_HIP(hipEventRecord(res.done[i], streams[i]));
   }
+  RRF_CHECK_HIP(hipGraphLaunch(rec->exec[0], st));
+  for (int i = 1; i < rec->S; ++i) RRF_CHECK_HIP(hipStreamWaitEvent(st, res.done[i], 0));
   RRF_CHECK_HIP(hipEventRecord(rec->done, st));
   return RRF_OK;
 }
@@ -1161,7 +1173,8 @@ bool same_shapes(const Recording* r, const std::vector<Mat>& mats, const std::ve
   return true;
 }
 
-int run_recorded(hipStream_t st, int dev, DeviceRes& res, std::vector<Slice>& work,
+int run_recorded(hipStream_t st, const hipStream_t* streams, int dev, DeviceRes& res,
+                 std::vector<Slice>& work,
                  const std::vector<Mat>& mats, const std::vector<int64_t>& cut, const void* ws,
                  const BatchedCfg& cfg, int q, int precision) {
   const uint64_t h = args_hash(mats, ws);
@@ -1214,7 +1227,7 @@ int run_recorded(hipStream_t st, int dev, DeviceRes& res, std::vector<Slice>& wo
       rec->n.push_back(x.n);
     }
     rec->args = h;
-    const int rc = record(st, res, work, rec);
+    const int rc = record(st, streams, work, rec);
     if (rc != RRF_OK) {
       const std::string msg = rrf_last_error();
       (void)free_recording(rec);
@@ -1223,7 +1236,7 @@ int run_recorded(hipStream_t st, int dev, DeviceRes& res, std::vector<Slice>& wo
     res.recs.push_back(rec);
   }
   rec->used = ++res.clock;
-  return replay(st, res, rec);
+  return replay(st, streams, res, rec);
 }
 
 }  // namespace
@@ -1257,7 +1270,8 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
   // rounds of one slice leave the chip partly idle in their latency-bound
   // launches (panels, small SVDs), which the other slices' GEMMs fill.
   const int S = (int)std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, count / 256));
-  RRF_TRY(slice_resources(res, std::max(S, 1)));
+  hipStream_t streams[kMaxSlices] = {};
+  RRF_TRY(slice_resources(res, st, streams));
   double total = 0.0;
   for (auto& x : mats) total += (double)x.m * x.n * x.n;
   std::vector<int64_t> cut(S + 1, count);
@@ -1292,7 +1306,7 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
     w.sh.svd_bytes = nb * svd_per_block;
   }
   if (use_graph && !trace_on())
-    return run_recorded(st, dev, res, work, mats, cut, ws, cfg, q, precision);
+    return run_recorded(st, streams, dev, res, work, mats, cut, ws, cfg, q, precision);
 
   // lockstep rounds streamed through the descriptor rings; the rings' slots
   // are reused only after every round a previous call enqueued (possibly on
@@ -1305,7 +1319,7 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
     return rc;
   }
   RRF_CHECK_HIP(hipEventRecord(res.start, st));
-  for (int i = 0; i < S; ++i) RRF_CHECK_HIP(hipStreamWaitEvent(res.streams[i], res.start, 0));
+  for (int i = 1; i < S; ++i) RRF_CHECK_HIP(hipStreamWaitEvent(streams[i], res.start, 0));
   std::vector<std::thread> threads;
   for (int i = 0; i < S; ++i) {
     threads.emplace_back([&, i]() {
@@ -1314,15 +1328,15 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
       if (e != hipSuccess) {
         w.rc = set_hip_error(e, "hipSetDevice", __FILE__, __LINE__);
       } else if (!w.mats.empty()) {
-        w.rc = run_slice(res.streams[i], res.rings[i], w.mats, w.sh, cfg, q, precision);
+        w.rc = run_slice(streams[i], res.rings[i], w.mats, w.sh, cfg, q, precision);
       }
       if (w.rc != RRF_OK) w.msg = rrf_last_error();
     });
   }
   for (auto& t : threads) t.join();
   // the caller's stream waits for every slice, also after a failure
-  for (int i = 0; i < S; ++i) {
-    RRF_CHECK_HIP(hipEventRecord(res.done[i], res.streams[i]));
+  for (int i = 1; i < S; ++i) {
+    RRF_CHECK_HIP(hipEventRecord(res.done[i], streams[i]));
     RRF_CHECK_HIP(hipStreamWaitEvent(st, res.done[i], 0));
   }
   RRF_CHECK_HIP(hipEventRecord(res.ring_done, st));
@@ -1349,7 +1363,6 @@ int randutv_batched_release() {
     for (auto* rec : r.recs) RRF_TRY(free_recording(rec));
     r.recs.clear();
     for (int i = 0; i < kMaxSlices; ++i) {
-      if (r.streams[i]) RRF_CHECK_HIP(hipStreamDestroy(r.streams[i]));
       if (r.done[i]) RRF_CHECK_HIP(hipEventDestroy(r.done[i]));
     }
     if (r.start) RRF_CHECK_HIP(hipEventDestroy(r.start));
