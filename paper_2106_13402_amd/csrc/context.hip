@@ -25,8 +25,6 @@ int device_context(DeviceContext** out) {
     return RRF_OK;
   }
   DeviceContext* c = new DeviceContext();
-  for (int i = 0; i < kSliceStreams; ++i)
-    RRF_CHECK_HIP(hipStreamCreateWithFlags(&c->slice[i], hipStreamNonBlocking));
   for (int i = 0; i < kSideStreams; ++i)
     RRF_CHECK_HIP(hipStreamCreateWithFlags(&c->side[i], hipStreamNonBlocking));
   for (int i = 0; i < kCtxEvents; ++i)

@@ -8,19 +8,20 @@
 namespace rrf {
 
 constexpr int kSideStreams = 2;
-constexpr int kSliceStreams = 3;
 constexpr int kCtxEvents = 16;
 
 // HIP spreads the streams of a process over a few hardware queues (four by
-// default) and a queue runs its kernels one after another. The batched
-// driver's slices run on the caller's stream and on `slice`, which are made
-// first so that each slice holds a queue of its own when the process has no
-// other streams; `side` comes after them.
+// default) and a queue runs its kernels one after another. Each queue the
+// process holds also costs the single-matrix drivers time (one idle queue
+// more made randUTV at n = 16384 about 9% slower), so the context holds few
+// streams: the two side streams, made at first use, and `extra`, made when
+// the batched driver first runs; that driver's slices run on the caller's
+// stream, the side streams and `extra`.
 struct DeviceContext {
-  hipStream_t slice[kSliceStreams] = {};
   hipStream_t side[kSideStreams] = {};
+  hipStream_t extra = nullptr;
   hipEvent_t ev[kCtxEvents] = {};
-  std::mutex mu;  // one factorization enqueues on these streams at a time
+  std::mutex mu;  // one driver enqueues on these streams at a time
 };
 
 int device_context(DeviceContext** out);

@@ -997,7 +997,7 @@ struct Recording {
 // Per-device resources kept between calls: the slices' descriptor rings, the
 // events that order the slices after and before the caller's stream, and the
 // recorded calls. Slice 0 runs on the caller's stream, the others on the
-// device context's slice streams.
+// device context's streams.
 struct DeviceRes {
   Ring rings[kMaxSlices];
   hipEvent_t done[kMaxSlices] = {};
@@ -1009,20 +1009,22 @@ struct DeviceRes {
 };
 std::unordered_map<int, DeviceRes> g_res;
 
-static_assert(kMaxSlices == kSliceStreams + 1, "one slice per context stream plus the caller's");
+static_assert(kMaxSlices == kSideStreams + 2, "slices on the caller's, side and extra streams");
 
 // The slices' streams of this call (`streams[0]` is the caller's) and the
-// events, created on first use.
-int slice_resources(DeviceRes& r, hipStream_t st, hipStream_t* streams) {
-  DeviceContext* ctx = nullptr;
-  RRF_TRY(device_context(&ctx));
+// events, created on first use; the caller holds `ctx->mu`.
+int slice_resources(DeviceRes& r, DeviceContext* ctx, hipStream_t st, hipStream_t* streams) {
+  if (!ctx->extra) RRF_CHECK_HIP(hipStreamCreateWithFlags(&ctx->extra, hipStreamNonBlocking));
   if (!r.start) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.start, hipEventDisableTiming));
   if (!r.ring_done) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.ring_done, hipEventDisableTiming));
   streams[0] = st;
-  for (int i = 0; i < kMaxSlices; ++i) {
-    if (i > 0) streams[i] = ctx->slice[i - 1];
-    if (!r.done[i]) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.done[i], hipEventDisableTiming));
+  for (int i = 0; i < kSideStreams; ++i) {
+    streams[1 + i] = ctx->side[i];
+    trace_unmark_stream(ctx->side[i]);  // the batched kernels keep their own classes
   }
+  streams[kMaxSlices - 1] = ctx->extra;
+  for (int i = 0; i < kMaxSlices; ++i)
+    if (!r.done[i]) RRF_CHECK_HIP(hipEventCreateWithFlags(&r.done[i], hipEventDisableTiming));
   return RRF_OK;
 }
 
@@ -1270,8 +1272,11 @@ int randutv_batched_run(hipStream_t st, int64_t count, const int64_t* m, const i
   // rounds of one slice leave the chip partly idle in their latency-bound
   // launches (panels, small SVDs), which the other slices' GEMMs fill.
   const int S = (int)std::min<int64_t>(kMaxSlices, std::max<int64_t>(1, count / 256));
+  DeviceContext* ctx = nullptr;
+  RRF_TRY(device_context(&ctx));
+  std::lock_guard<std::mutex> ctx_lk(ctx->mu);
   hipStream_t streams[kMaxSlices] = {};
-  RRF_TRY(slice_resources(res, st, streams));
+  RRF_TRY(slice_resources(res, ctx, st, streams));
   double total = 0.0;
   for (auto& x : mats) total += (double)x.m * x.n * x.n;
   std::vector<int64_t> cut(S + 1, count);
