@@ -154,7 +154,7 @@ int rrf_randutv_ex(int64_t m, int64_t n, const double* A, int64_t lda, int64_t b
  *    (64 MiB) inside the library, one per device, held until the process
  *    ends. A request whose rrf_workspace_size() exceeds it returns
  *    RRF_E_NOMEM before any device work (square FP64 inputs at q = 1 fit up
- *    to n = 1824 at b = 16, 1628 at b = 32, 1292 at b = 64, 824 at b = 128).
+ *    to n = 1807 at b = 16, 1611 at b = 32, 1280 at b = 64, 812 at b = 128).
  *  - The call itself performs no hipMalloc/hipFree and calls no allocating
  *    library routine. The first call on a device looks up the array's
  *    device address and creates the library's side streams there.

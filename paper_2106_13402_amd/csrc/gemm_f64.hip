@@ -188,7 +188,16 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(int64_t M, int64_t N
   for (int64_t j = blockIdx.y; j < N; j += gridDim.y) {
     const double* p = P + i + j * M;
     double s = 0.0;
-    for (int z = 0; z < S; ++z) s += p[(int64_t)z * MN];
+    int z = 0;
+    // eight loads in flight, added in split order
+    for (; z + 8 <= S; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(z + u) * MN];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; z < S; ++z) s += p[(int64_t)z * MN];
     double c = alpha * s;
     if (beta != 0.0) c += beta * C[i + j * ldc];
     C[i + j * ldc] = c;
@@ -228,6 +237,14 @@ inline bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 
 int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
           int64_t ldc, double* work, size_t work_elems) {
+  return dgemm_shaped(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work, work_elems,
+                      false, 0);
+}
+
+int dgemm_shaped(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 double* C, int64_t ldc, double* work, size_t work_elems, bool small_tiles,
+                 int want_splits) {
   if (M <= 0 || N <= 0) return RRF_OK;
   if (K <= 0 || alpha == 0.0) {
     if (beta == 1.0) return RRF_OK;
@@ -241,7 +258,7 @@ int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
   g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
   g.P = nullptr;
 
-  const bool big = (M >= 128 && N >= 128);
+  const bool big = !small_tiles && M >= 128 && N >= 128;
   const int BM = big ? 128 : 64, BN = big ? 128 : 64;
   const int64_t tiles = ceil_div(M, BM) * ceil_div(N, BN);
   // Split K when the tiles alone leave resident slots (two workgroups per CU,
@@ -251,7 +268,10 @@ int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, dou
   // on ties.
   const int64_t slots = 512;
   int splits = 1;
-  if (tiles < slots && K >= 2 * 256) {
+  if (want_splits > 1) {
+    splits = (int)std::min<int64_t>(want_splits, std::max<int64_t>(1, K / kBK));
+    while (splits > 1 && (size_t)splits * M * N > work_elems) --splits;
+  } else if (tiles < slots && K >= 2 * 256) {
     double best = 1.0;
     for (int64_t s = 2; s <= 16 && K / s >= 256; ++s) {
       if ((size_t)(s * M * N) > work_elems) break;

@@ -11,6 +11,13 @@ namespace rrf {
 int dgemm(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
           const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
           int64_t ldc, double* work, size_t work_elems);
+// dgemm with its launch shape chosen by the caller: 64 x 64 tiles when
+// `small_tiles`, and K split `want_splits` ways (fewer when the workspace
+// does not hold the partials; 0 or 1: the automatic choice).
+int dgemm_shaped(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                 const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                 double* C, int64_t ldc, double* work, size_t work_elems, bool small_tiles,
+                 int want_splits);
 // C = alpha sum_z P_z + beta C for split-K partials P_z = P + z M N (ld M),
 // summed in split order.
 int splitk_reduce(hipStream_t st, int64_t M, int64_t N, int splits, const double* P, double alpha,
@@ -82,6 +89,28 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                       double* W, int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt,
                       double* tau, double* zero, int64_t ldz, void* work, size_t work_bytes,
                       int* status);
+
+// The column-exchange kernel alone (one cooperative launch, the panel within
+// panel_plan); when `cond` is not null every workgroup returns at once unless
+// *cond != 0 (the CholeskyQR path's fallback).
+int panel_launch_if(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
+                    int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
+                    double* zero, int64_t ldz, void* work, size_t work_bytes, int* status,
+                    const int* cond);
+
+// ---- panel_cholqr.hip -----------------------------------------------------
+// The same factorization as householder_panel by CholeskyQR2 and
+// reconstruction of the reflectors, for 16 <= k <= 128, M >= 1024 and W not
+// overlapping P; ill-conditioned or rank-deficient panels fall back to the
+// column-exchange kernel on the device. Off when
+// RRF_PANEL_COLUMN=1 is in the environment (read at each call).
+bool cholqr_enabled();
+bool cholqr_panel_ok(int64_t M, int k, const double* P, int64_t ldp, const double* W,
+                     int64_t ldw);
+size_t cholqr_work_bytes(int64_t M, int k);
+int cholqr_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
+                 int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
+                 double* zero, int64_t ldz, void* work, size_t work_bytes, int* status);
 
 // ---- panel_tsqr.hip -------------------------------------------------------
 // The same factorization as householder_panel for 1 <= k <= 64 and

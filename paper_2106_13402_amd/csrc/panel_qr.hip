@@ -80,6 +80,7 @@ struct PanelArgs {
   double* red;        // kRing * Gw * slot doubles
   unsigned* flags;    // (Gw + 1) * kFlagStride, zero at launch
   int* status;
+  const int* cond;    // when not null: return at once unless *cond != 0
   int Gw;             // worker workgroups; workgroup Gw is the coordinator
   int rows_per;
   int ldl;            // LDS row stride of the row block (k + 1)
@@ -178,6 +179,10 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
   __shared__ double part[kThreads];
   __shared__ double part2[kThreads];
 
+  // the same value for every workgroup (written by an earlier launch)
+  if (a.cond != nullptr &&
+      __hip_atomic_load(const_cast<int*>(a.cond), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    return;
   const int tid = threadIdx.x;
   const int g = blockIdx.x;
   const bool coord = (g == a.Gw);
@@ -427,10 +432,20 @@ bool panel_plan(int64_t M, int k, PanelPlan* plan) {
 
 namespace {
 
-// One cooperative launch; the panel must satisfy panel_plan.
 int panel_launch(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
-                      int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
-                      double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
+                 int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
+                 double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
+  return panel_launch_if(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
+                         work_bytes, status, nullptr);
+}
+
+}  // namespace
+
+// One cooperative launch; the panel must satisfy panel_plan.
+int panel_launch_if(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, double* W,
+                    int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
+                    double* zero, int64_t ldz, void* work, size_t work_bytes, int* status,
+                    const int* cond) {
   PanelPlan plan;
   if (!panel_plan(M, k, &plan))
     return set_error(RRF_E_NOTSUP, "householder panel: needs 1 <= k <= 256, M >= k and the panel "
@@ -461,6 +476,7 @@ int panel_launch(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp,
   a.red = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + flag_bytes(plan.G));
   a.flags = flags;
   a.status = status;
+  a.cond = cond;
   a.Gw = plan.G;
   a.rows_per = plan.rows_per;
   a.ldl = k + 1;
@@ -472,13 +488,15 @@ int panel_launch(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp,
   const double pflops = 2.0 * (double)M * k * k;
   RRF_TRY(fill_u32(st, flags, (int64_t)(plan.G + 1) * kFlagStride, 0u));
   void* args[] = {&a};
-  int tok = trace_begin(st, kTrPanel, pflops, pbytes);
+  int tok = cond ? trace_begin(st, kTrPanelFallback, 0.0, 0.0) : trace_begin(st, kTrPanel, pflops, pbytes);
   hipError_t e = hipLaunchCooperativeKernel((const void*)panel_kernel, dim3(plan.G + 1),
                                             dim3(kThreads), args, (unsigned)plan.lds, st);
   trace_end(st, tok);
   RRF_CHECK_HIP(e);
   return RRF_OK;
 }
+
+namespace {
 
 // Largest panel height one launch takes for k columns (0 if none).
 int64_t fit_rows(int k) {
@@ -509,7 +527,7 @@ bool tree_enabled() {
 
 size_t panel_work_bytes(int64_t Mmax, int k) {
   if (k < 1 || k > kMaxCols || Mmax < k) return 0;
-  // every path some M <= Mmax may take, in either mode
+  // every path some M <= Mmax may take, in any mode
   size_t need = tsqr_work_bytes(Mmax, k);
   const int64_t fit = k <= kLaunchCols ? fit_rows(k) : 0;
   if (fit >= k) {
@@ -523,6 +541,9 @@ size_t panel_work_bytes(int64_t Mmax, int k) {
     if (a == 0 || b == 0) return Mmax > fit ? 0 : need;
     need = std::max(need, (size_t)round_up((int64_t)std::max(a, b), 256) + split_temp_bytes(k1, k2));
   }
+  // CholeskyQR: its flag, then either its buffers or the fallback's workspace
+  const size_t cq = cholqr_work_bytes(Mmax, k);
+  if (cq) need = std::max(need + 256, cq);
   return need;
 }
 
@@ -536,11 +557,15 @@ int householder_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t
                       int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt, double* tau,
                       double* zero, int64_t ldz, void* work, size_t work_bytes, int* status) {
   const bool tree = tree_enabled();
+  PanelPlan plan;
+  if (!tree && cholqr_enabled() && cholqr_panel_ok(M, k, P, ldp, W, ldw) &&
+      panel_plan(M, k, &plan))
+    return cholqr_panel(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
+                        work_bytes, status);
   if (tree && tsqr_panel_ok(M, k))
     return tsqr_panel(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
                       work_bytes, status);
   const bool split_for_tree = tree && k > kTreeCols && tsqr_panel_ok(M - k / 2, k - k / 2);
-  PanelPlan plan;
   if (!split_for_tree && k <= kLaunchCols && panel_plan(M, k, &plan))
     return panel_launch(st, M, k, P, ldp, W, ldw, R, ldr, Tf, ldt, tau, zero, ldz, work,
                         work_bytes, status);

@@ -47,6 +47,7 @@ const char* kNames[kTraceClasses] = {
     "dgemm_grouped_128x64",  "dgemm_grouped_128x32",  "dgemm_grouped_128x16",
     "dgemm_grouped_128x128", "gemm_x3_128x128",       "gemm_x3_64x64",
     "gemm_x6_128x128",       "gemm_x6_64x64",         "householder_panel_tree",
+    "cholqr_cholesky_inverse", "cholqr_reconstruct",  "householder_panel_fallback",
 };
 
 hipEvent_t get_event() {

@@ -10,7 +10,7 @@ enum TraceClass {
   kTrGemm64NN, kTrGemm64TN, kTrGemm64NT, kTrGemm64TT,
   kTrSplitReduce, kTrPanel, kTrJacobi, kTrGaussian, kTrElementwise, kTrGemmBf16,
   kTrGemmGrouped, kTrGemmGrouped128x64, kTrGemmGrouped128x32, kTrGemmGrouped128x16,
-  kTrGemmGrouped128x128, kTrGemmX3, kTrGemmX3Small, kTrGemmX6, kTrGemmX6Small, kTrPanelTsqr, kTraceClasses
+  kTrGemmGrouped128x128, kTrGemmX3, kTrGemmX3Small, kTrGemmX6, kTrGemmX6Small, kTrPanelTsqr, kTrCholInv, kTrPanelRecon, kTrPanelFallback, kTraceClasses
 };
 
 bool trace_on();

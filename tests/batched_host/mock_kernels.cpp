@@ -25,6 +25,7 @@
 
 #include "batched.hpp"
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 
 #include <mutex>
@@ -177,6 +178,17 @@ int set_error(int status, const char* msg) {
 
 extern "C" const char* rrf_last_error(void) { return "mock"; }
 bool trace_on() { return false; }
+void trace_unmark_stream(hipStream_t) {}
+// The driver runs slices 1 and 2 on the context's side streams.
+int device_context(DeviceContext** out) {
+  static DeviceContext* c = nullptr;
+  if (!c) {
+    c = new DeviceContext();
+    for (auto& st : c->side) (void)hipStreamCreateWithFlags(&st, 0);
+  }
+  *out = c;
+  return RRF_OK;
+}
 int fill_u32(hipStream_t, unsigned* p, int64_t count, unsigned v) {
   for (int64_t i = 0; i < count; ++i) p[i] = v;
   return RRF_OK;

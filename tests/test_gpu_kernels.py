@@ -128,29 +128,36 @@ PANEL_CASES = [(5, 1), (64, 32), (1000, 7), (513, 32), (4096, 128), (16384, 128)
                (32768, 128), (3000, 256), (32768, 256), (40000, 256)]
 
 
-@pytest.mark.parametrize("tree", [True, False])
+@pytest.mark.parametrize("kernel", ["cholqr", "column", "tree"])
 @pytest.mark.parametrize("M,k", PANEL_CASES)
-def test_householder_panel_matches_lapack(gpu, M, k, tree):
-    print(f"case: panel M={M} k={k} tree={tree}", flush=True)
+def test_householder_panel_matches_lapack(gpu, M, k, kernel):
+    print(f"case: panel M={M} k={k} kernel={kernel}", flush=True)
     rng = np.random.default_rng(M + k)
     P = rng.standard_normal((M, k))
-    _check_panel_lapack(P, *_panel(P, gpu, tree))
+    _check_panel_lapack(P, *_panel(P, gpu, kernel))
 
 
-def _panel(P, gpu, tree=True):
-    """rrf_householder_panel, with the tree kernel (default) or the
-    column-by-column one (RRF_PANEL_TREE=0)."""
+def _panel(P, gpu, kernel="tree"):
+    """rrf_householder_panel with the kernel chosen through the environment:
+    "cholqr" (the default: CholeskyQR where it applies, else the column
+    kernel), "column" (RRF_PANEL_COLUMN=1) or "tree" (RRF_PANEL_TREE=1).
+    A bool picks the tree (True) or the column kernel (False)."""
     import os
     from paper_2106_13402_amd import householder_panel
-    old = os.environ.get("RRF_PANEL_TREE")
-    os.environ["RRF_PANEL_TREE"] = "1" if tree else "0"
+    if isinstance(kernel, bool):
+        kernel = "tree" if kernel else "column"
+    env = {"RRF_PANEL_TREE": "1" if kernel == "tree" else "0",
+           "RRF_PANEL_COLUMN": "1" if kernel == "column" else "0"}
+    old = {key: os.environ.get(key) for key in env}
+    os.environ.update(env)
     try:
         return tuple(_host(x) for x in householder_panel(_to_dev(P, gpu)))
     finally:
-        if old is None:
-            del os.environ["RRF_PANEL_TREE"]
-        else:
-            os.environ["RRF_PANEL_TREE"] = old
+        for key, v in old.items():
+            if v is None:
+                del os.environ[key]
+            else:
+                os.environ[key] = v
 
 
 def _check_panel_lapack(P, W, R, Tf, tau):
@@ -208,6 +215,82 @@ def test_panel_tree_graded(gpu):
     qr, tau_ref = hqr(P)
     np.testing.assert_allclose(np.abs(np.diag(R)), np.abs(np.diag(qr)[:k]), atol=1e-14 * 20)
     np.testing.assert_allclose(tau[:8], tau_ref[:8], atol=1e-9)
+
+
+@pytest.mark.parametrize("M,k", [(1024, 16), (4096, 128), (16384, 128), (5000, 100), (33000, 128)])
+def test_panel_cholqr_matches_column_kernel(gpu, M, k):
+    """CholeskyQR with reconstructed reflectors and the column kernel give the
+    same W, R, Tf and tau to rounding on well-conditioned panels."""
+    print(f"case: cholqr vs column panel M={M} k={k}", flush=True)
+    P = np.random.default_rng(M + 3 * k).standard_normal((M, k))
+    a, b = _panel(P, gpu, "cholqr"), _panel(P, gpu, "column")
+    for x, y, name in zip(a, b, ("W", "R", "Tf", "tau")):
+        np.testing.assert_allclose(x, y, atol=1e-12 * max(1.0, np.abs(y).max()), err_msg=name)
+
+
+@pytest.mark.parametrize("decades", [4, 7, 11])
+def test_panel_cholqr_conditioning(gpu, decades):
+    """Columns whose singular values span 4 to 11 decades (what the sketch of
+    a decaying spectrum looks like): CholeskyQR2 keeps orthogonality to
+    rounding up to about 8 decades (cond(P) = 1e8, u cond^2 ~ 1); beyond,
+    its first Cholesky factorization breaks down and the column kernel
+    takes the panel. Either way Q is orthogonal and Q R = P to rounding,
+    and the leading, well-determined reflectors match LAPACK's."""
+    print(f"case: cholqr panel, {decades} decades", flush=True)
+    M, k = 4000, 64
+    from synthetic import haar
+    P = (haar(M, k, seed=6, stream=1) @ np.diag(10.0 ** -np.linspace(0, decades, k))
+         @ haar(k, k, seed=6, stream=2).T)
+    W, R, Tf, tau = _panel(P, gpu, "cholqr")
+    Q = np.eye(M, k) - W @ (Tf @ W[:k, :].T)
+    assert np.linalg.norm(Q.T @ Q - np.eye(k), 2) < 1e-14 * 20
+    assert np.linalg.norm(Q @ R - P, 2) < 1e-15 * 20 * np.linalg.norm(P, 2)
+    qr, tau_ref = hqr(P)
+    np.testing.assert_allclose(np.abs(np.diag(R)), np.abs(np.diag(qr)[:k]),
+                               atol=1e-14 * 20 * np.abs(P).max())
+    np.testing.assert_allclose(tau[:8], tau_ref[:8], atol=1e-9)
+
+
+@pytest.mark.parametrize("case", ["zero", "dependent", "graded14", "nan_free_zero_panel"])
+def test_panel_cholqr_falls_back(gpu, case):
+    """Ill-conditioned or rank-deficient panels raise the device flag in a
+    Cholesky pass and the column kernel factors the untouched panel: the
+    result is bitwise the column kernel's."""
+    print(f"case: cholqr fallback {case}", flush=True)
+    rng = np.random.default_rng(11)
+    M, k = 2000, 32
+    P = rng.standard_normal((M, k))
+    if case == "zero":
+        P[:, 7] = 0.0
+    elif case == "dependent":
+        P[:, 20] = P[:, 3] * 3.0 - P[:, 9]
+    elif case == "graded14":
+        from synthetic import haar
+        P = (haar(M, k, seed=8, stream=1) @ np.diag(10.0 ** -np.linspace(0, 14, k))
+             @ haar(k, k, seed=8, stream=2).T)
+    else:
+        P[:] = 0.0
+    a, b = _panel(P, gpu, "cholqr"), _panel(P, gpu, "column")
+    for x, y, name in zip(a, b, ("W", "R", "Tf", "tau")):
+        assert np.array_equal(x, y), name
+
+
+def test_panel_cholqr_triangular_input(gpu):
+    """A panel that is already upper triangular ([R0; 0]): every sub-column
+    is exactly zero, where dlarfg takes H = I; the reconstruction returns the
+    reflection tau = 2, v = e_j with row j of R negated instead (the same
+    convention as the tree kernel). Q R = P and Q is orthogonal."""
+    print("case: cholqr panel, triangular input", flush=True)
+    M, k = 2048, 32
+    rng = np.random.default_rng(12)
+    P = np.zeros((M, k))
+    P[:k] = np.triu(rng.standard_normal((k, k))) + 4.0 * np.eye(k)
+    W, R, Tf, tau = _panel(P, gpu, "cholqr")
+    Q = np.eye(M, k) - W @ (Tf @ W[:k, :].T)
+    assert np.linalg.norm(Q.T @ Q - np.eye(k), 2) < 1e-14 * 20
+    np.testing.assert_allclose(Q @ R, P, atol=1e-13 * np.abs(P).max())
+    np.testing.assert_allclose(np.abs(np.diag(R)), np.abs(np.diag(P[:k])), rtol=1e-13)
+    assert np.all(np.abs(W[k:]) < 1e-13)
 
 
 @pytest.mark.parametrize("tree", [False, True])
