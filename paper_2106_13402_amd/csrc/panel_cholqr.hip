@@ -82,11 +82,23 @@ __device__ inline int flag_value(const int* f) {
   return __hip_atomic_load(const_cast<int*>(f), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Thread t holds rows 8 (t >> 5) .. +7 and columns 4 (t & 31) .. +3 of the
-// identity-padded 128 x 128 matrix.
+// The identity-padded 128 x 128 matrix in 8 x 4 tiles, one per thread:
+// wave w holds rows 64 (w >> 2) .. +63 and columns 32 (w & 3) .. +31, so
+// that whole waves skip the steps whose trailing region misses them.
 struct TileIx {
-  int ti, tj, r0, c0;
-  __device__ explicit TileIx(int t) : ti(t >> 5), tj(t & 31), r0((t >> 5) * 8), c0((t & 31) * 4) {}
+  int ti, tj, r0, c0;  // tile row and column; first row and column
+  int R0, R1, C0, C1;  // rows and columns of the wave
+  __device__ explicit TileIx(int t) {
+    const int w = t >> 6, lane = t & 63;
+    ti = 8 * (w >> 2) + (lane >> 3);
+    tj = 8 * (w & 3) + (lane & 7);
+    r0 = 8 * ti;
+    c0 = kTC * tj;
+    R0 = 64 * (w >> 2);
+    R1 = R0 + 63;
+    C0 = 32 * (w & 3);
+    C1 = C0 + 31;
+  }
 };
 
 template <int J>
@@ -157,21 +169,25 @@ __device__ void upper_inverse(double (&X)[8][kTC], const double* Ml, double* vb,
         }
       }
       __syncthreads();
-      // rows above the block (factor 0 for the others); a wave whose 16
-      // rows all lie at or below the block has nothing to do
-      if (16 * (threadIdx.x >> 6) >= j0) return;
+      // rows above the block (factor 0 for the others) in the columns from
+      // the block on (X is upper triangular); other waves have nothing to do
+      if (ix.R0 >= j0 || ix.C1 < j0) return;
       double y[4][kTC];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int c = 0; c < kTC; ++c) y[q][c] = rb[q * kCqMax + ix.c0 + c];
+      double uf[8][4];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) uf[i][q] = Ml[(ix.r0 + i) * kLdm + j0 + q];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const bool above = ix.ti < jt || (ix.ti == jt && i < RB);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double v = Ml[(ix.r0 + i) * kLdm + j0 + q];
-          const double f = above ? v : 0.0;
+          const double f = above ? uf[i][q] : 0.0;
 #pragma unroll
           for (int c = 0; c < kTC; ++c) X[i][c] = fma(-f, y[q][c], X[i][c]);
         }
@@ -209,42 +225,45 @@ __global__ __launch_bounds__(kCqThreads) void cholinv_kernel(CholArgs a) {
     return;
   }
 
-  // right-looking blocked Cholesky of the upper triangle. Step b: the half
-  // wave holding the block's rows factors the 4 x 4 diagonal block (passed
-  // between its lanes through LDS), forms the block's rows of R and
-  // publishes them; after the barrier every wave with rows below the block
-  // applies the rank-4 update, taking both factors from the published rows
-  // (A is symmetric, so R(B, r) is the factor of row r as well)
-  __shared__ double dblk[16];
+  // right-looking blocked Cholesky of the upper triangle, two barriers per
+  // 4 x 4 block. The block's rows (published in LDS by the step before) go
+  // to wave 0, which factors the diagonal block and forms the block's rows
+  // of R in every column from the block on; then every wave whose tiles meet
+  // the trailing upper triangle applies the rank-4 update (A is symmetric,
+  // so R(B, r) is also the factor of row r), the owners of the block's rows
+  // keep R, and the owners of the next block's rows publish them.
+  double* rb = vb;                 // the block's rows (4 x 128)
+  double* rr = vb + 4 * kCqMax;    // the block's rows of R (4 x 128)
   __shared__ int bad;
   if (t == 0) bad = 0;
+  if (ix.ti == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < kTC; ++c) rb[q * kCqMax + ix.c0 + c] = A[q][c];
+  }
   __syncthreads();
   bool failed = false;
   for (int jt = 0; jt <= (k - 1) >> 3 && !failed; ++jt) {
     each_half_up([&](auto jc) {
       constexpr int JB = decltype(jc)::value;
-      constexpr int RB = 4 * JB;
+      constexpr int RB = 4 * JB;           // the block's rows in tile row jt
+      constexpr int RN = 4 - RB;           // the next block's rows in its tile row
       const int b = 2 * jt + JB;
       const int j0 = 4 * b;
       if (failed || j0 >= k) return;
-      double* rr = vb + JB * 4 * kCqMax;
-      if (ix.ti == jt) {
-        if (ix.tj == b) {
-#pragma unroll
-          for (int p = 0; p < 4; ++p)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) dblk[p * 4 + q] = A[RB + p][q];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        double r[4][4], dinv[4];
+      if (t < 64) {
+        double r[4][4], dinv[4], blk[4][4];
         bool ok = true;
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = p; q < 4; ++q) blk[p][q] = rb[p * kCqMax + j0 + q];
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
 #pragma unroll
           for (int q = p; q < 4; ++q) {
-            double v = dblk[p * 4 + q];
+            double v = blk[p][q];
 #pragma unroll
             for (int m = 0; m < p; ++m) v = fma(-r[m][p], r[m][q], v);
             if (q == p) {
@@ -257,24 +276,33 @@ __global__ __launch_bounds__(kCqThreads) void cholinv_kernel(CholArgs a) {
             }
           }
         }
-        if (!ok && ix.tj == b) bad = 1;
-        // the block's rows of R in my columns
+        if (!ok && t == 0) bad = 1;
+        double col[2][4];
 #pragma unroll
-        for (int c = 0; c < kTC; ++c) {
-          double x[4];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            double v = A[RB + q][c];
+          for (int q = 0; q < 4; ++q) col[h][q] = rb[q * kCqMax + t + 64 * h];
 #pragma unroll
-            for (int m = 0; m < q; ++m) v = fma(-r[m][q], x[m], v);
-            x[q] = v * dinv[q];
+        for (int h = 0; h < 2; ++h) {
+          const int cc = t + 64 * h;
+          if (cc > j0 + 3) {
+            double x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              double v = col[h][q];
+#pragma unroll
+              for (int m = 0; m < q; ++m) v = fma(-r[m][q], x[m], v);
+              x[q] = v * dinv[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) rr[q * kCqMax + cc] = x[q];
           }
+        }
+        if (t == 0) {  // the diagonal block of R
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const double v = ix.tj > b ? x[q] : (ix.tj == b && c >= q ? r[q][c] : 0.0);
-            A[RB + q][c] = v;
-            rr[q * kCqMax + ix.c0 + c] = v;
-          }
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) rr[q * kCqMax + j0 + m] = (m >= q) ? r[q][m] : 0.0;
         }
       }
       __syncthreads();
@@ -282,27 +310,46 @@ __global__ __launch_bounds__(kCqThreads) void cholinv_kernel(CholArgs a) {
         failed = true;
         return;
       }
-      if (16 * (t >> 6) + 15 <= j0 + 3) return;  // no row of this wave below the block
-      double z[4][kTC];
-      const bool cols_right = ix.tj > b;
+      const bool update = ix.R1 > j0 + 3 && ix.C1 > j0 + 3 && ix.R0 <= ix.C1;
+      const bool keep = ix.R0 <= j0 && j0 <= ix.R1 && ix.C1 >= j0;
+      if (update || keep) {
+        double z[4][kTC];
+        const bool cols_right = ix.tj > b;
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int c = 0; c < kTC; ++c) {
-          const double v = rr[q * kCqMax + ix.c0 + c];
-          z[q][c] = cols_right ? v : 0.0;
+          for (int c = 0; c < kTC; ++c) {
+            const double v = rr[q * kCqMax + ix.c0 + c];
+            z[q][c] = cols_right ? v : 0.0;
+          }
+        if (update) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const bool below = ix.ti > jt || (ix.ti == jt && i >= RB + 4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double v = rr[q * kCqMax + ix.r0 + i];
+              const double wq = below ? v : 0.0;
+#pragma unroll
+              for (int c = 0; c < kTC; ++c) A[i][c] = fma(-wq, z[q][c], A[i][c]);
+            }
+          }
         }
+        if (ix.ti == jt && ix.tj >= b) {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const bool below = ix.ti > jt || (ix.ti == jt && i >= RB + 4);
+          for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double v = rr[q * kCqMax + ix.r0 + i];
-          const double wq = below ? v : 0.0;
+            for (int c = 0; c < kTC; ++c) A[RB + q][c] = rr[q * kCqMax + ix.c0 + c];
+        }
+        // the next block's rows
+        if (ix.ti == jt + (JB == 1 ? 1 : 0)) {
 #pragma unroll
-          for (int c = 0; c < kTC; ++c) A[i][c] = fma(-wq, z[q][c], A[i][c]);
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < kTC; ++c) rb[q * kCqMax + ix.c0 + c] = A[RN + q][c];
         }
       }
+      __syncthreads();
     });
   }
   if (failed) {
@@ -356,107 +403,163 @@ __global__ __launch_bounds__(kCqThreads) void recon_kernel(ReconArgs a) {
       A[i][c] = (r < k && cc < k) ? a.Q[r + cc * a.ldq] : (r == cc ? 1.0 : 0.0);
     }
 
-  // blocked LU without pivoting of Q1 - S: the sign s_j = -sign(a_jj) of
-  // the current diagonal entry is subtracted when step j is reached, so
-  // every pivot has magnitude >= 1
+  // blocked LU without pivoting of Q1 - S, two barriers per 4 x 4 block:
+  // the sign s_j = -sign(a_jj) of the current diagonal entry is subtracted
+  // when step j is reached, so every pivot has magnitude >= 1. The block's
+  // rows and columns (published in LDS by the step before) go to wave 0,
+  // which factors the diagonal block and forms the block's rows of U in
+  // every column right of it and the multipliers of every row below it;
+  // then the waves whose tiles meet the trailing block update, the owners of
+  // the block's columns and rows keep L and U, and the owners of the next
+  // block's rows and columns publish them.
+  double* rbk = vb;                 // the block's rows (4 x 128)
+  double* cbk = vb + 4 * kCqMax;    // the block's columns (4 x 128)
+  double* ur = vb + 8 * kCqMax;     // U(B, c), c right of the block
+  double* lc = vb + 12 * kCqMax;    // L(r, B), r below the block
+  __shared__ double dblk[16];
+  if (ix.ti == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < kTC; ++c) rbk[q * kCqMax + ix.c0 + c] = A[q][c];
+  }
+  if (ix.tj == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) cbk[q * kCqMax + ix.r0 + i] = A[i][q];
+  }
+  __syncthreads();
   for (int jt = 0; jt <= (k - 1) >> 3; ++jt) {
     each_half_up([&](auto jc) {
       constexpr int JB = decltype(jc)::value;
       constexpr int RB = 4 * JB;
+      constexpr int RN = 4 - RB;
       const int b = 2 * jt + JB;
       const int j0 = 4 * b;
       if (j0 >= k) return;
-      double* rb = vb + JB * 4 * kCqMax;
-      double* cbb = cb + JB * 4 * kCqMax;
-      if (ix.ti == jt) {
+      if (t < 64) {
+        double d[4][4], sgn[4], pinv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int c = 0; c < kTC; ++c) rb[q * kCqMax + ix.c0 + c] = A[RB + q][c];
-      }
-      if (ix.tj == b) {
+          for (int q = 0; q < 4; ++q) d[p][q] = rbk[p * kCqMax + j0 + q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int p = 0; p < 4; ++p) {
+          sgn[p] = d[p][p] >= 0.0 ? -1.0 : 1.0;
+          d[p][p] -= sgn[p];
+          pinv[p] = 1.0 / d[p][p];
 #pragma unroll
-          for (int i = 0; i < 8; ++i) cbb[q * kCqMax + ix.r0 + i] = A[i][q];
-      }
-      __syncthreads();
-      // a wave whose rows all lie above the block's end has nothing to do
-      if (16 * (t >> 6) + 15 < j0) return;
-      // LU of the diagonal block with the signs, the same in every thread
-      double d[4][4], s[4], pinv[4];
+          for (int m = p + 1; m < 4; ++m) {
+            d[m][p] *= pinv[p];
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) d[p][q] = rb[p * kCqMax + j0 + q];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        s[p] = d[p][p] >= 0.0 ? -1.0 : 1.0;
-        d[p][p] -= s[p];
-        pinv[p] = 1.0 / d[p][p];
-#pragma unroll
-        for (int m = p + 1; m < 4; ++m) {
-          d[m][p] *= pinv[p];
-#pragma unroll
-          for (int q = p + 1; q < 4; ++q) d[m][q] = fma(-d[m][p], d[p][q], d[m][q]);
+            for (int q = p + 1; q < 4; ++q) d[m][q] = fma(-d[m][p], d[p][q], d[m][q]);
+          }
         }
-      }
-      if (ix.ti == jt && ix.tj == b) {
+        if (t == 0) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) sg[j0 + p] = s[p];
-      }
-      // rows of U for my columns right of the block: L_BB^-1 A(B, c)
-      const bool cols_right = ix.tj > b;
-      const bool cols_in = ix.tj == b;
-      double u[4][kTC];
+          for (int p = 0; p < 4; ++p) {
+            sg[j0 + p] = sgn[p];
 #pragma unroll
-      for (int c = 0; c < kTC; ++c) {
-        double x[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double v = rb[q * kCqMax + ix.c0 + c];
-#pragma unroll
-          for (int m = 0; m < q; ++m) v = fma(-d[q][m], x[m], v);
-          x[q] = v;
+            for (int q = 0; q < 4; ++q) dblk[p * 4 + q] = d[p][q];
+          }
         }
+        double rowv[2][4], colv[2][4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) u[q][c] = cols_right ? x[q] : 0.0;
-      }
-      // multipliers of my rows below the block, l = A(r, B) U_BB^-1, and
-      // the trailing update; the block's columns keep the multipliers below
-      // it and the block's LU in it
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const bool below = ix.ti > jt || (ix.ti == jt && i >= RB + 4);
-        const bool in = ix.ti == jt && i >= RB && i < RB + 4;
-        double x[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double v = cbb[q * kCqMax + ix.r0 + i];
-#pragma unroll
-          for (int m = 0; m < q; ++m) v = fma(-x[m], d[m][q], v);
-          x[q] = v * pinv[q];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double lq = below ? x[q] : 0.0;
-#pragma unroll
-          for (int c = 0; c < kTC; ++c) A[i][c] = fma(-lq, u[q][c], A[i][c]);
-        }
-        if (cols_in) {
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const double blk = d[(i - RB) & 3][q];
-            A[i][q] = below ? x[q] : (in ? blk : A[i][q]);
+            rowv[h][q] = rbk[q * kCqMax + t + 64 * h];
+            colv[h][q] = cbk[q * kCqMax + t + 64 * h];
+          }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int cc = t + 64 * h;
+          if (cc > j0 + 3) {
+            // U(B, cc) = L_BB^-1 A(B, cc)
+            double x[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              double v = rowv[h][q];
+#pragma unroll
+              for (int m = 0; m < q; ++m) v = fma(-d[q][m], x[m], v);
+              x[q] = v;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) ur[q * kCqMax + cc] = x[q];
+            // L(cc, B) = A(cc, B) U_BB^-1 for the row cc below the block
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              double v = colv[h][q];
+#pragma unroll
+              for (int m = 0; m < q; ++m) v = fma(-x[m], d[m][q], v);
+              x[q] = v * pinv[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lc[q * kCqMax + cc] = x[q];
           }
         }
       }
-      if (ix.ti == jt && cols_right) {
+      __syncthreads();
+      const bool update = ix.R1 > j0 + 3 && ix.C1 > j0 + 3;
+      const bool cols_own = ix.C0 <= j0 && j0 <= ix.C1 && ix.R1 >= j0;
+      const bool rows_own = ix.R0 <= j0 && j0 <= ix.R1 && ix.C1 > j0 + 3;
+      if (update || cols_own || rows_own) {
+        const bool cols_right = ix.tj > b;
+        double u[4][kTC];
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-          for (int c = 0; c < kTC; ++c) A[RB + q][c] = u[q][c];
+          for (int c = 0; c < kTC; ++c) {
+            const double v = ur[q * kCqMax + ix.c0 + c];
+            u[q][c] = cols_right ? v : 0.0;
+          }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const bool below = ix.ti > jt || (ix.ti == jt && i >= RB + 4);
+          const bool in = ix.ti == jt && i >= RB && i < RB + 4;
+          double l[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double v = lc[q * kCqMax + ix.r0 + i];
+            l[q] = below ? v : 0.0;
+          }
+          if (update) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+              for (int c = 0; c < kTC; ++c) A[i][c] = fma(-l[q], u[q][c], A[i][c]);
+          }
+          if (ix.tj == b) {
+            // the block's columns: multipliers below it, its LU in it
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const double blk = dblk[((i - RB) & 3) * 4 + q];
+              A[i][q] = below ? l[q] : (in ? blk : A[i][q]);
+            }
+          }
+        }
+        if (ix.ti == jt && cols_right) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < kTC; ++c) A[RB + q][c] = u[q][c];
+        }
+        // the next block's rows and columns
+        if (ix.ti == jt + (JB == 1 ? 1 : 0)) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int c = 0; c < kTC; ++c) rbk[q * kCqMax + ix.c0 + c] = A[RN + q][c];
+        }
+        if (ix.tj == b + 1) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cbk[q * kCqMax + ix.r0 + i] = A[i][q];
+        }
       }
+      __syncthreads();
     });
   }
 
@@ -522,19 +625,25 @@ __global__ __launch_bounds__(kCqThreads) void recon_kernel(ReconArgs a) {
         }
       }
       __syncthreads();
-      if (16 * (t >> 6) + 15 <= j0 + 3) return;  // no row of this wave below the block
+      // rows below the block in the columns up to its end (Y is lower
+      // triangular); other waves have nothing to do
+      if (ix.R1 <= j0 + 3 || ix.C0 > j0 + 3) return;
       double y[4][kTC];
 #pragma unroll
       for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int c = 0; c < kTC; ++c) y[q][c] = rb[q * kCqMax + ix.c0 + c];
+      double lf[8][4];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lf[i][q] = Ml[(ix.r0 + i) * kLdm + j0 + q];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const bool below = ix.ti > jt || (ix.ti == jt && i >= RB + 4);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double v = Ml[(ix.r0 + i) * kLdm + j0 + q];
-          const double f = below ? v : 0.0;
+          const double f = below ? lf[i][q] : 0.0;
 #pragma unroll
           for (int c = 0; c < kTC; ++c) X[i][c] = fma(-f, y[q][c], X[i][c]);
         }
