@@ -48,13 +48,13 @@ PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 # They describe the GEMM sources whose concatenation has this SHA-256 prefix.
 TRAFFIC_SOURCES = ("paper_2106_13402_amd/csrc/gemm_f64.hip",
                    "paper_2106_13402_amd/csrc/gemm_tile.hpp")
-TRAFFIC_SHA256_16 = "7b00cc8f3a0396a2"
+TRAFFIC_SHA256_16 = "ecd0d9b2ecc041be"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "dgemm_mfma_128x128_NN": 608540129,
-    "dgemm_mfma_128x128_TN": 595867251,
-    "dgemm_mfma_128x128_NT": 758557710,
-    "dgemm_mfma_128x128_NN:UV": 426821442,
-    "dgemm_mfma_128x128_TN:UV": 857670391,
+    "dgemm_mfma_128x128_NN": 608569199,
+    "dgemm_mfma_128x128_TN": 595920261,
+    "dgemm_mfma_128x128_NT": 759931359,
+    "dgemm_mfma_128x128_NN:UV": 426668034,
+    "dgemm_mfma_128x128_TN:UV": 857692318,
 }
 
 # Matrix-core counters of the same classes on the same sources
@@ -62,11 +62,11 @@ TRAFFIC_BYTES_PER_LAUNCH = {
 # from SQ_INSTS_VALU_MFMA_MOPS_F64 over the dispatch time, as a fraction of
 # peak, and SQ_VALU_MFMA_BUSY_CYCLES over the active cycles of all SIMDs.
 MFMA_COUNTERS = {
-    "dgemm_mfma_128x128_TN": (0.631, 0.658),
-    "dgemm_mfma_128x128_NN": (0.668, 0.692),
-    "dgemm_mfma_128x128_NT": (0.587, 0.620),
-    "dgemm_mfma_128x128_NN:UV": (0.575, 0.581),
-    "dgemm_mfma_128x128_TN:UV": (0.565, 0.592),
+    "dgemm_mfma_128x128_TN": (0.572, 0.627),
+    "dgemm_mfma_128x128_NN": (0.635, 0.693),
+    "dgemm_mfma_128x128_NT": (0.566, 0.625),
+    "dgemm_mfma_128x128_NN:UV": (0.558, 0.581),
+    "dgemm_mfma_128x128_TN:UV": (0.553, 0.591),
 }
 
 

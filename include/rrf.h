@@ -485,14 +485,22 @@ int rrf_dgemm(int transa, int transb, int64_t M, int64_t N, int64_t K, double al
  * triangular, ld ldr; may be NULL), Tf (k x k upper triangular, ld ldt), tau
  * (k). `work` must hold rrf_panel_workspace_size(M, k) bytes (enough for
  * either kernel below).
- * Kernel: one grid-wide exchange per column by default; with
- * RRF_PANEL_TREE=1 in the environment (read at each call), panels of k <= 64
- * and M <= 65536 (wider ones split into such halves) go through a tree of
- * QRs over 256-row blocks with the reflectors recovered from its Q. Both give
- * the dlarfg reflectors to rounding, except that the tree kernel returns
+ * Kernels: panels of 16 <= k <= 128 and M >= 1024 with W not overlapping P
+ * take CholeskyQR2 (two passes of Gram matrix, Cholesky factor and its
+ * inverse) and recover the reflectors from Q by an LU of Q(0:k, :) - S,
+ * each sign chosen at its pivot; if a Cholesky pivot fails (the panel is
+ * ill conditioned or rank deficient, or not finite) the column-exchange
+ * kernel factors the panel instead, on the device. Other panels, and all
+ * panels with RRF_PANEL_COLUMN=1 in the environment, use the
+ * column-exchange kernel (one grid-wide exchange per column); with
+ * RRF_PANEL_TREE=1, panels of k <= 64 and M <= 65536 (wider ones split into
+ * such halves) go through a tree of QRs over 256-row blocks with the
+ * reflectors recovered from its Q. All give the dlarfg reflectors to
+ * rounding on full-rank panels, except that the recovered reflectors are
  * tau = 2, v = e_j (and row j of R negated) where dlarfg gives H = I for an
- * exactly zero sub-column, and after an exact rank drop its later
- * reflectors are another exact choice. */
+ * exactly zero sub-column, and after an exact rank drop the tree's later
+ * reflectors are another exact choice. Environment variables are read at
+ * each call. */
 size_t rrf_panel_workspace_size(int64_t M, int64_t k);
 int rrf_householder_panel(int64_t M, int64_t k, double* P, int64_t ldp, double* W,
                           int64_t ldw, double* R, int64_t ldr, double* Tf, int64_t ldt,
