@@ -52,11 +52,15 @@ constexpr int kCholMinCols = 16;
 // about 1e7) that the second no longer restores it to rounding, and the
 // panel goes to the column kernel instead.
 constexpr double kPass2Tol = 0.25;
+// Largest |G2 - I| entry for which the second pass takes the first-order
+// factors instead of the Cholesky factorization (see cholinv_kernel).
+constexpr double kPass2Near = 1e-11;
 
 struct CholArgs {
   int k;
   const double* G;    // k x k, ld k
   double tol;         // smallest accepted pivot
+  double near;        // > 0: when every |G - I| entry is at most this, first-order factors
   double* R;          // k x k upper triangular factor, ld k
   double* Ri;         // its inverse, ld k
   int* flag;
@@ -205,6 +209,29 @@ __global__ __launch_bounds__(kCqThreads) void cholinv_kernel(CholArgs a) {
   const int t = threadIdx.x;
   const TileIx ix(t);
   const int k = a.k;
+  if (a.near > 0.0) {
+    // G = I + E with every |E_ij| <= near (the second pass of a well
+    // conditioned panel): R = I + F, F the upper triangle of E with its
+    // diagonal halved, satisfies R^T R = G + F^T F, and I - F is R^-1 up to
+    // F^2; with near = 1e-11 and k <= 128 both residuals are below 2e-18,
+    // under the rounding of the exact factorization. (NaN compares false
+    // and takes the factorization below, which reports it.)
+    bool near = true;
+    for (int e = t; e < k * k; e += kCqThreads) {
+      const int r = e % k, cc = e / k;
+      near = near && fabs(a.G[e] - (r == cc ? 1.0 : 0.0)) <= a.near;
+    }
+    if (__syncthreads_and(near)) {
+      for (int e = t; e < k * k; e += kCqThreads) {
+        const int r = e % k, cc = e / k;
+        const double g = a.G[e];
+        const double f = cc > r ? g : (cc == r ? 0.5 * (g - 1.0) : 0.0);
+        a.R[e] = (r == cc ? 1.0 : 0.0) + f;
+        a.Ri[e] = (r == cc ? 1.0 : 0.0) - f;
+      }
+      return;
+    }
+  }
 
   double A[8][kTC];
   bool finite = true;
@@ -224,7 +251,6 @@ __global__ __launch_bounds__(kCqThreads) void cholinv_kernel(CholArgs a) {
     if (t == 0) *a.flag = 1;
     return;
   }
-
   // right-looking blocked Cholesky of the upper triangle, two barriers per
   // 4 x 4 block. The block's rows (published in LDS by the step before) go
   // to wave 0, which factors the diagonal block and forms the block's rows
@@ -729,9 +755,9 @@ CqLayout cq_layout(void* work, int64_t M, int k) {
   return L;
 }
 
-int launch_cholinv(hipStream_t st, int k, const double* G, double tol, double* R, double* Ri,
-                   int* flag) {
-  CholArgs a{k, G, tol, R, Ri, flag};
+int launch_cholinv(hipStream_t st, int k, const double* G, double tol, double near, double* R,
+                   double* Ri, int* flag) {
+  CholArgs a{k, G, tol, near, R, Ri, flag};
   int tok = trace_begin(st, kTrCholInv, (2.0 / 3.0) * k * (double)k * k, 8.0 * 3.0 * k * k);
   hipLaunchKernelGGL(cholinv_kernel, dim3(1), dim3(kCqThreads), kCqLds, st, a);
   trace_end(st, tok);
@@ -780,13 +806,13 @@ int cholqr_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp,
   // pass 1: P -> W
   RRF_TRY(dgemm_shaped(st, true, false, k, k, M, 1.0, P, ldp, P, ldp, 0.0, L.G, k, L.part,
                        L.part_elems, true, gs));
-  RRF_TRY(launch_cholinv(st, k, L.G, 0.0, L.Ra, L.Ri, L.flag));
+  RRF_TRY(launch_cholinv(st, k, L.G, 0.0, 0.0, L.Ra, L.Ri, L.flag));
   RRF_TRY(dgemm_shaped(st, false, false, M, k, k, 1.0, P, ldp, L.Ri, k, 0.0, W, ldw, nullptr,
                        0, true, 1));
   // pass 2: W -> S1, the orthonormal factor
   RRF_TRY(dgemm_shaped(st, true, false, k, k, M, 1.0, W, ldw, W, ldw, 0.0, L.G, k, L.part,
                        L.part_elems, true, gs));
-  RRF_TRY(launch_cholinv(st, k, L.G, kPass2Tol, L.Rc, L.Ri, L.flag));
+  RRF_TRY(launch_cholinv(st, k, L.G, kPass2Tol, kPass2Near, L.Rc, L.Ri, L.flag));
   RRF_TRY(dgemm_shaped(st, false, false, M, k, k, 1.0, W, ldw, L.Ri, k, 0.0, L.S1, M, nullptr,
                        0, true, 1));
   if (want_r)
