@@ -14,13 +14,17 @@
 //
 // so that I - W Tf W^T has Q's columns (times S) as its first k columns and
 // the reflectors follow the dlarfg sign rule. The tall products run on the
-// FP64 matrix cores (dgemm_shaped); the k x k steps run in one workgroup each,
-// every thread holding an 8 x 4 tile of the (identity-padded) 128 x 128
-// matrix in registers, one barrier per column.
+// FP64 matrix cores (dgemm_shaped); the k x k steps run in one 512-thread
+// workgroup each, every thread holding an 8 x 4 tile of the
+// (identity-padded) 128 x 128 matrix in registers, over 4 x 4 blocks with
+// one or two barriers per block. When the first pass leaves the second
+// pass's Gram matrix within 1e-11 of I, that pass takes first-order factors
+// instead of factorizing.
 //
 // When a pass meets a Cholesky pivot at or below its threshold (the panel is
-// ill conditioned or rank deficient, or holds a NaN or an infinity) a device flag is
-// raised, the later small kernels return at once, and the column-exchange
+// ill conditioned or rank deficient, or holds a NaN or an infinity) a device
+// flag is raised, the later small kernels return at once, and the
+// column-exchange
 // kernel, launched conditionally after them, factors the untouched panel; it
 // returns at once when the flag is clear. The panel P is therefore never
 // written before that launch: W must not overlap P, and the in-place clear
@@ -39,8 +43,8 @@ namespace rrf {
 namespace {
 
 constexpr int kCqThreads = 512;
-constexpr int kTC = 4;  // columns of a thread's tile (8 rows x 4 columns)
-constexpr int kCqMax = 128;   // columns
+constexpr int kTC = 4;       // columns of a thread's tile (8 rows x 4 columns)
+constexpr int kCqMax = 128;  // columns
 constexpr int kLdm = kCqMax + 1;
 constexpr size_t kCqLds = ((size_t)kCqMax * kLdm + 16 * kCqMax) * sizeof(double);
 constexpr int kGramMaxSplits = 64;
@@ -60,7 +64,7 @@ struct CholArgs {
   int k;
   const double* G;    // k x k, ld k
   double tol;         // smallest accepted pivot
-  double near;        // > 0: when every |G - I| entry is at most this, first-order factors
+  double near;        // > 0: first-order factors when every |G - I| entry is at most this
   double* R;          // k x k upper triangular factor, ld k
   double* Ri;         // its inverse, ld k
   int* flag;
@@ -124,10 +128,13 @@ __device__ __forceinline__ void each_half_down(F&& f) {
 
 // The algorithms below run over 4 x 4 blocks: block b covers rows and
 // columns 4b .. 4b+3, which are rows 4*JB .. 4*JB+3 of tile row b / 2
-// (JB = b & 1) and the whole of tile column b. One barrier per block: the
-// rows (and columns) of block b are published in LDS, every thread takes
-// the 4 x 4 diagonal block from there and factors or inverts it itself,
-// then updates its own tile.
+// (JB = b & 1) and the whole of tile column b. In the Cholesky and LU
+// factorizations wave 0 factors the diagonal block and publishes the
+// block's rows (and columns) of the factors in LDS, then the waves that
+// meet the trailing region update their tiles (two barriers per block); in
+// the triangular inverse and solve the threads holding the block's rows
+// transform them with the diagonal block and publish them, then the waves
+// concerned update (one barrier per block).
 
 // X = U^-1 for U upper triangular in LDS (row stride kLdm): X starts as I;
 // from the last block up, X(B, :) <- U_BB^-1 X(B, :) by the rows of block B,
@@ -411,8 +418,8 @@ __global__ __launch_bounds__(kCqThreads) void cholinv_kernel(CholArgs a) {
 __global__ __launch_bounds__(kCqThreads) void recon_kernel(ReconArgs a) {
   extern __shared__ double lds[];
   double* Ml = lds;
-  double* vb = lds + kCqMax * kLdm;  // row blocks (2 x 4 x 128)
-  double* cb = vb + 8 * kCqMax;      // column blocks (2 x 4 x 128)
+  double* vb = lds + kCqMax * kLdm;  // 16 x 128 exchange rows after the matrix
+  double* cb = vb + 8 * kCqMax;      // its second half
   __shared__ double sg[kCqMax];
   if (flag_value(a.flag) != 0) return;
   const int t = threadIdx.x;
@@ -626,7 +633,7 @@ __global__ __launch_bounds__(kCqThreads) void recon_kernel(ReconArgs a) {
       constexpr int RB = 4 * JB;
       const int j0 = 8 * jt + RB;
       if (j0 >= k) return;
-      double* rb = cb + JB * 4 * kCqMax;  // the column blocks are free now
+      double* rb = cb + JB * 4 * kCqMax;  // free once the LU is done
       if (ix.ti == jt) {
         double lb[4][4];
 #pragma unroll
