@@ -217,10 +217,12 @@ def test_panel_tree_graded(gpu):
     np.testing.assert_allclose(tau[:8], tau_ref[:8], atol=1e-9)
 
 
-@pytest.mark.parametrize("M,k", [(1024, 16), (4096, 128), (16384, 128), (5000, 100), (33000, 128)])
+@pytest.mark.parametrize("M,k", [(1024, 16), (4096, 128), (16384, 128), (5000, 100), (33000, 128),
+                                 (2048, 33), (3000, 97), (1500, 50)])
 def test_panel_cholqr_matches_column_kernel(gpu, M, k):
     """CholeskyQR with reconstructed reflectors and the column kernel give the
-    same W, R, Tf and tau to rounding on well-conditioned panels."""
+    same W, R, Tf and tau to rounding on well-conditioned panels (k not a
+    multiple of 4 leaves the last 4 x 4 block partly padding)."""
     print(f"case: cholqr vs column panel M={M} k={k}", flush=True)
     P = np.random.default_rng(M + 3 * k).standard_normal((M, k))
     a, b = _panel(P, gpu, "cholqr"), _panel(P, gpu, "column")
