@@ -21,7 +21,7 @@ randUTV, the RSVD, the 32768 x 8192 sharp-gap workload in the four precision
 modes ("gap") and the batched call on 4096 small matrices (n ~ U{64..512},
 m ~ U{n..2n}, graded spectrum, q = 1, automatic b) in matrices per second.
 The full object (kernel tables, e_k arrays, per-mode details) is written to
-`--full-json` (default gpurun_out/bench_full.json).
+the file `--full-json` names (none by default).
 
     python bench.py [--steps K] [--warmup W] [--n N] [--b B] [--q Q]
 """
@@ -290,7 +290,7 @@ def powerurv_leg(A, U, T, V, s, kgrid, b, q, args, dev, fp64_acc):
 
 # ------------------------------------------------------------- batched leg
 def gap_leg(args, dev):
-    """The rectangular sharp-gap workload (SURVEY C4): m = 32768, n = 8192,
+    """The rectangular sharp-gap workload: m = 32768, n = 8192,
     A = Q1 diag(s) Q2^T + 1e-12 N(0,1) with s_j = 1 for j <= 1000 and 1e-10
     after, b = 256, q = 2, U and V formed, in FP64, with the bfloat16 sketch
     and with the x3 updates. e_k on k = 900, 904, ..., 1100. Below the gap
@@ -674,9 +674,9 @@ def main() -> int:
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the boosted, early-stop and RSVD legs")
     ap.add_argument("--batch", type=int, default=4096, help="matrices in the batched leg")
-    ap.add_argument("--full-json", default=os.path.join("gpurun_out", "bench_full.json"),
+    ap.add_argument("--full-json", default="",
                     help="file for the full results (kernel tables, e_k arrays); "
-                         "empty to skip")
+                         "none when empty")
     ap.add_argument("--batch-q", type=int, default=1)
     args = ap.parse_args()
 

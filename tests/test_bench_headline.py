@@ -59,7 +59,7 @@ def _full_object():
     out["batched"] = {"value": 15601.5, "unit": "matrices/s", "ms_per_call": 262.5,
                       "model_tflops": 11.28, "residual_fro_rel": {"max": 6.6e-15},
                       "kernels": _kernels(), "cpu_baseline": {"value": 2.38}}
-    out["full_results"] = "gpurun_out/bench_full.json"
+    out["full_results"] = "results/bench_full.json"
     return out
 
 
