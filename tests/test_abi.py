@@ -104,6 +104,29 @@ def test_workspace_size(lib):
     assert f(_lib.RRF_ALG_POWERURV, n, n, 128, 2, _lib.RRF_PREC_BF16_X3) == 0
 
 
+def test_panel_workspace_size(lib):
+    """rrf_panel_workspace_size(M, k) covers every panel height up to M, so it
+    never shrinks as M grows (also across the 1024 rows from which panels of
+    16 to 128 columns take CholeskyQR2); from there on it holds the CholeskyQR
+    buffers: the status and flag words, the M x k orthonormal factor and six
+    k x k matrices. Unsupported shapes give 0."""
+    f = lib.rrf_panel_workspace_size
+    for k in (1, 16, 33, 64, 100, 128, 200, 256):
+        prev = 0
+        for M in (k, 300, 1000, 1023, 1024, 1025, 2048, 4096, 16384, 32768, 40000):
+            if M < k:
+                continue
+            w = f(M, k)
+            assert w > 0, (M, k)
+            assert w >= prev, (M, k, w, prev)
+            prev = w
+            if 16 <= k <= 128 and M >= 1024:
+                assert w >= 256 + 256 + 8 * M * k + 6 * 8 * k * k, (M, k, w)
+    assert f(100, 101) == 0       # M < k
+    assert f(4096, 257) == 0      # k > 256
+    assert f(4096, 0) == 0
+
+
 def test_component_argument_errors(lib):
     assert lib.rrf_dgemm(2, 0, 1, 1, 1, 1.0, DUMMY, 1, DUMMY, 1, 0.0, DUMMY, 1, NULL, 0, NULL) == -1
     assert lib.rrf_dgemm(0, 0, 4, 4, 4, 1.0, DUMMY, 3, DUMMY, 4, 0.0, DUMMY, 4, NULL, 0, NULL) == -8
