@@ -416,7 +416,10 @@ int rrf_batched_autotune(int precision, int32_t q, int64_t count, const int64_t*
                          const rrf_opts* opts);
 /* Replace the loaded tuning tables by those of the cache file `path` (NULL:
  * unload them, so b = 0 follows the built-in rule). -1 when the file cannot
- * be read or is not a valid cache. Without any call the library loads
+ * be read or is not a valid cache (the format the autotuner writes; every
+ * integer field a whole number in range, every bucket 1 <= nmin <= nmax with
+ * 1 <= b <= 64, tile_mask within the tile set and 0 <= leaf <= 64): a
+ * rejected file leaves the loaded tables as they were. Without any call the library loads
  * $RRF_TUNE_CACHE (empty: none), else tuning/batched.json beside librrf.so,
  * on its first lookup. */
 int rrf_batched_tune_load(const char* path);

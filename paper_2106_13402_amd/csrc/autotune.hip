@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <cctype>
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -184,6 +185,24 @@ bool num_field(const Json& o, const char* k, double* out) {
   return true;
 }
 
+// Integer field `k` of `o`. Absent: *out keeps its value and the result is
+// !required. Present: it must be a whole number in [lo, hi] (|lo|, |hi| at
+// most 2^53, so both are exact doubles); NaN, infinities, fractions and
+// values out of range fail, and the conversion is always defined.
+bool int_field(const Json& o, const char* k, int64_t lo, int64_t hi, bool required,
+               int64_t* out) {
+  const Json* v = o.get(k);
+  if (!v) return !required;
+  if (v->kind != Json::kNum) return false;
+  const double d = v->num;
+  if (!std::isfinite(d) || d != std::floor(d) || d < (double)lo || d > (double)hi) return false;
+  *out = (int64_t)d;
+  return true;
+}
+
+constexpr int64_t kIntLo = INT32_MIN, kIntHi = INT32_MAX;
+constexpr int64_t kWhole = int64_t(1) << 53;
+
 bool cfg_valid(const BatchedCfg& c) {
   return c.b >= 1 && c.b <= 64 && (c.tile_mask & ~kTileMaskAll) == 0 && c.leaf >= 0 && c.leaf <= 64;
 }
@@ -204,27 +223,29 @@ bool parse_tables(const std::string& text, std::vector<Table>* out) {
     if (t.kind != Json::kObj) return false;
     Table tb;
     const Json* arch = t.get("arch");
-    double prec = 0, q = 1, count = 0;
-    if (!arch || arch->kind != Json::kStr || !num_field(t, "precision", &prec)) return false;
-    num_field(t, "q", &q);
-    num_field(t, "count", &count);
+    int64_t prec = 0, q = 1, count = 0;
+    if (!arch || arch->kind != Json::kStr || !int_field(t, "precision", kIntLo, kIntHi, true, &prec) ||
+        !int_field(t, "q", kIntLo, kIntHi, false, &q) ||
+        !int_field(t, "count", -kWhole, kWhole, false, &count))
+      return false;
     tb.arch = arch->str;
     tb.precision = (int)prec;
     tb.q = (int)q;
-    tb.count = (int64_t)count;
+    tb.count = count;
     const Json* bs = t.get("buckets");
     if (!bs || bs->kind != Json::kArr) return false;
     for (const auto& bj : bs->arr) {
-      double nmin, nmax, b, mask = kTileMaskAll, leaf = 0, ms = 0, cand = 0;
-      if (bj.kind != Json::kObj || !num_field(bj, "nmin", &nmin) || !num_field(bj, "nmax", &nmax) ||
-          !num_field(bj, "b", &b))
+      int64_t nmin = 0, nmax = 0, b = 0, mask = kTileMaskAll, leaf = 0, cand = 0;
+      double ms = 0;
+      if (bj.kind != Json::kObj || !int_field(bj, "nmin", -kWhole, kWhole, true, &nmin) ||
+          !int_field(bj, "nmax", -kWhole, kWhole, true, &nmax) ||
+          !int_field(bj, "b", -kWhole, kWhole, true, &b) ||
+          !int_field(bj, "tile_mask", kIntLo, kIntHi, false, &mask) ||
+          !int_field(bj, "leaf", kIntLo, kIntHi, false, &leaf) ||
+          !int_field(bj, "candidates", kIntLo, kIntHi, false, &cand))
         return false;
-      num_field(bj, "tile_mask", &mask);
-      num_field(bj, "leaf", &leaf);
       num_field(bj, "ms", &ms);
-      num_field(bj, "candidates", &cand);
-      Bucket bk{(int64_t)nmin, (int64_t)nmax, BatchedCfg{(int64_t)b, (int)mask, (int)leaf}, ms,
-                (int)cand};
+      Bucket bk{nmin, nmax, BatchedCfg{b, (int)mask, (int)leaf}, ms, (int)cand};
       if (bk.nmin < 1 || bk.nmax < bk.nmin || !cfg_valid(bk.cfg)) return false;
       tb.buckets.push_back(bk);
     }

@@ -45,6 +45,13 @@ def test_valid_cache_loads(tmp_path):
                                                  "buckets": [{"nmin": 1, "nmax": 4, "b": 16,
                                                               "tile_mask": 64}]}]},
     '{"format": "rrf-batched-tune-1", "tables": []} trailing',
+    # integer fields must hold whole numbers in range (no undefined casts)
+    json.dumps(GOOD).replace('"nmin": 65', '"nmin": 1e300'),
+    json.dumps(GOOD).replace('"b": 32', '"b": nan'),
+    json.dumps(GOOD).replace('"leaf": 16', '"leaf": -inf'),
+    json.dumps(GOOD).replace('"b": 32', '"b": 32.5'),
+    json.dumps(GOOD).replace('"precision": 0', '"precision": 1e20'),
+    json.dumps(GOOD).replace('"candidates": 18', '"candidates": 4294967296'),
 ])
 def test_malformed_cache_rejected(tmp_path, bad):
     with pytest.raises(rrf.RRFError) as e:
