@@ -7,6 +7,8 @@
 // a replay into the same buffers after they were overwritten with NaN (A
 // restored for an in-place call), and a replay into newly allocated outputs
 // (the descriptors rebuilt and uploaded); the last results are written.
+// At the end the driver's resources are released and every allocation the
+// harness made is freed, so a leak checker sees only what the driver lost.
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -18,6 +20,7 @@
 extern "C" long mock_errors();
 extern "C" long mock_graph_launches();
 extern "C" void* mock_malloc(size_t);
+extern "C" void mock_free(void*);
 
 static void poison(double* p, size_t count) {
   for (size_t i = 0; i < count; ++i) p[i] = NAN;
@@ -38,22 +41,27 @@ int main(int argc, char** argv) {
   std::vector<std::vector<double>> Ahost(count);
   std::vector<double*> U(count), T(count), V(count);
   std::vector<uint64_t> seeds(count);
+  std::vector<void*> owned;
+  auto alloc = [&](size_t bytes) {
+    owned.push_back(mock_malloc(bytes));
+    return (double*)owned.back();
+  };
   for (int64_t j = 0; j < count; ++j) {
     int64_t s[3];
     if (fread(s, 8, 3, f) != 3) return 2;
     m[j] = s[0]; n[j] = s[1]; lda[j] = s[2];
-    double* a = (double*)mock_malloc(8 * lda[j] * n[j]);
+    double* a = alloc(8 * lda[j] * n[j]);
     if (fread(a, 8, lda[j] * n[j], f) != (size_t)(lda[j] * n[j])) return 2;
     Ahost[j].assign(a, a + lda[j] * n[j]);
     A[j] = a;
-    T[j] = inplace ? a : (double*)mock_malloc(8 * m[j] * n[j]);
-    U[j] = wu ? (double*)mock_malloc(8 * m[j] * m[j]) : nullptr;
-    V[j] = wv ? (double*)mock_malloc(8 * n[j] * n[j]) : nullptr;
+    T[j] = inplace ? a : alloc(8 * m[j] * n[j]);
+    U[j] = wu ? alloc(8 * m[j] * m[j]) : nullptr;
+    V[j] = wv ? alloc(8 * n[j] * n[j]) : nullptr;
     seeds[j] = seed + j;
   }
   fclose(f);
   size_t ws = rrf::randutv_batched_workspace(count, m.data(), n.data(), b, precision);
-  void* w = mock_malloc(ws);
+  void* w = alloc(ws);
   ((int*)w)[0] = 0; ((int*)w)[1] = 0;
   auto call = [&]() {
     const rrf::BatchedCfg cfg{b, rrf::kTileMaskAll, leaf};
@@ -74,15 +82,15 @@ int main(int argc, char** argv) {
   if (graph && rc == 0) {
     for (int64_t j = 0; j < count; ++j) {
       if (inplace) {
-        double* a = (double*)mock_malloc(8 * lda[j] * n[j]);
+        double* a = alloc(8 * lda[j] * n[j]);
         memcpy(a, Ahost[j].data(), 8 * lda[j] * n[j]);
         A[j] = a;
         T[j] = a;
       } else {
-        T[j] = (double*)mock_malloc(8 * m[j] * n[j]);
+        T[j] = alloc(8 * m[j] * n[j]);
       }
-      if (wu) U[j] = (double*)mock_malloc(8 * m[j] * m[j]);
-      if (wv) V[j] = (double*)mock_malloc(8 * n[j] * n[j]);
+      if (wu) U[j] = alloc(8 * m[j] * m[j]);
+      if (wv) V[j] = alloc(8 * n[j] * n[j]);
     }
     rc = call();
   }
@@ -95,5 +103,8 @@ int main(int argc, char** argv) {
     if (wv) fwrite(V[j], 8, n[j] * n[j], o);
   }
   fclose(o);
-  return rc;
+  const int rel = rrf::randutv_batched_release();
+  for (void* p : owned) mock_free(p);
+  if (rel != 0) printf("release rc=%d\n", rel);
+  return rc != 0 ? rc : rel;
 }
