@@ -167,16 +167,18 @@ const char* hipGetErrorString(hipError_t) { return "mock"; }
 
 namespace rrf {
 
-int set_hip_error(hipError_t, const char* what, const char* file, int line) {
+// The error helpers are weak: a build that links the library's own
+// (api.hip) takes those.
+__attribute__((weak)) int set_hip_error(hipError_t, const char* what, const char* file, int line) {
   fprintf(stderr, "hip error %s %s:%d\n", what, file, line);
   return RRF_E_HIP;
 }
-int set_error(int status, const char* msg) {
+__attribute__((weak)) int set_error(int status, const char* msg) {
   fprintf(stderr, "error %d: %s\n", status, msg);
   return status;
 }
 
-extern "C" const char* rrf_last_error(void) { return "mock"; }
+extern "C" __attribute__((weak)) const char* rrf_last_error(void) { return "mock"; }
 bool trace_on() { return false; }
 void trace_unmark_stream(hipStream_t) {}
 // The driver runs slices 1 and 2 on the context's side streams.

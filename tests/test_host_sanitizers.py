@@ -9,6 +9,10 @@ float-cast-overflow) and LeakSanitizer, built with the host compiler; no GPU.
   unsanitized there), each held to the
   oracle as there, with the driver's resources released at the end so that
   anything it loses shows as a leak.
+* The autotuner's search through the library's C ABI (api.hip, autotune.hip
+  and the driver against the test double; tests/batched_host/
+  tune_search_host.cpp): on a caller's workload of tall and wide matrices
+  and on the synthetic buckets, then the cache it writes read back.
 * The tuning-cache reader (autotune.hip) through rrf_batched_tune_load and
   rrf_batched_config (tests/batched_host/tune_host.cpp): a valid cache, the
   malformed ones, numbers that no integer field can hold (1e300, nan, inf,
@@ -62,16 +66,22 @@ def objects(tmp_path_factory):
         pytest.skip("the host compiler's sanitizer runtimes are not available")
     flags = ["-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", f"-I{hip_inc}",
              f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", "-Wno-attributes", *SAN]
+    # api.hip's allocation-free entry point declares a device array; on the
+    # host it is an ordinary array and its symbol address the array's own
+    api_flags = ["-D__align__(x)=alignas(x)", "-DHIP_SYMBOL(x)=((const void*)&(x))"]
     objs = {}
     for name, src in (("driver", os.path.join(CSRC, "randutv_batched.hip")),
                       ("autotune", os.path.join(CSRC, "autotune.hip")),
+                      ("api", os.path.join(CSRC, "api.hip")),
                       ("mock", os.path.join(HOST, "mock_kernels.cpp")),
                       ("harness", os.path.join(HOST, "harness.cpp")),
-                      ("tune_host", os.path.join(HOST, "tune_host.cpp"))):
+                      ("tune_host", os.path.join(HOST, "tune_host.cpp")),
+                      ("tune_search", os.path.join(HOST, "tune_search_host.cpp"))):
         cpp = out / f"{name}.cpp"
         shutil.copyfile(src, cpp)
         obj = str(out / f"{name}.o")
-        subprocess.run([gxx, *flags, "-c", str(cpp), "-o", obj], check=True)
+        subprocess.run([gxx, *flags, *(api_flags if name == "api" else []), "-c", str(cpp),
+                        "-o", obj], check=True)
         objs[name] = obj
 
     def link(exe, names, libs=()):
@@ -82,6 +92,8 @@ def objects(tmp_path_factory):
 
     return {"planner": link("planner", ["driver", "mock", "harness"]),
             "tune": link("tune", ["autotune", "driver", "mock", "tune_host"], ["-ldl"]),
+            "search": link("search", ["api", "autotune", "driver", "mock", "tune_search"],
+                           ["-ldl"]),
             "out": out}
 
 
@@ -220,3 +232,38 @@ def test_tune_cache_mutations_sanitized(objects):
                 b, mask, leaf, _ = map(int, s[2:].split(","))
                 assert 1 <= b <= 64 and 0 <= mask < 32 and 0 <= leaf <= 64, (paths[k - 1], s)
     assert sum(rc == -1 for rc, _ in res[1:]) > len(muts) // 2
+
+
+def _search(objects, cache, mode, count, hi):
+    r = subprocess.run([objects["search"], cache, mode, str(count), str(hi)], capture_output=True,
+                       text=True, timeout=600, env={**os.environ, **ENV, "RRF_TUNE_CACHE": ""})
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    lines = r.stdout.splitlines()
+    _, rc, errors = lines[0].split()
+    return int(rc), int(errors), {ln.split()[0]: ln.split()[1:] for ln in lines[1:]}, lines
+
+
+# lookups are printed for n = 1..8 and 64
+LOOKUP_N = [1, 2, 3, 4, 5, 6, 7, 8, 64]
+
+
+@pytest.mark.parametrize("mode,count,hi", [("workload", 200, 6), ("buckets", 64, 6)])
+def test_tune_search_sanitized(objects, mode, count, hi):
+    cache = str(objects["out"] / f"search_{mode}.json")
+    rc, errors, look, lines = _search(objects, cache, mode, count, hi)
+    assert rc == 0 and errors == 0, lines
+    assert look["loaded"] == look["tuned"]  # the written cache reads back the same
+    assert all(s.endswith(",0") for s in look["builtin"])
+    # the workload's matrices (n <= 6) all fall in the bucket 1-64, which is
+    # tuned; the synthetic buckets stop at nmax = 6
+    tuned = [s.endswith(",1") for s in look["tuned"]]
+    assert tuned == [n <= (64 if mode == "workload" else hi) for n in LOOKUP_N], look["tuned"]
+    with open(cache) as f:
+        tabs = json.load(f)["tables"]
+    assert [t["arch"] for t in tabs] == ["gfx950"] and tabs[0]["count"] == count
+    assert tabs[0]["buckets"][0]["nmin"] == 1
+
+
+def test_tune_search_workload_limit_sanitized(objects):
+    rc, errors, _, lines = _search(objects, str(objects["out"] / "limit.json"), "workload", 300, 4)
+    assert rc == 3 and errors == 0, lines  # RRF_E_NOTSUP: at most 256 matrices
