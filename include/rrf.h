@@ -48,6 +48,10 @@ extern "C" {
 #define RRF_E_NOTSUP    3  /* valid request outside what is implemented        */
 #define RRF_E_NUMERIC   4  /* non-finite input (only with check_finite)         */
 #define RRF_E_INTERNAL  5  /* a device-side consistency check failed           */
+/* Fault injection for tests of callers' error paths, read at every call:
+ * RRF_TEST_FAIL=hip in the environment fails every entry point's device
+ * check (RRF_E_HIP); RRF_TEST_FAIL=alloc fails the device allocation of the
+ * library-managed workspace (RRF_E_NOMEM), leaving no workspace cached. */
 
 /* ---- precision modes -------------------------------------------------- */
 #define RRF_PREC_FP64   0  /* every step in binary64                           */

@@ -2,6 +2,7 @@
 // management, status read-back, and the exported building blocks.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -42,9 +43,18 @@ int set_error(int status, const char* msg) {
 
 namespace {
 
+// Fault injection for tests of the error paths, read at every call:
+// RRF_TEST_FAIL=hip fails the device check, RRF_TEST_FAIL=alloc the device
+// allocation of the library-managed workspace; each then takes the path a
+// real failure takes.
+bool fail_injected(const char* what) {
+  const char* v = getenv("RRF_TEST_FAIL");
+  return v != nullptr && strcmp(v, what) == 0;
+}
+
 int device_ready(int* dev) {
   int count = 0;
-  hipError_t e = hipGetDeviceCount(&count);
+  hipError_t e = fail_injected("hip") ? hipErrorNoDevice : hipGetDeviceCount(&count);
   if (e != hipSuccess || count < 1) return set_error(RRF_E_HIP, "no HIP device available");
   RRF_CHECK_HIP(hipGetDevice(dev));
   return RRF_OK;
@@ -78,7 +88,7 @@ int cached_workspace(int dev, size_t bytes, void** out) {
       c.ptr = nullptr;
       c.bytes = 0;
     }
-    hipError_t e = hipMalloc(&c.ptr, bytes);
+    hipError_t e = fail_injected("alloc") ? hipErrorOutOfMemory : hipMalloc(&c.ptr, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       c.ptr = nullptr;

@@ -1,18 +1,25 @@
-// Host harness of the batched autotuner's search (autotune.hip) through the
-// library's own C ABI (api.hip: argument checks, workspace sizing, grouping
-// by configuration and orientation), built with the host compiler and linked
-// with the batched driver and its test double (mock_kernels.cpp). HIP events
-// report made-up but deterministic times, so the search runs its whole
-// course (install a candidate, record, replay, time, keep the fastest) with
-// no device. Entry points the batched path never reaches are stubs that fail.
+// Host harness of the library's own C ABI (api.hip: argument checks,
+// workspace management, grouping by configuration and orientation) for the
+// batched call and its autotuner (autotune.hip), built with the host compiler
+// and linked with the batched driver and its test double (mock_kernels.cpp).
+// HIP events report made-up but deterministic times, so the autotuner's
+// search runs its whole course (install a candidate, record, replay, time,
+// keep the fastest) with no device. Entry points the batched path never
+// reaches are stubs that fail.
 //
-//   tune_search_host <cache> workload <count> <nhi>   tune on `count` matrices
-//                                                     with n in [1, nhi]
-//   tune_search_host <cache> buckets <count> <nmax>   tune the synthetic buckets
+//   api_host <cache> workload <count> <nhi>   tune on `count` matrices with n
+//                                             in [1, nhi] (m in [n/2, 2n])
+//   api_host <cache> buckets <count> <nmax>   tune the synthetic buckets
+//   api_host - batched <count> <nhi>          rrf_randutv_batched on such a
+//                                             batch with the library-managed
+//                                             workspace, under the caller's
+//                                             environment, then again with
+//                                             RRF_TEST_FAIL unset
 //
-// Output: "autotune <rc> <mock errors>", then the configurations for
-// n = 1..8 and 64 as tuned, after an unload (the built-in rule), and after
-// loading the cache the search wrote.
+// Output of the tuning modes: "autotune <rc> <mock errors>", then the
+// configurations for n = 1..8 and 64 as tuned, after an unload (the built-in
+// rule), and after loading the cache the search wrote. Of the batched mode:
+// "batched <rc> <mock errors>" for each call.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -128,6 +135,7 @@ int main(int argc, char** argv) {
   if (argc != 5) return 2;
   const char* cache = argv[1];
   const bool workload = strcmp(argv[2], "workload") == 0;
+  const bool batched = strcmp(argv[2], "batched") == 0;
   const int64_t count = atoll(argv[3]), hi = atoll(argv[4]);
   std::vector<int64_t> m(count), n(count);
   uint64_t x = 12345;
@@ -137,6 +145,28 @@ int main(int argc, char** argv) {
     x = x * 6364136223846793005ull + 1442695040888963407ull;
     const int64_t lo = n[j] / 2 > 0 ? n[j] / 2 : 1;
     m[j] = lo + (int64_t)((x >> 33) % (uint64_t)(2 * n[j] - lo + 1));
+  }
+  if (batched) {
+    std::vector<double*> A(count), T(count), U(count), V(count);
+    std::vector<const double*> Ac(count);
+    for (int64_t j = 0; j < count; ++j) {
+      void* p = nullptr;
+      (void)hipMalloc(&p, 8 * (size_t)(m[j] * n[j] + 2 * m[j] * n[j] + m[j] * m[j] + n[j] * n[j]));
+      A[j] = static_cast<double*>(p);
+      T[j] = A[j] + m[j] * n[j];
+      U[j] = T[j] + m[j] * n[j];
+      V[j] = U[j] + m[j] * m[j];
+      Ac[j] = A[j];
+      (void)rrf::gaussian(nullptr, 7, (uint64_t)j, m[j], n[j], A[j], m[j]);
+    }
+    for (int call = 0; call < 2; ++call) {
+      if (call == 1) unsetenv("RRF_TEST_FAIL");
+      const int rc = rrf_randutv_batched(count, m.data(), n.data(), Ac.data(), m.data(), 0, 1, 7,
+                                         U.data(), T.data(), V.data(), nullptr);
+      printf("batched %d %ld\n", rc, mock_errors());
+    }
+    for (int64_t j = 0; j < count; ++j) (void)hipFree(A[j]);
+    return rrf_release_workspace() == 0 ? 0 : 3;
   }
   const int rc = workload ? rrf_batched_autotune(RRF_PREC_FP64, 1, count, m.data(), n.data(),
                                                  1024, 7, cache, nullptr)

@@ -11,8 +11,10 @@ float-cast-overflow) and LeakSanitizer, built with the host compiler; no GPU.
   anything it loses shows as a leak.
 * The autotuner's search through the library's C ABI (api.hip, autotune.hip
   and the driver against the test double; tests/batched_host/
-  tune_search_host.cpp): on a caller's workload of tall and wide matrices
-  and on the synthetic buckets, then the cache it writes read back.
+  api_host.cpp): on a caller's workload of tall and wide matrices and on
+  the synthetic buckets, then the cache it writes read back; and the
+  batched call through the same ABI with the library-managed workspace,
+  with allocation and device failures injected by RRF_TEST_FAIL.
 * The tuning-cache reader (autotune.hip) through rrf_batched_tune_load and
   rrf_batched_config (tests/batched_host/tune_host.cpp): a valid cache, the
   malformed ones, numbers that no integer field can hold (1e300, nan, inf,
@@ -76,7 +78,7 @@ def objects(tmp_path_factory):
                       ("mock", os.path.join(HOST, "mock_kernels.cpp")),
                       ("harness", os.path.join(HOST, "harness.cpp")),
                       ("tune_host", os.path.join(HOST, "tune_host.cpp")),
-                      ("tune_search", os.path.join(HOST, "tune_search_host.cpp"))):
+                      ("api_host", os.path.join(HOST, "api_host.cpp"))):
         cpp = out / f"{name}.cpp"
         shutil.copyfile(src, cpp)
         obj = str(out / f"{name}.o")
@@ -92,7 +94,7 @@ def objects(tmp_path_factory):
 
     return {"planner": link("planner", ["driver", "mock", "harness"]),
             "tune": link("tune", ["autotune", "driver", "mock", "tune_host"], ["-ldl"]),
-            "search": link("search", ["api", "autotune", "driver", "mock", "tune_search"],
+            "api": link("api_host", ["api", "autotune", "driver", "mock", "api_host"],
                            ["-ldl"]),
             "out": out}
 
@@ -235,7 +237,7 @@ def test_tune_cache_mutations_sanitized(objects):
 
 
 def _search(objects, cache, mode, count, hi):
-    r = subprocess.run([objects["search"], cache, mode, str(count), str(hi)], capture_output=True,
+    r = subprocess.run([objects["api"], cache, mode, str(count), str(hi)], capture_output=True,
                        text=True, timeout=600, env={**os.environ, **ENV, "RRF_TUNE_CACHE": ""})
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     lines = r.stdout.splitlines()
@@ -267,3 +269,14 @@ def test_tune_search_sanitized(objects, mode, count, hi):
 def test_tune_search_workload_limit_sanitized(objects):
     rc, errors, _, lines = _search(objects, str(objects["out"] / "limit.json"), "workload", 300, 4)
     assert rc == 3 and errors == 0, lines  # RRF_E_NOTSUP: at most 256 matrices
+
+
+@pytest.mark.parametrize("inject,status", [("", 0), ("alloc", 2), ("hip", 1)])
+def test_batched_abi_fault_injection_sanitized(objects, inject, status):
+    # RRF_E_NOMEM / RRF_E_HIP from the injected failure; the next call, with
+    # the variable unset, allocates the workspace and runs
+    r = subprocess.run([objects["api"], "-", "batched", "40", "9"], capture_output=True,
+                       text=True, timeout=600,
+                       env={**os.environ, **ENV, "RRF_TUNE_CACHE": "", "RRF_TEST_FAIL": inject})
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    assert r.stdout.split() == ["batched", str(status), "0", "batched", "0", "0"], r.stdout
