@@ -26,4 +26,10 @@ struct DeviceContext {
 
 int device_context(DeviceContext** out);
 
+// Lets `kernel` launch with up to `bytes` of dynamic LDS on the current
+// device. hipFuncSetAttribute acts on the current device only, so the
+// attribute is set once per (kernel, device), and again when a later call
+// asks for more; callable from several host threads at once.
+int allow_dynamic_lds(const void* kernel, size_t bytes);
+
 }  // namespace rrf

@@ -30,6 +30,7 @@
 #include <cfloat>
 
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
 
@@ -407,19 +408,11 @@ __global__ __launch_bounds__(64) void jacobi_small_kernel(SvdArgs a) {
   finish_block<64>(k, Aw, Vw, ld, sig, perm, coef, pick, Usb, Vsb, db);
 }
 
-bool g_attr_set = false;
-bool g_small_attr_set = false;
-
 // LDS of the one-wave kernel for blocks up to k.
 size_t small_lds(int k) { return (size_t)2 * k * (k + 1) * 8; }
 
 int launch_small(hipStream_t st, const SvdArgs& a, int kmax) {
-  if (!g_small_attr_set) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_small_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)small_lds(kSmallK)));
-    g_small_attr_set = true;
-  }
+  RRF_TRY(allow_dynamic_lds((const void*)jacobi_small_kernel, small_lds(kSmallK)));
   int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * kmax * kmax * a.count);
   hipLaunchKernelGGL(jacobi_small_kernel, dim3(a.count), dim3(64), small_lds(kmax), st, a);
   trace_end(st, tok);
@@ -435,12 +428,7 @@ int launch_large(hipStream_t st, SvdArgs& a, int kmax, void* work, size_t work_b
   if (a.use_lds < 2 && (work == nullptr || work_bytes < both * a.count))
     return set_error(RRF_E_NOMEM, "block svd: workspace too small");
   a.gA = a.use_lds == 2 ? nullptr : reinterpret_cast<double*>(work);
-  if (!g_attr_set) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)jacobi_svd_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)kLdsBudget));
-    g_attr_set = true;
-  }
+  RRF_TRY(allow_dynamic_lds((const void*)jacobi_svd_kernel, kLdsBudget));
   const size_t lds = a.use_lds == 2 ? both : (a.use_lds == 1 ? one : 0);
   int tok = trace_begin(st, kTrJacobi, 0.0, 8.0 * 3.0 * kmax * kmax * a.count);
   hipLaunchKernelGGL(jacobi_svd_kernel, dim3(a.count), dim3(kThreads), lds, st, a);

@@ -35,6 +35,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
 
@@ -715,16 +716,9 @@ __global__ __launch_bounds__(256) void zero_if_ok_kernel(int64_t rows, int64_t c
     Z[r + c * ldz] = 0.0;
 }
 
-bool g_attr_set = false;
-
 int set_attrs() {
-  if (g_attr_set) return RRF_OK;
-  RRF_CHECK_HIP(hipFuncSetAttribute((const void*)cholinv_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCqLds));
-  RRF_CHECK_HIP(hipFuncSetAttribute((const void*)recon_kernel,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCqLds));
-  g_attr_set = true;
-  return RRF_OK;
+  RRF_TRY(allow_dynamic_lds((const void*)cholinv_kernel, kCqLds));
+  return allow_dynamic_lds((const void*)recon_kernel, kCqLds);
 }
 
 int gram_splits(int64_t M) { return (int)std::min<int64_t>(kGramMaxSplits, std::max<int64_t>(1, M / 256)); }

@@ -41,6 +41,7 @@
 #include <cstdlib>
 
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
 
@@ -407,8 +408,6 @@ __global__ __launch_bounds__(kThreads) void panel_kernel(PanelArgs a) {
   }
 }
 
-bool g_attr_set = false;
-
 size_t flag_bytes(int Gw) { return (size_t)round_up((int64_t)(Gw + 1) * kFlagStride * 4, 256); }
 int slot_doubles(int k) { return (int)round_up((int64_t)3 * k, 32); }
 
@@ -452,12 +451,7 @@ int panel_launch_if(hipStream_t st, int64_t M, int k, const double* P, int64_t l
                                    "within the LDS of 255 workgroups");
   if (work_bytes < plan.work || work == nullptr)
     return set_error(RRF_E_NOMEM, "householder panel: workspace too small");
-  if (!g_attr_set) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)panel_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)kLdsBudget));
-    g_attr_set = true;
-  }
+  RRF_TRY(allow_dynamic_lds((const void*)panel_kernel, kLdsBudget));
   unsigned* flags = reinterpret_cast<unsigned*>(work);
   PanelArgs a{};
   a.M = M;

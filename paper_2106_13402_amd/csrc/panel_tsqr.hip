@@ -37,6 +37,7 @@
 #include <algorithm>
 
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
 
@@ -709,8 +710,6 @@ __global__ __launch_bounds__(kThreads) void tsqr_kernel(Args a) {
   }
 }
 
-bool g_attr_set = false;
-
 size_t flags_bytes(int G) { return (size_t)round_up((int64_t)(2 * G + 1) * kFlagStride * 4, 256); }
 int tree_levels(int G) {
   int L = 0;
@@ -744,12 +743,7 @@ int tsqr_panel(hipStream_t st, int64_t M, int k, const double* P, int64_t ldp, d
   const size_t need = tsqr_work_bytes(M, k);
   if (work == nullptr || work_bytes < need)
     return set_error(RRF_E_NOMEM, "tree panel: workspace too small");
-  if (!g_attr_set) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)tsqr_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)kLdsBytes));
-    g_attr_set = true;
-  }
+  RRF_TRY(allow_dynamic_lds((const void*)tsqr_kernel, kLdsBytes));
   const int G = (int)ceil_div(M, kLeaf);
   Args a{};
   a.M = M;

@@ -28,6 +28,7 @@
 
 #include "batched.hpp"
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
 
@@ -561,8 +562,6 @@ __global__ __launch_bounds__(256) void round_columns_batched_kernel(
     d.out16[i + n * d.ld16] = (i < d.M) ? bf16_from_f32(c[i] * s) : (uint16_t)0;
 }
 
-bool g_col_attr = false;
-
 }  // namespace
 
 int maxabs(hipStream_t st, int64_t rows, int64_t cols, const double* X, int64_t ld,
@@ -675,12 +674,7 @@ int gemm_bf16_tn(hipStream_t st, int64_t M, int64_t N, int64_t K, const uint16_t
                      dim3(kThreads), 0, st, g);
   trace_end(st, tok);
   RRF_CHECK_HIP(hipGetLastError());
-  if (!g_col_attr) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)reduce_columns_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)(kColLds * sizeof(float))));
-    g_col_attr = true;
-  }
+  RRF_TRY(allow_dynamic_lds((const void*)reduce_columns_kernel, kColLds * sizeof(float)));
   const size_t lds = M <= kColLds ? (size_t)M * sizeof(float) : 0;
   tok = trace_begin(st, kTrSplitReduce, (double)splits * M * N,
                     4.0 * splits * M * N + (out64 ? 8.0 : 2.0) * M * N);

@@ -27,6 +27,7 @@
 #include <cfloat>
 
 #include "common.hpp"
+#include "context.hpp"
 #include "kernels.hpp"
 #include "trace.hpp"
 
@@ -258,8 +259,6 @@ __global__ __launch_bounds__(256) void copy_square_kernel(int k, const double* B
   }
 }
 
-bool g_attr_set = false;
-
 }  // namespace
 
 size_t left_svd_work_bytes(int k) {
@@ -276,12 +275,7 @@ int left_svd(hipStream_t st, int k, const double* B, int64_t ldb, double* U, dou
   unsigned* rot = reinterpret_cast<unsigned*>(reinterpret_cast<char*>(work) +
                                               round_up((int64_t)k * k * 8, 256));
   const size_t lds = (size_t)2 * kCB * k * sizeof(double);
-  if (!g_attr_set) {
-    RRF_CHECK_HIP(hipFuncSetAttribute((const void*)block_round_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)(2 * kCB * kMaxK * sizeof(double))));
-    g_attr_set = true;
-  }
+  RRF_TRY(allow_dynamic_lds((const void*)block_round_kernel, 2 * kCB * kMaxK * sizeof(double)));
   int tok = trace_begin(st, kTrJacobi, 0.0, 0.0);
   RRF_TRY(fill_u32(st, rot, kMaxOuter, 0u));
   hipLaunchKernelGGL(copy_square_kernel, dim3((unsigned)ceil_div((int64_t)k * k, 256)), dim3(256),

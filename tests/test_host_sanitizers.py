@@ -23,6 +23,13 @@ float-cast-overflow) and LeakSanitizer, built with the host compiler; no GPU.
   returns 0 or -1, a rejected file leaves the lookups as they were, and no
   sanitizer fires.
 
+Under ThreadSanitizer (a build of its own): the batched driver's direct
+mode with four slices, whose rounds run on four host threads; and
+allow_dynamic_lds (context.hip, tests/batched_host/context_host.cpp), which
+the kernels' launchers call from those threads, hammered from eight threads
+on three devices: the attribute is set once per (kernel, device), raised
+for a larger request, and a failed request changes nothing.
+
 Each source is copied to a .cpp file first, so the compiler line names no
 HIP source; device code is not built.
 """
@@ -46,57 +53,87 @@ ENV = {"ASAN_OPTIONS": "detect_leaks=1:halt_on_error=1",
        "UBSAN_OPTIONS": "print_stacktrace=1:halt_on_error=1"}
 
 
-def _sanitizers_work(gxx, out):
+TSAN = ["-fsanitize=thread", "-fno-omit-frame-pointer"]
+TSAN_ENV = {"TSAN_OPTIONS": "halt_on_error=1"}
+
+
+def _sanitizers_work(gxx, out, san=SAN, env=ENV):
     src = out / "probe.cpp"
-    src.write_text("#include <vector>\nint main(){std::vector<int> v(3);return v[1];}\n")
+    src.write_text("#include <thread>\n#include <vector>\nint main(){std::vector<int> v(3);"
+                   "std::thread t([&]{v[0]=1;});t.join();return v[1];}\n")
     exe = str(out / "probe")
     try:
-        subprocess.run([gxx, *SAN, str(src), "-o", exe], check=True, capture_output=True)
-        return subprocess.run([exe], env={**os.environ, **ENV}).returncode == 0
+        subprocess.run([gxx, *san, str(src), "-o", exe, "-pthread"], check=True,
+                       capture_output=True)
+        return subprocess.run([exe], env={**os.environ, **env}).returncode == 0
     except (subprocess.CalledProcessError, OSError):
         return False
 
 
-@pytest.fixture(scope="module")
-def objects(tmp_path_factory):
-    gxx = shutil.which("g++")
+def _build(gxx, out, san, sources, links):
     hip_inc = "/opt/rocm/include"
-    if not gxx or not os.path.isdir(hip_inc):
-        pytest.skip("needs g++ and the HIP headers")
-    out = tmp_path_factory.mktemp("sanitized")
-    if not _sanitizers_work(gxx, out):
-        pytest.skip("the host compiler's sanitizer runtimes are not available")
     flags = ["-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", f"-I{hip_inc}",
-             f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", "-Wno-attributes", *SAN]
+             f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}", "-Wno-attributes", *san]
     # api.hip's allocation-free entry point declares a device array; on the
     # host it is an ordinary array and its symbol address the array's own
     api_flags = ["-D__align__(x)=alignas(x)", "-DHIP_SYMBOL(x)=((const void*)&(x))"]
     objs = {}
-    for name, src in (("driver", os.path.join(CSRC, "randutv_batched.hip")),
-                      ("autotune", os.path.join(CSRC, "autotune.hip")),
-                      ("api", os.path.join(CSRC, "api.hip")),
-                      ("mock", os.path.join(HOST, "mock_kernels.cpp")),
-                      ("harness", os.path.join(HOST, "harness.cpp")),
-                      ("tune_host", os.path.join(HOST, "tune_host.cpp")),
-                      ("api_host", os.path.join(HOST, "api_host.cpp"))):
+    for name, src in sources:
         cpp = out / f"{name}.cpp"
         shutil.copyfile(src, cpp)
         obj = str(out / f"{name}.o")
         subprocess.run([gxx, *flags, *(api_flags if name == "api" else []), "-c", str(cpp),
                         "-o", obj], check=True)
         objs[name] = obj
-
-    def link(exe, names, libs=()):
+    exes = {}
+    for exe, names, libs in links:
         path = str(out / exe)
-        subprocess.run([gxx, *SAN, *[objs[n] for n in names], "-o", path, "-pthread", *libs],
+        subprocess.run([gxx, *san, *[objs[n] for n in names], "-o", path, "-pthread", *libs],
                        check=True)
-        return path
+        exes[exe] = path
+    return exes
 
-    return {"planner": link("planner", ["driver", "mock", "harness"]),
-            "tune": link("tune", ["autotune", "driver", "mock", "tune_host"], ["-ldl"]),
-            "api": link("api_host", ["api", "autotune", "driver", "mock", "api_host"],
-                           ["-ldl"]),
+
+@pytest.fixture(scope="module")
+def objects(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if not gxx or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("needs g++ and the HIP headers")
+    out = tmp_path_factory.mktemp("sanitized")
+    if not _sanitizers_work(gxx, out):
+        pytest.skip("the host compiler's sanitizer runtimes are not available")
+    exes = _build(gxx, out, SAN,
+                  [("driver", os.path.join(CSRC, "randutv_batched.hip")),
+                   ("autotune", os.path.join(CSRC, "autotune.hip")),
+                   ("api", os.path.join(CSRC, "api.hip")),
+                   ("mock", os.path.join(HOST, "mock_kernels.cpp")),
+                   ("harness", os.path.join(HOST, "harness.cpp")),
+                   ("tune_host", os.path.join(HOST, "tune_host.cpp")),
+                   ("api_host", os.path.join(HOST, "api_host.cpp"))],
+                  [("planner", ["driver", "mock", "harness"], []),
+                   ("tune", ["autotune", "driver", "mock", "tune_host"], ["-ldl"]),
+                   ("api_host", ["api", "autotune", "driver", "mock", "api_host"], ["-ldl"])])
+    return {"planner": exes["planner"], "tune": exes["tune"], "api": exes["api_host"],
             "out": out}
+
+
+@pytest.fixture(scope="module")
+def tsan_objects(tmp_path_factory):
+    gxx = shutil.which("g++")
+    if not gxx or not os.path.isdir("/opt/rocm/include"):
+        pytest.skip("needs g++ and the HIP headers")
+    out = tmp_path_factory.mktemp("tsan")
+    if not _sanitizers_work(gxx, out, TSAN, TSAN_ENV):
+        pytest.skip("the host compiler's thread sanitizer runtime is not available")
+    exes = _build(gxx, out, TSAN,
+                  [("driver", os.path.join(CSRC, "randutv_batched.hip")),
+                   ("mock", os.path.join(HOST, "mock_kernels.cpp")),
+                   ("harness", os.path.join(HOST, "harness.cpp")),
+                   ("context", os.path.join(CSRC, "context.hip")),
+                   ("context_host", os.path.join(HOST, "context_host.cpp"))],
+                  [("planner", ["driver", "mock", "harness"], []),
+                   ("context_host", ["context", "context_host"], [])])
+    return {**exes, "out": out}
 
 
 @pytest.fixture
@@ -280,3 +317,31 @@ def test_batched_abi_fault_injection_sanitized(objects, inject, status):
                        env={**os.environ, **ENV, "RRF_TUNE_CACHE": "", "RRF_TEST_FAIL": inject})
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert r.stdout.split() == ["batched", str(status), "0", "batched", "0", "0"], r.stdout
+
+
+def test_planner_threads_tsan(tsan_objects, monkeypatch):
+    # 1100 matrices: four slices, the direct mode runs each on a host thread
+    for k, v in TSAN_ENV.items():
+        monkeypatch.setenv(k, v)
+    rng = np.random.default_rng(11)
+    ns = rng.integers(1, 7, size=1100)
+    shapes = [(int(rng.integers(n, 2 * n + 1)), int(n)) for n in ns]
+    planner._run((tsan_objects["planner"], tsan_objects["out"]), shapes, 4, 1, 13, graph=False)
+
+
+def test_allow_dynamic_lds_tsan(tsan_objects):
+    r = subprocess.run([tsan_objects["context_host"]], capture_output=True, text=True,
+                       timeout=300, env={**os.environ, **TSAN_ENV})
+    assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
+    lines = r.stdout.splitlines()
+    assert "unexpected" not in lines
+    calls = {}
+    for ln in lines:
+        parts = ln.split()
+        if len(parts) == 3 and parts[0] in ("0", "1"):
+            calls.setdefault((int(parts[0]), int(parts[1])), []).append(int(parts[2]))
+    assert sorted(calls) == [(k, d) for k in (0, 1) for d in range(3)]
+    for seq in calls.values():  # once per (kernel, device), raised only for a larger request
+        assert seq == sorted(set(seq)) and seq[-1] == 128 * 1024 and len(seq) <= 2, seq
+    assert "failed 1" in lines and "after 0" in lines  # RRF_E_HIP, then RRF_OK
+    assert [ln for ln in lines if ln.startswith("2 ")] == ["2 1 102400"]
