@@ -18,6 +18,20 @@ int dgemm_shaped(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t
                  const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
                  double* C, int64_t ldc, double* work, size_t work_elems, bool small_tiles,
                  int want_splits);
+// C = alpha op(A) op(B) where C is also one operand, with no temporary:
+// C = A (op(A) = A, lda = ldc) needs M >= 128 and N = 128; C = B (op(B) = B,
+// ldb = ldc) needs M = 128 and N >= 128. The product runs on 128 x 128
+// tiles, one tile across the dimension in which the aliased operand is
+// read, so each workgroup reads only the rows (columns) it writes, and every
+// read precedes the epilogue's stores (a split-K product writes C only in
+// its reduction, after all partial products). dgemm_in_place_fits tells
+// whether a call qualifies; dgemm_in_place returns RRF_E_NOTSUP without
+// launching when it does not.
+bool dgemm_in_place_fits(bool ta, bool tb, int64_t M, int64_t N, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, const double* C, int64_t ldc);
+int dgemm_in_place(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                   const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                   int64_t ldc, double* work, size_t work_elems);
 // C = alpha sum_z P_z + beta C for split-K partials P_z = P + z M N (ld M),
 // summed in split order.
 int splitk_reduce(hipStream_t st, int64_t M, int64_t N, int splits, const double* P, double alpha,

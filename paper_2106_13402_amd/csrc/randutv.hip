@@ -306,10 +306,14 @@ int boosted_sample(hipStream_t st, int64_t i, int64_t Mi, int64_t Ni, int64_t b,
   return RRF_OK;
 }
 
-// X(:, 0:k) <- X(:, 0:k) S  (rows x k times k x k) through `tmp`.
+// X(:, 0:k) <- X(:, 0:k) S  (rows x k times k x k): in place when one
+// 128-wide tile spans X's k columns, else through `tmp`.
 int right_mult(hipStream_t st, int64_t rows, int64_t k, double* X, int64_t ldx, const double* S,
                double* tmp, double* split, size_t split_elems) {
   if (rows <= 0 || k <= 0) return RRF_OK;
+  if (dgemm_in_place_fits(false, false, rows, k, X, ldx, S, k, X, ldx))
+    return dgemm_in_place(st, false, false, rows, k, k, 1.0, X, ldx, S, k, X, ldx, split,
+                          split_elems);
   RRF_TRY(dgemm(st, false, false, rows, k, k, 1.0, X, ldx, S, k, 0.0, tmp, rows, split,
                 split_elems));
   return copy_matrix(st, rows, k, tmp, rows, X, ldx);
@@ -626,9 +630,14 @@ int randutv_run(hipStream_t st, int64_t m, int64_t n, const double* A, int64_t l
     if (!last) {
       const int64_t N3 = n - c2;
       double* T2r = T + c0 + c2 * ldt;  // T(I2, J3) <- Us^T T(I2, J3)
-      RRF_TRY(dgemm(st, true, false, kb, N3, kb, 1.0, Usi, kb, T2r, ldt, 0.0, B.Zl, kb, nullptr,
-                    0));
-      RRF_TRY(copy_matrix(st, kb, N3, B.Zl, kb, T2r, ldt));
+      if (dgemm_in_place_fits(true, false, kb, N3, Usi, kb, T2r, ldt, T2r, ldt)) {
+        RRF_TRY(dgemm_in_place(st, true, false, kb, N3, kb, 1.0, Usi, kb, T2r, ldt, T2r, ldt,
+                               nullptr, 0));
+      } else {
+        RRF_TRY(dgemm(st, true, false, kb, N3, kb, 1.0, Usi, kb, T2r, ldt, 0.0, B.Zl, kb,
+                      nullptr, 0));
+        RRF_TRY(copy_matrix(st, kb, N3, B.Zl, kb, T2r, ldt));
+      }
     }
     if (U)
       RRF_TRY(right_mult(su, m, kb, U + c0 * ldu, ldu, Usi, B.back[0].tmp, B.back[0].split, SE));

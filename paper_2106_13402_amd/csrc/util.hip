@@ -141,6 +141,23 @@ int thin_q(hipStream_t st, int64_t M, int64_t k, const double* W, int64_t ldw, c
   return dgemm(st, false, false, M, k, k, -1.0, W, ldw, C, k, 1.0, Q, ldq, nullptr, 0);
 }
 
+bool dgemm_in_place_fits(bool ta, bool tb, int64_t M, int64_t N, const double* A, int64_t lda,
+                         const double* B, int64_t ldb, const double* C, int64_t ldc) {
+  if (A == C) return !ta && lda == ldc && M >= 128 && N == 128;
+  if (B == C) return !tb && ldb == ldc && M == 128 && N >= 128;
+  return false;
+}
+
+int dgemm_in_place(hipStream_t st, bool ta, bool tb, int64_t M, int64_t N, int64_t K, double alpha,
+                   const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                   int64_t ldc, double* work, size_t work_elems) {
+  if (!dgemm_in_place_fits(ta, tb, M, N, A, lda, B, ldb, C, ldc))
+    return set_error(RRF_E_NOTSUP, "dgemm_in_place: shape or aliasing not supported");
+  // M, N >= 128 without small tiles: dgemm_shaped takes 128 x 128 tiles
+  return dgemm_shaped(st, ta, tb, M, N, K, alpha, A, lda, B, ldb, 0.0, C, ldc, work, work_elems,
+                      false, 0);
+}
+
 int copy_matrix(hipStream_t st, int64_t rows, int64_t cols, const double* S, int64_t lds,
                 double* D, int64_t ldd) {
   if (rows <= 0 || cols <= 0) return RRF_OK;
