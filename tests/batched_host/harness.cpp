@@ -28,14 +28,15 @@ static void poison(double* p, size_t count) {
 
 int main(int argc, char** argv) {
   FILE* f = fopen(argv[1], "rb");
-  int64_t hdr[10];
-  if (fread(hdr, 8, 10, f) != 10) return 2;
+  int64_t hdr[11];
+  if (fread(hdr, 8, 11, f) != 11) return 2;
   const int64_t count = hdr[0], b = hdr[1], q = hdr[2];
   const uint64_t seed = hdr[3];
   const bool wu = hdr[4], wv = hdr[5], inplace = hdr[6];
   const int precision = (int)hdr[7];
   const bool graph = hdr[8] != 0;
   const int leaf = (int)hdr[9];
+  const int tile_mask = (int)hdr[10];
   std::vector<int64_t> m(count), n(count), lda(count);
   std::vector<const double*> A(count);
   std::vector<std::vector<double>> Ahost(count);
@@ -64,7 +65,7 @@ int main(int argc, char** argv) {
   void* w = alloc(ws);
   ((int*)w)[0] = 0; ((int*)w)[1] = 0;
   auto call = [&]() {
-    const rrf::BatchedCfg cfg{b, rrf::kTileMaskAll, leaf};
+    const rrf::BatchedCfg cfg{b, tile_mask, leaf};
     return rrf::randutv_batched_run(nullptr, count, m.data(), n.data(), A.data(), lda.data(), cfg,
                                     (int)q, seeds.data(), wu ? U.data() : nullptr, T.data(),
                                     wv ? V.data() : nullptr, w, ws, precision, graph);

@@ -214,8 +214,12 @@ int gemm_grouped(hipStream_t st_, bool ta, bool tb, int tile, bool vec, const Ge
     for (int64_t t = 0; t < tiles; ++t) {
       const long wg = prefix[p] + t;
       const int64_t i0 = (t % tm) * R, j0 = (t / tm) * Cc;
-      for (int64_t i = i0; i < std::min(i0 + R, g.M); ++i)
-        for (int64_t j = j0; j < std::min(j0 + Cc, g.N); ++j) {
+      const int64_t i1 = std::min(i0 + R, g.M), j1 = std::min(j0 + Cc, g.N);
+      // the kernel reads all of a tile's operands (and C for beta != 0)
+      // before its epilogue stores, so C may be the A or B it reads
+      std::vector<double> tile((size_t)(i1 - i0) * (j1 - j0));
+      for (int64_t i = i0; i < i1; ++i)
+        for (int64_t j = j0; j < j1; ++j) {
           double s = 0.0;
           for (int64_t k = 0; k < g.K; ++k) {
             const double a = ta ? rd(g.A + k + i * g.lda, wg) : rd(g.A + i + k * g.lda, wg);
@@ -224,8 +228,11 @@ int gemm_grouped(hipStream_t st_, bool ta, bool tb, int tile, bool vec, const Ge
           }
           double c = g.alpha * s;
           if (g.beta != 0.0) c += g.beta * rd(g.C + i + j * g.ldc, wg);
-          wr(g.C + i + j * g.ldc, c, wg);
+          tile[(size_t)(i - i0) + (size_t)(j - j0) * (i1 - i0)] = c;
         }
+      for (int64_t i = i0; i < i1; ++i)
+        for (int64_t j = j0; j < j1; ++j)
+          wr(g.C + i + j * g.ldc, tile[(size_t)(i - i0) + (size_t)(j - j0) * (i1 - i0)], wg);
     }
   }
   return RRF_OK;

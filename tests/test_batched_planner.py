@@ -7,7 +7,8 @@ every access (inside an allocation, no cross-workgroup conflict within a
 launch, no read of unwritten device memory). The emulated factorizations
 are then held to the oracle like the GPU results: U, V orthogonal,
 A = U T V^T, T upper trapezoidal with diagonal blocks, |T| equal to the
-oracle's. Cases cover ragged batches, n < b, the column split of tall
+oracle's. Cases cover ragged batches, n < b, the narrow tile family of the
+autotuner, the column split of tall
 panels (twice), T aliasing A, padded lda, and no U / no V. No GPU needed.
 """
 import os
@@ -48,14 +49,14 @@ def harness(tmp_path_factory):
 
 
 def _run(harness, shapes, b, q, seed, wu=True, wv=True, inplace=False, pad=0, precision=0,
-         graph=False, leaf=0):
+         graph=False, leaf=0, tile_mask=31):
     exe, out = harness
     rng = np.random.default_rng(len(shapes) * 7 + b + q)
     As = []
     fin, fout = str(out / "in.bin"), str(out / "out.bin")
     with open(fin, "wb") as f:
-        f.write(struct.pack("<10q", len(shapes), b, q, seed, int(wu), int(wv), int(inplace),
-                            precision, int(graph), leaf))
+        f.write(struct.pack("<11q", len(shapes), b, q, seed, int(wu), int(wv), int(inplace),
+                            precision, int(graph), leaf, tile_mask))
         for m, n in shapes:
             A = rng.standard_normal((m, n))
             As.append(A)
@@ -148,3 +149,13 @@ def test_planner_mixed_sketch(harness, graph):
     _run(harness, [(40, 30), (64, 64), (33, 17), (100, 64), (9, 4), (70, 70)], 8, 1, 5,
          precision=1, graph=graph)
     _run(harness, [(300, 200), (64, 10)], 32, 2, 11, precision=1, graph=graph)
+
+
+@MODES
+def test_planner_narrow_tiles(harness, graph):
+    # the autotuner's narrow tile family (128 x 32, 128 x 16; 64 x 64 is
+    # always allowed): every product of the plan on those shapes
+    narrow = (1 << 2) | (1 << 3)
+    _run(harness, [(200, 64), (150, 70), (33, 17), (64, 64)], 32, 1, 3, graph=graph,
+         tile_mask=narrow)
+    _run(harness, [(90, 40), (16, 16), (70, 33)], 16, 1, 8, graph=graph, tile_mask=narrow)
