@@ -327,12 +327,22 @@ void load_default_locked() {
 }
 
 // Architecture name of the current device (gcnArchName up to the first ':'),
-// empty without a device.
+// empty without a device. The properties are queried once per device: a
+// batched call with b = 0 looks up every matrix's configuration, and a
+// property query per matrix would cost the host thousands of queries per call.
+std::mutex g_arch_mu;
+std::map<int, std::string> g_arch;
+
 std::string current_arch() {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) {
     (void)hipGetLastError();
     return "";
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_arch_mu);
+    auto it = g_arch.find(dev);
+    if (it != g_arch.end()) return it->second;
   }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) {
@@ -341,7 +351,10 @@ std::string current_arch() {
   }
   std::string a = prop.gcnArchName;
   const size_t c = a.find(':');
-  return c == std::string::npos ? a : a.substr(0, c);
+  if (c != std::string::npos) a = a.substr(0, c);
+  std::lock_guard<std::mutex> lk(g_arch_mu);
+  g_arch[dev] = a;
+  return a;
 }
 
 BatchedCfg builtin_config(int64_t m, int64_t n) {

@@ -19,7 +19,7 @@
 // Output of the tuning modes: "autotune <rc> <mock errors>", then the
 // configurations for n = 1..8 and 64 as tuned, after an unload (the built-in
 // rule), and after loading the cache the search wrote. Of the batched mode:
-// "batched <rc> <mock errors>" for each call.
+// "batched <rc> <mock errors> <device property queries so far>" for each call.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -33,7 +33,9 @@
 
 extern "C" long mock_errors();
 
+static long g_prop_queries = 0;
 hipError_t hipGetDeviceProperties(hipDeviceProp_t* prop, int) {
+  ++g_prop_queries;
   memset(prop, 0, sizeof *prop);
   strcpy(prop->gcnArchName, "gfx950:sramecc+:xnack-");
   return hipSuccess;
@@ -163,7 +165,7 @@ int main(int argc, char** argv) {
       if (call == 1) unsetenv("RRF_TEST_FAIL");
       const int rc = rrf_randutv_batched(count, m.data(), n.data(), Ac.data(), m.data(), 0, 1, 7,
                                          U.data(), T.data(), V.data(), nullptr);
-      printf("batched %d %ld\n", rc, mock_errors());
+      printf("batched %d %ld %ld\n", rc, mock_errors(), g_prop_queries);
     }
     for (int64_t j = 0; j < count; ++j) (void)hipFree(A[j]);
     return rrf_release_workspace() == 0 ? 0 : 3;
