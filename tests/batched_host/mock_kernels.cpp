@@ -9,6 +9,9 @@
 //    within one launch (the kernels have no ordering between workgroups);
 //  * device memory starts as NaN, so a read of anything not written first
 //    poisons the results.
+// A grouped-GEMM tile reads all its operands before it stores, as the
+// kernel's epilogue does, so a product may write over an operand that only
+// its own workgroup reads.
 // Used only by tests/test_batched_planner.py; nothing here runs on a GPU.
 #include <hip/hip_runtime.h>
 
